@@ -1,0 +1,190 @@
+/*
+ * ipc.h -- C ABI of the MI355X IPC gel-pad step library (libipcgel.so).
+ *
+ * One call advances a tetrahedral gel pad and a kinematically driven indenter
+ * by one implicit time step of the Incremental Potential Contact model: the
+ * soft-body step the paper runs through GIPC after setting attachment targets
+ * (paper sections "General GIPC Simulation Pipeline" and "GIPC Attachments";
+ * the IPC model and its guarantees are cited in "Choice of the Simulation
+ * Methods"). Newton on Neo-Hookean elasticity plus a log barrier, PSD-projected
+ * Hessians, spatial-hash contact culling, block-Jacobi PCG and a CCD-filtered
+ * backtracking line search, all in HIP kernels on one GPU.
+ *
+ * Conventions
+ *  - Vertex ids: gel vertices 0..n_verts-1, then indenter vertices.
+ *  - Positions are FP64, interleaved xyz (3 doubles per vertex).
+ *  - Every call returns an int32 status: 0 = IPC_OK, > 0 = warning (the state
+ *    was committed and is feasible: no interpenetration, every tet J > 0),
+ *    < 0 = error (state unchanged). No exception or abort crosses the ABI.
+ *  - Host arrays passed in are copied; the caller keeps ownership of every
+ *    buffer it passes. The library owns device state from create to destroy.
+ *  - Different scenes may be used from different threads; one scene must not
+ *    be used by two threads at once.
+ */
+#ifndef IPC_H
+#define IPC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define IPC_API __attribute__((visibility("default")))
+#else
+#define IPC_API
+#endif
+
+#define IPC_OK 0
+#define IPC_W_NEWTON_MAXITER 1 /* Newton hit max_newton; last iterate committed */
+#define IPC_W_PCG_MAXITER 2    /* a PCG solve hit its iteration cap */
+#define IPC_W_LS_STALL 3       /* line search shrank below ls_min_ratio; Newton ended */
+#define IPC_W_TARGET_LAG 4     /* an indenter vertex ends > 1e-3 dhat from its target */
+#define IPC_E_INVALID_ARG -1
+#define IPC_E_BAD_MESH -2      /* non-positive rest volume, index out of range, non-manifold */
+#define IPC_E_INFEASIBLE -3    /* initial state has a pair at d <= 0 or a tet with J <= 0 */
+#define IPC_E_OOM -4           /* allocator or memory budget refused */
+#define IPC_E_DEVICE -5        /* HIP runtime error */
+#define IPC_E_BUSY -6          /* scene already has a step in flight */
+#define IPC_E_CAPACITY -7      /* contact list growth failed */
+
+#define IPC_FP64 0   /* every stage in FP64 */
+#define IPC_MIXED 1  /* FP32 assembly/SpMV/PCG vectors, FP64 dots, distances, CCD, energies */
+
+#define IPC_HOST 0
+#define IPC_DEVICE 1
+
+typedef struct ipc_scene ipc_scene;
+typedef struct ipc_batch ipc_batch;
+typedef int64_t ipc_ticket;
+
+/* Scene description. The gel is a tet mesh (positively oriented tets); the
+ * indenter is a triangle mesh in its local frame whose vertices are pulled to
+ * the rigid pose of each step by a penalty k_target per vertex. */
+typedef struct ipc_scene_desc {
+    int32_t n_verts;          /* gel vertices */
+    const double *X;          /* n_verts x 3 rest positions (host) */
+    int32_t n_tets;
+    const int32_t *T;         /* n_tets x 4 (host) */
+    const uint8_t *fixed;     /* n_verts Dirichlet mask, may be NULL (host) */
+    double E, nu, rho;        /* Neo-Hookean material */
+    int32_t n_ind_verts;
+    const double *ind_Y;      /* n_ind_verts x 3, indenter local frame (host) */
+    int32_t n_ind_tris;
+    const int32_t *ind_tris;  /* n_ind_tris x 3 (host) */
+    double ind_pose0[12];     /* initial indenter pose, row-major 3x4 [R|c] */
+    double dt;                /* time step (s) */
+    double dhat, kappa;       /* barrier activation distance (m), stiffness (N/m) */
+    double k_target;          /* kinematic target penalty (N/m) */
+    double newton_tol;        /* converged when max |p_i| over free DOFs <= newton_tol (m) */
+    double pcg_tol;           /* PCG stops at r^T M^-1 r <= pcg_tol^2 r0^T M^-1 r0 */
+    double gravity[3];
+    double mu_friction, eps_v;/* lagged friction (0 = off) */
+    double ccd_s;             /* ACCD keep-gap fraction (0.1) */
+    double ls_min_ratio;      /* line search stall ratio (2^-30) */
+    int32_t self_contact;     /* 1: gel-gel PT/EE pairs take part */
+    int32_t precision;        /* IPC_FP64 or IPC_MIXED */
+    int32_t max_newton;       /* 0: 100 */
+    int32_t pcg_max_iter;     /* 0: 10 * 3 * (all vertices) */
+    int32_t ccd_max_iter;     /* 0: 10000 */
+} ipc_scene_desc;
+
+/* Device memory and stream plumbing. alloc/free may be NULL (then hipMalloc /
+ * hipFree); the Python binding routes them to PyTorch's caching allocator.
+ * stream is a hipStream_t (NULL = default stream). mem_budget <= 0: none. */
+typedef void *(*ipc_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*ipc_free_fn)(void *ptr, size_t bytes, void *stream, void *user);
+typedef struct ipc_runtime {
+    void *stream;
+    ipc_alloc_fn alloc;
+    ipc_free_fn free;
+    void *user;
+    int64_t mem_budget;
+} ipc_runtime;
+
+/* One step request: the indenter's target pose at t+1 (row-major 3x4). */
+typedef struct ipc_step_req {
+    double pose[12];
+} ipc_step_req;
+
+typedef struct ipc_step_stats {
+    int32_t status;
+    int32_t newton_iters;     /* Newton iterations (each one assemble + solve) */
+    int32_t pcg_iters;        /* PCG iterations summed over the step */
+    int32_t ls_halvings;
+    int32_t n_candidates;     /* static candidates at the last iterate */
+    int32_t n_active;         /* active pairs (d < dhat) at the last iterate */
+    double alpha_ccd, alpha;  /* last Newton iteration */
+    double energy;            /* incremental potential at the committed state */
+    double pinf;              /* last |p|_inf */
+    double max_target_lag;    /* max |y_j - yhat_j| over indenter vertices (m) */
+    double ms_total;          /* wall time of the step on the host (ms) */
+    double ms_phase[8];       /* assemble, contact, pcg, ccd, line search, other */
+} ipc_step_stats;
+
+/* Create a scene. Validates the mesh (indices, rest volumes > 0, manifold
+ * surface), precomputes rest shape, lumped mass, surface primitives and the
+ * matrix pattern, and uploads everything. On error *out = NULL, nothing leaks. */
+IPC_API int32_t ipc_create_scene(const ipc_scene_desc *d, const ipc_runtime *rt, ipc_scene **out);
+IPC_API void ipc_destroy_scene(ipc_scene *s);
+/* Resident bytes plus per-step scratch estimate for admission control. */
+IPC_API int64_t ipc_scene_footprint_bytes(const ipc_scene_desc *d);
+/* One implicit step toward r->pose; blocks until done on the scene's stream. */
+IPC_API int32_t ipc_step(ipc_scene *s, const ipc_step_req *r, ipc_step_stats *st);
+/* Surface vertex positions in ascending gel-vertex id order (3 doubles each)
+ * and the mean of all gel vertices ("object position"). where = IPC_HOST or
+ * IPC_DEVICE for xyz; obj_pos (host, may be NULL). cap in doubles. */
+IPC_API int32_t ipc_read_surface(const ipc_scene *s, double *xyz, int64_t cap, int32_t where, void *stream,
+                         double obj_pos[3]);
+/* Surface topology: gel surface triangles (outward, vertex ids) and the
+ * ascending list of gel surface vertex ids. Either pointer may be NULL. */
+IPC_API int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris,
+                             int32_t *verts, int64_t vert_cap, int32_t *n_surf_verts);
+/* Reset: positions to rest, velocities to zero, indenter to its initial pose
+ * (paper section "General GIPC Simulation Pipeline"). */
+IPC_API int32_t ipc_reset(ipc_scene *s);
+/* Save / load x, v and the step index to / from a caller-owned host blob. */
+IPC_API int64_t ipc_state_bytes(const ipc_scene *s);
+IPC_API int32_t ipc_save_state(const ipc_scene *s, void *blob, int64_t cap);
+IPC_API int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes);
+/* Sizes: out[0..7] = n_all, n_gel, n_tets, n_points, n_edges, n_tris, n_ind, n_gel_tris. */
+IPC_API int32_t ipc_scene_sizes(const ipc_scene *s, int32_t *out);
+
+/* Batched asynchronous stepping. Every scene of a submit must be idle (else
+ * IPC_E_BUSY, nothing queued). ipc_step == submit of one + wait. */
+IPC_API int32_t ipc_batch_create(const ipc_runtime *rt, ipc_batch **out);
+IPC_API void ipc_batch_destroy(ipc_batch *b);
+IPC_API int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, const ipc_step_req *r,
+                         ipc_ticket *t);
+/* 1 if done (stats filled), 0 if pending, < 0 on error. */
+IPC_API int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
+IPC_API int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
+
+IPC_API const char *ipc_status_str(int32_t status);
+/* Last error message of the calling thread; returns its length. */
+IPC_API int32_t ipc_last_error(char *buf, size_t cap);
+
+/* ---- test-only entry points: pure functions of the given state ----------
+ * Host arrays of 3 doubles per vertex (all vertices). They use the step
+ * context (predictor and targets) set by ipcx_begin_step. */
+IPC_API int32_t ipcx_begin_step(ipc_scene *s, const ipc_step_req *r);
+IPC_API int32_t ipcx_newton_iterate(ipc_scene *s, const double *x_in, double *x_out, ipc_step_stats *st);
+/* Candidates at x (p NULL) or over [x, x+p]: int32 triples (type, a, b) in
+ * canonical order; PT a = point vertex id, b = triangle index; EE a < b edge
+ * indices. Triangle and edge numbering as ipcx_primitives reports. */
+IPC_API int32_t ipcx_candidates(ipc_scene *s, const double *x, const double *p, int32_t *out, int64_t cap,
+                        int64_t *count);
+IPC_API int32_t ipcx_primitives(const ipc_scene *s, int32_t *points, int32_t *edges, int32_t *tris);
+IPC_API int32_t ipcx_gradient(ipc_scene *s, const double *x, double *g);
+IPC_API int32_t ipcx_hess_apply(ipc_scene *s, const double *x, const double *v, double *y);
+IPC_API int32_t ipcx_pcg(ipc_scene *s, const double *x, double *p, int32_t *iters);
+IPC_API int32_t ipcx_energy(ipc_scene *s, const double *x, double *E);
+IPC_API int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double *alpha);
+IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);
+IPC_API int32_t ipcx_get_state(const ipc_scene *s, double *x, double *v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
