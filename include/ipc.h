@@ -181,6 +181,15 @@ IPC_API int32_t ipcx_hess_apply(ipc_scene *s, const double *x, const double *v, 
 IPC_API int32_t ipcx_pcg(ipc_scene *s, const double *x, double *p, int32_t *iters);
 IPC_API int32_t ipcx_energy(ipc_scene *s, const double *x, double *E);
 IPC_API int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double *alpha);
+/* Per-kernel timing with HIP events on the scene's stream: enable (resets the
+ * totals) / read launches and summed milliseconds of a kernel class:
+ * 0 PCG SpMV kernel, 1 PCG update kernel, 2 elastic elements, 3 assembly
+ * gather, 4 broad phase, 5 narrow phase + barrier, 6 energy, 7 CCD. */
+IPC_API int32_t ipcx_profile(ipc_scene *s, int32_t enable);
+IPC_API int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches, double *ms_total);
+/* out[0..7] = stored elastic blocks, stored BELL entries incl. padding, vertices,
+ * active pairs, tets, static candidates, swept candidates, gather entries. */
+IPC_API int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out);
 IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);
 IPC_API int32_t ipcx_get_state(const ipc_scene *s, double *x, double *v);
 

@@ -30,6 +30,19 @@ constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
 constexpr int kElemBlocks = 10;   // upper-triangle 3x3 blocks of a 12x12 element matrix
 
+// kernels timed by the optional profiler
+enum ProfKernel {
+    kProfPcgA = 0,        // SpMV + fused direction update (PCG A)
+    kProfPcgB = 1,        // PCG vector update + preconditioner (PCG B)
+    kProfElastic = 2,     // Neo-Hookean element kernel
+    kProfAssemble = 3,    // gradient + matrix gather
+    kProfBroad = 4,       // boxes, hash, queries
+    kProfBarrier = 5,     // narrow phase + barrier + incidence
+    kProfEnergy = 6,      // line-search energy
+    kProfCcd = 7,         // additive CCD
+    kProfKernels = 8
+};
+
 // Rigid pose [R|c], row-major 3x4, passed to kernels by value.
 struct Pose {
     double m[12];
@@ -159,6 +172,17 @@ class Scene {
     Readback *hb = nullptr;          // pinned
     int step_index = 0;
     bool busy = false;
+    int last_pcg_iters = 0;          // iterations of the last PCG solve
+    int64_t nnzb = 0;                // stored (non-padding) elastic blocks
+
+    // optional per-kernel timing with HIP events on the scene's stream
+    bool prof = false;
+    struct ProfAcc {
+        int64_t launches = 0;
+        double ms = 0.0;
+    } prof_acc[kProfKernels];
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 
     ~Scene();
 };
@@ -199,6 +223,12 @@ void exclusive_scan(Scene &s, const int32_t *in, int32_t *out, int n, int32_t *t
 void ensure_iscratch(Scene &s, size_t n);
 void ensure_query(Scene &s, size_t n);
 
+// profiler: prof_begin/prof_end bracket launches of one kernel class;
+// prof_collect (after a stream sync) accumulates the elapsed times
+void prof_begin(Scene &s, int kernel, hipEvent_t *pair);
+void prof_end(Scene &s, int kernel, hipEvent_t *pair);
+void prof_collect(Scene &s);
+
 // errors
 void set_error(const std::string &msg);
 int32_t hip_fail(hipError_t e, const char *where);
@@ -216,6 +246,7 @@ struct HipError {
 };
 struct OomError {};
 struct CapacityError {};
+struct InfeasibleError {};
 
 template <class T>
 T *dalloc(Scene &s, size_t count)

@@ -149,115 +149,12 @@ __device__ __forceinline__ double pair_distance(int kind, const double *x)
     return sqrt(dist_residual(sp, x, r, c, u, G));
 }
 
-// grad / Hessian of s = |r(x, beta*(x))|^2 at fixed type (envelope theorem
-// plus implicit differentiation of the optimal parameters)
-__device__ double dist_sq_derivs(const DistSpec &sp, const double *x, double gs[12], double Hs[144])
-{
-    double r[3], c[4], u[2][3], G[3];
-    double s = dist_residual(sp, x, r, c, u, G);
-    for (int k = 0; k < 4; ++k)
-        for (int i = 0; i < 3; ++i) gs[3 * k + i] = 2.0 * c[k] * r[i];
-    for (int a = 0; a < 144; ++a) Hs[a] = 0.0;
-    for (int k = 0; k < 4; ++k)
-        for (int l = 0; l < 4; ++l) {
-            double v = 2.0 * c[k] * c[l];
-            for (int i = 0; i < 3; ++i) Hs[(3 * k + i) * 12 + 3 * l + i] = v;
-        }
-    if (sp.np > 0) {
-        double W[12][2];
-        for (int k = 0; k < 4; ++k)
-            for (int i = 0; i < 3; ++i)
-                for (int m = 0; m < sp.np; ++m) W[3 * k + i][m] = 2.0 * (sp.D[m][k] * r[i] + c[k] * u[m][i]);
-        double S00, S01 = 0.0, S11 = 0.0;
-        if (sp.np == 1) {
-            S00 = 1.0 / (2.0 * G[0]);
-        } else {
-            double a = 2.0 * G[0], b = 2.0 * G[1], d = 2.0 * G[2];
-            double det = a * d - b * b;
-            S00 = d / det;
-            S01 = -b / det;
-            S11 = a / det;
-        }
-        for (int p = 0; p < 12; ++p)
-            for (int q = 0; q < 12; ++q) {
-                double acc = W[p][0] * S00 * W[q][0];
-                if (sp.np == 2) acc += W[p][0] * S01 * W[q][1] + W[p][1] * S01 * W[q][0] + W[p][1] * S11 * W[q][1];
-                Hs[p * 12 + q] -= acc;
-            }
-    }
-    return s;
-}
-
 __device__ __forceinline__ void barrier3(double d, double dhat, double b[3])
 {
     double t = d - dhat, L = log(d / dhat);
     b[0] = -t * t * L;
     b[1] = -2.0 * t * L - t * t / d;
     b[2] = -2.0 * L - 4.0 * t / d + t * t / (d * d);
-}
-
-// cyclic Jacobi on a symmetric 12x12 (row-major), then clamp negative
-// eigenvalues: A <- V diag(max(w,0)) V^T. V is caller scratch.
-__device__ void psd_project12(double *A, double *V)
-{
-    for (int i = 0; i < 144; ++i) V[i] = (i % 13 == 0) ? 1.0 : 0.0;
-    double fro = 0.0;
-    for (int i = 0; i < 144; ++i) fro += A[i] * A[i];
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < 12; ++p)
-            for (int q = p + 1; q < 12; ++q) off += A[p * 12 + q] * A[p * 12 + q];
-        if (off <= 1e-36 * fro || off == 0.0) break;
-        for (int p = 0; p < 11; ++p)
-            for (int q = p + 1; q < 12; ++q) {
-                double apq = A[p * 12 + q];
-                if (apq == 0.0) continue;
-                double theta = (A[q * 12 + q] - A[p * 12 + p]) / (2.0 * apq);
-                double t = fabs(theta) > 1e150 ? 0.5 / theta
-                                               : (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < 12; ++k) {
-                    double akp = A[k * 12 + p], akq = A[k * 12 + q];
-                    A[k * 12 + p] = c * akp - s * akq;
-                    A[k * 12 + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < 12; ++k) {
-                    double apk = A[p * 12 + k], aqk = A[q * 12 + k];
-                    A[p * 12 + k] = c * apk - s * aqk;
-                    A[q * 12 + k] = s * apk + c * aqk;
-                }
-                A[p * 12 + q] = 0.0;
-                A[q * 12 + p] = 0.0;
-                for (int k = 0; k < 12; ++k) {
-                    double vkp = V[k * 12 + p], vkq = V[k * 12 + q];
-                    V[k * 12 + p] = c * vkp - s * vkq;
-                    V[k * 12 + q] = s * vkp + c * vkq;
-                }
-            }
-    }
-    double w[12];
-    bool neg = false;
-    for (int i = 0; i < 12; ++i) {
-        w[i] = A[i * 12 + i];
-        neg |= w[i] < 0.0;
-    }
-    if (!neg) {
-        // A now holds the diagonalised matrix; rebuild V diag(w) V^T
-        for (int i = 0; i < 12; ++i)
-            for (int j = 0; j < 12; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k < 12; ++k) acc += V[i * 12 + k] * w[k] * V[j * 12 + k];
-                A[i * 12 + j] = acc;
-            }
-        return;
-    }
-    for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j) {
-            double acc = 0.0;
-            for (int k = 0; k < 12; ++k)
-                if (w[k] > 0.0) acc += V[i * 12 + k] * w[k] * V[j * 12 + k];
-            A[i * 12 + j] = acc;
-        }
 }
 
 // vertex ids of a candidate: PT (p, t0, t1, t2), EE (a0, a1, b0, b1)
@@ -316,22 +213,26 @@ __global__ void k_boxes(int N, int nv, const int32_t *__restrict__ vids, int str
     }
 }
 
+// per-block sums of the largest axis extent of each box
 __global__ void k_box_extent(int N, const double *__restrict__ box, double *__restrict__ part)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < N)
         for (int c = 0; c < 3; ++c) e = fmax(e, box[(3 + c) * N + i] - box[c * N + i]);
-    e = block_max_all(e);
+    e = block_sum_all(e);
     if (threadIdx.x == 0) part[blockIdx.x] = e;
 }
 
-__global__ void k_cell_size(int nb, const double *__restrict__ part, double *cell_h)
+// cell size = mean extent of the edge and triangle boxes (never below the
+// inflation dhat): most primitives span 1-3 cells per axis, large ones more
+__global__ void k_cell_size(int nb, const double *__restrict__ part, double count, double floor_h,
+                            double *cell_h)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, part[i]);
-    v = block_max_all(v);
-    if (threadIdx.x == 0) *cell_h = 1.01 * v;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+    v = block_sum_all(v);
+    if (threadIdx.x == 0) *cell_h = fmax(v / count, floor_h);
 }
 
 __device__ __forceinline__ int cell_of(double v, double h) { return (int)floor(v / h); }
@@ -340,21 +241,27 @@ __device__ __forceinline__ uint32_t cell_hash(int ix, int iy, int iz, uint32_t m
     return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
 }
 
+// Cells spanned per axis by one box are bounded by this; a larger span means
+// a non-finite or absurd position, which is flagged and skipped.
+constexpr int kMaxSpan = 4096;
+
 template <bool FILL>
 __global__ void k_hash_insert(int N, const double *__restrict__ box, const double *__restrict__ cell_h, uint32_t mask,
                               int32_t *__restrict__ counter, const int32_t *__restrict__ start,
-                              int4 *__restrict__ entries, int entry_cap)
+                              int4 *__restrict__ entries, int entry_cap, int32_t *__restrict__ bad)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double h = *cell_h;
     int lo[3], hi[3];
     for (int c = 0; c < 3; ++c) {
-        lo[c] = cell_of(box[c * N + i], h);
-        hi[c] = cell_of(box[(3 + c) * N + i], h);
-        // the cell size bounds every box to two cells per axis; anything else
-        // is a non-finite position: skip it instead of looping over garbage
-        if (hi[c] < lo[c] || hi[c] - lo[c] > 2) return;
+        double a = box[c * N + i], b = box[(3 + c) * N + i];
+        if (!(a <= b) || !((b - a) / h < (double)kMaxSpan)) {
+            if (!FILL) atomicOr(bad, 1);
+            return;
+        }
+        lo[c] = cell_of(a, h);
+        hi[c] = cell_of(b, h);
     }
     for (int iz = lo[2]; iz <= hi[2]; ++iz)
         for (int iy = lo[1]; iy <= hi[1]; ++iy)
@@ -412,12 +319,12 @@ __global__ void __launch_bounds__(kBlock) k_query(int NA, const double *__restri
     for (int c = 0; c < 3; ++c) {
         alo[c] = abox[c * NA + qa];
         ahi[c] = abox[(3 + c) * NA + qa];
-        clo[c] = cell_of(alo[c], h);
-        chi[c] = cell_of(ahi[c], h);
-        if (chi[c] < clo[c] || chi[c] - clo[c] > 2) {
+        if (!(alo[c] <= ahi[c]) || !((ahi[c] - alo[c]) / h < (double)kMaxSpan)) {
             if (COUNT) qcount[qa] = 0;
             return;
         }
+        clo[c] = cell_of(alo[c], h);
+        chi[c] = cell_of(ahi[c], h);
     }
     int va[2];
     int a_id;
@@ -510,7 +417,65 @@ __global__ void k_compact(int64_t nc, const int32_t *__restrict__ flag, const in
     if (i < nc && flag[i]) out[pos[i]] = (int32_t)i;
 }
 
-// kappa * w * b(d) for each active pair: gradient and PSD-projected Hessian
+// Shared per-pair data of the distance derivatives at fixed type: residual r,
+// coefficients c at beta*, parameter directions u, and the 12 x np block W of
+// s_xb with S = s_bb^-1 (np <= 2).
+struct DistDeriv {
+    int np;
+    double r[3], c[4], W[12][2], S00, S01, S11, s;
+};
+
+__device__ void dist_deriv_setup(const DistSpec &sp, const double *x, DistDeriv &dd)
+{
+    double u[2][3], G[3];
+    dd.np = sp.np;
+    dd.s = dist_residual(sp, x, dd.r, dd.c, u, G);
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int m = 0; m < 2; ++m)
+                dd.W[3 * k + i][m] = m < sp.np ? 2.0 * (sp.D[m][k] * dd.r[i] + dd.c[k] * u[m][i]) : 0.0;
+    dd.S00 = dd.S01 = dd.S11 = 0.0;
+    if (sp.np == 1) {
+        dd.S00 = 1.0 / (2.0 * G[0]);
+    } else if (sp.np == 2) {
+        double a = 2.0 * G[0], b = 2.0 * G[1], d = 2.0 * G[2];
+        double det = a * d - b * b;
+        dd.S00 = d / det;
+        dd.S01 = -b / det;
+        dd.S11 = a / det;
+    }
+}
+
+// d2s/dx_p dx_q at fixed type
+__device__ __forceinline__ double dist_hess_entry(const DistDeriv &dd, int p, int q)
+{
+    int k = p / 3, i = p % 3, l = q / 3, j = q % 3;
+    double v = (i == j) ? 2.0 * dd.c[k] * dd.c[l] : 0.0;
+    if (dd.np > 0) {
+        double acc = dd.W[p][0] * dd.S00 * dd.W[q][0];
+        if (dd.np == 2)
+            acc += dd.W[p][0] * dd.S01 * dd.W[q][1] + dd.W[p][1] * dd.S01 * dd.W[q][0] + dd.W[p][1] * dd.S11 * dd.W[q][1];
+        v -= acc;
+    }
+    return v;
+}
+
+// Round-robin (circle method) pairing of 12 indices: in round r the six
+// disjoint pairs meet; over 11 rounds every pair meets once.
+__device__ __forceinline__ void rr_pair(int round, int i, int &p, int &q)
+{
+    int pa = i, pb = 11 - i;
+    int a = pa == 0 ? 0 : ((pa - 1 + round) % 11) + 1;
+    int b = ((pb - 1 + round) % 11) + 1;
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+// kappa * w * b(d) for each active pair: gradient and PSD-projected Hessian.
+// One wavefront per pair: lanes evaluate Hessian entries, then a parallel
+// cyclic Jacobi (six disjoint rotations per round) diagonalises the 12x12 in
+// LDS and negative eigenvalues are clamped to zero. Matrices that are already
+// PSD are kept as assembled.
 __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, const int32_t *__restrict__ act_idx,
                                                 int64_t cap, const int32_t *__restrict__ cand, Topo tp,
                                                 const double *__restrict__ edge_rest_sq,
@@ -519,8 +484,12 @@ __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, c
                                                 int32_t *__restrict__ act_v, double *__restrict__ act_g,
                                                 double *__restrict__ act_H)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double A[144], V[144], A0[144];
+    __shared__ double rc[6], rs[6];
+    __shared__ int rp[6], rq[6];
+    int64_t k = blockIdx.x;
     if (k >= nact) return;
+    const int lane = threadIdx.x;
     int ci = act_idx[k];
     int type = cand[ci], a = cand[cap + ci], b = cand[2 * cap + ci];
     int v[4];
@@ -528,24 +497,23 @@ __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, c
     cand_vertices(tp, type, a, b, v);
     gather12(x, v, x12);
     DistSpec sp = type == 0 ? c_pt_spec[classify_pt(x12)] : c_ee_spec[classify_ee(x12)];
-    double gs[12], H[144], Vs[144];
-    double s = dist_sq_derivs(sp, x12, gs, H);
-    double d = sqrt(s);
+    DistDeriv dd;
+    dist_deriv_setup(sp, x12, dd);
+    double d = sqrt(dd.s);
     double bb[3];
     barrier3(d, dhat, bb);
-    // grad d = gs / (2d); hess d = Hs / (2d) - gs gs^T / (4 d^3)
-    double gd[12];
-    for (int i = 0; i < 12; ++i) gd[i] = gs[i] / (2.0 * d);
+    // gs = 2 c_k r_i, gd = gs / (2d)
     double inv2d = 1.0 / (2.0 * d), inv4d3 = 1.0 / (4.0 * d * d * d);
-    for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j) H[i * 12 + j] = H[i * 12 + j] * inv2d - gs[i] * gs[j] * inv4d3;
+    // EE mollifier
     double w = 1.0, m1 = 0.0, m2 = 0.0;
-    double gc[12];
     bool moll = false;
+    double ea[3], eb[3], aa = 0.0, bq = 0.0, ab = 0.0;
     if (type == 1) {
         double eps_x = kMollifier * edge_rest_sq[a] * edge_rest_sq[b];
-        double ea[3] = {x12[3] - x12[0], x12[4] - x12[1], x12[5] - x12[2]};
-        double eb[3] = {x12[9] - x12[6], x12[10] - x12[7], x12[11] - x12[8]};
+        for (int i = 0; i < 3; ++i) {
+            ea[i] = x12[3 + i] - x12[i];
+            eb[i] = x12[9 + i] - x12[6 + i];
+        }
         double cr[3] = {ea[1] * eb[2] - ea[2] * eb[1], ea[2] * eb[0] - ea[0] * eb[2], ea[0] * eb[1] - ea[1] * eb[0]};
         double cval = d3(cr, cr);
         if (cval < eps_x) {
@@ -553,62 +521,130 @@ __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, c
             w = -cval * cval / (eps_x * eps_x) + 2.0 * cval / eps_x;
             m1 = -2.0 * cval / (eps_x * eps_x) + 2.0 / eps_x;
             m2 = -2.0 / (eps_x * eps_x);
-            double aa = d3(ea, ea), bq = d3(eb, eb), ab = d3(ea, eb);
-            double ga[3], gb[3];
-            for (int i = 0; i < 3; ++i) {
-                ga[i] = 2.0 * bq * ea[i] - 2.0 * ab * eb[i];
-                gb[i] = 2.0 * aa * eb[i] - 2.0 * ab * ea[i];
-                gc[i] = -ga[i];
-                gc[3 + i] = ga[i];
-                gc[6 + i] = -gb[i];
-                gc[9 + i] = gb[i];
-            }
-            // Hessian of c in (a, b) with a = x1 - x0, b = x3 - x2
-            const double sa[4] = {-1, 1, 0, 0}, sb[4] = {0, 0, -1, 1};
-            for (int p = 0; p < 4; ++p)
-                for (int q = 0; q < 4; ++q)
-                    for (int i = 0; i < 3; ++i)
-                        for (int j = 0; j < 3; ++j) {
-                            double dij = i == j ? 1.0 : 0.0;
-                            double haa = 2.0 * bq * dij - 2.0 * eb[i] * eb[j];
-                            double hbb = 2.0 * aa * dij - 2.0 * ea[i] * ea[j];
-                            double hab = 4.0 * ea[i] * eb[j] - 2.0 * ab * dij - 2.0 * eb[i] * ea[j];
-                            double hba = 4.0 * ea[j] * eb[i] - 2.0 * ab * dij - 2.0 * eb[j] * ea[i];
-                            double hc = sa[p] * sa[q] * haa + sb[p] * sb[q] * hbb + sa[p] * sb[q] * hab + sb[p] * sa[q] * hba;
-                            int row = 3 * p + i, col = 3 * q + j;
-                            // full pair Hessian assembled in place below; keep c-terms now
-                            Vs[row * 12 + col] = hc;
-                        }
+            aa = d3(ea, ea);
+            bq = d3(eb, eb);
+            ab = d3(ea, eb);
         }
     }
-    double g12[12];
-    for (int i = 0; i < 12; ++i) {
-        double gv = w * bb[1] * gd[i];
-        if (moll) gv += bb[0] * m1 * gc[i];
-        g12[i] = kappa * gv;
-    }
-    for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j) {
-            double hv = w * (bb[2] * gd[i] * gd[j] + bb[1] * H[i * 12 + j]);
-            if (moll) {
-                hv += bb[0] * (m2 * gc[i] * gc[j] + m1 * Vs[i * 12 + j]);
-                hv += bb[1] * m1 * (gc[i] * gd[j] + gd[i] * gc[j]);
-            }
-            H[i * 12 + j] = kappa * hv;
+    const double sa[4] = {-1, 1, 0, 0}, sb[4] = {0, 0, -1, 1};
+    auto gs_of = [&](int p) { return 2.0 * dd.c[p / 3] * dd.r[p % 3]; };
+    auto gc_of = [&](int p) {
+        int kk = p / 3, i = p % 3;
+        double ga = 2.0 * bq * ea[i] - 2.0 * ab * eb[i];
+        double gb = 2.0 * aa * eb[i] - 2.0 * ab * ea[i];
+        return sa[kk] * ga + sb[kk] * gb;
+    };
+    // entries of the unprojected pair Hessian
+    for (int e = lane; e < 144; e += 64) {
+        int p = e / 12, q = e % 12;
+        double gsp = gs_of(p), gsq = gs_of(q);
+        double gdp = gsp * inv2d, gdq = gsq * inv2d;
+        double hd = dist_hess_entry(dd, p, q) * inv2d - gsp * gsq * inv4d3;
+        double hv = w * (bb[2] * gdp * gdq + bb[1] * hd);
+        if (moll) {
+            int kp = p / 3, i = p % 3, kq = q / 3, j = q % 3;
+            double dij = i == j ? 1.0 : 0.0;
+            double haa = 2.0 * bq * dij - 2.0 * eb[i] * eb[j];
+            double hbb = 2.0 * aa * dij - 2.0 * ea[i] * ea[j];
+            double hab = 4.0 * ea[i] * eb[j] - 2.0 * ab * dij - 2.0 * eb[i] * ea[j];
+            double hba = 4.0 * ea[j] * eb[i] - 2.0 * ab * dij - 2.0 * eb[j] * ea[i];
+            double hc = sa[kp] * sa[kq] * haa + sb[kp] * sb[kq] * hbb + sa[kp] * sb[kq] * hab + sb[kp] * sa[kq] * hba;
+            double gcp = gc_of(p), gcq = gc_of(q);
+            hv += bb[0] * (m2 * gcp * gcq + m1 * hc);
+            hv += bb[1] * m1 * (gcp * gdq + gdp * gcq);
         }
-    psd_project12(H, Vs);
-    // Dirichlet vertices: their rows and columns drop out (identity rows live
-    // in the elastic matrix)
-    for (int pv = 0; pv < 4; ++pv)
-        if (fixed[v[pv]])
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 12; ++j) {
-                    H[(3 * pv + i) * 12 + j] = 0.0;
-                    H[j * 12 + 3 * pv + i] = 0.0;
+        A[e] = kappa * hv;
+        A0[e] = A[e];
+        V[e] = (p == q) ? 1.0 : 0.0;
+    }
+    if (lane < 12) {
+        double gv = w * bb[1] * gs_of(lane) * inv2d;
+        if (moll) gv += bb[0] * m1 * gc_of(lane);
+        act_g[(int64_t)lane * act_cap + k] = kappa * gv;
+    }
+    if (lane < 4) act_v[(int64_t)lane * act_cap + k] = v[lane];
+    __syncthreads();
+
+    // parallel cyclic Jacobi
+    double fro = 0.0;
+    for (int e = lane; e < 144; e += 64) fro += A[e] * A[e];
+    fro = wave_sum(fro);
+    fro = __shfl(fro, 0, 64);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int e = lane; e < 144; e += 64) {
+            int p = e / 12, q = e % 12;
+            if (p < q) off += A[e] * A[e];
+        }
+        off = wave_sum(off);
+        off = __shfl(off, 0, 64);
+        if (off <= 1e-36 * fro || off == 0.0) break;
+        for (int round = 0; round < 11; ++round) {
+            if (lane < 6) {
+                int p, q;
+                rr_pair(round, lane, p, q);
+                double apq = A[p * 12 + q];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    double theta = (A[q * 12 + q] - A[p * 12 + p]) / (2.0 * apq);
+                    double t = fabs(theta) > 1e150 ? 0.5 / theta
+                                                   : (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    sn = t * c;
                 }
-    for (int i = 0; i < 4; ++i) act_v[(int64_t)i * act_cap + k] = v[i];
-    for (int i = 0; i < 12; ++i) act_g[(int64_t)i * act_cap + k] = g12[i];
-    for (int i = 0; i < 144; ++i) act_H[(int64_t)i * act_cap + k] = H[i];
+                rc[lane] = c;
+                rs[lane] = sn;
+                rp[lane] = p;
+                rq[lane] = q;
+            }
+            __syncthreads();
+            // rows p, q of A and columns p, q of V
+            for (int task = lane; task < 72; task += 64) {
+                int rr = task / 12, col = task % 12;
+                int p = rp[rr], q = rq[rr];
+                double c = rc[rr], sn = rs[rr];
+                double apk = A[p * 12 + col], aqk = A[q * 12 + col];
+                A[p * 12 + col] = c * apk - sn * aqk;
+                A[q * 12 + col] = sn * apk + c * aqk;
+                double vkp = V[col * 12 + p], vkq = V[col * 12 + q];
+                V[col * 12 + p] = c * vkp - sn * vkq;
+                V[col * 12 + q] = sn * vkp + c * vkq;
+            }
+            __syncthreads();
+            // columns p, q of A
+            for (int task = lane; task < 72; task += 64) {
+                int rr = task / 12, row = task % 12;
+                int p = rp[rr], q = rq[rr];
+                double c = rc[rr], sn = rs[rr];
+                double akp = A[row * 12 + p], akq = A[row * 12 + q];
+                A[row * 12 + p] = c * akp - sn * akq;
+                A[row * 12 + q] = sn * akp + c * akq;
+            }
+            __syncthreads();
+            if (lane < 6 && rs[lane] != 0.0) {
+                A[rp[lane] * 12 + rq[lane]] = 0.0;
+                A[rq[lane] * 12 + rp[lane]] = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    bool neg = false;
+    for (int i = 0; i < 12; ++i) neg |= A[i * 12 + i] < 0.0;
+    for (int e = lane; e < 144; e += 64) {
+        int i = e / 12, j = e % 12;
+        double val = A0[e];
+        if (neg) {
+            val = 0.0;
+            for (int kk = 0; kk < 12; ++kk) {
+                double wk = A[kk * 12 + kk];
+                if (wk > 0.0) val += V[i * 12 + kk] * wk * V[j * 12 + kk];
+            }
+        }
+        // Dirichlet vertices drop out (their identity rows live in the elastic matrix)
+        if (fixed[v[i / 3]] || fixed[v[j / 3]]) val = 0.0;
+        act_H[(int64_t)e * act_cap + k] = val;
+    }
+    if (lane < 12 && fixed[v[lane / 3]]) act_g[(int64_t)lane * act_cap + k] = 0.0;
 }
 
 template <bool FILL>
@@ -784,26 +820,42 @@ void launch_boxes(Scene &s, const double *x, const double *p)
                        p, r, s.ebox);
     hipLaunchKernelGGL(k_boxes, dim3(nblocks(s.n_tris)), dim3(kBlock), 0, s.stream, s.n_tris, 3, s.trv, s.n_tris, x, p,
                        r, s.tbox);
-    // cell size = 1.01 * largest box extent: every box spans <= 2 cells per axis
-    int nbe = nblocks(s.n_edges), nbt = nblocks(s.n_tris), nbp = nblocks(s.n_pts);
+    int nbe = nblocks(s.n_edges), nbt = nblocks(s.n_tris);
     hipLaunchKernelGGL(k_box_extent, dim3(nbe), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox, s.red_scratch);
     hipLaunchKernelGGL(k_box_extent, dim3(nbt), dim3(kBlock), 0, s.stream, s.n_tris, s.tbox, s.red_scratch + nbe);
-    hipLaunchKernelGGL(k_box_extent, dim3(nbp), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
-                       s.red_scratch + nbe + nbt);
-    hipLaunchKernelGGL(k_cell_size, dim3(1), dim3(kBlock), 0, s.stream, nbe + nbt + nbp, s.red_scratch, s.cell_h);
+    hipLaunchKernelGGL(k_cell_size, dim3(1), dim3(kBlock), 0, s.stream, nbe + nbt, s.red_scratch,
+                       (double)(s.n_edges + s.n_tris), 2.0 * r, s.cell_h);
 }
 
-static void build_hash(Scene &s, HashTable &ht, int N, const double *box)
+// table for N boxes with room for `cap` entries (power-of-two buckets)
+static void alloc_table(Scene &s, HashTable &ht, int64_t cap)
+{
+    if (ht.entries.p) {
+        dfree(s, ht.entries.p);
+        dfree(s, ht.bucket_count.p);
+        dfree(s, ht.bucket_start.p);
+    }
+    int bits = 10;
+    while ((int64_t(1) << bits) < 2 * cap && bits < 28) ++bits;
+    ht.table_bits = bits;
+    size_t tsize = size_t(1) << bits;
+    ht.bucket_count.p = dalloc<int32_t>(s, tsize + 1);
+    ht.bucket_start.p = dalloc<int32_t>(s, tsize + 1);
+    ht.entries.p = dalloc<int4>(s, (size_t)cap);
+    ht.entries.n = (size_t)cap;
+}
+
+static void build_hash(Scene &s, HashTable &ht, int N, const double *box, int32_t *bad)
 {
     uint32_t tsize = 1u << ht.table_bits, mask = tsize - 1;
+    int cap = (int)ht.entries.n;
     IPC_HIP(hipMemsetAsync(ht.bucket_count.p, 0, sizeof(int32_t) * (tsize + 1), s.stream));
-    int cap = 8 * N;
     hipLaunchKernelGGL((k_hash_insert<false>), dim3(nblocks(N)), dim3(kBlock), 0, s.stream, N, box, s.cell_h, mask,
-                       ht.bucket_count.p, nullptr, nullptr, cap);
+                       ht.bucket_count.p, nullptr, nullptr, cap, bad);
     exclusive_scan(s, ht.bucket_count.p, ht.bucket_start.p, (int)tsize, ht.bucket_start.p + tsize);
     IPC_HIP(hipMemsetAsync(ht.bucket_count.p, 0, sizeof(int32_t) * (tsize + 1), s.stream));
     hipLaunchKernelGGL((k_hash_insert<true>), dim3(nblocks(N)), dim3(kBlock), 0, s.stream, N, box, s.cell_h, mask,
-                       ht.bucket_count.p, ht.bucket_start.p, ht.entries.p, cap);
+                       ht.bucket_count.p, ht.bucket_start.p, ht.entries.p, cap, bad);
 }
 
 static void grow_candidates(Scene &s, int32_t **buf, int64_t *cap, int64_t need)
@@ -816,39 +868,65 @@ static void grow_candidates(Scene &s, int32_t **buf, int64_t *cap, int64_t need)
 }
 
 // Candidate pairs at x (p null) or over [x, x+p] into *out (SoA triples with
-// stride *cap, grown as needed). Returns the count.
+// stride *cap, grown as needed). Returns the count. Hash tables that overflow
+// their entry capacity are grown and the phase is redone.
 int64_t run_broad_phase(Scene &s, const double *x, const double *p, int32_t **out, int64_t *cap)
 {
+    if (!s.ht_tri.entries.p) alloc_table(s, s.ht_tri, 16 * (int64_t)std::max(s.n_tris, 1));
+    if (!s.ht_edge.entries.p) alloc_table(s, s.ht_edge, 16 * (int64_t)std::max(s.n_edges, 1));
+    int32_t *bad = s.pcg_state + 9;
     launch_boxes(s, x, p);
-    build_hash(s, s.ht_tri, s.n_tris, s.tbox);
-    build_hash(s, s.ht_edge, s.n_edges, s.ebox);
-    uint32_t mt = (1u << s.ht_tri.table_bits) - 1, me = (1u << s.ht_edge.table_bits) - 1;
     Topo tp = topo(s);
     PairRules R = rules(s);
-    // counts for both families, one scan over [points | edges]
     int nq = s.n_pts + s.n_edges;
     ensure_query(s, (size_t)nq);
-    hipLaunchKernelGGL((k_query<0, true>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox, s.n_tris,
-                       s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, 8 * s.n_tris, s.q_count, nullptr,
-                       nullptr, nullptr, nullptr, (int64_t)0);
-    hipLaunchKernelGGL((k_query<1, true>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox,
-                       s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p, s.ht_edge.entries.p,
-                       8 * s.n_edges, s.q_count + s.n_pts, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
-    exclusive_scan(s, s.q_count, s.q_off, nq, s.q_off + nq);
-    int32_t total = 0;
-    IPC_HIP(hipMemcpyAsync(&s.hb->flag, s.q_off + nq, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    total = s.hb->flag;
-    grow_candidates(s, out, cap, total);
-    int64_t C = *cap;
-    int32_t *ob = *out;
-    hipLaunchKernelGGL((k_query<0, false>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
-                       s.n_tris, s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, 8 * s.n_tris, nullptr,
-                       s.q_off, ob, ob + C, ob + 2 * C, (int64_t)0);
-    hipLaunchKernelGGL((k_query<1, false>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox,
-                       s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p, s.ht_edge.entries.p, 8 * s.n_edges,
-                       nullptr, s.q_off + s.n_pts, ob, ob + C, ob + 2 * C, (int64_t)0);
-    return total;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        IPC_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s.stream));
+        build_hash(s, s.ht_tri, s.n_tris, s.tbox, bad);
+        build_hash(s, s.ht_edge, s.n_edges, s.ebox, bad);
+        uint32_t mt = (1u << s.ht_tri.table_bits) - 1, me = (1u << s.ht_edge.table_bits) - 1;
+        int capt = (int)s.ht_tri.entries.n, cape = (int)s.ht_edge.entries.n;
+        hipLaunchKernelGGL((k_query<0, true>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
+                           s.n_tris, s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, capt,
+                           s.q_count, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+        hipLaunchKernelGGL((k_query<1, true>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox,
+                           s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p, s.ht_edge.entries.p, cape,
+                           s.q_count + s.n_pts, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+        exclusive_scan(s, s.q_count, s.q_off, nq, s.q_off + nq);
+        int32_t *tt = s.ht_tri.bucket_start.p + ((size_t)1 << s.ht_tri.table_bits);
+        int32_t *te = s.ht_edge.bucket_start.p + ((size_t)1 << s.ht_edge.table_bits);
+        IPC_HIP(hipMemcpyAsync(&s.hb->flag, s.q_off + nq, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipMemcpyAsync(&s.hb->iters, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipMemcpyAsync(&s.hb->count, tt, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipMemcpyAsync(reinterpret_cast<int32_t *>(&s.hb->count) + 1, te, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipStreamSynchronize(s.stream));
+        if (s.hb->iters) throw InfeasibleError{};
+        int32_t ent_t = reinterpret_cast<int32_t *>(&s.hb->count)[0];
+        int32_t ent_e = reinterpret_cast<int32_t *>(&s.hb->count)[1];
+        bool redo = false;
+        if (ent_t > capt) {
+            alloc_table(s, s.ht_tri, (int64_t)ent_t * 3 / 2 + 1024);
+            redo = true;
+        }
+        if (ent_e > cape) {
+            alloc_table(s, s.ht_edge, (int64_t)ent_e * 3 / 2 + 1024);
+            redo = true;
+        }
+        if (redo) continue;
+        int32_t total = s.hb->flag;
+        grow_candidates(s, out, cap, total);
+        int64_t C = *cap;
+        int32_t *ob = *out;
+        hipLaunchKernelGGL((k_query<0, false>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
+                           s.n_tris, s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, capt,
+                           nullptr, s.q_off, ob, ob + C, ob + 2 * C, (int64_t)0);
+        hipLaunchKernelGGL((k_query<1, false>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges,
+                           s.ebox, s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p,
+                           s.ht_edge.entries.p, cape, nullptr, s.q_off + s.n_pts, ob, ob + C, ob + 2 * C, (int64_t)0);
+        return total;
+    }
+    throw CapacityError{};
 }
 
 static void grow_active(Scene &s, int64_t need)
@@ -897,7 +975,7 @@ void launch_barrier(Scene &s, const double *x)
 {
     if (s.n_act == 0) return;
     Topo tp = topo(s);
-    hipLaunchKernelGGL(k_barrier, dim3(nblocks(s.n_act, 64)), dim3(64), 0, s.stream, s.n_act, s.act_cap, s.act_idx,
+    hipLaunchKernelGGL(k_barrier, dim3((unsigned)s.n_act), dim3(64), 0, s.stream, s.n_act, s.act_cap, s.act_idx,
                        s.cand_cap, s.cand, tp, s.edge_rest_sq, x, s.fixed, s.prm.dhat, s.prm.kappa, s.act_v,
                        s.act_g, s.act_H);
 }

@@ -12,6 +12,8 @@
 //          p += alpha d, r -= alpha q, z = M^-1 r and the r.z partials.
 // The host launches chunks of iterations and reads the done flag once per
 // chunk; a finished solve turns the remaining launches into no-ops.
+#include <algorithm>
+
 #include "device_util.h"
 #include "ipc_internal.h"
 
@@ -108,8 +110,63 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const double *__rest
     }
 }
 
+// PCG kernel A: four lanes per matrix row, one 64-row BELL slice per block.
+// Lane q of a row sums slots q, q+4, ...; the four partial products are
+// combined with lane shuffles in a fixed order. Lane 0 of the row adds the
+// contact incidence terms and writes d and q.
+constexpr int kLanesPerRow = 4;
+
+__device__ __forceinline__ void spmv_row_part(int row, int part, const int32_t *__restrict__ slice_ptr,
+                                              const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                              const double *__restrict__ z, const double *__restrict__ dold,
+                                              double beta, bool beta_on, double y[3])
+{
+    int sl = row / kSlice, lane = row % kSlice;
+    int s0 = slice_ptr[sl], s1 = slice_ptr[sl + 1];
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
+        int64_t base = (int64_t)slot * kSlice + lane;
+        int col = bcol[base];
+        if (col < 0) break;
+        const double *A = bval + (int64_t)slot * 9 * kSlice + lane;
+        double v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
+        if (beta_on) {
+            v0 += beta * dold[3 * col];
+            v1 += beta * dold[3 * col + 1];
+            v2 += beta * dold[3 * col + 2];
+        }
+        y0 += A[0 * kSlice] * v0 + A[1 * kSlice] * v1 + A[2 * kSlice] * v2;
+        y1 += A[3 * kSlice] * v0 + A[4 * kSlice] * v1 + A[5 * kSlice] * v2;
+        y2 += A[6 * kSlice] * v0 + A[7 * kSlice] * v1 + A[8 * kSlice] * v2;
+    }
+    y[0] = y0;
+    y[1] = y1;
+    y[2] = y2;
+}
+
+__device__ __forceinline__ void contact_row(int row, const int32_t *__restrict__ c_ptr, const int32_t *__restrict__ c_list,
+                                            const int32_t *__restrict__ act_v, const double *__restrict__ act_H,
+                                            int64_t act_cap, const double *__restrict__ z,
+                                            const double *__restrict__ dold, double beta, bool beta_on, double y[3])
+{
+    for (int t = c_ptr[row]; t < c_ptr[row + 1]; ++t) {
+        int src = c_list[t], p = src >> 2, a = src & 3;
+        for (int b = 0; b < 4; ++b) {
+            if (b == a) continue;
+            int vb = act_v[(int64_t)b * act_cap + p];
+            double v[3] = {z[3 * vb], z[3 * vb + 1], z[3 * vb + 2]};
+            if (beta_on)
+                for (int c = 0; c < 3; ++c) v[c] += beta * dold[3 * vb + c];
+            for (int i = 0; i < 3; ++i) {
+                const double *H = act_H + (int64_t)((3 * a + i) * 12 + 3 * b) * act_cap + p;
+                y[i] += H[0] * v[0] + H[act_cap] * v[1] + H[2 * act_cap] * v[2];
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_pcg_A(
-    int it, int n, int nb, double tol2, const int32_t *__restrict__ slice_ptr, const int32_t *__restrict__ bcol,
+    int it, int n, int nbB, double tol2, const int32_t *__restrict__ slice_ptr, const int32_t *__restrict__ bcol,
     const double *__restrict__ bval, const int32_t *__restrict__ c_ptr, const int32_t *__restrict__ c_list,
     const int32_t *__restrict__ act_v, const double *__restrict__ act_H, int64_t act_cap,
     const double *__restrict__ z, const double *__restrict__ dold, double *__restrict__ dnew,
@@ -118,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(
     if (st->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = reduce_partials(part_rz, nb);
+        double rz0 = reduce_partials(part_rz, nbB);
         if (!(rz0 > 0.0)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 st->done = 1;
@@ -128,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) st->stop = tol2 * rz0;
     } else {
-        double rz_cur = reduce_partials(part_rz + (size_t)((it - 1) & 1) * nb, nb);
+        double rz_cur = reduce_partials(part_rz + (size_t)((it - 1) & 1) * nbB, nbB);
         if (rz_cur <= st->stop) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 st->done = 1;
@@ -136,18 +193,27 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(
             }
             return;
         }
-        double rz_prev = reduce_partials(part_rz + (size_t)(it & 1) * nb, nb);
+        double rz_prev = reduce_partials(part_rz + (size_t)(it & 1) * nbB, nbB);
         beta = rz_cur / rz_prev;
     }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // block = one slice of 64 rows; lanes (4r .. 4r+3) of a wavefront share row r
+    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int row = blockIdx.x * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    int part = lane % kLanesPerRow;
+    double y[3] = {0.0, 0.0, 0.0};
+    bool live = row < n;
+    if (live) spmv_row_part(row, part, slice_ptr, bcol, bval, z, dold, beta, it > 1, y);
+    for (int c = 0; c < 3; ++c) {
+        y[c] += __shfl_xor(y[c], 1, kWave);
+        y[c] += __shfl_xor(y[c], 2, kWave);
+    }
     double dq = 0.0;
-    if (i < n) {
-        double y[3];
-        spmv_row(i, slice_ptr, bcol, bval, c_ptr, c_list, act_v, act_H, act_cap, z, dold, beta, it > 1, y);
+    if (live && part == 0) {
+        contact_row(row, c_ptr, c_list, act_v, act_H, act_cap, z, dold, beta, it > 1, y);
         for (int c = 0; c < 3; ++c) {
-            double dv = it > 1 ? z[3 * i + c] + beta * dold[3 * i + c] : z[3 * i + c];
-            dnew[3 * i + c] = dv;
-            q[3 * i + c] = y[c];
+            double dv = it > 1 ? z[3 * row + c] + beta * dold[3 * row + c] : z[3 * row + c];
+            dnew[3 * row + c] = dv;
+            q[3 * row + c] = y[c];
             dq += dv * y[c];
         }
     }
@@ -155,14 +221,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(
     if (threadIdx.x == 0) part_dq[blockIdx.x] = dq;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_B(int it, int n, int nb, const double *__restrict__ q,
+__global__ void __launch_bounds__(kBlock) k_pcg_B(int it, int n, int nbA, int nb, const double *__restrict__ q,
                                                    const double *__restrict__ dcur, const double *__restrict__ Minv,
                                                    double *__restrict__ sol, double *__restrict__ r,
                                                    double *__restrict__ z, const double *__restrict__ part_dq,
                                                    double *__restrict__ part_rz, PcgState *st)
 {
     if (st->done) return;
-    double dq = reduce_partials(part_dq, nb);
+    double dq = reduce_partials(part_dq, nbA);
     double rz_prev = reduce_partials(part_rz + (size_t)((it - 1) & 1) * nb, nb);
     double alpha = rz_prev / dq;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -454,33 +520,46 @@ double run_target_lag(Scene &s)
 
 int run_pcg(Scene &s, int *hit_cap)
 {
-    int n = s.n, nb = nblocks(n);
+    int n = s.n, nbB = nblocks(n), nbA = s.n_slices;
     PcgState *st = reinterpret_cast<PcgState *>(s.pcg_state);
-    double *part_dq = s.pcg_part, *part_rz = s.pcg_part + nb;
+    double *part_dq = s.pcg_part, *part_rz = s.pcg_part + nbA;
     double tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
     int maxit = s.prm.pcg_max_iter > 0 ? s.prm.pcg_max_iter : 30 * n;
-    hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(kBlock), 0, s.stream, n, s.grad, s.Minv, s.r, s.z, s.sol, part_rz,
+    hipLaunchKernelGGL(k_pcg_init, dim3(nbB), dim3(kBlock), 0, s.stream, n, s.grad, s.Minv, s.r, s.z, s.sol, part_rz,
                        st);
     double *dbuf[2] = {s.dA, s.dB};
-    int it = 1, chunk = 8;
+    int it = 1;
+    // first chunk: most of the previous solve's count, then short chunks, so
+    // few launches run after convergence
+    int chunk = s.last_pcg_iters > 16 ? (s.last_pcg_iters * 7) / 8 : 8;
     *hit_cap = 0;
+    hipEvent_t ev[2];
     while (it <= maxit) {
         int c = chunk < maxit - it + 1 ? chunk : maxit - it + 1;
         for (int j = 0; j < c; ++j, ++it) {
-            hipLaunchKernelGGL(k_pcg_A, dim3(nb), dim3(kBlock), 0, s.stream, it, n, nb, tol2, s.slice_ptr, s.bcol,
+            bool timed = (it & 3) == 1;  // time one launch in four when profiling
+            if (timed) prof_begin(s, kProfPcgA, ev);
+            hipLaunchKernelGGL(k_pcg_A, dim3(nbA), dim3(kBlock), 0, s.stream, it, n, nbB, tol2, s.slice_ptr, s.bcol,
                                s.bval, s.c_ptr, s.c_list, s.act_v, s.act_H, s.act_cap, s.z, dbuf[(it + 1) & 1],
                                dbuf[it & 1], s.q, part_dq, part_rz, st);
-            hipLaunchKernelGGL(k_pcg_B, dim3(nb), dim3(kBlock), 0, s.stream, it, n, nb, s.q, dbuf[it & 1], s.Minv,
-                               s.sol, s.r, s.z, part_dq, part_rz, st);
+            if (timed) prof_end(s, kProfPcgA, ev);
+            if (timed) prof_begin(s, kProfPcgB, ev);
+            hipLaunchKernelGGL(k_pcg_B, dim3(nbB), dim3(kBlock), 0, s.stream, it, n, nbA, nbB, s.q, dbuf[it & 1],
+                               s.Minv, s.sol, s.r, s.z, part_dq, part_rz, st);
+            if (timed) prof_end(s, kProfPcgB, ev);
         }
         IPC_HIP(hipMemcpyAsync(&s.hb->flag, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
         IPC_HIP(hipMemcpyAsync(&s.hb->iters, &st->iters, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
         IPC_HIP(hipStreamSynchronize(s.stream));
-        if (s.hb->flag) return s.hb->iters;
-        if (chunk < 64) chunk *= 2;
+        prof_collect(s);
+        if (s.hb->flag) {
+            s.last_pcg_iters = s.hb->iters;
+            return s.hb->iters;
+        }
+        chunk = 8;
     }
-    // cap: one more A launch would only test the stop; report the cap
     *hit_cap = 1;
+    s.last_pcg_iters = maxit;
     return maxit;
 }
 

@@ -60,9 +60,51 @@ void dfree(Scene &s, void *p)
         }
 }
 
+void prof_begin(Scene &s, int kernel, hipEvent_t *pair)
+{
+    if (!s.prof) return;
+    for (int k = 0; k < 2; ++k) {
+        if (s.ev_pool.empty()) {
+            hipEvent_t e;
+            IPC_HIP(hipEventCreate(&e));
+            s.ev_pool.push_back(e);
+        }
+        pair[k] = s.ev_pool.back();
+        s.ev_pool.pop_back();
+    }
+    IPC_HIP(hipEventRecord(pair[0], s.stream));
+}
+
+void prof_end(Scene &s, int kernel, hipEvent_t *pair)
+{
+    if (!s.prof) return;
+    IPC_HIP(hipEventRecord(pair[1], s.stream));
+    s.ev_pending.push_back({kernel, {pair[0], pair[1]}});
+}
+
+void prof_collect(Scene &s)
+{
+    if (s.ev_pending.empty()) return;
+    for (auto &p : s.ev_pending) {
+        float ms = 0.f;
+        IPC_HIP(hipEventSynchronize(p.second.second));
+        IPC_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        s.prof_acc[p.first].launches++;
+        s.prof_acc[p.first].ms += ms;
+        s.ev_pool.push_back(p.second.first);
+        s.ev_pool.push_back(p.second.second);
+    }
+    s.ev_pending.clear();
+}
+
 Scene::~Scene()
 {
     if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &p : ev_pending) {
+        ev_pool.push_back(p.second.first);
+        ev_pool.push_back(p.second.second);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto &o : owned) arena.release(o.first, o.second);
     owned.clear();
     if (hb) (void)hipHostFree(hb);
@@ -120,15 +162,6 @@ static int ceil_log2(int64_t v)
     int b = 0;
     while ((int64_t(1) << b) < v) ++b;
     return b;
-}
-
-static void alloc_hash(Scene &s, HashTable &ht, int nprim)
-{
-    ht.table_bits = std::max(10, ceil_log2(4 * (int64_t)std::max(nprim, 1)));
-    size_t tsize = size_t(1) << ht.table_bits;
-    ht.bucket_count.p = dalloc<int32_t>(s, tsize + 1);
-    ht.bucket_start.p = dalloc<int32_t>(s, tsize + 1);
-    ht.entries.p = dalloc<int4>(s, 8 * (size_t)std::max(nprim, 1));
 }
 
 static int64_t partial_need(const Scene &s, int64_t nc)
@@ -258,6 +291,8 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
         slice_ptr[sl + 1] = slice_ptr[sl] + w;
     }
     s.n_slots = slice_ptr[s.n_slices];
+    s.nnzb = 0;
+    for (int row = 0; row < n; ++row) s.nnzb += 1 + (int64_t)nbr[row].size();
     size_t nent = (size_t)s.n_slots * kSlice;
     std::vector<int32_t> bcol(nent, -1);
     for (int row = 0; row < n; ++row) {
@@ -349,8 +384,6 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     s.pbox = dalloc<double>(s, 6 * (size_t)std::max(s.n_pts, 1));
     s.ebox = dalloc<double>(s, 6 * (size_t)std::max(s.n_edges, 1));
     s.tbox = dalloc<double>(s, 6 * (size_t)std::max(s.n_tris, 1));
-    alloc_hash(s, s.ht_tri, s.n_tris);
-    alloc_hash(s, s.ht_edge, s.n_edges);
     s.cell_h = dalloc<double>(s, 1);
     int64_t red = 4 * (int64_t)nblocks(std::max({(int64_t)n, (int64_t)s.n_pts, (int64_t)s.n_edges, (int64_t)s.n_tris})) + 64;
     s.red_scratch = dalloc<double>(s, red);
@@ -363,7 +396,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     s.dB = dalloc<double>(s, n3);
     s.q = dalloc<double>(s, n3);
     s.sol = dalloc<double>(s, n3);
-    s.pcg_part = dalloc<double>(s, 3 * (size_t)nblocks(n) + 8);
+    s.pcg_part = dalloc<double>(s, (size_t)s.n_slices + 2 * (size_t)nblocks(n) + 8);
     s.pcg_state = dalloc<int32_t>(s, 16);
     IPC_HIP(hipMemsetAsync(s.pcg_state, 0, sizeof(int32_t) * 16, s.stream));
     s.surf_verts = upload(s, s.h_surf_verts);
@@ -423,15 +456,24 @@ struct IterOut {
 static void assemble_at(Scene &s, const double *x, double *ms)
 {
     auto t0 = Clock::now();
+    hipEvent_t ev[2];
+    prof_begin(s, kProfBroad, ev);
     s.n_cand = run_broad_phase(s, x, nullptr, &s.cand, &s.cand_cap);
+    prof_end(s, kProfBroad, ev);
     ensure_cand_aux(s);
+    prof_begin(s, kProfBarrier, ev);
     run_narrow_phase(s, x);
     launch_barrier(s, x);
     launch_contact_incidence(s);
+    prof_end(s, kProfBarrier, ev);
     if (ms) ms[1] += ms_since(t0);
     t0 = Clock::now();
+    prof_begin(s, kProfElastic, ev);
     launch_elastic_elements(s, x);
+    prof_end(s, kProfElastic, ev);
+    prof_begin(s, kProfAssemble, ev);
     launch_assemble(s, x);
+    prof_end(s, kProfAssemble, ev);
     if (ms) {
         IPC_HIP(hipStreamSynchronize(s.stream));
         ms[0] += ms_since(t0);
@@ -451,17 +493,26 @@ static IterOut newton_iterate(Scene &s, double *x, double *ms)
         return o;
     }
     t0 = Clock::now();
+    hipEvent_t ev[2];
+    prof_begin(s, kProfBroad, ev);
     s.n_cand_sw = run_broad_phase(s, x, s.sol, &s.cand_sw, &s.sw_cap);
+    prof_end(s, kProfBroad, ev);
     ensure_cand_aux(s);
+    prof_begin(s, kProfCcd, ev);
     o.alpha_ccd = run_ccd(s, x, s.sol);
+    prof_end(s, kProfCcd, ev);
     if (ms) ms[3] += ms_since(t0);
     t0 = Clock::now();
     double alpha = std::min(1.0, o.alpha_ccd), alpha0 = alpha;
     int inf = 0;
+    prof_begin(s, kProfEnergy, ev);
     double E0 = run_energy(s, x, s.cand_sw, s.n_cand_sw, &inf);
+    prof_end(s, kProfEnergy, ev);
     for (;;) {
         launch_trial(s, x, s.sol, alpha, s.xtrial);
+        prof_begin(s, kProfEnergy, ev);
         double E = run_energy(s, s.xtrial, s.cand_sw, s.n_cand_sw, &inf);
+        prof_end(s, kProfEnergy, ev);
         if (E <= E0) {
             IPC_HIP(hipMemcpyAsync(x, s.xtrial, sizeof(double) * 3 * s.n, hipMemcpyDeviceToDevice, s.stream));
             o.energy = E;
@@ -518,6 +569,7 @@ static int32_t step_scene(Scene &s, const ipc_step_req &req, ipc_step_stats *st)
     st->max_target_lag = run_target_lag(s);
     if (status == IPC_OK && st->max_target_lag > 1e-3 * s.prm.dhat) status = IPC_W_TARGET_LAG;
     IPC_HIP(hipStreamSynchronize(s.stream));
+    prof_collect(s);
     st->status = status;
     st->ms_total = ms_since(t_start);
     s.step_index++;
@@ -542,6 +594,9 @@ static int32_t guarded(F &&f)
     } catch (const CapacityError &) {
         set_error("contact list capacity exceeded");
         return IPC_E_CAPACITY;
+    } catch (const InfeasibleError &) {
+        set_error("non-finite or absurd positions in the contact broad phase");
+        return IPC_E_INFEASIBLE;
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return IPC_E_OOM;
@@ -1005,6 +1060,40 @@ int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double *alpha)
         *alpha = std::min(1.0, run_ccd(*s, s->xw, s->pw));
         return IPC_OK;
     });
+}
+
+int32_t ipcx_profile(ipc_scene *s, int32_t enable)
+{
+    if (!s) return IPC_E_INVALID_ARG;
+    return guarded([&]() -> int32_t {
+        IPC_HIP(hipStreamSynchronize(s->stream));
+        prof_collect(*s);
+        s->prof = enable != 0;
+        for (auto &a : s->prof_acc) a = Scene::ProfAcc{};
+        return IPC_OK;
+    });
+}
+
+int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches, double *ms_total)
+{
+    if (!s || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    if (launches) *launches = s->prof_acc[kernel].launches;
+    if (ms_total) *ms_total = s->prof_acc[kernel].ms;
+    return IPC_OK;
+}
+
+int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
+{
+    if (!s || !out) return IPC_E_INVALID_ARG;
+    out[0] = s->nnzb;
+    out[1] = (int64_t)s->n_slots * kSlice;
+    out[2] = s->n;
+    out[3] = s->n_act;
+    out[4] = s->m;
+    out[5] = s->n_cand;
+    out[6] = s->n_cand_sw;
+    out[7] = s->n_gather;
+    return IPC_OK;
 }
 
 int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v)

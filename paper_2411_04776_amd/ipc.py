@@ -107,6 +107,9 @@ _SIGS = {
     "ipcx_pcg": (C.c_int32, [C.c_void_p, _D, _D, _I]),
     "ipcx_energy": (C.c_int32, [C.c_void_p, _D, _D]),
     "ipcx_ccd": (C.c_int32, [C.c_void_p, _D, _D, _D]),
+    "ipcx_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "ipcx_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
+    "ipcx_matrix_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_set_state": (C.c_int32, [C.c_void_p, _D, _D]),
     "ipcx_get_state": (C.c_int32, [C.c_void_p, _D, _D]),
 }
@@ -381,6 +384,26 @@ class GelScene:
         a = C.c_double()
         _check(lib().ipcx_ccd(self.ptr, _d(x), _d(p), C.byref(a)), "ipcx_ccd")
         return a.value
+
+    def profile(self, enable=True):
+        _check(lib().ipcx_profile(self.ptr, int(enable)), "ipcx_profile")
+
+    PROF_KERNELS = ("pcg_spmv", "pcg_update", "elastic", "assemble", "broad_phase", "barrier", "energy", "ccd")
+
+    def profile_read(self):
+        out = {}
+        for k, name in enumerate(self.PROF_KERNELS):
+            n = C.c_int64()
+            ms = C.c_double()
+            lib().ipcx_profile_read(self.ptr, k, C.byref(n), C.byref(ms))
+            out[name] = (n.value, ms.value)
+        return out
+
+    def matrix_info(self):
+        o = np.zeros(8, dtype=np.int64)
+        lib().ipcx_matrix_info(self.ptr, o.ctypes.data_as(_I64))
+        keys = ("nnzb", "bell_entries", "n", "n_active", "n_tets", "n_cand", "n_cand_swept", "n_gather")
+        return dict(zip(keys, map(int, o)))
 
     @property
     def x(self):
