@@ -1,24 +1,33 @@
 // ipc_internal.h -- internal types of the MI355X IPC gel-pad step library.
 //
+// Every kernel runs over a *list of scenes*: a launch carries an array of
+// per-scene device views (SceneDev) and a block-offset table that gives each
+// scene a contiguous range of blocks sized from that scene alone. One scene
+// stepping on its own is a list of one; the batched form puts many scenes in
+// the same launches. Because a scene's blocks, its per-block partials and its
+// reduction order depend only on that scene, its results are bitwise the
+// same alone and in any mix.
+//
 // Layout in HBM (one scene):
-//   vertex vectors (x, v, gradient, PCG vectors): interleaved xyz, 3*n values,
-//     streamed contiguously by the vector kernels;
+//   vertex vectors (x, v, gradient, PCG vectors): interleaved xyz, 3*n values;
 //   per-tet data (indices, Dm^-1, volume, element gradient/Hessian blocks):
-//     structure of arrays, one array per component, so a wavefront of 64
-//     tets reads 64 consecutive values per component;
-//   the elastic matrix: blocked sliced ELL with 3x3 blocks, a slice = 64
-//     rows = one wavefront, each slice padded to its longest row, stored
-//     component-major inside the slice (value[(slot*9+c)*64 + lane]) so that
-//     every load of a slot is one coalesced 512-byte access; slot 0 of every
-//     row is its diagonal block;
-//   contact pairs: structure of arrays over active pairs (4 vertex ids,
-//     12 gradient and 144 Hessian components), applied in SpMV through a
-//     per-vertex incidence list sorted by pair index (no float atomics).
+//     structure of arrays, one array per component (coalesced per wavefront);
+//   the elastic matrix: blocked sliced ELL with 3x3 blocks, a slice = 64 rows
+//     = one wavefront, padded to its longest row, stored component-major in
+//     the slice (value[(slot*9+c)*64 + lane]); slot 0 of a row is its diagonal;
+//   contact pairs: structure of arrays over active pairs (4 vertex ids, 12
+//     gradient and 144 Hessian components), applied in SpMV through per-vertex
+//     incidence lists sorted by pair index (no float atomics anywhere).
+// In the mixed form the element Hessians and gradients, matrix values,
+// preconditioner, assembled gradient and PCG vectors are FP32 (dot products
+// accumulate in FP64); positions, Dm^-1, distances, CCD and energies stay FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -28,7 +37,8 @@ namespace ipcg {
 
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
-constexpr int kElemBlocks = 10;   // upper-triangle 3x3 blocks of a 12x12 element matrix
+constexpr int kLanesPerRow = 4;   // SpMV lanes per matrix row
+constexpr int kScanTile = 1024;   // elements per scan tile
 
 // kernels timed by the optional profiler
 enum ProfKernel {
@@ -43,10 +53,99 @@ enum ProfKernel {
     kProfKernels = 8
 };
 
-// Rigid pose [R|c], row-major 3x4, passed to kernels by value.
-struct Pose {
-    double m[12];
+struct PcgState {
+    int32_t done;
+    int32_t iters;
+    double stop;
 };
+
+// Per-scene values produced on the device and read back once per phase for
+// the whole list (one copy for all scenes).
+struct SceneOut {
+    int32_t n_cand;       // static candidates
+    int32_t n_sw;         // swept candidates
+    int32_t n_act;        // active pairs
+    int32_t ent_tri, ent_edge;  // hash entries needed
+    int32_t bad;          // non-finite positions seen by the broad phase
+    int32_t infeasible;   // energy: a tet with J <= 0 or a pair with d <= 0
+    int32_t pcg_done, pcg_iters;
+    int32_t pad;
+    double pinf;          // max |p| over free DOFs
+    double alpha_ccd;
+    double energy;
+    double lag;           // max indenter target lag
+    double obj[3];        // mean of gel vertices
+};
+
+// Device view of one scene: sizes, parameters and pointers. Pointers to
+// precision-dependent arrays are void*; kernels templated on the real type R
+// cast them.
+struct SceneDev {
+    int n, n_gel, n_ind, m, n_pts, n_edges, n_tris, n_slices, n_slots, n_surf;
+    int self_contact, ccd_max_iter, precision, nb_vert, pcg_maxit;
+    double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
+    double pose[12];
+    double alpha;      // line-search trial step
+    // state (FP64)
+    double *x, *v, *xt, *xtilde, *yhat, *X0, *Yloc, *xtrial, *mass;
+    uint8_t *fixed;
+    // tets
+    int32_t *tv;
+    double *Bm, *vol;
+    void *eg, *eH;
+    int32_t *vt_ptr, *vt_src;
+    // elastic matrix
+    int32_t *slice_ptr, *bcol, *g_ptr, *g_src;
+    void *bval, *Minv, *grad;
+    // surface primitives and broad phase
+    int32_t *pts, *ev, *trv, *surf_verts;
+    double *edge_rest_sq;
+    double *pbox, *ebox, *tbox, *cell_h;
+    int32_t *ht_count[2], *ht_start[2];
+    int4 *ht_entries[2];
+    int32_t ht_bits[2], ht_cap[2];
+    int32_t *q_count, *q_off;
+    // candidates: static list and swept list (SoA type, a, b with stride cap)
+    int32_t *cand, *cand_sw;
+    int64_t cand_cap, sw_cap;
+    double *cand_d;
+    int32_t *act_flag;
+    // active pairs
+    int32_t *act_idx, *act_v;
+    void *act_g, *act_H;
+    int64_t act_cap;
+    int32_t *c_ptr, *c_cnt, *c_list;
+    // PCG
+    void *r, *z, *dA, *dB, *q, *sol;
+    double *pcg_part;
+    PcgState *pcg;
+    // reduction scratch (doubles) and scan scratch (ints)
+    double *red;
+    int32_t *scan_tmp;
+    int64_t red_len, scan_len;
+};
+
+// A launch over a list of scenes: block b belongs to scene s when
+// blk_off[s] <= b < blk_off[s+1].
+struct Launch {
+    SceneDev *const *sc;
+    const int32_t *blk_off;
+    SceneOut *out;
+    int ns;
+};
+
+__device__ __forceinline__ int scene_of_block(const Launch &L, int &local)
+{
+    int lo = 0, hi = L.ns;
+    int b = blockIdx.x;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (L.blk_off[mid] <= b) lo = mid; else hi = mid;
+    }
+    local = b - L.blk_off[lo];
+    return lo;
+}
+__device__ __forceinline__ int blocks_of(const Launch &L, int s) { return L.blk_off[s + 1] - L.blk_off[s]; }
 
 struct Params {
     double E, nu, rho, mu, lam;
@@ -58,17 +157,6 @@ struct Params {
     int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter;
 };
 
-// Small values read back to the host after a phase (pinned host memory).
-struct Readback {
-    int64_t count;       // candidate / active counts
-    int32_t flag;        // overflow / infeasible / done flags
-    int32_t iters;
-    double value;        // reduced scalar (energy, alpha, |p|_inf)
-    double value2;
-};
-
-class Scene;
-
 // Device allocation through the runtime's callbacks (PyTorch's caching
 // allocator from Python) or hipMalloc.
 struct DeviceArena {
@@ -78,19 +166,7 @@ struct DeviceArena {
     void release(void *p, size_t bytes);
 };
 
-template <class T>
-struct DArr {
-    T *p = nullptr;
-    size_t n = 0;
-};
-
-// Broad-phase working set for one primitive family used as a hash target.
-struct HashTable {
-    int32_t table_bits = 0;
-    DArr<int32_t> bucket_count;   // table_size + 1
-    DArr<int32_t> bucket_start;   // table_size + 1
-    DArr<int4> entries;           // (ix, iy, iz, id)
-};
+class Batch;
 
 class Scene {
   public:
@@ -99,146 +175,34 @@ class Scene {
     DeviceArena arena;
     std::vector<std::pair<void *, size_t>> owned;
 
-    // sizes
-    int n = 0, n_gel = 0, n_ind = 0, m = 0;
-    int n_pts = 0, n_edges = 0, n_tris = 0, n_gel_tris = 0, n_gel_edges = 0;
-    int n_slices = 0, n_slots = 0;     // BELL
-    int64_t n_gather = 0;              // BSR gather entries
+    SceneDev h{};          // host mirror of the device view
+    SceneDev *dev = nullptr;
+    bool dev_dirty = true; // h changed since the last upload
 
-    // host copies of topology (ABI queries, tests)
+    int64_t nnzb = 0, n_gather = 0;
+    int n_gel_tris = 0;
+    double *xsave = nullptr;   // test hooks: the state x kept across a hook call
+    double *ysurf = nullptr;   // staging for surface read-back to the host
+    std::unique_ptr<Batch> solo;  // the list of one used by ipc_step and the hooks
     std::vector<int32_t> h_pts, h_edges, h_tris, h_surf_verts;
     std::vector<double> h_Yloc;
-    Pose pose0{};
-
-    // state
-    double *x = nullptr, *v = nullptr, *xt = nullptr, *xtilde = nullptr, *yhat = nullptr;
-    double *X0 = nullptr, *Yloc = nullptr, *xtrial = nullptr;
-    uint8_t *fixed = nullptr;
-    double *mass = nullptr;
-    // tets (SoA)
-    int32_t *tv = nullptr;       // 4 * m
-    double *Bm = nullptr;        // 9 * m
-    double *vol = nullptr;       // m
-    double *eg = nullptr;        // 12 * m element gradients
-    double *eH = nullptr;        // 90 * m element Hessian blocks
-    int32_t *vt_ptr = nullptr, *vt_src = nullptr;   // vertex -> (tet*4 + local)
-    // BELL matrix
-    int32_t *slice_ptr = nullptr;    // n_slices + 1, in slots
-    int32_t *bcol = nullptr;         // n_slots * 64
-    double *bval = nullptr;          // n_slots * 9 * 64
-    int32_t *g_ptr = nullptr;        // n_slots * 64 + 1
-    int32_t *g_src = nullptr;        // tet*16 + a*4 + b
-    double *grad = nullptr, *Minv = nullptr;
-    // surface primitives
-    int32_t *pts = nullptr, *ev = nullptr, *trv = nullptr;   // ev: 2*ne SoA, trv: 3*nt SoA
-    double *edge_rest_sq = nullptr;
-    // boxes (SoA lo xyz, hi xyz)
-    double *pbox = nullptr, *ebox = nullptr, *tbox = nullptr;
-    HashTable ht_tri, ht_edge;
-    double *cell_h = nullptr;        // device scalar
-    double *red_scratch = nullptr;   // reduction partials
-    int32_t *i_scratch = nullptr;    // integer scan scratch
-    size_t i_scratch_n = 0;
-    int32_t *q_count = nullptr, *q_off = nullptr;  // per query counts / offsets
-    size_t q_n = 0;
-    // candidates
-    int64_t cand_cap = 0;
-    int32_t *cand = nullptr;         // 3 * cand_cap (type, a, b) SoA
-    int64_t n_cand = 0;
-    int64_t sw_cap = 0;
-    int32_t *cand_sw = nullptr;
-    int64_t n_cand_sw = 0;
-    double *cand_d = nullptr;        // cand_cap
-    int32_t *act_flag = nullptr;     // cand_cap + 1
-    // active pairs
-    int64_t act_cap = 0, n_act = 0;
-    int32_t *act_idx = nullptr;      // act_cap
-    int32_t *act_v = nullptr;        // 4 * act_cap
-    double *act_g = nullptr;         // 12 * act_cap
-    double *act_H = nullptr;         // 144 * act_cap
-    int32_t *c_ptr = nullptr;        // n + 1
-    int32_t *c_cnt = nullptr;        // n
-    int32_t *c_list = nullptr;       // 4 * act_cap
-    // PCG
-    double *r = nullptr, *z = nullptr, *dA = nullptr, *dB = nullptr, *q = nullptr, *sol = nullptr;
-    double *pcg_part = nullptr;      // 3 * nblocks partials
-    int32_t *pcg_state = nullptr;    // done flag, iterations
-    double *accd_t = nullptr;        // reduction partials of CCD / energy
-    int64_t part_cap = 0;
-    int64_t aux_cap = 0;             // capacity of cand_d / act_flag
-    int32_t *surf_verts = nullptr;   // gel surface vertex ids, ascending
-    double *xw = nullptr, *pw = nullptr, *yw = nullptr;  // work vectors (test hooks, readback)
-    double *mean_part = nullptr;
-    Readback *hb = nullptr;          // pinned
+    double pose0[12] = {};
     int step_index = 0;
-    bool busy = false;
-    int last_pcg_iters = 0;          // iterations of the last PCG solve
-    int64_t nnzb = 0;                // stored (non-padding) elastic blocks
+    std::atomic<bool> busy{false};  // a step, read or hook holds the scene
+    int last_pcg_iters = 0;
+    SceneOut last{};       // last values read back
 
-    // optional per-kernel timing with HIP events on the scene's stream
+    // optional per-kernel timing with HIP events
     bool prof = false;
     struct ProfAcc {
         int64_t launches = 0;
         double ms = 0.0;
     } prof_acc[kProfKernels];
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 
     ~Scene();
 };
 
-// ---- kernel launchers (defined in the .hip files) -------------------------
-
-// predictor / misc
-void launch_begin_step(Scene &s, const Pose &pose);
-void launch_end_step(Scene &s);
-void launch_trial(Scene &s, const double *x, const double *p, double alpha, double *out);
-void launch_rest_precompute(Scene &s);
-
-// elasticity and assembly
-void launch_elastic_elements(Scene &s, const double *x);
-void launch_assemble(Scene &s, const double *x);
-
-// contact
-void launch_boxes(Scene &s, const double *x, const double *p);
-int64_t run_broad_phase(Scene &s, const double *x, const double *p, int32_t **out, int64_t *cap);
-int64_t run_narrow_phase(Scene &s, const double *x);
-void launch_barrier(Scene &s, const double *x);
-void launch_contact_incidence(Scene &s);
-double run_ccd(Scene &s, const double *x, const double *p);
-double run_energy(Scene &s, const double *x, const int32_t *cand, int64_t nc, int *infeasible);
-
-void ensure_cand_aux(Scene &s);
-void launch_gather_surface(Scene &s, double *dst, hipStream_t strm);
-double *run_gel_mean(Scene &s, hipStream_t strm);
-double run_target_lag(Scene &s);
-
-// solver
-int run_pcg(Scene &s, int *hit_cap);
-double run_pinf(Scene &s);
-void launch_hess_apply(Scene &s, const double *v, double *y);
-
-// scan helpers
-void exclusive_scan(Scene &s, const int32_t *in, int32_t *out, int n, int32_t *total_dev);
-void ensure_iscratch(Scene &s, size_t n);
-void ensure_query(Scene &s, size_t n);
-
-// profiler: prof_begin/prof_end bracket launches of one kernel class;
-// prof_collect (after a stream sync) accumulates the elapsed times
-void prof_begin(Scene &s, int kernel, hipEvent_t *pair);
-void prof_end(Scene &s, int kernel, hipEvent_t *pair);
-void prof_collect(Scene &s);
-
 // errors
-void set_error(const std::string &msg);
-int32_t hip_fail(hipError_t e, const char *where);
-
-#define IPC_HIP(call)                                                   \
-    do {                                                                \
-        hipError_t _e = (call);                                         \
-        if (_e != hipSuccess) throw ipcg::HipError(_e, #call);          \
-    } while (0)
-
 struct HipError {
     hipError_t e;
     const char *what;
@@ -248,18 +212,121 @@ struct OomError {};
 struct CapacityError {};
 struct InfeasibleError {};
 
+#define IPC_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) throw ipcg::HipError(_e, #call);          \
+    } while (0)
+
+void set_error(const std::string &msg);
+
+void *dalloc_bytes(Scene &s, size_t bytes);
 template <class T>
 T *dalloc(Scene &s, size_t count)
 {
-    size_t bytes = count * sizeof(T);
-    if (bytes == 0) bytes = sizeof(T);
-    void *p = s.arena.alloc(bytes);
-    if (!p) throw OomError{};
-    s.owned.push_back({p, bytes});
-    return reinterpret_cast<T *>(p);
+    return reinterpret_cast<T *>(dalloc_bytes(s, count * sizeof(T)));
 }
 void dfree(Scene &s, void *p);
 
 inline int nblocks(int64_t n, int b = kBlock) { return (int)((n + b - 1) / b); }
+
+// ---- a list of scenes stepping together --------------------------------------
+
+// Phases with a block count per scene; a scene with 0 blocks sits the phase out.
+enum PhaseKind {
+    kPhVert = 0,  // vertices, kBlock threads
+    kPhTet,       // tets (+ vertices for the body energy: kPhBody)
+    kPhBody,      // tets + vertices
+    kPhEntry,     // stored BELL entries
+    kPhSlice,     // BELL slices (PCG A)
+    kPhPts, kPhEdges, kPhTris, kPhSurf, kPhInd,
+    kPhCand,      // static candidates
+    kPhCandSw,    // swept candidates
+    kPhAct,       // active pairs, one 64-thread block each
+    kPhActT,      // active pairs, kBlock threads
+    kPhOne,       // one block per scene
+    kPhTilesT, kPhTilesE, kPhTilesQ, kPhTilesC, kPhTilesA,  // scan tiles
+    kPhKinds
+};
+
+class Batch {
+  public:
+    std::vector<Scene *> sc;
+    hipStream_t stream = nullptr;
+    SceneDev **d_list = nullptr;     // device array of scene view pointers
+    int32_t *d_off[kPhKinds] = {};   // device block-offset tables
+    std::vector<int32_t> h_off[kPhKinds];
+    SceneOut *d_out = nullptr;       // per-scene read-back slots (device)
+    SceneOut *h_out = nullptr;       // pinned
+    double *d_alpha = nullptr;       // per-scene line-search step (device)
+    std::vector<double> h_alpha;
+    std::vector<int32_t> fail;       // per-scene error status set by host phases (0 = fine)
+    int cap = 0;
+    // pinned staging for host-to-device copies of phase maps, views and steps:
+    // slots are reused only after the stream has been synchronized
+    char *h_stage = nullptr;
+    size_t stage_cap = 0, stage_used = 0;
+    void *stage(const void *src, size_t bytes);
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+
+    ~Batch();
+    void bind(const std::vector<Scene *> &scenes, hipStream_t strm);
+    Launch launch(PhaseKind k) const { return Launch{d_list, d_off[k], d_out, (int)sc.size()}; }
+    int blocks(PhaseKind k) const { return h_off[k].empty() ? 0 : h_off[k].back(); }
+    void set_phase(PhaseKind k, const std::vector<int32_t> &per_scene_blocks);
+    void upload_views();
+    void read_out();
+    bool prof() const;
+    void prof_begin(int kernel, hipEvent_t *pair);
+    void prof_end(int kernel, hipEvent_t *pair);
+    void prof_collect();
+};
+
+// launch `kernel` over phase `kind` of batch b with `bs` threads per block;
+// the first kernel argument is the phase's Launch descriptor
+#define IPC_LAUNCH(b, kernel, kind, bs, ...)                                                              \
+    do {                                                                                                  \
+        int _nb = (b).blocks(kind);                                                                       \
+        if (_nb > 0) hipLaunchKernelGGL(kernel, dim3(_nb), dim3(bs), 0, (b).stream, (b).launch(kind), ##__VA_ARGS__); \
+    } while (0)
+
+// ---- kernel launchers (defined in the .hip files) -------------------------
+
+void launch_begin_step(Batch &b);
+void launch_end_step(Batch &b);
+void launch_trial(Batch &b);       // uses b.h_alpha (uploaded by the caller to b.d_alpha)
+void launch_accept(Batch &b);
+void launch_rest_precompute(Batch &b);
+void run_lag_and_mean(Batch &b);
+void launch_gather_surface(Scene &s, double *dst, hipStream_t strm);
+
+void launch_elastic_elements(Batch &b);
+void launch_assemble(Batch &b);
+
+// 0: static at x, 1: swept over [x, x + p]. A scene whose positions are not
+// finite, or whose tables or lists cannot grow, gets b.fail set and must be
+// dropped from the phase maps by the caller before the next phase.
+void run_broad_phase(Batch &b, int which);
+void run_narrow_phase(Batch &b);
+void launch_barrier(Batch &b);
+void launch_contact_incidence(Batch &b);
+void run_ccd(Batch &b);
+void run_energy(Batch &b, bool trial);
+void launch_energy_body(Batch &b, bool trial);
+
+void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap);
+void run_pinf(Batch &b);
+void launch_hess_apply(Batch &b);  // y (S.q) = H v (S.dB)
+
+enum ScanWhich { kScanTri = 0, kScanEdge = 1, kScanQuery = 2, kScanContact = 3, kScanActive = 4 };
+// len[s] < 0: scene s sits out; query_sw selects the swept-candidate total
+void segmented_scan(Batch &b, ScanWhich which, PhaseKind tiles, const std::vector<int64_t> &len, int query_sw = 0);
+
+void mark_dirty(Scene &s);
+// per-scene growth of the dynamic buffers (host; sets s.dev_dirty)
+void grow_table(Scene &s, int table, int64_t entries);
+void grow_candidates(Scene &s, int which, int64_t need);
+void grow_active(Scene &s, int64_t need);
 
 }  // namespace ipcg

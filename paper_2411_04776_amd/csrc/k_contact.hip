@@ -13,6 +13,11 @@
 // the exact FP64 box test and is reported once, from the cell that holds the
 // low corner of the two boxes' intersection. Each query's output segment is
 // sorted, so the list comes out in canonical (type, a, b) order.
+//
+// Every kernel runs over a list of scenes (see ipc_internal.h); per-scene
+// counts live on the device and are read back once per phase for all scenes.
+#include <functional>
+
 #include "device_util.h"
 #include "ipc_internal.h"
 
@@ -183,25 +188,42 @@ __device__ __forceinline__ void gather12(const double *x, const int v[4], double
         for (int i = 0; i < 3; ++i) x12[3 * k + i] = x[3 * v[k] + i];
 }
 
+
+template <class R>
+__device__ __forceinline__ R *as(void *p)
+{
+    return reinterpret_cast<R *>(p);
+}
+
 // ---------------------------------------------------------------------------
 // boxes and the spatial hash
 // ---------------------------------------------------------------------------
 
-// box over vertex positions at x (and x + p if p != null), inflated by r
-__global__ void k_boxes(int N, int nv, const int32_t *__restrict__ vids, int stride, const double *__restrict__ x,
-                        const double *__restrict__ p, double r, double *__restrict__ box)
+// box over the primitive's vertex positions at x (and x + p for the swept
+// set), inflated by dhat/2. kind 0 points, 1 edges, 2 triangles.
+template <class R>
+__global__ void k_boxes(Launch L, int kind, int swept)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int N = kind == 0 ? S.n_pts : (kind == 1 ? S.n_edges : S.n_tris);
+    int i = lb * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const int32_t *vids = kind == 0 ? S.pts : (kind == 1 ? S.ev : S.trv);
+    double *box = kind == 0 ? S.pbox : (kind == 1 ? S.ebox : S.tbox);
+    int nv = kind + 1;
+    const double *x = S.x;
+    const R *p = swept ? as<R>(S.sol) : nullptr;
+    double r = 0.5 * S.dhat;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int k = 0; k < nv; ++k) {
-        int v = vids[k * stride + i];
+        int v = vids[(int64_t)k * N + i];
         for (int c = 0; c < 3; ++c) {
             double a = x[3 * v + c];
             lo[c] = fmin(lo[c], a);
             hi[c] = fmax(hi[c], a);
             if (p) {
-                double b = __dadd_rn(a, p[3 * v + c]);
+                double b = __dadd_rn(a, (double)p[3 * v + c]);
                 lo[c] = fmin(lo[c], b);
                 hi[c] = fmax(hi[c], b);
             }
@@ -213,26 +235,34 @@ __global__ void k_boxes(int N, int nv, const int32_t *__restrict__ vids, int str
     }
 }
 
-// per-block sums of the largest axis extent of each box
-__global__ void k_box_extent(int N, const double *__restrict__ box, double *__restrict__ part)
+// per-block sums of the largest axis extent of each box (edges at
+// red[0..nbe), triangles after them)
+__global__ void k_box_extent(Launch L, int kind, Launch edges)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int N = kind == 1 ? S.n_edges : S.n_tris;
+    const double *box = kind == 1 ? S.ebox : S.tbox;
+    int i = lb * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < N)
         for (int c = 0; c < 3; ++c) e = fmax(e, box[(3 + c) * N + i] - box[c * N + i]);
     e = block_sum_all(e);
-    if (threadIdx.x == 0) part[blockIdx.x] = e;
+    int off = kind == 1 ? 0 : blocks_of(edges, s);
+    if (threadIdx.x == 0) S.red[off + lb] = e;
 }
 
 // cell size = mean extent of the edge and triangle boxes (never below the
 // inflation dhat): most primitives span 1-3 cells per axis, large ones more
-__global__ void k_cell_size(int nb, const double *__restrict__ part, double count, double floor_h,
-                            double *cell_h)
+__global__ void k_cell_size(Launch one, Launch edges, Launch tris)
 {
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nb = blocks_of(edges, s) + blocks_of(tris, s);
     double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += S.red[i];
     v = block_sum_all(v);
-    if (threadIdx.x == 0) *cell_h = fmax(v / count, floor_h);
+    if (threadIdx.x == 0) *S.cell_h = fmax(v / (double)(S.n_edges + S.n_tris), S.dhat);
 }
 
 __device__ __forceinline__ int cell_of(double v, double h) { return (int)floor(v / h); }
@@ -245,19 +275,37 @@ __device__ __forceinline__ uint32_t cell_hash(int ix, int iy, int iz, uint32_t m
 // a non-finite or absurd position, which is flagged and skipped.
 constexpr int kMaxSpan = 4096;
 
-template <bool FILL>
-__global__ void k_hash_insert(int N, const double *__restrict__ box, const double *__restrict__ cell_h, uint32_t mask,
-                              int32_t *__restrict__ counter, const int32_t *__restrict__ start,
-                              int4 *__restrict__ entries, int entry_cap, int32_t *__restrict__ bad)
+// zero a per-scene int array: 0/1 hash bucket counts, 2 contact counts
+__global__ void k_zero(Launch L, int which)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int32_t *a = which == 0 ? S.ht_count[0] : (which == 1 ? S.ht_count[1] : S.c_cnt);
+    int64_t len = which == 2 ? (int64_t)S.n + 1 : ((int64_t)1 << S.ht_bits[which]) + 1;
+    for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i < len; i += (int64_t)blocks_of(L, s) * blockDim.x)
+        a[i] = 0;
+}
+
+template <bool FILL>
+__global__ void k_hash_insert(Launch L, int table)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int N = table == 0 ? S.n_tris : S.n_edges;
+    const double *box = table == 0 ? S.tbox : S.ebox;
+    int i = lb * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    double h = *cell_h;
+    uint32_t mask = (1u << S.ht_bits[table]) - 1;
+    int32_t *counter = S.ht_count[table];
+    const int32_t *start = S.ht_start[table];
+    int4 *entries = S.ht_entries[table];
+    int cap = S.ht_cap[table];
+    double h = *S.cell_h;
     int lo[3], hi[3];
     for (int c = 0; c < 3; ++c) {
         double a = box[c * N + i], b = box[(3 + c) * N + i];
         if (!(a <= b) || !((b - a) / h < (double)kMaxSpan)) {
-            if (!FILL) atomicOr(bad, 1);
+            if (!FILL) atomicOr(&L.out[s].bad, 1);
             return;
         }
         lo[c] = cell_of(a, h);
@@ -268,91 +316,89 @@ __global__ void k_hash_insert(int N, const double *__restrict__ box, const doubl
             for (int ix = lo[0]; ix <= hi[0]; ++ix) {
                 uint32_t bkt = cell_hash(ix, iy, iz, mask);
                 int pos = atomicAdd(&counter[bkt], 1);
-                if (FILL && start[bkt] + pos < entry_cap) entries[start[bkt] + pos] = make_int4(ix, iy, iz, i);
+                if (FILL && start[bkt] + pos < cap) entries[start[bkt] + pos] = make_int4(ix, iy, iz, i);
             }
 }
 
-struct PairRules {
-    const int32_t *pts;
-    const uint8_t *fixed;
-    int n_gel;
-    int self_contact;
-};
-
-__device__ __forceinline__ bool pt_admissible(const PairRules &R, int a, int t0, int t1, int t2)
+__device__ __forceinline__ bool pt_admissible(const SceneDev &S, int a, int t0, int t1, int t2)
 {
     if (a == t0 || a == t1 || a == t2) return false;
-    bool ai = a >= R.n_gel, ti = t0 >= R.n_gel;
+    bool ai = a >= S.n_gel, ti = t0 >= S.n_gel;
     if (ai && ti) return false;
-    if (!ai && !ti && !R.self_contact) return false;
-    if (R.fixed[a] && R.fixed[t0] && R.fixed[t1] && R.fixed[t2]) return false;
+    if (!ai && !ti && !S.self_contact) return false;
+    if (S.fixed[a] && S.fixed[t0] && S.fixed[t1] && S.fixed[t2]) return false;
     return true;
 }
-__device__ __forceinline__ bool ee_admissible(const PairRules &R, int a0, int a1, int b0, int b1)
+__device__ __forceinline__ bool ee_admissible(const SceneDev &S, int a0, int a1, int b0, int b1)
 {
     if (a0 == b0 || a0 == b1 || a1 == b0 || a1 == b1) return false;
-    bool ai = a0 >= R.n_gel, bi = b0 >= R.n_gel;
+    bool ai = a0 >= S.n_gel, bi = b0 >= S.n_gel;
     if (ai && bi) return false;
-    if (!ai && !bi && !R.self_contact) return false;
-    if (R.fixed[a0] && R.fixed[a1] && R.fixed[b0] && R.fixed[b1]) return false;
+    if (!ai && !bi && !S.self_contact) return false;
+    if (S.fixed[a0] && S.fixed[a1] && S.fixed[b0] && S.fixed[b1]) return false;
     return true;
 }
 
 // One thread per query primitive (PT: surface point index, EE: edge index).
-// COUNT: per-query number of accepted pairs. Else write them at off[q] and
-// sort the segment by b.
+// COUNT: per-query number of accepted pairs. Else write them at q_off and
+// sort the query's segment by b. swept selects the output list.
 template <int KIND, bool COUNT>
-__global__ void __launch_bounds__(kBlock) k_query(int NA, const double *__restrict__ abox, int NB,
-                                                   const double *__restrict__ bbox, Topo tp, PairRules R,
-                                                   const double *__restrict__ cell_h, uint32_t mask,
-                                                   const int32_t *__restrict__ start, const int4 *__restrict__ entries,
-                                                   int entry_cap, int32_t *__restrict__ qcount,
-                                                   const int32_t *__restrict__ qoff,
-                                                   int32_t *__restrict__ out_type, int32_t *__restrict__ out_a,
-                                                   int32_t *__restrict__ out_b, int64_t out_base)
+__global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
 {
-    int qa = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int NA = KIND == 0 ? S.n_pts : S.n_edges;
+    int NB = KIND == 0 ? S.n_tris : S.n_edges;
+    int qa = lb * blockDim.x + threadIdx.x;
     if (qa >= NA) return;
-    double h = *cell_h;
+    const double *abox = KIND == 0 ? S.pbox : S.ebox;
+    const double *bbox = KIND == 0 ? S.tbox : S.ebox;
+    const int table = KIND == 0 ? 0 : 1;
+    uint32_t mask = (1u << S.ht_bits[table]) - 1;
+    const int32_t *start = S.ht_start[table];
+    const int4 *entries = S.ht_entries[table];
+    int cap = S.ht_cap[table];
+    int qidx = (KIND == 0 ? 0 : S.n_pts) + qa;
+    double h = *S.cell_h;
     double alo[3], ahi[3];
     int clo[3], chi[3];
     for (int c = 0; c < 3; ++c) {
         alo[c] = abox[c * NA + qa];
         ahi[c] = abox[(3 + c) * NA + qa];
         if (!(alo[c] <= ahi[c]) || !((ahi[c] - alo[c]) / h < (double)kMaxSpan)) {
-            if (COUNT) qcount[qa] = 0;
+            if (COUNT) S.q_count[qidx] = 0;
             return;
         }
         clo[c] = cell_of(alo[c], h);
         chi[c] = cell_of(ahi[c], h);
     }
-    int va[2];
-    int a_id;
+    int va0, va1 = -1, a_id;
     if (KIND == 0) {
-        va[0] = R.pts[qa];
-        a_id = va[0];
+        va0 = S.pts[qa];
+        a_id = va0;
     } else {
-        va[0] = tp.ev[qa];
-        va[1] = tp.ev[tp.ne + qa];
+        va0 = S.ev[qa];
+        va1 = S.ev[S.n_edges + qa];
         a_id = qa;
     }
+    int32_t *out = swept ? S.cand_sw : S.cand;
+    int64_t ocap = swept ? S.sw_cap : S.cand_cap;
     int count = 0;
-    int64_t o = 0;
-    if (!COUNT) o = out_base + qoff[qa];
+    int64_t o = COUNT ? 0 : (int64_t)S.q_off[qidx];
     for (int iz = clo[2]; iz <= chi[2]; ++iz)
         for (int iy = clo[1]; iy <= chi[1]; ++iy)
             for (int ix = clo[0]; ix <= chi[0]; ++ix) {
                 uint32_t bkt = cell_hash(ix, iy, iz, mask);
-                int kend = min(start[bkt + 1], entry_cap);
+                int kend = min(start[bkt + 1], cap);
                 for (int k = start[bkt]; k < kend; ++k) {
                     int4 en = entries[k];
                     if (en.x != ix || en.y != iy || en.z != iz) continue;
                     int b = en.w;
                     if (KIND == 0) {
-                        if (!pt_admissible(R, va[0], tp.trv[b], tp.trv[tp.nt + b], tp.trv[2 * tp.nt + b])) continue;
+                        if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
                     } else {
                         if (b <= qa) continue;
-                        if (!ee_admissible(R, va[0], va[1], tp.ev[b], tp.ev[tp.ne + b])) continue;
+                        if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
                     }
                     bool ov = true;
                     double corner[3];
@@ -364,28 +410,27 @@ __global__ void __launch_bounds__(kBlock) k_query(int NA, const double *__restri
                     if (!ov) continue;
                     if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
                         continue;
-                    if (COUNT) {
-                        ++count;
-                    } else {
-                        out_type[o + count] = KIND;
-                        out_a[o + count] = a_id;
-                        out_b[o + count] = b;
-                        ++count;
+                    if (!COUNT && o + count < ocap) {
+                        out[o + count] = KIND;
+                        out[ocap + o + count] = a_id;
+                        out[2 * ocap + o + count] = b;
                     }
+                    ++count;
                 }
             }
     if (COUNT) {
-        qcount[qa] = count;
+        S.q_count[qidx] = count;
     } else {
-        // insertion sort of this query's segment by b
-        for (int i = 1; i < count; ++i) {
-            int key = out_b[o + i];
+        int32_t *ob = out + 2 * ocap + o;
+        int len = (int)min((int64_t)count, ocap - o);  // equal to count once the list has grown
+        for (int i = 1; i < len; ++i) {
+            int key = ob[i];
             int j = i - 1;
-            while (j >= 0 && out_b[o + j] > key) {
-                out_b[o + j + 1] = out_b[o + j];
+            while (j >= 0 && ob[j] > key) {
+                ob[j + 1] = ob[j];
                 --j;
             }
-            out_b[o + j + 1] = key;
+            ob[j + 1] = key;
         }
     }
 }
@@ -394,27 +439,31 @@ __global__ void __launch_bounds__(kBlock) k_query(int NA, const double *__restri
 // narrow phase, barrier, incidence
 // ---------------------------------------------------------------------------
 
-__global__ void k_narrow(int64_t nc, int64_t cap, const int32_t *__restrict__ cand, Topo tp,
-                         const double *__restrict__ x, double dhat, double *__restrict__ dout,
-                         int32_t *__restrict__ active)
+__device__ __forceinline__ Topo topo_of(const SceneDev &S) { return Topo{S.ev, S.trv, S.n_edges, S.n_tris}; }
+
+__global__ void k_narrow(Launch L)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nc) return;
-    int type = cand[i], a = cand[cap + i], b = cand[2 * cap + i];
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (i >= L.out[s].n_cand) return;
+    int64_t cap = S.cand_cap;
+    int type = S.cand[i], a = S.cand[cap + i], b = S.cand[2 * cap + i];
     int v[4];
     double x12[12];
-    cand_vertices(tp, type, a, b, v);
-    gather12(x, v, x12);
+    cand_vertices(topo_of(S), type, a, b, v);
+    gather12(S.x, v, x12);
     double d = pair_distance(type, x12);
-    dout[i] = d;
-    active[i] = d < dhat ? 1 : 0;
+    S.cand_d[i] = d;
+    S.act_flag[i] = d < S.dhat ? 1 : 0;
 }
 
-__global__ void k_compact(int64_t nc, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                          int32_t *__restrict__ out)
+__global__ void k_compact(Launch L)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nc && flag[i]) out[pos[i]] = (int32_t)i;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (i < L.out[s].n_cand && S.act_flag[i]) S.act_idx[S.q_off[i]] = (int32_t)i;
 }
 
 // Shared per-pair data of the distance derivatives at fixed type: residual r,
@@ -476,26 +525,29 @@ __device__ __forceinline__ void rr_pair(int round, int i, int &p, int &q)
 // cyclic Jacobi (six disjoint rotations per round) diagonalises the 12x12 in
 // LDS and negative eigenvalues are clamped to zero. Matrices that are already
 // PSD are kept as assembled.
-__global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, const int32_t *__restrict__ act_idx,
-                                                int64_t cap, const int32_t *__restrict__ cand, Topo tp,
-                                                const double *__restrict__ edge_rest_sq,
-                                                const double *__restrict__ x, const uint8_t *__restrict__ fixed,
-                                                double dhat, double kappa,
-                                                int32_t *__restrict__ act_v, double *__restrict__ act_g,
-                                                double *__restrict__ act_H)
+template <class R>
+__global__ void __launch_bounds__(64) k_barrier(Launch L)
 {
     __shared__ double A[144], V[144], A0[144];
     __shared__ double rc[6], rs[6];
     __shared__ int rp[6], rq[6];
-    int64_t k = blockIdx.x;
-    if (k >= nact) return;
+    int lbk, s = scene_of_block(L, lbk);
+    const SceneDev &S = *L.sc[s];
+    int64_t k = lbk;
+    if (k >= L.out[s].n_act) return;
     const int lane = threadIdx.x;
-    int ci = act_idx[k];
-    int type = cand[ci], a = cand[cap + ci], b = cand[2 * cap + ci];
+    const int64_t cap = S.cand_cap, act_cap = S.act_cap;
+    const double dhat = S.dhat, kappa = S.kappa;
+    const double *edge_rest_sq = S.edge_rest_sq;
+    const uint8_t *fixed = S.fixed;
+    R *act_g = as<R>(S.act_g), *act_H = as<R>(S.act_H);
+    int32_t *act_v = S.act_v;
+    int ci = S.act_idx[k];
+    int type = S.cand[ci], a = S.cand[cap + ci], b = S.cand[2 * cap + ci];
     int v[4];
     double x12[12];
-    cand_vertices(tp, type, a, b, v);
-    gather12(x, v, x12);
+    cand_vertices(topo_of(S), type, a, b, v);
+    gather12(S.x, v, x12);
     DistSpec sp = type == 0 ? c_pt_spec[classify_pt(x12)] : c_ee_spec[classify_ee(x12)];
     DistDeriv dd;
     dist_deriv_setup(sp, x12, dd);
@@ -560,7 +612,7 @@ __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, c
     if (lane < 12) {
         double gv = w * bb[1] * gs_of(lane) * inv2d;
         if (moll) gv += bb[0] * m1 * gc_of(lane);
-        act_g[(int64_t)lane * act_cap + k] = kappa * gv;
+        act_g[(int64_t)lane * act_cap + k] = (R)(kappa * gv);
     }
     if (lane < 4) act_v[(int64_t)lane * act_cap + k] = v[lane];
     __syncthreads();
@@ -642,31 +694,35 @@ __global__ void __launch_bounds__(64) k_barrier(int64_t nact, int64_t act_cap, c
         }
         // Dirichlet vertices drop out (their identity rows live in the elastic matrix)
         if (fixed[v[i / 3]] || fixed[v[j / 3]]) val = 0.0;
-        act_H[(int64_t)e * act_cap + k] = val;
+        act_H[(int64_t)e * act_cap + k] = (R)val;
     }
-    if (lane < 12 && fixed[v[lane / 3]]) act_g[(int64_t)lane * act_cap + k] = 0.0;
+    if (lane < 12 && fixed[v[lane / 3]]) act_g[(int64_t)lane * act_cap + k] = R(0);
 }
+
 
 template <bool FILL>
-__global__ void k_incidence(int64_t nact, int64_t act_cap, const int32_t *__restrict__ act_v,
-                            const uint8_t *__restrict__ fixed, int32_t *__restrict__ cnt,
-                            const int32_t *__restrict__ ptr, int32_t *__restrict__ list)
+__global__ void k_incidence(Launch L)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nact) return;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (k >= L.out[s].n_act) return;
     for (int a = 0; a < 4; ++a) {
-        int v = act_v[(int64_t)a * act_cap + k];
-        if (fixed[v]) continue;
-        int pos = atomicAdd(&cnt[v], 1);
-        if (FILL) list[ptr[v] + pos] = (int32_t)(k * 4 + a);
+        int v = S.act_v[(int64_t)a * S.act_cap + k];
+        if (S.fixed[v]) continue;
+        int pos = atomicAdd(&S.c_cnt[v], 1);
+        if (FILL) S.c_list[S.c_ptr[v] + pos] = (int32_t)(k * 4 + a);
     }
 }
 
-__global__ void k_incidence_sort(int n, const int32_t *__restrict__ ptr, int32_t *__restrict__ list)
+__global__ void k_incidence_sort(Launch L)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int s0 = ptr[i], s1 = ptr[i + 1];
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    int s0 = S.c_ptr[i], s1 = S.c_ptr[i + 1];
+    int32_t *list = S.c_list;
     for (int k = s0 + 1; k < s1; ++k) {
         int key = list[k];
         int j = k - 1;
@@ -715,325 +771,342 @@ __device__ double accd_pair(int kind, const double *x0, const double *p0, double
     return t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_accd(int64_t nc, int64_t cap, const int32_t *__restrict__ cand, Topo tp,
-                                                 const double *__restrict__ x, const double *__restrict__ p, double s,
-                                                 int max_iter, double *__restrict__ part)
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_accd(Launch L)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
     double t = 1.0;
-    if (i < nc) {
-        int type = cand[i], a = cand[cap + i], b = cand[2 * cap + i];
+    if (i < L.out[s].n_sw) {
+        int64_t cap = S.sw_cap;
+        int type = S.cand_sw[i], a = S.cand_sw[cap + i], b = S.cand_sw[2 * cap + i];
         int v[4];
         double x12[12], p12[12];
-        cand_vertices(tp, type, a, b, v);
-        gather12(x, v, x12);
-        gather12(p, v, p12);
-        t = accd_pair(type, x12, p12, s, 1.0, max_iter);
+        cand_vertices(topo_of(S), type, a, b, v);
+        gather12(S.x, v, x12);
+        const R *p = as<R>(S.sol);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) p12[3 * k + c] = (double)p[3 * v[k] + c];
+        t = accd_pair(type, x12, p12, S.ccd_s, 1.0, S.ccd_max_iter);
     }
     t = block_min_all(t);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (threadIdx.x == 0) S.red[lb] = t;
 }
 
-__global__ void k_final_min(int nb, const double *__restrict__ part, double *out)
+__global__ void k_final_ccd(Launch one, Launch prod)
 {
-    double v = INFINITY;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmin(v, part[i]);
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nb = blocks_of(prod, s);
+    double v = 1.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmin(v, S.red[i]);
     v = block_min_all(v);
-    if (threadIdx.x == 0) *out = v;
+    if (threadIdx.x == 0) one.out[s].alpha_ccd = v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_energy_contact(int64_t nc, int64_t cap, const int32_t *__restrict__ cand,
-                                                           Topo tp, const double *__restrict__ edge_rest_sq,
-                                                           const double *__restrict__ x, double dhat, double kappa,
-                                                           double *__restrict__ part, int32_t *flag)
+// barrier energy over the swept candidates, partials after the body partials
+__global__ void __launch_bounds__(kBlock) k_energy_contact(Launch L, Launch body, int trial)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const double *x = trial ? S.xtrial : S.x;
+    int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
     double val = 0.0;
-    if (i < nc) {
-        int type = cand[i], a = cand[cap + i], b = cand[2 * cap + i];
+    if (i < L.out[s].n_sw) {
+        int64_t cap = S.sw_cap;
+        int type = S.cand_sw[i], a = S.cand_sw[cap + i], b = S.cand_sw[2 * cap + i];
         int v[4];
         double x12[12];
-        cand_vertices(tp, type, a, b, v);
+        cand_vertices(topo_of(S), type, a, b, v);
         gather12(x, v, x12);
         double d = pair_distance(type, x12);
         if (!(d > 0.0)) {
-            atomicOr(flag, 1);
-        } else if (d < dhat) {
+            atomicOr(&L.out[s].infeasible, 1);
+        } else if (d < S.dhat) {
             double bb[3];
-            barrier3(d, dhat, bb);
+            barrier3(d, S.dhat, bb);
             double w = 1.0;
             if (type == 1) {
-                double eps_x = kMollifier * edge_rest_sq[a] * edge_rest_sq[b];
+                double eps_x = kMollifier * S.edge_rest_sq[a] * S.edge_rest_sq[b];
                 double ea[3] = {x12[3] - x12[0], x12[4] - x12[1], x12[5] - x12[2]};
                 double eb[3] = {x12[9] - x12[6], x12[10] - x12[7], x12[11] - x12[8]};
-                double cr[3] = {ea[1] * eb[2] - ea[2] * eb[1], ea[2] * eb[0] - ea[0] * eb[2],
-                                ea[0] * eb[1] - ea[1] * eb[0]};
+                double cr[3] = {ea[1] * eb[2] - ea[2] * eb[1], ea[2] * eb[0] - ea[0] * eb[2], ea[0] * eb[1] - ea[1] * eb[0]};
                 double c = d3(cr, cr);
                 if (c < eps_x) w = -c * c / (eps_x * eps_x) + 2.0 * c / eps_x;
             }
-            val = kappa * w * bb[0];
+            val = S.kappa * w * bb[0];
         }
     }
     CSum cs = {val, 0.0};
     cs = block_csum(cs);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = cs.s;
-        part[2 * blockIdx.x + 1] = cs.c;
+        int off = blocks_of(body, s) + lb;
+        S.red[2 * off] = cs.s;
+        S.red[2 * off + 1] = cs.c;
     }
 }
 
-// final compensated sum over body + contact partials
-__global__ void k_energy_final(int nb, const double *__restrict__ part, double *out)
+__global__ void k_clear_infeasible(Launch one)
 {
+    int lb, s = scene_of_block(one, lb);
+    if (threadIdx.x == 0) one.out[s].infeasible = 0;
+}
+
+// final compensated sum over the body and contact partials of one scene
+__global__ void k_energy_final(Launch one, Launch body, Launch cont)
+{
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nb = blocks_of(body, s) + blocks_of(cont, s);
     CSum acc = {0.0, 0.0};
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        CSum t = {part[2 * i], part[2 * i + 1]};
+        CSum t = {S.red[2 * i], S.red[2 * i + 1]};
         acc = csum_add(acc, t);
     }
     acc = block_csum(acc);
-    if (threadIdx.x == 0) *out = acc.s + acc.c;
+    if (threadIdx.x == 0) one.out[s].energy = acc.s + acc.c;
 }
 
 // ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
 
-static Topo topo(Scene &s) { return Topo{s.ev, s.trv, s.n_edges, s.n_tris}; }
-static PairRules rules(Scene &s) { return PairRules{s.pts, s.fixed, s.n_gel, s.prm.self_contact}; }
+static bool mixed(const Batch &b) { return b.sc[0]->prm.precision == IPC_MIXED; }
 
-void ensure_query(Scene &s, size_t n)
+static std::vector<int32_t> per_scene(const Batch &b, PhaseKind gate, const std::function<int32_t(const Scene &)> &f)
 {
-    if (s.q_n >= n) return;
-    if (s.q_count) dfree(s, s.q_count);
-    if (s.q_off) dfree(s, s.q_off);
-    s.q_count = dalloc<int32_t>(s, n + 1);
-    s.q_off = dalloc<int32_t>(s, n + 1);
-    s.q_n = n;
+    std::vector<int32_t> v(b.sc.size());
+    for (size_t i = 0; i < b.sc.size(); ++i)
+        v[i] = b.h_off[gate][i + 1] > b.h_off[gate][i] ? f(*b.sc[i]) : 0;
+    return v;
 }
 
-void launch_boxes(Scene &s, const double *x, const double *p)
+static void one_per_active(Batch &b, PhaseKind gate)
 {
-    double r = 0.5 * s.prm.dhat;
-    hipLaunchKernelGGL(k_boxes, dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, 1, s.pts, s.n_pts, x, p, r,
-                       s.pbox);
-    hipLaunchKernelGGL(k_boxes, dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges, 2, s.ev, s.n_edges, x,
-                       p, r, s.ebox);
-    hipLaunchKernelGGL(k_boxes, dim3(nblocks(s.n_tris)), dim3(kBlock), 0, s.stream, s.n_tris, 3, s.trv, s.n_tris, x, p,
-                       r, s.tbox);
-    int nbe = nblocks(s.n_edges), nbt = nblocks(s.n_tris);
-    hipLaunchKernelGGL(k_box_extent, dim3(nbe), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox, s.red_scratch);
-    hipLaunchKernelGGL(k_box_extent, dim3(nbt), dim3(kBlock), 0, s.stream, s.n_tris, s.tbox, s.red_scratch + nbe);
-    hipLaunchKernelGGL(k_cell_size, dim3(1), dim3(kBlock), 0, s.stream, nbe + nbt, s.red_scratch,
-                       (double)(s.n_edges + s.n_tris), 2.0 * r, s.cell_h);
+    b.set_phase(kPhOne, per_scene(b, gate, [](const Scene &) { return 1; }));
 }
 
-// table for N boxes with room for `cap` entries (power-of-two buckets)
-static void alloc_table(Scene &s, HashTable &ht, int64_t cap)
+// Candidate pairs at x (which 0) or over [x, x+p] (which 1) for every scene
+// active in the vertex phase. Hash tables that overflow their entry capacity
+// are grown and the phase is redone.
+void run_broad_phase(Batch &b, int which)
 {
-    if (ht.entries.p) {
-        dfree(s, ht.entries.p);
-        dfree(s, ht.bucket_count.p);
-        dfree(s, ht.bucket_start.p);
+    hipEvent_t ev[2];
+    b.prof_begin(kProfBroad, ev);
+    bool mx = mixed(b);
+    if (mx) {
+        IPC_LAUNCH(b, k_boxes<float>, kPhPts, kBlock, 0, which);
+        IPC_LAUNCH(b, k_boxes<float>, kPhEdges, kBlock, 1, which);
+        IPC_LAUNCH(b, k_boxes<float>, kPhTris, kBlock, 2, which);
+    } else {
+        IPC_LAUNCH(b, k_boxes<double>, kPhPts, kBlock, 0, which);
+        IPC_LAUNCH(b, k_boxes<double>, kPhEdges, kBlock, 1, which);
+        IPC_LAUNCH(b, k_boxes<double>, kPhTris, kBlock, 2, which);
     }
-    int bits = 10;
-    while ((int64_t(1) << bits) < 2 * cap && bits < 28) ++bits;
-    ht.table_bits = bits;
-    size_t tsize = size_t(1) << bits;
-    ht.bucket_count.p = dalloc<int32_t>(s, tsize + 1);
-    ht.bucket_start.p = dalloc<int32_t>(s, tsize + 1);
-    ht.entries.p = dalloc<int4>(s, (size_t)cap);
-    ht.entries.n = (size_t)cap;
-}
-
-static void build_hash(Scene &s, HashTable &ht, int N, const double *box, int32_t *bad)
-{
-    uint32_t tsize = 1u << ht.table_bits, mask = tsize - 1;
-    int cap = (int)ht.entries.n;
-    IPC_HIP(hipMemsetAsync(ht.bucket_count.p, 0, sizeof(int32_t) * (tsize + 1), s.stream));
-    hipLaunchKernelGGL((k_hash_insert<false>), dim3(nblocks(N)), dim3(kBlock), 0, s.stream, N, box, s.cell_h, mask,
-                       ht.bucket_count.p, nullptr, nullptr, cap, bad);
-    exclusive_scan(s, ht.bucket_count.p, ht.bucket_start.p, (int)tsize, ht.bucket_start.p + tsize);
-    IPC_HIP(hipMemsetAsync(ht.bucket_count.p, 0, sizeof(int32_t) * (tsize + 1), s.stream));
-    hipLaunchKernelGGL((k_hash_insert<true>), dim3(nblocks(N)), dim3(kBlock), 0, s.stream, N, box, s.cell_h, mask,
-                       ht.bucket_count.p, ht.bucket_start.p, ht.entries.p, cap, bad);
-}
-
-static void grow_candidates(Scene &s, int32_t **buf, int64_t *cap, int64_t need)
-{
-    if (*buf && need <= *cap) return;
-    int64_t nc = need + need / 2 + 1024;
-    if (*buf) dfree(s, *buf);
-    *buf = dalloc<int32_t>(s, 3 * nc);
-    *cap = nc;
-}
-
-// Candidate pairs at x (p null) or over [x, x+p] into *out (SoA triples with
-// stride *cap, grown as needed). Returns the count. Hash tables that overflow
-// their entry capacity are grown and the phase is redone.
-int64_t run_broad_phase(Scene &s, const double *x, const double *p, int32_t **out, int64_t *cap)
-{
-    if (!s.ht_tri.entries.p) alloc_table(s, s.ht_tri, 16 * (int64_t)std::max(s.n_tris, 1));
-    if (!s.ht_edge.entries.p) alloc_table(s, s.ht_edge, 16 * (int64_t)std::max(s.n_edges, 1));
-    int32_t *bad = s.pcg_state + 9;
-    launch_boxes(s, x, p);
-    Topo tp = topo(s);
-    PairRules R = rules(s);
-    int nq = s.n_pts + s.n_edges;
-    ensure_query(s, (size_t)nq);
+    IPC_LAUNCH(b, k_box_extent, kPhEdges, kBlock, 1, b.launch(kPhEdges));
+    IPC_LAUNCH(b, k_box_extent, kPhTris, kBlock, 2, b.launch(kPhEdges));
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_cell_size, kPhOne, kBlock, b.launch(kPhEdges), b.launch(kPhTris));
+    size_t ns = b.sc.size();
+    std::vector<uint8_t> redo(ns, 0), live(ns, 0);
+    for (size_t i = 0; i < ns; ++i) live[i] = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
+    auto tiles_of = [&](int t) {
+        std::vector<int32_t> v(ns, 0);
+        for (size_t i = 0; i < ns; ++i)
+            if (live[i]) v[i] = nblocks((int64_t(1) << b.sc[i]->h.ht_bits[t]) + 1);
+        return v;
+    };
     for (int attempt = 0; attempt < 4; ++attempt) {
-        IPC_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s.stream));
-        build_hash(s, s.ht_tri, s.n_tris, s.tbox, bad);
-        build_hash(s, s.ht_edge, s.n_edges, s.ebox, bad);
-        uint32_t mt = (1u << s.ht_tri.table_bits) - 1, me = (1u << s.ht_edge.table_bits) - 1;
-        int capt = (int)s.ht_tri.entries.n, cape = (int)s.ht_edge.entries.n;
-        hipLaunchKernelGGL((k_query<0, true>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
-                           s.n_tris, s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, capt,
-                           s.q_count, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
-        hipLaunchKernelGGL((k_query<1, true>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges, s.ebox,
-                           s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p, s.ht_edge.entries.p, cape,
-                           s.q_count + s.n_pts, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
-        exclusive_scan(s, s.q_count, s.q_off, nq, s.q_off + nq);
-        int32_t *tt = s.ht_tri.bucket_start.p + ((size_t)1 << s.ht_tri.table_bits);
-        int32_t *te = s.ht_edge.bucket_start.p + ((size_t)1 << s.ht_edge.table_bits);
-        IPC_HIP(hipMemcpyAsync(&s.hb->flag, s.q_off + nq, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipMemcpyAsync(&s.hb->iters, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipMemcpyAsync(&s.hb->count, tt, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipMemcpyAsync(reinterpret_cast<int32_t *>(&s.hb->count) + 1, te, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipStreamSynchronize(s.stream));
-        if (s.hb->iters) throw InfeasibleError{};
-        int32_t ent_t = reinterpret_cast<int32_t *>(&s.hb->count)[0];
-        int32_t ent_e = reinterpret_cast<int32_t *>(&s.hb->count)[1];
-        bool redo = false;
-        if (ent_t > capt) {
-            alloc_table(s, s.ht_tri, (int64_t)ent_t * 3 / 2 + 1024);
-            redo = true;
+        std::vector<int64_t> lt(ns, -1), le(ns, -1), lq(ns, -1);
+        for (size_t i = 0; i < ns; ++i) {
+            if (!live[i]) continue;
+            const SceneDev &S = b.sc[i]->h;
+            lt[i] = int64_t(1) << S.ht_bits[0];
+            le[i] = int64_t(1) << S.ht_bits[1];
+            lq[i] = (int64_t)S.n_pts + S.n_edges;
         }
-        if (ent_e > cape) {
-            alloc_table(s, s.ht_edge, (int64_t)ent_e * 3 / 2 + 1024);
-            redo = true;
+        // zero the buckets, count, scan, zero again, fill; then count queries
+        b.set_phase(kPhTilesT, tiles_of(0));
+        b.set_phase(kPhTilesE, tiles_of(1));
+        IPC_LAUNCH(b, k_zero, kPhTilesT, kBlock, 0);
+        IPC_LAUNCH(b, k_zero, kPhTilesE, kBlock, 1);
+        IPC_LAUNCH(b, k_hash_insert<false>, kPhTris, kBlock, 0);
+        IPC_LAUNCH(b, k_hash_insert<false>, kPhEdges, kBlock, 1);
+        segmented_scan(b, kScanTri, kPhTilesT, lt);
+        segmented_scan(b, kScanEdge, kPhTilesE, le);
+        b.set_phase(kPhTilesT, tiles_of(0));
+        b.set_phase(kPhTilesE, tiles_of(1));
+        IPC_LAUNCH(b, k_zero, kPhTilesT, kBlock, 0);
+        IPC_LAUNCH(b, k_zero, kPhTilesE, kBlock, 1);
+        IPC_LAUNCH(b, k_hash_insert<true>, kPhTris, kBlock, 0);
+        IPC_LAUNCH(b, k_hash_insert<true>, kPhEdges, kBlock, 1);
+        IPC_LAUNCH(b, (k_query<0, true>), kPhPts, kBlock, which);
+        IPC_LAUNCH(b, (k_query<1, true>), kPhEdges, kBlock, which);
+        segmented_scan(b, kScanQuery, kPhTilesQ, lq, which);
+        b.read_out();
+        bool any_redo = false;
+        for (size_t i = 0; i < ns; ++i) {
+            redo[i] = 0;
+            if (!live[i]) continue;
+            Scene &s = *b.sc[i];
+            if (b.h_out[i].bad) {
+                b.fail[i] = IPC_E_INFEASIBLE;
+                continue;
+            }
+            try {
+                if (b.h_out[i].ent_tri > s.h.ht_cap[0]) {
+                    grow_table(s, 0, (int64_t)b.h_out[i].ent_tri * 3 / 2 + 1024);
+                    redo[i] = 1;
+                }
+                if (b.h_out[i].ent_edge > s.h.ht_cap[1]) {
+                    grow_table(s, 1, (int64_t)b.h_out[i].ent_edge * 3 / 2 + 1024);
+                    redo[i] = 1;
+                }
+            } catch (const OomError &) {
+                b.fail[i] = IPC_E_OOM;
+                redo[i] = 0;
+            }
+            any_redo |= redo[i] != 0;
         }
-        if (redo) continue;
-        int32_t total = s.hb->flag;
-        grow_candidates(s, out, cap, total);
-        int64_t C = *cap;
-        int32_t *ob = *out;
-        hipLaunchKernelGGL((k_query<0, false>), dim3(nblocks(s.n_pts)), dim3(kBlock), 0, s.stream, s.n_pts, s.pbox,
-                           s.n_tris, s.tbox, tp, R, s.cell_h, mt, s.ht_tri.bucket_start.p, s.ht_tri.entries.p, capt,
-                           nullptr, s.q_off, ob, ob + C, ob + 2 * C, (int64_t)0);
-        hipLaunchKernelGGL((k_query<1, false>), dim3(nblocks(s.n_edges)), dim3(kBlock), 0, s.stream, s.n_edges,
-                           s.ebox, s.n_edges, s.ebox, tp, R, s.cell_h, me, s.ht_edge.bucket_start.p,
-                           s.ht_edge.entries.p, cape, nullptr, s.q_off + s.n_pts, ob, ob + C, ob + 2 * C, (int64_t)0);
-        return total;
+        if (any_redo && attempt < 3) {
+            b.upload_views();
+            continue;
+        }
+        for (size_t i = 0; i < ns; ++i) {
+            if (!live[i] || b.fail[i]) continue;
+            if (redo[i]) {
+                b.fail[i] = IPC_E_CAPACITY;
+                continue;
+            }
+            try {
+                grow_candidates(*b.sc[i], which, which ? b.h_out[i].n_sw : b.h_out[i].n_cand);
+            } catch (const OomError &) {
+                b.fail[i] = IPC_E_OOM;
+            }
+        }
+        b.upload_views();
+        // failed scenes still run the fill pass: every write is bounded by
+        // their list capacity, and the caller drops them afterwards
+        IPC_LAUNCH(b, (k_query<0, false>), kPhPts, kBlock, which);
+        IPC_LAUNCH(b, (k_query<1, false>), kPhEdges, kBlock, which);
+        b.prof_end(kProfBroad, ev);
+        return;
     }
-    throw CapacityError{};
-}
-
-static void grow_active(Scene &s, int64_t need)
-{
-    if (s.act_idx && need <= s.act_cap) return;
-    int64_t nc = need + need / 2 + 256;
-    if (s.act_idx) {
-        dfree(s, s.act_idx);
-        dfree(s, s.act_v);
-        dfree(s, s.act_g);
-        dfree(s, s.act_H);
-        dfree(s, s.c_list);
-    }
-    s.act_idx = dalloc<int32_t>(s, nc);
-    s.act_v = dalloc<int32_t>(s, 4 * nc);
-    s.act_g = dalloc<double>(s, 12 * nc);
-    s.act_H = dalloc<double>(s, 144 * nc);
-    s.c_list = dalloc<int32_t>(s, 4 * nc);
-    s.act_cap = nc;
 }
 
 // distances of the static candidates; active = d < dhat, compacted
-int64_t run_narrow_phase(Scene &s, const double *x)
+void run_narrow_phase(Batch &b)
 {
-    int64_t nc = s.n_cand;
-    if (nc == 0) {
-        s.n_act = 0;
-        return 0;
+    hipEvent_t ev[2];
+    b.prof_begin(kProfBarrier, ev);
+    size_t ns = b.sc.size();
+    std::vector<int64_t> len(ns, -1);
+    std::vector<int32_t> nbk(ns, 0);
+    for (size_t i = 0; i < ns; ++i) {
+        if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
+        len[i] = b.h_out[i].n_cand;
+        nbk[i] = nblocks(b.h_out[i].n_cand);
     }
-    Topo tp = topo(s);
-    hipLaunchKernelGGL(k_narrow, dim3(nblocks(nc)), dim3(kBlock), 0, s.stream, nc, s.cand_cap, s.cand, tp, x,
-                       s.prm.dhat, s.cand_d, s.act_flag);
-    ensure_query(s, (size_t)nc);
-    exclusive_scan(s, s.act_flag, s.q_off, (int)nc, s.q_off + nc);
-    IPC_HIP(hipMemcpyAsync(&s.hb->flag, s.q_off + nc, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    int64_t na = s.hb->flag;
-    grow_active(s, na);
-    if (na > 0)
-        hipLaunchKernelGGL(k_compact, dim3(nblocks(nc)), dim3(kBlock), 0, s.stream, nc, s.act_flag, s.q_off, s.act_idx);
-    s.n_act = na;
-    return na;
-}
-
-void launch_barrier(Scene &s, const double *x)
-{
-    if (s.n_act == 0) return;
-    Topo tp = topo(s);
-    hipLaunchKernelGGL(k_barrier, dim3((unsigned)s.n_act), dim3(64), 0, s.stream, s.n_act, s.act_cap, s.act_idx,
-                       s.cand_cap, s.cand, tp, s.edge_rest_sq, x, s.fixed, s.prm.dhat, s.prm.kappa, s.act_v,
-                       s.act_g, s.act_H);
-}
-
-void launch_contact_incidence(Scene &s)
-{
-    IPC_HIP(hipMemsetAsync(s.c_cnt, 0, sizeof(int32_t) * (s.n + 1), s.stream));
-    if (s.n_act > 0)
-        hipLaunchKernelGGL((k_incidence<false>), dim3(nblocks(s.n_act)), dim3(kBlock), 0, s.stream, s.n_act, s.act_cap,
-                           s.act_v, s.fixed, s.c_cnt, nullptr, nullptr);
-    exclusive_scan(s, s.c_cnt, s.c_ptr, s.n, s.c_ptr + s.n);
-    if (s.n_act > 0) {
-        IPC_HIP(hipMemsetAsync(s.c_cnt, 0, sizeof(int32_t) * (s.n + 1), s.stream));
-        hipLaunchKernelGGL((k_incidence<true>), dim3(nblocks(s.n_act)), dim3(kBlock), 0, s.stream, s.n_act, s.act_cap,
-                           s.act_v, s.fixed, s.c_cnt, s.c_ptr, s.c_list);
-        hipLaunchKernelGGL(k_incidence_sort, dim3(nblocks(s.n)), dim3(kBlock), 0, s.stream, s.n, s.c_ptr, s.c_list);
+    b.set_phase(kPhCand, nbk);
+    IPC_LAUNCH(b, k_narrow, kPhCand, kBlock);
+    segmented_scan(b, kScanActive, kPhTilesA, len);
+    b.read_out();
+    bool dropped = false;
+    for (size_t i = 0; i < ns; ++i) {
+        if (len[i] < 0) continue;
+        try {
+            grow_active(*b.sc[i], b.h_out[i].n_act);
+        } catch (const OomError &) {
+            b.fail[i] = IPC_E_OOM;
+            nbk[i] = 0;
+            dropped = true;
+        }
     }
+    b.upload_views();
+    if (dropped) b.set_phase(kPhCand, nbk);
+    IPC_LAUNCH(b, k_compact, kPhCand, kBlock);
+    b.prof_end(kProfBarrier, ev);
 }
 
-double run_ccd(Scene &s, const double *x, const double *p)
+void launch_barrier(Batch &b)
 {
-    int64_t nc = s.n_cand_sw;
-    if (nc == 0) return 1.0;
-    int nb = nblocks(nc);
-    Topo tp = topo(s);
-    double *part = s.accd_t;
-    hipLaunchKernelGGL(k_accd, dim3(nb), dim3(kBlock), 0, s.stream, nc, s.sw_cap, s.cand_sw, tp, x, p, s.prm.ccd_s,
-                       s.prm.ccd_max_iter, part);
-    hipLaunchKernelGGL(k_final_min, dim3(1), dim3(kBlock), 0, s.stream, nb, part, s.red_scratch);
-    IPC_HIP(hipMemcpyAsync(&s.hb->value, s.red_scratch, sizeof(double), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    return s.hb->value;
+    hipEvent_t ev[2];
+    b.prof_begin(kProfBarrier, ev);
+    size_t ns = b.sc.size();
+    std::vector<int32_t> na(ns);
+    for (size_t i = 0; i < ns; ++i) na[i] = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] ? b.h_out[i].n_act : 0;
+    b.set_phase(kPhAct, na);
+    if (mixed(b))
+        IPC_LAUNCH(b, k_barrier<float>, kPhAct, 64);
+    else
+        IPC_LAUNCH(b, k_barrier<double>, kPhAct, 64);
+    b.prof_end(kProfBarrier, ev);
 }
 
-int launch_energy_body(Scene &s, const double *x, double *part, int32_t *flag);
-
-// Incremental potential at x over the given candidate list. Sets
-// *infeasible if a tet has J <= 0 or a pair d <= 0.
-double run_energy(Scene &s, const double *x, const int32_t *cand, int64_t nc, int *infeasible)
+void launch_contact_incidence(Batch &b)
 {
-    int32_t *flag = s.pcg_state + 8;
-    IPC_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s.stream));
-    double *part = s.accd_t;  // 2 doubles per block
-    int nb_body = launch_energy_body(s, x, part, flag);
-    int nb_c = 0;
-    int64_t capc = cand == s.cand_sw ? s.sw_cap : s.cand_cap;
-    if (nc > 0) {
-        nb_c = nblocks(nc);
-        Topo tp = topo(s);
-        hipLaunchKernelGGL(k_energy_contact, dim3(nb_c), dim3(kBlock), 0, s.stream, nc, capc, cand, tp, s.edge_rest_sq,
-                           x, s.prm.dhat, s.prm.kappa, part + 2 * nb_body, flag);
+    size_t ns = b.sc.size();
+    std::vector<int32_t> na(ns), nz(ns);
+    std::vector<int64_t> len(ns, -1);
+    for (size_t i = 0; i < ns; ++i) {
+        bool on = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
+        na[i] = on ? nblocks(b.h_out[i].n_act) : 0;
+        nz[i] = on ? nblocks((int64_t)b.sc[i]->h.n + 1) : 0;
+        len[i] = on ? b.sc[i]->h.n : -1;
     }
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s.stream, nb_body + nb_c, part, s.red_scratch);
-    IPC_HIP(hipMemcpyAsync(&s.hb->value, s.red_scratch, sizeof(double), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipMemcpyAsync(&s.hb->flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    *infeasible = s.hb->flag != 0;
-    return *infeasible ? INFINITY : s.hb->value;
+    b.set_phase(kPhActT, na);
+    b.set_phase(kPhTilesC, nz);
+    IPC_LAUNCH(b, k_zero, kPhTilesC, kBlock, 2);
+    IPC_LAUNCH(b, k_incidence<false>, kPhActT, kBlock);
+    segmented_scan(b, kScanContact, kPhTilesC, len);
+    b.set_phase(kPhTilesC, nz);
+    IPC_LAUNCH(b, k_zero, kPhTilesC, kBlock, 2);
+    IPC_LAUNCH(b, k_incidence<true>, kPhActT, kBlock);
+    IPC_LAUNCH(b, k_incidence_sort, kPhVert, kBlock);
+}
+
+void run_ccd(Batch &b)
+{
+    hipEvent_t ev[2];
+    b.prof_begin(kProfCcd, ev);
+    size_t ns = b.sc.size();
+    std::vector<int32_t> nb(ns);
+    for (size_t i = 0; i < ns; ++i)
+        nb[i] = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] ? nblocks(b.h_out[i].n_sw) : 0;
+    b.set_phase(kPhCandSw, nb);
+    if (mixed(b))
+        IPC_LAUNCH(b, k_accd<float>, kPhCandSw, kBlock);
+    else
+        IPC_LAUNCH(b, k_accd<double>, kPhCandSw, kBlock);
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_final_ccd, kPhOne, kBlock, b.launch(kPhCandSw));
+    b.prof_end(kProfCcd, ev);
+}
+
+void launch_energy_body(Batch &b, bool trial);
+
+// Incremental potential (FP64, compensated) at x or x_trial over the swept
+// candidate list, for every scene active in the vertex phase.
+void run_energy(Batch &b, bool trial)
+{
+    hipEvent_t ev[2];
+    b.prof_begin(kProfEnergy, ev);
+    size_t ns = b.sc.size();
+    std::vector<int32_t> nb(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        nb[i] = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] ? nblocks(b.h_out[i].n_sw) : 0;
+        b.h_out[i].infeasible = 0;
+    }
+    b.set_phase(kPhCandSw, nb);
+    b.set_phase(kPhBody, per_scene(b, kPhVert, [](const Scene &s) { return nblocks((int64_t)s.h.m + s.h.n); }));
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_clear_infeasible, kPhOne, 64);
+    launch_energy_body(b, trial);
+    IPC_LAUNCH(b, k_energy_contact, kPhCandSw, kBlock, b.launch(kPhBody), (int)trial);
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_energy_final, kPhOne, kBlock, b.launch(kPhBody), b.launch(kPhCandSw));
+    b.prof_end(kProfEnergy, ev);
 }
 
 }  // namespace ipcg

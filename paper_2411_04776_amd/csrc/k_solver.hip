@@ -1,17 +1,21 @@
-// k_solver.hip -- block-Jacobi PCG, SpMV, vector kernels, scans.
+// k_solver.hip -- block-Jacobi PCG, vector kernels and segmented scans, all
+// over a list of scenes (one launch per phase for every scene in the list).
 //
 // PCG solves H p = -g from p = 0 and stops when the preconditioned residual
 // r^T M^-1 r reaches pcg_tol^2 times its initial value. Each iteration is two
-// kernels with all scalars kept on the device:
-//   A(it): every block reduces the r.z partials of the previous iterations
-//          in a fixed order (so all blocks agree bit for bit), decides the
-//          stop, forms d = z + beta d_prev for its rows and for the columns it
-//          gathers, applies H (BELL blocks + contact incidence lists) and
-//          writes q = H d and the d.q partials;
-//   B(it): every block reduces the d.q partials, alpha = rz / dq, then
-//          p += alpha d, r -= alpha q, z = M^-1 r and the r.z partials.
-// The host launches chunks of iterations and reads the done flag once per
-// chunk; a finished solve turns the remaining launches into no-ops.
+// kernels with every scalar kept on the device:
+//   A(it): every block of a scene reduces that scene's r.z partials of the
+//          previous iterations in a fixed order (all blocks agree bit for
+//          bit), decides the stop, forms d = z + beta d_prev for its rows and
+//          for the columns it gathers, applies H (BELL blocks + contact
+//          incidence lists, four lanes per row) and writes q = H d and d.q;
+//   B(it): every block reduces the scene's d.q partials, alpha = rz / dq,
+//          then p += alpha d, r -= alpha q, z = M^-1 r and the r.z partials.
+// Kernel boundaries cost ~3 us on MI355X against 8-28 us for a cooperative
+// grid-wide barrier, so an iteration is two launches rather than one
+// persistent kernel. The host launches chunks of iterations and reads the
+// per-scene done flags once per chunk; finished scenes turn the remaining
+// launches into no-ops.
 #include <algorithm>
 
 #include "device_util.h"
@@ -19,117 +23,63 @@
 
 namespace ipcg {
 
-struct PcgState {
-    int32_t done;
-    int32_t iters;
-    double stop;
-};
-
-// q_row = sum over the row's BELL blocks and contact entries of H_ij * dv_j,
-// with dv_j = z_j + beta * dold_j (beta_on = 0: dv = z)
-__device__ __forceinline__ void spmv_row(int row, const int32_t *__restrict__ slice_ptr,
-                                         const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                                         const int32_t *__restrict__ c_ptr, const int32_t *__restrict__ c_list,
-                                         const int32_t *__restrict__ act_v, const double *__restrict__ act_H,
-                                         int64_t act_cap, const double *__restrict__ z,
-                                         const double *__restrict__ dold, double beta, bool beta_on,
-                                         double out[3])
+template <class R>
+__device__ __forceinline__ R *as(void *p)
 {
-    int sl = row / kSlice, lane = row % kSlice;
-    int s0 = slice_ptr[sl], s1 = slice_ptr[sl + 1];
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    for (int slot = s0; slot < s1; ++slot) {
-        int64_t base = (int64_t)slot * kSlice + lane;
-        int col = bcol[base];
-        if (col < 0) break;
-        const double *A = bval + (int64_t)slot * 9 * kSlice + lane;
-        double v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
-        if (beta_on) {
-            v0 += beta * dold[3 * col];
-            v1 += beta * dold[3 * col + 1];
-            v2 += beta * dold[3 * col + 2];
-        }
-        y0 += A[0 * kSlice] * v0 + A[1 * kSlice] * v1 + A[2 * kSlice] * v2;
-        y1 += A[3 * kSlice] * v0 + A[4 * kSlice] * v1 + A[5 * kSlice] * v2;
-        y2 += A[6 * kSlice] * v0 + A[7 * kSlice] * v1 + A[8 * kSlice] * v2;
-    }
-    for (int t = c_ptr[row]; t < c_ptr[row + 1]; ++t) {
-        int src = c_list[t], p = src >> 2, a = src & 3;
-        for (int b = 0; b < 4; ++b) {
-            if (b == a) continue;  // the diagonal block lives in the BELL diagonal
-            int vb = act_v[(int64_t)b * act_cap + p];
-            double v0 = z[3 * vb], v1 = z[3 * vb + 1], v2 = z[3 * vb + 2];
-            if (beta_on) {
-                v0 += beta * dold[3 * vb];
-                v1 += beta * dold[3 * vb + 1];
-                v2 += beta * dold[3 * vb + 2];
-            }
-            const double *H = act_H + p;
-            int r0 = 3 * a;
-            y0 += H[(int64_t)((r0 + 0) * 12 + 3 * b + 0) * act_cap] * v0 +
-                  H[(int64_t)((r0 + 0) * 12 + 3 * b + 1) * act_cap] * v1 +
-                  H[(int64_t)((r0 + 0) * 12 + 3 * b + 2) * act_cap] * v2;
-            y1 += H[(int64_t)((r0 + 1) * 12 + 3 * b + 0) * act_cap] * v0 +
-                  H[(int64_t)((r0 + 1) * 12 + 3 * b + 1) * act_cap] * v1 +
-                  H[(int64_t)((r0 + 1) * 12 + 3 * b + 2) * act_cap] * v2;
-            y2 += H[(int64_t)((r0 + 2) * 12 + 3 * b + 0) * act_cap] * v0 +
-                  H[(int64_t)((r0 + 2) * 12 + 3 * b + 1) * act_cap] * v1 +
-                  H[(int64_t)((r0 + 2) * 12 + 3 * b + 2) * act_cap] * v2;
-        }
-    }
-    out[0] = y0;
-    out[1] = y1;
-    out[2] = y2;
+    return reinterpret_cast<R *>(p);
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const double *__restrict__ grad,
-                                                      const double *__restrict__ Minv, double *__restrict__ r,
-                                                      double *__restrict__ z, double *__restrict__ sol,
-                                                      double *__restrict__ part_rz0, PcgState *st)
+// partial-sum layout in pcg_part: [d.q: n_slices][r.z slot 0: nb_vert][slot 1: nb_vert]
+__device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    return S.pcg_part + S.n_slices + (size_t)(it & 1) * S.nb_vert;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_pcg_init(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    R *r = as<R>(S.r), *z = as<R>(S.z), *sol = as<R>(S.sol);
+    const R *g = as<R>(S.grad), *Mi = as<R>(S.Minv);
     double rz = 0.0;
-    if (i < n) {
-        double ri[3], zi[3];
-        for (int c = 0; c < 3; ++c) ri[c] = -grad[3 * i + c];
-        for (int a = 0; a < 3; ++a)
-            zi[a] = Minv[9 * i + 3 * a] * ri[0] + Minv[9 * i + 3 * a + 1] * ri[1] + Minv[9 * i + 3 * a + 2] * ri[2];
+    if (i < S.n) {
+        R ri[3], zi[3];
+        for (int c = 0; c < 3; ++c) ri[c] = -g[3 * i + c];
+        for (int a = 0; a < 3; ++a) zi[a] = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
         for (int c = 0; c < 3; ++c) {
             r[3 * i + c] = ri[c];
             z[3 * i + c] = zi[c];
-            sol[3 * i + c] = 0.0;
-            rz += ri[c] * zi[c];
+            sol[3 * i + c] = R(0);
+            rz += (double)ri[c] * (double)zi[c];
         }
     }
     rz = block_sum_all(rz);
-    if (threadIdx.x == 0) part_rz0[blockIdx.x] = rz;
+    if (threadIdx.x == 0) rz_slot(S, 0)[lb] = rz;
     if (i == 0) {
-        st->done = 0;
-        st->iters = 0;
-        st->stop = 0.0;
+        S.pcg->done = 0;
+        S.pcg->iters = 0;
+        S.pcg->stop = 0.0;
+        L.out[s].pcg_done = 0;
+        L.out[s].pcg_iters = 0;
     }
 }
 
-// PCG kernel A: four lanes per matrix row, one 64-row BELL slice per block.
-// Lane q of a row sums slots q, q+4, ...; the four partial products are
-// combined with lane shuffles in a fixed order. Lane 0 of the row adds the
-// contact incidence terms and writes d and q.
-constexpr int kLanesPerRow = 4;
-
-__device__ __forceinline__ void spmv_row_part(int row, int part, const int32_t *__restrict__ slice_ptr,
-                                              const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                                              const double *__restrict__ z, const double *__restrict__ dold,
-                                              double beta, bool beta_on, double y[3])
+template <class R>
+__device__ __forceinline__ void spmv_row_part(const SceneDev &S, int row, int part, const R *__restrict__ z,
+                                              const R *__restrict__ dold, R beta, bool beta_on, double y[3])
 {
     int sl = row / kSlice, lane = row % kSlice;
-    int s0 = slice_ptr[sl], s1 = slice_ptr[sl + 1];
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    int s0 = S.slice_ptr[sl], s1 = S.slice_ptr[sl + 1];
+    const R *bval = as<R>(S.bval);
+    R y0 = R(0), y1 = R(0), y2 = R(0);
     for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
         int64_t base = (int64_t)slot * kSlice + lane;
-        int col = bcol[base];
+        int col = S.bcol[base];
         if (col < 0) break;
-        const double *A = bval + (int64_t)slot * 9 * kSlice + lane;
-        double v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
+        const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
+        R v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
         if (beta_on) {
             v0 += beta * dold[3 * col];
             v1 += beta * dold[3 * col + 1];
@@ -144,196 +94,275 @@ __device__ __forceinline__ void spmv_row_part(int row, int part, const int32_t *
     y[2] = y2;
 }
 
-__device__ __forceinline__ void contact_row(int row, const int32_t *__restrict__ c_ptr, const int32_t *__restrict__ c_list,
-                                            const int32_t *__restrict__ act_v, const double *__restrict__ act_H,
-                                            int64_t act_cap, const double *__restrict__ z,
-                                            const double *__restrict__ dold, double beta, bool beta_on, double y[3])
+// off-diagonal blocks of the active contact pairs incident to `row`
+template <class R>
+__device__ __forceinline__ void contact_row(const SceneDev &S, int row, const R *__restrict__ z,
+                                            const R *__restrict__ dold, R beta, bool beta_on, double y[3])
 {
-    for (int t = c_ptr[row]; t < c_ptr[row + 1]; ++t) {
-        int src = c_list[t], p = src >> 2, a = src & 3;
+    const R *H = as<R>(S.act_H);
+    for (int t = S.c_ptr[row]; t < S.c_ptr[row + 1]; ++t) {
+        int src = S.c_list[t], p = src >> 2, a = src & 3;
         for (int b = 0; b < 4; ++b) {
-            if (b == a) continue;
-            int vb = act_v[(int64_t)b * act_cap + p];
-            double v[3] = {z[3 * vb], z[3 * vb + 1], z[3 * vb + 2]};
+            if (b == a) continue;  // the diagonal block lives in the BELL diagonal
+            int vb = S.act_v[(int64_t)b * S.act_cap + p];
+            R v[3] = {z[3 * vb], z[3 * vb + 1], z[3 * vb + 2]};
             if (beta_on)
                 for (int c = 0; c < 3; ++c) v[c] += beta * dold[3 * vb + c];
             for (int i = 0; i < 3; ++i) {
-                const double *H = act_H + (int64_t)((3 * a + i) * 12 + 3 * b) * act_cap + p;
-                y[i] += H[0] * v[0] + H[act_cap] * v[1] + H[2 * act_cap] * v[2];
+                const R *h = H + (int64_t)((3 * a + i) * 12 + 3 * b) * S.act_cap + p;
+                y[i] += (double)(h[0] * v[0] + h[S.act_cap] * v[1] + h[2 * S.act_cap] * v[2]);
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_A(
-    int it, int n, int nbB, double tol2, const int32_t *__restrict__ slice_ptr, const int32_t *__restrict__ bcol,
-    const double *__restrict__ bval, const int32_t *__restrict__ c_ptr, const int32_t *__restrict__ c_list,
-    const int32_t *__restrict__ act_v, const double *__restrict__ act_H, int64_t act_cap,
-    const double *__restrict__ z, const double *__restrict__ dold, double *__restrict__ dnew,
-    double *__restrict__ q, double *__restrict__ part_dq, const double *__restrict__ part_rz, PcgState *st)
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
 {
-    if (st->done) return;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = reduce_partials(part_rz, nbB);
+        double rz0 = reduce_partials(rz_slot(S, 0), S.nb_vert);
         if (!(rz0 > 0.0)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                st->done = 1;
-                st->iters = 0;
+            if (lb == 0 && threadIdx.x == 0) {
+                S.pcg->done = 1;
+                S.pcg->iters = 0;
+                L.out[s].pcg_done = 1;
+                L.out[s].pcg_iters = 0;
             }
             return;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->stop = tol2 * rz0;
+        if (lb == 0 && threadIdx.x == 0) S.pcg->stop = S.pcg_tol2 * rz0;
     } else {
-        double rz_cur = reduce_partials(part_rz + (size_t)((it - 1) & 1) * nbB, nbB);
-        if (rz_cur <= st->stop) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                st->done = 1;
-                st->iters = it - 1;
+        double rz_cur = reduce_partials(rz_slot(S, it - 1), S.nb_vert);
+        bool conv = rz_cur <= S.pcg->stop;
+        if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
+            if (lb == 0 && threadIdx.x == 0) {
+                S.pcg->done = 1;
+                S.pcg->iters = it - 1;
+                L.out[s].pcg_done = conv ? 1 : 2;
+                L.out[s].pcg_iters = it - 1;
             }
             return;
         }
-        double rz_prev = reduce_partials(part_rz + (size_t)(it & 1) * nbB, nbB);
+        double rz_prev = reduce_partials(rz_slot(S, it), S.nb_vert);
         beta = rz_cur / rz_prev;
     }
+    const R *z = as<R>(S.z);
+    const R *dold = as<R>((it & 1) ? S.dB : S.dA);
+    R *dnew = as<R>((it & 1) ? S.dA : S.dB);
+    R *q = as<R>(S.q);
     // block = one slice of 64 rows; lanes (4r .. 4r+3) of a wavefront share row r
     int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int row = blockIdx.x * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    int row = lb * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
     int part = lane % kLanesPerRow;
     double y[3] = {0.0, 0.0, 0.0};
-    bool live = row < n;
-    if (live) spmv_row_part(row, part, slice_ptr, bcol, bval, z, dold, beta, it > 1, y);
+    bool live = row < S.n;
+    R rb = (R)beta;
+    if (live) spmv_row_part<R>(S, row, part, z, dold, rb, it > 1, y);
     for (int c = 0; c < 3; ++c) {
         y[c] += __shfl_xor(y[c], 1, kWave);
         y[c] += __shfl_xor(y[c], 2, kWave);
     }
     double dq = 0.0;
     if (live && part == 0) {
-        contact_row(row, c_ptr, c_list, act_v, act_H, act_cap, z, dold, beta, it > 1, y);
+        contact_row<R>(S, row, z, dold, rb, it > 1, y);
         for (int c = 0; c < 3; ++c) {
-            double dv = it > 1 ? z[3 * row + c] + beta * dold[3 * row + c] : z[3 * row + c];
+            R dv = it > 1 ? z[3 * row + c] + rb * dold[3 * row + c] : z[3 * row + c];
+            R qv = (R)y[c];
             dnew[3 * row + c] = dv;
-            q[3 * row + c] = y[c];
-            dq += dv * y[c];
+            q[3 * row + c] = qv;
+            dq += (double)dv * (double)qv;
         }
     }
     dq = block_sum_all(dq);
-    if (threadIdx.x == 0) part_dq[blockIdx.x] = dq;
+    if (threadIdx.x == 0) S.pcg_part[lb] = dq;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_B(int it, int n, int nbA, int nb, const double *__restrict__ q,
-                                                   const double *__restrict__ dcur, const double *__restrict__ Minv,
-                                                   double *__restrict__ sol, double *__restrict__ r,
-                                                   double *__restrict__ z, const double *__restrict__ part_dq,
-                                                   double *__restrict__ part_rz, PcgState *st)
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
 {
-    if (st->done) return;
-    double dq = reduce_partials(part_dq, nbA);
-    double rz_prev = reduce_partials(part_rz + (size_t)((it - 1) & 1) * nb, nb);
-    double alpha = rz_prev / dq;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    if (S.pcg->done) return;
+    double dq = reduce_partials(S.pcg_part, S.n_slices);
+    double rz_prev = reduce_partials(rz_slot(S, it - 1), S.nb_vert);
+    R alpha = (R)(rz_prev / dq);
+    const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
+    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv);
+    R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
+    int i = lb * blockDim.x + threadIdx.x;
     double rz = 0.0;
-    if (i < n) {
-        double ri[3];
+    if (i < S.n) {
+        R ri[3];
         for (int c = 0; c < 3; ++c) {
             sol[3 * i + c] += alpha * dcur[3 * i + c];
             ri[c] = r[3 * i + c] - alpha * q[3 * i + c];
             r[3 * i + c] = ri[c];
         }
         for (int a = 0; a < 3; ++a) {
-            double za = Minv[9 * i + 3 * a] * ri[0] + Minv[9 * i + 3 * a + 1] * ri[1] + Minv[9 * i + 3 * a + 2] * ri[2];
+            R za = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
             z[3 * i + a] = za;
-            rz += ri[a] * za;
+            rz += (double)ri[a] * (double)za;
         }
     }
     rz = block_sum_all(rz);
-    if (threadIdx.x == 0) part_rz[(size_t)(it & 1) * nb + blockIdx.x] = rz;
+    if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
 }
 
-__global__ void k_spmv(int n, const int32_t *__restrict__ slice_ptr, const int32_t *__restrict__ bcol,
-                       const double *__restrict__ bval, const int32_t *__restrict__ c_ptr,
-                       const int32_t *__restrict__ c_list, const int32_t *__restrict__ act_v,
-                       const double *__restrict__ act_H, int64_t act_cap, const double *__restrict__ v,
-                       double *__restrict__ y)
+// y = H v for the test hook: v in S.dB, y in S.q
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_spmv(Launch L)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double o[3];
-    spmv_row(i, slice_ptr, bcol, bval, c_ptr, c_list, act_v, act_H, act_cap, v, nullptr, 0.0, false, o);
-    for (int c = 0; c < 3; ++c) y[3 * i + c] = o[c];
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const R *v = as<R>(S.dB);
+    R *y = as<R>(S.q);
+    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int row = lb * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    int part = lane % kLanesPerRow;
+    double o[3] = {0.0, 0.0, 0.0};
+    bool live = row < S.n;
+    if (live) spmv_row_part<R>(S, row, part, v, nullptr, R(0), false, o);
+    for (int c = 0; c < 3; ++c) {
+        o[c] += __shfl_xor(o[c], 1, kWave);
+        o[c] += __shfl_xor(o[c], 2, kWave);
+    }
+    if (live && part == 0) {
+        contact_row<R>(S, row, v, nullptr, R(0), false, o);
+        for (int c = 0; c < 3; ++c) y[3 * row + c] = (R)o[c];
+    }
 }
 
-// max |p| over free DOFs
-__global__ void k_pinf(int n, const double *__restrict__ p, const uint8_t *__restrict__ fixed,
-                       double *__restrict__ part)
+// ---- per-vertex kernels ------------------------------------------------------
+
+template <class R>
+__global__ void k_pinf(Launch L)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const R *p = as<R>(S.sol);
+    int i = lb * blockDim.x + threadIdx.x;
     double v = 0.0;
-    if (i < n && !fixed[i]) v = fmax(fabs(p[3 * i]), fmax(fabs(p[3 * i + 1]), fabs(p[3 * i + 2])));
+    if (i < S.n && !S.fixed[i])
+        v = fmax(fabs((double)p[3 * i]), fmax(fabs((double)p[3 * i + 1]), fabs((double)p[3 * i + 2])));
     v = block_max_all(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    if (threadIdx.x == 0) S.red[lb] = v;
 }
 
-__global__ void k_final_max(int nb, const double *__restrict__ part, double *out)
+// one block per scene: max over the producer's per-block partials
+__global__ void k_final_pinf(Launch one, Launch prod)
 {
-    double v = -INFINITY;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, part[i]);
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nb = blocks_of(prod, s);
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, S.red[i]);
     v = block_max_all(v);
-    if (threadIdx.x == 0) *out = v;
+    if (threadIdx.x == 0) one.out[s].pinf = v;
 }
 
-// x_out = x + alpha p (one rounding per component, as the line search defines)
-__global__ void k_trial(int m3, const double *__restrict__ x, const double *__restrict__ p, double alpha,
-                        double *__restrict__ out)
+// x_trial = x + alpha p (one rounding per component, as the line search
+// defines it); alpha per scene
+template <class R>
+__global__ void k_trial(Launch L, const double *__restrict__ alpha)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m3) out[i] = __dadd_rn(x[i], __dmul_rn(alpha, p[i]));
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const R *p = as<R>(S.sol);
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    double a = alpha[s];
+    for (int c = 0; c < 3; ++c) S.xtrial[3 * i + c] = __dadd_rn(S.x[3 * i + c], __dmul_rn(a, (double)p[3 * i + c]));
 }
 
-// Step start: keep x^t, inertial predictor for free gel vertices, indenter
-// targets from the pose.
-__global__ void k_begin_step(int n, int n_gel, const double *__restrict__ x, const double *__restrict__ v,
-                             const uint8_t *__restrict__ fixed, const double *__restrict__ Yloc, Pose P, double h,
-                             double gx, double gy, double gz, double *__restrict__ xt, double *__restrict__ xtilde,
-                             double *__restrict__ yhat)
+__global__ void k_accept(Launch L)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double g[3] = {gx, gy, gz};
-    for (int c = 0; c < 3; ++c) xt[3 * i + c] = x[3 * i + c];
-    if (i < n_gel) {
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    for (int c = 0; c < 3; ++c) S.x[3 * i + c] = S.xtrial[3 * i + c];
+}
+
+// step start: keep x^t, inertial predictor for free gel vertices, indenter
+// targets from the scene's pose
+__global__ void k_begin_step(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    double h = S.h;
+    for (int c = 0; c < 3; ++c) S.xt[3 * i + c] = S.x[3 * i + c];
+    if (i < S.n_gel) {
         for (int c = 0; c < 3; ++c) {
-            double xv = x[3 * i + c];
-            xtilde[3 * i + c] = fixed[i] ? xv : xv + h * v[3 * i + c] + h * h * g[c];
-            yhat[3 * i + c] = xv;
+            double xv = S.x[3 * i + c];
+            S.xtilde[3 * i + c] = S.fixed[i] ? xv : xv + h * S.v[3 * i + c] + h * h * S.grav[c];
+            S.yhat[3 * i + c] = xv;
         }
     } else {
-        const double *y = Yloc + 3 * (i - n_gel);
+        const double *y = S.Yloc + 3 * (i - S.n_gel);
+        const double *P = S.pose;
         for (int c = 0; c < 3; ++c) {
-            yhat[3 * i + c] = P.m[c * 4 + 0] * y[0] + P.m[c * 4 + 1] * y[1] + P.m[c * 4 + 2] * y[2] + P.m[c * 4 + 3];
-            xtilde[3 * i + c] = x[3 * i + c];
+            S.yhat[3 * i + c] = P[c * 4 + 0] * y[0] + P[c * 4 + 1] * y[1] + P[c * 4 + 2] * y[2] + P[c * 4 + 3];
+            S.xtilde[3 * i + c] = S.x[3 * i + c];
         }
     }
 }
 
-__global__ void k_end_step(int m3, const double *__restrict__ x, const double *__restrict__ xt, double inv_h,
-                           double *__restrict__ v)
+__global__ void k_end_step(Launch L)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m3) v[i] = (x[i] - xt[i]) * inv_h;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    double inv_h = 1.0 / S.h;
+    for (int c = 0; c < 3; ++c) S.v[3 * i + c] = (S.x[3 * i + c] - S.xt[3 * i + c]) * inv_h;
 }
 
-__global__ void k_target_lag(int n, int n_gel, const double *__restrict__ x, const double *__restrict__ yhat,
-                             double *__restrict__ part)
+// max target lag over indenter vertices and per-block sums of gel positions
+__global__ void k_lag_mean(Launch L)
 {
-    int i = n_gel + blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
-    if (i < n) {
-        double d0 = x[3 * i] - yhat[3 * i], d1 = x[3 * i + 1] - yhat[3 * i + 1], d2 = x[3 * i + 2] - yhat[3 * i + 2];
-        v = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    double lag = 0.0, m[3] = {0.0, 0.0, 0.0};
+    if (i < S.n) {
+        if (i >= S.n_gel) {
+            double d0 = S.x[3 * i] - S.yhat[3 * i], d1 = S.x[3 * i + 1] - S.yhat[3 * i + 1],
+                   d2 = S.x[3 * i + 2] - S.yhat[3 * i + 2];
+            lag = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        } else {
+            for (int c = 0; c < 3; ++c) m[c] = S.x[3 * i + c];
+        }
     }
-    v = block_max_all(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    lag = block_max_all(lag);
+    for (int c = 0; c < 3; ++c) m[c] = block_sum_all(m[c]);
+    if (threadIdx.x == 0) {
+        S.red[4 * lb] = lag;
+        for (int c = 0; c < 3; ++c) S.red[4 * lb + 1 + c] = m[c];
+    }
+}
+
+__global__ void k_final_lag_mean(Launch one, Launch prod)
+{
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nb = blocks_of(prod, s);
+    double lag = 0.0, m[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        lag = fmax(lag, S.red[4 * i]);
+        for (int c = 0; c < 3; ++c) m[c] += S.red[4 * i + 1 + c];
+    }
+    lag = block_max_all(lag);
+    for (int c = 0; c < 3; ++c) m[c] = block_sum_all(m[c]);
+    if (threadIdx.x == 0) {
+        one.out[s].lag = lag;
+        for (int c = 0; c < 3; ++c) one.out[s].obj[c] = m[c] / (double)S.n_gel;
+    }
 }
 
 __global__ void k_gather_surface(int ns, const int32_t *__restrict__ ids, const double *__restrict__ x,
@@ -347,30 +376,28 @@ __global__ void k_gather_surface(int ns, const int32_t *__restrict__ ids, const 
     out[3 * i + 2] = x[3 * v + 2];
 }
 
-// per-block sums of gel vertex coordinates, then a fixed-order final sum
-__global__ void k_mean_part(int n_gel, const double *__restrict__ x, double *__restrict__ part)
+// ---- segmented exclusive scan of per-scene int32 arrays ------------------------
+// Each scene's array is cut into tiles of kScanTile values (its own block
+// range); per-tile sums are scanned by one block per scene; then each tile
+// writes its exclusive prefix. out[len] and the scene's read-back slot get
+// the total.
+
+struct ScanSel {
+    const int32_t *in;
+    int32_t *out;
+    int64_t len;
+};
+
+__device__ __forceinline__ ScanSel scan_sel(const SceneDev &S, const SceneOut &O, int which)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int c = 0; c < 3; ++c) {
-        double v = i < n_gel ? x[3 * i + c] : 0.0;
-        v = block_sum_all(v);
-        if (threadIdx.x == 0) part[3 * blockIdx.x + c] = v;
+    switch (which) {
+    case kScanTri: return {S.ht_count[0], S.ht_start[0], (int64_t)1 << S.ht_bits[0]};
+    case kScanEdge: return {S.ht_count[1], S.ht_start[1], (int64_t)1 << S.ht_bits[1]};
+    case kScanQuery: return {S.q_count, S.q_off, (int64_t)S.n_pts + S.n_edges};
+    case kScanContact: return {S.c_cnt, S.c_ptr, (int64_t)S.n};
+    default: return {S.act_flag, S.q_off, (int64_t)O.n_cand};
     }
 }
-
-__global__ void k_mean_final(int nb, int n_gel, double *__restrict__ part, double *__restrict__ out)
-{
-    for (int c = 0; c < 3; ++c) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[3 * i + c];
-        acc = block_sum_all(acc);
-        if (threadIdx.x == 0) out[c] = acc / (double)n_gel;
-    }
-}
-
-// ---- exclusive scan of int32 (three passes) ------------------------------
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ int block_exclusive_scan(int v, int *total)
 {
@@ -393,174 +420,196 @@ __device__ int block_exclusive_scan(int v, int *total)
     return woff + incl - v;
 }
 
-__global__ void k_scan_tiles(int n, const int32_t *__restrict__ in, int32_t *__restrict__ tile_sums)
+constexpr int kScanItems = kScanTile / kBlock;
+
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(Launch L, int which)
 {
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int s = 0;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    ScanSel sel = scan_sel(S, L.out[s], which);
+    int64_t base = (int64_t)lb * kScanTile + threadIdx.x * kScanItems;
+    int sum = 0;
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += in[base + k];
+        if (base + k < sel.len) sum += sel.in[base + k];
     int tot;
-    block_exclusive_scan(s, &tot);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+    block_exclusive_scan(sum, &tot);
+    if (threadIdx.x == 0) S.scan_tmp[lb] = tot;
 }
 
-__global__ void k_scan_top(int nt, int32_t *__restrict__ tile_sums, int32_t *__restrict__ total)
+__global__ void __launch_bounds__(kBlock) k_scan_top(Launch one, Launch tiles, int which, int query_sw)
 {
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    int nt = blocks_of(tiles, s);
     int carry = 0;
     for (int base = 0; base < nt; base += kBlock) {
         int i = base + threadIdx.x;
-        int v = i < nt ? tile_sums[i] : 0;
+        int v = i < nt ? S.scan_tmp[i] : 0;
         int tot;
         int ex = block_exclusive_scan(v, &tot);
-        if (i < nt) tile_sums[i] = carry + ex;
+        if (i < nt) S.scan_tmp[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) {
+        SceneOut &O = one.out[s];
+        ScanSel sel = scan_sel(S, O, which);
+        sel.out[sel.len] = carry;
+        if (which == kScanTri) O.ent_tri = carry;
+        if (which == kScanEdge) O.ent_edge = carry;
+        if (which == kScanQuery) {
+            if (query_sw)
+                O.n_sw = carry;
+            else
+                O.n_cand = carry;
+        }
+        if (which == kScanActive) O.n_act = carry;
+    }
 }
 
-__global__ void k_scan_apply(int n, const int32_t *__restrict__ in, const int32_t *__restrict__ tile_off,
-                             int32_t *__restrict__ out)
+__global__ void __launch_bounds__(kBlock) k_scan_apply(Launch L, int which)
 {
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    ScanSel sel = scan_sel(S, L.out[s], which);
+    int64_t base = (int64_t)lb * kScanTile + threadIdx.x * kScanItems;
     int vals[kScanItems];
-    int s = 0;
+    int sum = 0;
     for (int k = 0; k < kScanItems; ++k) {
-        vals[k] = (base + k < n) ? in[base + k] : 0;
-        s += vals[k];
+        vals[k] = (base + k < sel.len) ? sel.in[base + k] : 0;
+        sum += vals[k];
     }
     int tot;
-    int ex = block_exclusive_scan(s, &tot) + tile_off[blockIdx.x];
+    int ex = block_exclusive_scan(sum, &tot) + S.scan_tmp[lb];
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) out[base + k] = ex;
+        if (base + k < sel.len) sel.out[base + k] = ex;
         ex += vals[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
 }
 
-void ensure_iscratch(Scene &s, size_t n)
+// ---- launchers ----------------------------------------------------------------
+
+static bool mixed(const Batch &b) { return b.sc[0]->prm.precision == IPC_MIXED; }
+
+void segmented_scan(Batch &b, ScanWhich which, PhaseKind tiles, const std::vector<int64_t> &len, int query_sw)
 {
-    if (s.i_scratch_n >= n) return;
-    if (s.i_scratch) dfree(s, s.i_scratch);
-    size_t want = n < 1024 ? 1024 : n * 2;
-    s.i_scratch = dalloc<int32_t>(s, want);
-    s.i_scratch_n = want;
+    size_t ns = b.sc.size();
+    std::vector<int32_t> nt(ns), one(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        nt[i] = len[i] < 0 ? 0 : std::max<int32_t>(1, (int32_t)((len[i] + kScanTile - 1) / kScanTile));
+        one[i] = len[i] < 0 ? 0 : 1;
+    }
+    b.set_phase(tiles, nt);
+    b.set_phase(kPhOne, one);
+    IPC_LAUNCH(b, k_scan_tiles, tiles, kBlock, (int)which);
+    IPC_LAUNCH(b, k_scan_top, kPhOne, kBlock, b.launch(tiles), (int)which, query_sw);
+    IPC_LAUNCH(b, k_scan_apply, tiles, kBlock, (int)which);
 }
 
-// out must hold n + 1 entries (out[n] = total); total_dev gets the total too.
-void exclusive_scan(Scene &s, const int32_t *in, int32_t *out, int n, int32_t *total_dev)
+void launch_begin_step(Batch &b) { IPC_LAUNCH(b, k_begin_step, kPhVert, kBlock); }
+void launch_end_step(Batch &b) { IPC_LAUNCH(b, k_end_step, kPhVert, kBlock); }
+
+void launch_trial(Batch &b)
 {
-    int nt = (n + kScanTile - 1) / kScanTile;
-    if (nt == 0) nt = 1;
-    ensure_iscratch(s, (size_t)nt + 1);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, s.stream, n, in, s.i_scratch);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s.stream, nt, s.i_scratch, total_dev);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, s.stream, n, in, s.i_scratch, out);
+    if (mixed(b))
+        IPC_LAUNCH(b, k_trial<float>, kPhVert, kBlock, (const double *)b.d_alpha);
+    else
+        IPC_LAUNCH(b, k_trial<double>, kPhVert, kBlock, (const double *)b.d_alpha);
 }
 
-// ---- launchers --------------------------------------------------------------
+void launch_accept(Batch &b) { IPC_LAUNCH(b, k_accept, kPhVert, kBlock); }
 
-void launch_begin_step(Scene &s, const Pose &pose)
+static void one_per_active(Batch &b, PhaseKind prod)
 {
-    hipLaunchKernelGGL(k_begin_step, dim3(nblocks(s.n)), dim3(kBlock), 0, s.stream, s.n, s.n_gel, s.x, s.v, s.fixed,
-                       s.Yloc, pose, s.prm.dt, s.prm.grav[0], s.prm.grav[1], s.prm.grav[2], s.xt, s.xtilde, s.yhat);
+    std::vector<int32_t> one(b.sc.size());
+    for (size_t i = 0; i < b.sc.size(); ++i) one[i] = b.h_off[prod][i + 1] > b.h_off[prod][i] ? 1 : 0;
+    b.set_phase(kPhOne, one);
 }
 
-void launch_end_step(Scene &s)
+void run_lag_and_mean(Batch &b)
 {
-    hipLaunchKernelGGL(k_end_step, dim3(nblocks(3 * s.n)), dim3(kBlock), 0, s.stream, 3 * s.n, s.x, s.xt,
-                       1.0 / s.prm.dt, s.v);
-}
-
-void launch_trial(Scene &s, const double *x, const double *p, double alpha, double *out)
-{
-    hipLaunchKernelGGL(k_trial, dim3(nblocks(3 * s.n)), dim3(kBlock), 0, s.stream, 3 * s.n, x, p, alpha, out);
-}
-
-void launch_hess_apply(Scene &s, const double *v, double *y)
-{
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(s.n)), dim3(kBlock), 0, s.stream, s.n, s.slice_ptr, s.bcol, s.bval,
-                       s.c_ptr, s.c_list, s.act_v, s.act_H, s.act_cap, v, y);
+    IPC_LAUNCH(b, k_lag_mean, kPhVert, kBlock);
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_final_lag_mean, kPhOne, kBlock, b.launch(kPhVert));
 }
 
 void launch_gather_surface(Scene &s, double *dst, hipStream_t strm)
 {
     int ns = (int)s.h_surf_verts.size();
-    hipLaunchKernelGGL(k_gather_surface, dim3(nblocks(ns)), dim3(kBlock), 0, strm, ns, s.surf_verts, s.x, dst);
+    hipLaunchKernelGGL(k_gather_surface, dim3(nblocks(ns)), dim3(kBlock), 0, strm, ns, s.h.surf_verts, s.h.x, dst);
 }
 
-double *run_gel_mean(Scene &s, hipStream_t strm)
+void run_pinf(Batch &b)
 {
-    int nb = nblocks(s.n_gel);
-    hipLaunchKernelGGL(k_mean_part, dim3(nb), dim3(kBlock), 0, strm, s.n_gel, s.x, s.mean_part);
-    double *out = s.mean_part + 3 * (size_t)nb;
-    hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kBlock), 0, strm, nb, s.n_gel, s.mean_part, out);
-    return out;
+    if (mixed(b))
+        IPC_LAUNCH(b, k_pinf<float>, kPhVert, kBlock);
+    else
+        IPC_LAUNCH(b, k_pinf<double>, kPhVert, kBlock);
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_final_pinf, kPhOne, kBlock, b.launch(kPhVert));
 }
 
-double run_pinf(Scene &s)
+void launch_hess_apply(Batch &b)
 {
-    int nb = nblocks(s.n);
-    hipLaunchKernelGGL(k_pinf, dim3(nb), dim3(kBlock), 0, s.stream, s.n, s.sol, s.fixed, s.red_scratch);
-    hipLaunchKernelGGL(k_final_max, dim3(1), dim3(kBlock), 0, s.stream, nb, s.red_scratch, s.red_scratch + nb);
-    IPC_HIP(hipMemcpyAsync(&s.hb->value, s.red_scratch + nb, sizeof(double), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    return s.hb->value;
+    if (mixed(b))
+        IPC_LAUNCH(b, k_spmv<float>, kPhSlice, kBlock);
+    else
+        IPC_LAUNCH(b, k_spmv<double>, kPhSlice, kBlock);
 }
 
-double run_target_lag(Scene &s)
+// PCG for every scene with blocks in the kPhVert / kPhSlice maps.
+void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
 {
-    if (s.n_ind == 0) return 0.0;
-    int nb = nblocks(s.n_ind);
-    hipLaunchKernelGGL(k_target_lag, dim3(nb), dim3(kBlock), 0, s.stream, s.n, s.n_gel, s.x, s.yhat, s.red_scratch);
-    hipLaunchKernelGGL(k_final_max, dim3(1), dim3(kBlock), 0, s.stream, nb, s.red_scratch, s.red_scratch + nb);
-    IPC_HIP(hipMemcpyAsync(&s.hb->value, s.red_scratch + nb, sizeof(double), hipMemcpyDeviceToHost, s.stream));
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    return s.hb->value;
-}
-
-int run_pcg(Scene &s, int *hit_cap)
-{
-    int n = s.n, nbB = nblocks(n), nbA = s.n_slices;
-    PcgState *st = reinterpret_cast<PcgState *>(s.pcg_state);
-    double *part_dq = s.pcg_part, *part_rz = s.pcg_part + nbA;
-    double tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
-    int maxit = s.prm.pcg_max_iter > 0 ? s.prm.pcg_max_iter : 30 * n;
-    hipLaunchKernelGGL(k_pcg_init, dim3(nbB), dim3(kBlock), 0, s.stream, n, s.grad, s.Minv, s.r, s.z, s.sol, part_rz,
-                       st);
-    double *dbuf[2] = {s.dA, s.dB};
+    size_t ns = b.sc.size();
+    bool mx = mixed(b);
+    if (mx)
+        IPC_LAUNCH(b, k_pcg_init<float>, kPhVert, kBlock);
+    else
+        IPC_LAUNCH(b, k_pcg_init<double>, kPhVert, kBlock);
+    int maxit = 0, last = 0;
+    for (size_t i = 0; i < ns; ++i) {
+        if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
+        const Scene &s = *b.sc[i];
+        maxit = std::max(maxit, s.h.pcg_maxit);
+        last = std::max(last, s.last_pcg_iters);
+    }
+    iters.assign(ns, 0);
+    hit_cap.assign(ns, 0);
     int it = 1;
-    // first chunk: most of the previous solve's count, then short chunks, so
-    // few launches run after convergence
-    int chunk = s.last_pcg_iters > 16 ? (s.last_pcg_iters * 7) / 8 : 8;
-    *hit_cap = 0;
+    int chunk = last > 16 ? (last * 7) / 8 : 8;
     hipEvent_t ev[2];
-    while (it <= maxit) {
-        int c = chunk < maxit - it + 1 ? chunk : maxit - it + 1;
+    // launch it = maxit + 1 too: its A kernel records the cap of the scenes
+    // that did not converge
+    while (it <= maxit + 1) {
+        int c = std::min(chunk, maxit + 2 - it);
         for (int j = 0; j < c; ++j, ++it) {
-            bool timed = (it & 3) == 1;  // time one launch in four when profiling
-            if (timed) prof_begin(s, kProfPcgA, ev);
-            hipLaunchKernelGGL(k_pcg_A, dim3(nbA), dim3(kBlock), 0, s.stream, it, n, nbB, tol2, s.slice_ptr, s.bcol,
-                               s.bval, s.c_ptr, s.c_list, s.act_v, s.act_H, s.act_cap, s.z, dbuf[(it + 1) & 1],
-                               dbuf[it & 1], s.q, part_dq, part_rz, st);
-            if (timed) prof_end(s, kProfPcgA, ev);
-            if (timed) prof_begin(s, kProfPcgB, ev);
-            hipLaunchKernelGGL(k_pcg_B, dim3(nbB), dim3(kBlock), 0, s.stream, it, n, nbA, nbB, s.q, dbuf[it & 1],
-                               s.Minv, s.sol, s.r, s.z, part_dq, part_rz, st);
-            if (timed) prof_end(s, kProfPcgB, ev);
+            bool timed = b.prof() && (it & 3) == 1;  // time one launch in four when profiling
+            if (timed) b.prof_begin(kProfPcgA, ev);
+            if (mx)
+                IPC_LAUNCH(b, k_pcg_A<float>, kPhSlice, kBlock, it);
+            else
+                IPC_LAUNCH(b, k_pcg_A<double>, kPhSlice, kBlock, it);
+            if (timed) b.prof_end(kProfPcgA, ev);
+            if (timed) b.prof_begin(kProfPcgB, ev);
+            if (mx)
+                IPC_LAUNCH(b, k_pcg_B<float>, kPhVert, kBlock, it);
+            else
+                IPC_LAUNCH(b, k_pcg_B<double>, kPhVert, kBlock, it);
+            if (timed) b.prof_end(kProfPcgB, ev);
         }
-        IPC_HIP(hipMemcpyAsync(&s.hb->flag, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipMemcpyAsync(&s.hb->iters, &st->iters, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        IPC_HIP(hipStreamSynchronize(s.stream));
-        prof_collect(s);
-        if (s.hb->flag) {
-            s.last_pcg_iters = s.hb->iters;
-            return s.hb->iters;
-        }
+        b.read_out();
+        b.prof_collect();
+        bool all = true;
+        for (size_t i = 0; i < ns; ++i)
+            if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && !b.h_out[i].pcg_done) all = false;
+        if (all) break;
         chunk = 8;
     }
-    *hit_cap = 1;
-    s.last_pcg_iters = maxit;
-    return maxit;
+    for (size_t i = 0; i < ns; ++i) {
+        if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
+        iters[i] = b.h_out[i].pcg_done ? b.h_out[i].pcg_iters : b.sc[i]->h.pcg_maxit;
+        hit_cap[i] = b.h_out[i].pcg_done != 1;
+        b.sc[i]->last_pcg_iters = iters[i];
+    }
 }
 
 }  // namespace ipcg

@@ -1,4 +1,5 @@
-// scene.hip -- scene construction, the Newton step driver and the C ABI.
+// scene.hip -- scene construction, the Newton driver over a list of scenes,
+// the continuous-batching engine and the C ABI.
 //
 // One step (the GIPC step of the paper's "General GIPC Simulation Pipeline":
 // targets of the kinematic vertices are set, then the solver computes new
@@ -11,13 +12,24 @@
 //          swept candidates over [x, x + p], additive CCD bound alpha_ccd,
 //          halve alpha from min(1, alpha_ccd) until Phi(x + alpha p) <= Phi(x);
 //   commit: v = (x - x^t) / h.
+// A Newton *round* runs one iteration for every scene of a list that is still
+// iterating, one launch per phase for all of them; each scene keeps its own
+// iteration count, step length and stop decisions. ipc_step is a round loop
+// over a list of one scene. The batch engine keeps a list of scenes in flight
+// and admits newly submitted requests at every round boundary (continuous
+// batching): work of new scenes overlaps with scenes in mid-step.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 
 #include "ipc_internal.h"
@@ -50,8 +62,19 @@ void DeviceArena::release(void *p, size_t bytes)
     used -= (int64_t)bytes;
 }
 
+void *dalloc_bytes(Scene &s, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = s.arena.alloc(bytes);
+    if (!p) throw OomError{};
+    s.owned.push_back({p, bytes});
+    return p;
+}
+
 void dfree(Scene &s, void *p)
 {
+    if (!p) return;
     for (auto it = s.owned.begin(); it != s.owned.end(); ++it)
         if (it->first == p) {
             s.arena.release(p, it->second);
@@ -60,54 +83,14 @@ void dfree(Scene &s, void *p)
         }
 }
 
-void prof_begin(Scene &s, int kernel, hipEvent_t *pair)
-{
-    if (!s.prof) return;
-    for (int k = 0; k < 2; ++k) {
-        if (s.ev_pool.empty()) {
-            hipEvent_t e;
-            IPC_HIP(hipEventCreate(&e));
-            s.ev_pool.push_back(e);
-        }
-        pair[k] = s.ev_pool.back();
-        s.ev_pool.pop_back();
-    }
-    IPC_HIP(hipEventRecord(pair[0], s.stream));
-}
-
-void prof_end(Scene &s, int kernel, hipEvent_t *pair)
-{
-    if (!s.prof) return;
-    IPC_HIP(hipEventRecord(pair[1], s.stream));
-    s.ev_pending.push_back({kernel, {pair[0], pair[1]}});
-}
-
-void prof_collect(Scene &s)
-{
-    if (s.ev_pending.empty()) return;
-    for (auto &p : s.ev_pending) {
-        float ms = 0.f;
-        IPC_HIP(hipEventSynchronize(p.second.second));
-        IPC_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
-        s.prof_acc[p.first].launches++;
-        s.prof_acc[p.first].ms += ms;
-        s.ev_pool.push_back(p.second.first);
-        s.ev_pool.push_back(p.second.second);
-    }
-    s.ev_pending.clear();
-}
+void mark_dirty(Scene &s) { s.dev_dirty = true; }
 
 Scene::~Scene()
 {
     if (stream) (void)hipStreamSynchronize(stream);
-    for (auto &p : ev_pending) {
-        ev_pool.push_back(p.second.first);
-        ev_pool.push_back(p.second.second);
-    }
-    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    (void)hipDeviceSynchronize();
     for (auto &o : owned) arena.release(o.first, o.second);
     owned.clear();
-    if (hb) (void)hipHostFree(hb);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,26 +140,154 @@ static T *upload(Scene &s, const std::vector<T> &h)
     return d;
 }
 
-static int ceil_log2(int64_t v)
+static size_t real_size(const Scene &s) { return s.prm.precision == IPC_MIXED ? sizeof(float) : sizeof(double); }
+
+// Allocations that replace existing buffers: all new buffers are obtained
+// first, the old ones are released only once every allocation succeeded, so
+// a refused allocation leaves the scene as it was.
+struct Staged {
+    Scene &s;
+    std::vector<void *> got;
+    explicit Staged(Scene &sc) : s(sc) {}
+    ~Staged()
+    {
+        for (void *p : got) dfree(s, p);
+    }
+    template <class T>
+    T *get(size_t count)
+    {
+        T *p = dalloc<T>(s, count);
+        got.push_back(p);
+        return p;
+    }
+    void *get_bytes(size_t bytes)
+    {
+        void *p = dalloc_bytes(s, bytes);
+        got.push_back(p);
+        return p;
+    }
+    void commit() { got.clear(); }
+};
+
+// reduction / scan scratch sized for hash tables of 2^b0 and 2^b1 buckets and
+// candidate lists of cc entries (only ever grows)
+static void ensure_scratch(Scene &s, int b0, int b1, int64_t cc)
 {
-    int b = 0;
-    while ((int64_t(1) << b) < v) ++b;
-    return b;
+    SceneDev &H = s.h;
+    int64_t red = std::max({2 * ((int64_t)nblocks((int64_t)H.m + H.n) + nblocks(cc)) + 16,
+                            (int64_t)nblocks(H.n_edges) + nblocks(H.n_tris) + 16, 4 * (int64_t)nblocks(H.n) + 16,
+                            (int64_t)nblocks(cc) + 16});
+    auto tiles = [](int64_t len) { return (len + kScanTile) / kScanTile + 1; };
+    int64_t sc = std::max({tiles((int64_t(1) << b0) + 1), tiles((int64_t(1) << b1) + 1),
+                           tiles((int64_t)H.n_pts + H.n_edges), tiles(H.n + 1), tiles(cc + 1)}) + 16;
+    bool gr = !H.red || H.red_len < red, gs = !H.scan_tmp || H.scan_len < sc;
+    Staged st(s);
+    double *nr = gr ? st.get<double>(red) : nullptr;
+    int32_t *nsc = gs ? st.get<int32_t>(sc) : nullptr;
+    st.commit();
+    if (gr) {
+        dfree(s, H.red);
+        H.red = nr;
+        H.red_len = red;
+    }
+    if (gs) {
+        dfree(s, H.scan_tmp);
+        H.scan_tmp = nsc;
+        H.scan_len = sc;
+    }
+    if (gr || gs) s.dev_dirty = true;
 }
 
-static int64_t partial_need(const Scene &s, int64_t nc)
+void grow_table(Scene &s, int t, int64_t entries)
 {
-    return 2 * ((int64_t)nblocks((int64_t)s.m + s.n) + nblocks(nc) + 16);
+    SceneDev &H = s.h;
+    int bits = 10;
+    while ((int64_t(1) << bits) < 2 * entries && bits < 28) ++bits;
+    size_t tsize = size_t(1) << bits;
+    Staged st(s);
+    int32_t *cnt = st.get<int32_t>(tsize + 1), *start = st.get<int32_t>(tsize + 1);
+    int4 *ent = st.get<int4>((size_t)entries);
+    ensure_scratch(s, t == 0 ? bits : H.ht_bits[0], t == 1 ? bits : H.ht_bits[1], std::max(H.cand_cap, H.sw_cap));
+    st.commit();
+    dfree(s, H.ht_count[t]);
+    dfree(s, H.ht_start[t]);
+    dfree(s, H.ht_entries[t]);
+    H.ht_bits[t] = bits;
+    H.ht_count[t] = cnt;
+    H.ht_start[t] = start;
+    H.ht_entries[t] = ent;
+    H.ht_cap[t] = (int32_t)std::min<int64_t>(entries, INT32_MAX);
+    s.dev_dirty = true;
 }
+
+void grow_candidates(Scene &s, int which, int64_t need)
+{
+    SceneDev &H = s.h;
+    int32_t *&buf = which ? H.cand_sw : H.cand;
+    int64_t &cap = which ? H.sw_cap : H.cand_cap;
+    if (buf && need <= cap) return;
+    int64_t nc = need + need / 2 + 1024;
+    // q_off doubles as the output of the active-flag scan
+    int64_t q = std::max<int64_t>((int64_t)H.n_pts + H.n_edges, std::max(which ? H.cand_cap : nc, which ? nc : H.sw_cap)) + 1;
+    Staged st(s);
+    int32_t *nb = st.get<int32_t>(3 * (size_t)nc);
+    double *nd = which ? nullptr : st.get<double>(nc);
+    int32_t *nf = which ? nullptr : st.get<int32_t>(nc + 1);
+    int32_t *nqc = st.get<int32_t>(q), *nqo = st.get<int32_t>(q);
+    ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max({H.cand_cap, H.sw_cap, nc}));
+    st.commit();
+    dfree(s, buf);
+    buf = nb;
+    cap = nc;
+    if (!which) {
+        dfree(s, H.cand_d);
+        dfree(s, H.act_flag);
+        H.cand_d = nd;
+        H.act_flag = nf;
+    }
+    dfree(s, H.q_count);
+    dfree(s, H.q_off);
+    H.q_count = nqc;
+    H.q_off = nqo;
+    s.dev_dirty = true;
+}
+
+void grow_active(Scene &s, int64_t need)
+{
+    SceneDev &H = s.h;
+    if (H.act_idx && need <= H.act_cap) return;
+    int64_t nc = need + need / 2 + 256;
+    size_t rs = real_size(s);
+    Staged st(s);
+    int32_t *ni = st.get<int32_t>(nc), *nv = st.get<int32_t>(4 * (size_t)nc);
+    void *ng = st.get_bytes(12 * (size_t)nc * rs), *nh = st.get_bytes(144 * (size_t)nc * rs);
+    int32_t *nl = st.get<int32_t>(4 * (size_t)nc);
+    st.commit();
+    dfree(s, H.act_idx);
+    dfree(s, H.act_v);
+    dfree(s, H.act_g);
+    dfree(s, H.act_H);
+    dfree(s, H.c_list);
+    H.act_idx = ni;
+    H.act_v = nv;
+    H.act_g = ng;
+    H.act_H = nh;
+    H.c_list = nl;
+    H.act_cap = nc;
+    s.dev_dirty = true;
+}
+
+static void activate(Batch &b, const std::vector<uint8_t> &on);
 
 static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
 {
+    int n_gel_tris = 0, n_gel_edges = 0;
     const int ng = d.n_verts, m = d.n_tets, ni = d.n_ind_verts;
-    s.n_gel = ng;
-    s.n_ind = ni;
-    s.n = ng + ni;
-    s.m = m;
-    const int n = s.n;
+    s.h.n_gel = ng;
+    s.h.n_ind = ni;
+    s.h.n = ng + ni;
+    s.h.m = m;
+    const int n = s.h.n;
     // ---- validation
     for (int64_t k = 0; k < 4 * (int64_t)m; ++k)
         if (d.T[k] < 0 || d.T[k] >= ng) {
@@ -236,12 +347,12 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
         itris.push_back({d.ind_tris[3 * k] + ng, d.ind_tris[3 * k + 1] + ng, d.ind_tris[3 * k + 2] + ng});
     canonical_tris(itris);
     auto gedges = unique_edges(gtris), iedges = unique_edges(itris);
-    s.n_gel_tris = (int)gtris.size();
-    s.n_tris = (int)(gtris.size() + itris.size());
-    s.n_gel_edges = (int)gedges.size();
-    s.n_edges = (int)(gedges.size() + iedges.size());
-    s.h_tris.resize(3 * (size_t)s.n_tris);
-    s.h_edges.resize(2 * (size_t)s.n_edges);
+    n_gel_tris = (int)gtris.size();
+    s.h.n_tris = (int)(gtris.size() + itris.size());
+    n_gel_edges = (int)gedges.size();
+    s.h.n_edges = (int)(gedges.size() + iedges.size());
+    s.h_tris.resize(3 * (size_t)s.h.n_tris);
+    s.h_edges.resize(2 * (size_t)s.h.n_edges);
     {
         size_t k = 0;
         for (auto &t : gtris) { s.h_tris[3 * k] = t[0]; s.h_tris[3 * k + 1] = t[1]; s.h_tris[3 * k + 2] = t[2]; ++k; }
@@ -259,7 +370,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
             s.h_pts.push_back(i);
             if (i < ng) s.h_surf_verts.push_back(i);
         }
-    s.n_pts = (int)s.h_pts.size();
+    s.h.n_pts = (int)s.h_pts.size();
 
     // ---- vertex -> tet incidence (tet order)
     std::vector<int32_t> vt_ptr(n + 1, 0), vt_src(4 * (size_t)m);
@@ -280,9 +391,9 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
         std::sort(l.begin(), l.end());
         l.erase(std::unique(l.begin(), l.end()), l.end());
     }
-    s.n_slices = (n + kSlice - 1) / kSlice;
-    std::vector<int32_t> slice_ptr(s.n_slices + 1, 0);
-    for (int sl = 0; sl < s.n_slices; ++sl) {
+    s.h.n_slices = (n + kSlice - 1) / kSlice;
+    std::vector<int32_t> slice_ptr(s.h.n_slices + 1, 0);
+    for (int sl = 0; sl < s.h.n_slices; ++sl) {
         int w = 1;
         for (int l = 0; l < kSlice; ++l) {
             int row = sl * kSlice + l;
@@ -290,10 +401,10 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
         }
         slice_ptr[sl + 1] = slice_ptr[sl] + w;
     }
-    s.n_slots = slice_ptr[s.n_slices];
+    s.h.n_slots = slice_ptr[s.h.n_slices];
     s.nnzb = 0;
     for (int row = 0; row < n; ++row) s.nnzb += 1 + (int64_t)nbr[row].size();
-    size_t nent = (size_t)s.n_slots * kSlice;
+    size_t nent = (size_t)s.h.n_slots * kSlice;
     std::vector<int32_t> bcol(nent, -1);
     for (int row = 0; row < n; ++row) {
         int sl = row / kSlice, l = row % kSlice;
@@ -327,15 +438,15 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     std::vector<int32_t> tv(4 * (size_t)m);
     for (int e = 0; e < m; ++e)
         for (int a = 0; a < 4; ++a) tv[(size_t)a * m + e] = d.T[4 * e + a];
-    std::vector<int32_t> ev(2 * (size_t)s.n_edges), trv(3 * (size_t)s.n_tris);
-    for (int k = 0; k < s.n_edges; ++k) {
+    std::vector<int32_t> ev(2 * (size_t)s.h.n_edges), trv(3 * (size_t)s.h.n_tris);
+    for (int k = 0; k < s.h.n_edges; ++k) {
         ev[k] = s.h_edges[2 * k];
-        ev[(size_t)s.n_edges + k] = s.h_edges[2 * k + 1];
+        ev[(size_t)s.h.n_edges + k] = s.h_edges[2 * k + 1];
     }
-    for (int k = 0; k < s.n_tris; ++k)
-        for (int c = 0; c < 3; ++c) trv[(size_t)c * s.n_tris + k] = s.h_tris[3 * k + c];
-    std::vector<double> ers(s.n_edges);
-    for (int k = 0; k < s.n_edges; ++k) {
+    for (int k = 0; k < s.h.n_tris; ++k)
+        for (int c = 0; c < 3; ++c) trv[(size_t)c * s.h.n_tris + k] = s.h_tris[3 * k + c];
+    std::vector<double> ers(s.h.n_edges);
+    for (int k = 0; k < s.h.n_edges; ++k) {
         const double *a = &X0[3 * (size_t)s.h_edges[2 * k]], *b = &X0[3 * (size_t)s.h_edges[2 * k + 1]];
         double dd[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
         ers[k] = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
@@ -344,93 +455,280 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     if (d.fixed)
         for (int i = 0; i < ng; ++i) fixed[i] = d.fixed[i] ? 1 : 0;
     s.h_Yloc.assign(d.ind_Y, d.ind_Y + 3 * (size_t)ni);
-    std::memcpy(s.pose0.m, d.ind_pose0, sizeof(double) * 12);
+    std::memcpy(s.pose0, d.ind_pose0, sizeof(double) * 12);
 
-    // ---- device buffers
+    // ---- device buffers and the device view
+    SceneDev &H = s.h;
+    size_t rs = real_size(s);
     size_t n3 = 3 * (size_t)n;
-    s.X0 = upload(s, X0);
-    s.x = dalloc<double>(s, n3);
-    IPC_HIP(hipMemcpyAsync(s.x, s.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
-    s.v = dalloc<double>(s, n3);
-    IPC_HIP(hipMemsetAsync(s.v, 0, sizeof(double) * n3, s.stream));
-    s.xt = dalloc<double>(s, n3);
-    s.xtilde = dalloc<double>(s, n3);
-    s.yhat = dalloc<double>(s, n3);
-    s.xtrial = dalloc<double>(s, n3);
-    IPC_HIP(hipMemcpyAsync(s.xt, s.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
-    IPC_HIP(hipMemcpyAsync(s.xtilde, s.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
-    IPC_HIP(hipMemcpyAsync(s.yhat, s.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
-    s.Yloc = upload(s, s.h_Yloc);
-    s.fixed = upload(s, fixed);
-    s.mass = dalloc<double>(s, n);
-    s.tv = upload(s, tv);
-    s.Bm = dalloc<double>(s, 9 * (size_t)m);
-    s.vol = dalloc<double>(s, m);
-    s.eg = dalloc<double>(s, 12 * (size_t)m);
-    s.eH = dalloc<double>(s, 90 * (size_t)m);
-    s.vt_ptr = upload(s, vt_ptr);
-    s.vt_src = upload(s, vt_src);
-    s.slice_ptr = upload(s, slice_ptr);
-    s.bcol = upload(s, bcol);
-    s.bval = dalloc<double>(s, nent * 9);
-    s.g_ptr = upload(s, g_ptr);
-    s.g_src = upload(s, g_src);
-    s.grad = dalloc<double>(s, n3);
-    s.Minv = dalloc<double>(s, 9 * (size_t)n);
-    s.pts = upload(s, s.h_pts);
-    s.ev = upload(s, ev);
-    s.trv = upload(s, trv);
-    s.edge_rest_sq = upload(s, ers);
-    s.pbox = dalloc<double>(s, 6 * (size_t)std::max(s.n_pts, 1));
-    s.ebox = dalloc<double>(s, 6 * (size_t)std::max(s.n_edges, 1));
-    s.tbox = dalloc<double>(s, 6 * (size_t)std::max(s.n_tris, 1));
-    s.cell_h = dalloc<double>(s, 1);
-    int64_t red = 4 * (int64_t)nblocks(std::max({(int64_t)n, (int64_t)s.n_pts, (int64_t)s.n_edges, (int64_t)s.n_tris})) + 64;
-    s.red_scratch = dalloc<double>(s, red);
-    s.c_ptr = dalloc<int32_t>(s, n + 1);
-    s.c_cnt = dalloc<int32_t>(s, n + 1);
-    IPC_HIP(hipMemsetAsync(s.c_ptr, 0, sizeof(int32_t) * (n + 1), s.stream));
-    s.r = dalloc<double>(s, n3);
-    s.z = dalloc<double>(s, n3);
-    s.dA = dalloc<double>(s, n3);
-    s.dB = dalloc<double>(s, n3);
-    s.q = dalloc<double>(s, n3);
-    s.sol = dalloc<double>(s, n3);
-    s.pcg_part = dalloc<double>(s, (size_t)s.n_slices + 2 * (size_t)nblocks(n) + 8);
-    s.pcg_state = dalloc<int32_t>(s, 16);
-    IPC_HIP(hipMemsetAsync(s.pcg_state, 0, sizeof(int32_t) * 16, s.stream));
-    s.surf_verts = upload(s, s.h_surf_verts);
-    s.xw = dalloc<double>(s, n3);
-    s.pw = dalloc<double>(s, n3);
-    s.yw = dalloc<double>(s, n3);
-    s.mean_part = dalloc<double>(s, 3 * (size_t)nblocks(n) + 8);
-    // candidates and active pairs start small and grow
-    s.cand_cap = 0;
-    s.sw_cap = 0;
-    s.act_cap = 0;
-    IPC_HIP(hipHostMalloc((void **)&s.hb, sizeof(Readback), 0));
-    std::memset(s.hb, 0, sizeof(Readback));
-    launch_rest_precompute(s);
+    H.n_surf = (int)s.h_surf_verts.size();
+    H.nb_vert = nblocks(n);
+    H.mu = s.prm.mu;
+    H.lam = s.prm.lam;
+    H.h = s.prm.dt;
+    H.inv_h2 = 1.0 / (s.prm.dt * s.prm.dt);
+    H.dhat = s.prm.dhat;
+    H.kappa = s.prm.kappa;
+    H.k_target = s.prm.k_target;
+    H.rho = s.prm.rho;
+    for (int c = 0; c < 3; ++c) H.grav[c] = s.prm.grav[c];
+    H.ccd_s = s.prm.ccd_s;
+    H.pcg_tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
+    H.self_contact = s.prm.self_contact;
+    H.ccd_max_iter = s.prm.ccd_max_iter;
+    H.precision = s.prm.precision;
+    std::memcpy(H.pose, d.ind_pose0, sizeof(double) * 12);
+    H.X0 = upload(s, X0);
+    H.x = dalloc<double>(s, n3);
+    H.v = dalloc<double>(s, n3);
+    H.xt = dalloc<double>(s, n3);
+    H.xtilde = dalloc<double>(s, n3);
+    H.yhat = dalloc<double>(s, n3);
+    H.xtrial = dalloc<double>(s, n3);
+    for (double *p : {H.x, H.xt, H.xtilde, H.yhat, H.xtrial})
+        IPC_HIP(hipMemcpyAsync(p, H.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
+    IPC_HIP(hipMemsetAsync(H.v, 0, sizeof(double) * n3, s.stream));
+    H.Yloc = upload(s, s.h_Yloc);
+    H.fixed = upload(s, fixed);
+    H.mass = dalloc<double>(s, n);
+    H.tv = upload(s, tv);
+    H.Bm = dalloc<double>(s, 9 * (size_t)m);
+    H.vol = dalloc<double>(s, m);
+    H.eg = dalloc_bytes(s, 12 * (size_t)m * rs);
+    H.eH = dalloc_bytes(s, 90 * (size_t)m * rs);
+    H.vt_ptr = upload(s, vt_ptr);
+    H.vt_src = upload(s, vt_src);
+    H.slice_ptr = upload(s, slice_ptr);
+    H.bcol = upload(s, bcol);
+    H.bval = dalloc_bytes(s, nent * 9 * rs);
+    H.g_ptr = upload(s, g_ptr);
+    H.g_src = upload(s, g_src);
+    H.grad = dalloc_bytes(s, n3 * rs);
+    H.Minv = dalloc_bytes(s, 9 * (size_t)n * rs);
+    H.pts = upload(s, s.h_pts);
+    H.ev = upload(s, ev);
+    H.trv = upload(s, trv);
+    H.surf_verts = upload(s, s.h_surf_verts);
+    H.edge_rest_sq = upload(s, ers);
+    H.pbox = dalloc<double>(s, 6 * (size_t)std::max(H.n_pts, 1));
+    H.ebox = dalloc<double>(s, 6 * (size_t)std::max(H.n_edges, 1));
+    H.tbox = dalloc<double>(s, 6 * (size_t)std::max(H.n_tris, 1));
+    H.cell_h = dalloc<double>(s, 1);
+    H.c_ptr = dalloc<int32_t>(s, n + 1);
+    H.c_cnt = dalloc<int32_t>(s, n + 1);
+    IPC_HIP(hipMemsetAsync(H.c_ptr, 0, sizeof(int32_t) * (n + 1), s.stream));
+    for (void **p : {&H.r, &H.z, &H.dA, &H.dB, &H.q, &H.sol}) *p = dalloc_bytes(s, n3 * rs);
+    IPC_HIP(hipMemsetAsync(H.sol, 0, n3 * rs, s.stream));
+    H.pcg_part = dalloc<double>(s, (size_t)H.n_slices + 2 * (size_t)H.nb_vert + 8);
+    H.pcg = dalloc<PcgState>(s, 1);
+    IPC_HIP(hipMemsetAsync(H.pcg, 0, sizeof(PcgState), s.stream));
+    grow_table(s, 0, 16 * (int64_t)std::max(H.n_tris, 1));
+    grow_table(s, 1, 16 * (int64_t)std::max(H.n_edges, 1));
+    grow_candidates(s, 0, 1024);
+    grow_candidates(s, 1, 1024);
+    grow_active(s, 256);
+    H.pcg_maxit = s.prm.pcg_max_iter > 0 ? s.prm.pcg_max_iter : 30 * n;
+    s.n_gel_tris = n_gel_tris;
+    s.xsave = dalloc<double>(s, n3);
+    s.ysurf = dalloc<double>(s, 3 * (size_t)std::max(H.n_surf, 1));
+    s.dev = dalloc<SceneDev>(s, 1);
+    s.dev_dirty = true;
+    // rest shape and lumped mass on the device, through the scene's list of one
+    s.solo.reset(new Batch());
+    Batch &b = *s.solo;
+    b.bind({&s}, s.stream);
+    activate(b, {1});
+    launch_rest_precompute(b);
     IPC_HIP(hipStreamSynchronize(s.stream));
-    IPC_HIP(hipGetLastError());
+    (void)n_gel_edges;
     return IPC_OK;
 }
 
-void ensure_cand_aux(Scene &s)
+// ---------------------------------------------------------------------------
+// a list of scenes stepping together
+// ---------------------------------------------------------------------------
+
+Batch::~Batch()
 {
-    if (s.aux_cap < s.cand_cap) {
-        if (s.cand_d) dfree(s, s.cand_d);
-        if (s.act_flag) dfree(s, s.act_flag);
-        s.cand_d = dalloc<double>(s, s.cand_cap);
-        s.act_flag = dalloc<int32_t>(s, s.cand_cap + 1);
-        s.aux_cap = s.cand_cap;
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &p : ev_pending) {
+        ev_pool.push_back(p.second.first);
+        ev_pool.push_back(p.second.second);
     }
-    int64_t need = partial_need(s, std::max(s.sw_cap, s.cand_cap));
-    if (s.part_cap < need) {
-        if (s.accd_t) dfree(s, s.accd_t);
-        s.accd_t = dalloc<double>(s, need);
-        s.part_cap = need;
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    (void)hipFree(d_list);
+    for (auto &d : d_off) (void)hipFree(d);
+    (void)hipFree(d_out);
+    (void)hipFree(d_alpha);
+    if (h_out) (void)hipHostFree(h_out);
+    if (h_stage) (void)hipHostFree(h_stage);
+}
+
+void *Batch::stage(const void *src, size_t bytes)
+{
+    size_t need = (bytes + 63) & ~size_t(63);
+    if (!h_stage) {
+        stage_cap = std::max<size_t>(size_t(1) << 20, need);
+        IPC_HIP(hipHostMalloc((void **)&h_stage, stage_cap, 0));
+        stage_used = 0;
     }
+    if (stage_used + need > stage_cap) {
+        IPC_HIP(hipStreamSynchronize(stream));
+        stage_used = 0;
+        if (need > stage_cap) {
+            IPC_HIP(hipHostFree(h_stage));
+            h_stage = nullptr;
+            stage_cap = need;
+            IPC_HIP(hipHostMalloc((void **)&h_stage, stage_cap, 0));
+        }
+    }
+    void *p = h_stage + stage_used;
+    std::memcpy(p, src, bytes);
+    stage_used += need;
+    return p;
+}
+
+void Batch::bind(const std::vector<Scene *> &scenes, hipStream_t strm)
+{
+    bool same = scenes == sc && strm == stream && d_list;
+    int ns = (int)scenes.size();
+    fail.assign(ns, 0);
+    h_alpha.assign(ns, 0.0);
+    if (same) {
+        upload_views();
+        return;
+    }
+    stream = strm;
+    sc = scenes;
+    if (ns > cap) {
+        int nc = std::max(ns, std::max(4, 2 * cap));
+        IPC_HIP(hipStreamSynchronize(stream));
+        (void)hipFree(d_list);
+        for (auto &d : d_off) (void)hipFree(d);
+        (void)hipFree(d_out);
+        (void)hipFree(d_alpha);
+        if (h_out) (void)hipHostFree(h_out);
+        d_list = nullptr;
+        d_out = nullptr;
+        d_alpha = nullptr;
+        h_out = nullptr;
+        for (auto &d : d_off) d = nullptr;
+        cap = 0;
+        IPC_HIP(hipMalloc(&d_list, sizeof(SceneDev *) * nc));
+        for (auto &d : d_off) IPC_HIP(hipMalloc(&d, sizeof(int32_t) * (nc + 1)));
+        IPC_HIP(hipMalloc(&d_out, sizeof(SceneOut) * nc));
+        IPC_HIP(hipMalloc(&d_alpha, sizeof(double) * nc));
+        IPC_HIP(hipHostMalloc((void **)&h_out, sizeof(SceneOut) * nc, 0));
+        std::memset(h_out, 0, sizeof(SceneOut) * nc);
+        IPC_HIP(hipMemsetAsync(d_out, 0, sizeof(SceneOut) * nc, stream));
+        cap = nc;
+    }
+    std::vector<SceneDev *> ptrs(ns);
+    for (int i = 0; i < ns; ++i) ptrs[i] = sc[i]->dev;
+    if (ns)
+        IPC_HIP(hipMemcpyAsync(d_list, stage(ptrs.data(), sizeof(SceneDev *) * ns), sizeof(SceneDev *) * ns,
+                               hipMemcpyHostToDevice, stream));
+    for (auto &h : h_off) h.clear();
+    upload_views();
+}
+
+void Batch::set_phase(PhaseKind k, const std::vector<int32_t> &per_scene_blocks)
+{
+    std::vector<int32_t> off(per_scene_blocks.size() + 1, 0);
+    for (size_t i = 0; i < per_scene_blocks.size(); ++i) off[i + 1] = off[i] + per_scene_blocks[i];
+    if (off == h_off[k]) return;
+    h_off[k].swap(off);
+    size_t bytes = sizeof(int32_t) * h_off[k].size();
+    IPC_HIP(hipMemcpyAsync(d_off[k], stage(h_off[k].data(), bytes), bytes, hipMemcpyHostToDevice, stream));
+}
+
+void Batch::upload_views()
+{
+    for (Scene *s : sc)
+        if (s->dev_dirty) {
+            IPC_HIP(hipMemcpyAsync(s->dev, stage(&s->h, sizeof(SceneDev)), sizeof(SceneDev), hipMemcpyHostToDevice,
+                                   stream));
+            s->dev_dirty = false;
+        }
+}
+
+void Batch::read_out()
+{
+    if (sc.empty()) return;
+    IPC_HIP(hipMemcpyAsync(h_out, d_out, sizeof(SceneOut) * sc.size(), hipMemcpyDeviceToHost, stream));
+    IPC_HIP(hipStreamSynchronize(stream));
+    stage_used = 0;
+    for (size_t i = 0; i < sc.size(); ++i) sc[i]->last = h_out[i];
+}
+
+bool Batch::prof() const { return sc.size() == 1 && sc[0]->prof; }
+
+void Batch::prof_begin(int kernel, hipEvent_t *pair)
+{
+    (void)kernel;
+    if (!prof()) return;
+    for (int k = 0; k < 2; ++k) {
+        if (ev_pool.empty()) {
+            hipEvent_t e;
+            IPC_HIP(hipEventCreate(&e));
+            ev_pool.push_back(e);
+        }
+        pair[k] = ev_pool.back();
+        ev_pool.pop_back();
+    }
+    IPC_HIP(hipEventRecord(pair[0], stream));
+}
+
+void Batch::prof_end(int kernel, hipEvent_t *pair)
+{
+    if (!prof()) return;
+    IPC_HIP(hipEventRecord(pair[1], stream));
+    ev_pending.push_back({kernel, {pair[0], pair[1]}});
+}
+
+void Batch::prof_collect()
+{
+    if (ev_pending.empty()) return;
+    for (auto &p : ev_pending) {
+        float ms = 0.f;
+        IPC_HIP(hipEventSynchronize(p.second.second));
+        IPC_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        if (!sc.empty()) {
+            sc[0]->prof_acc[p.first].launches++;
+            sc[0]->prof_acc[p.first].ms += ms;
+        }
+        ev_pool.push_back(p.second.first);
+        ev_pool.push_back(p.second.second);
+    }
+    ev_pending.clear();
+}
+
+// phase maps of the per-item kernels for the scenes with on[i] set; the
+// others get no blocks and sit the phases out
+static void activate(Batch &b, const std::vector<uint8_t> &on)
+{
+    size_t ns = b.sc.size();
+    std::vector<int32_t> v(ns), t(ns), e(ns), sl(ns), p(ns), ed(ns), tr(ns), bd(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const SceneDev &H = b.sc[i]->h;
+        bool a = on[i] != 0;
+        v[i] = a ? nblocks(H.n) : 0;
+        t[i] = a ? nblocks(H.m) : 0;
+        e[i] = a ? nblocks((int64_t)H.n_slots * kSlice) : 0;
+        sl[i] = a ? H.n_slices : 0;
+        p[i] = a ? nblocks(H.n_pts) : 0;
+        ed[i] = a ? nblocks(H.n_edges) : 0;
+        tr[i] = a ? nblocks(H.n_tris) : 0;
+        bd[i] = a ? nblocks((int64_t)H.m + H.n) : 0;
+    }
+    b.set_phase(kPhVert, v);
+    b.set_phase(kPhTet, t);
+    b.set_phase(kPhEntry, e);
+    b.set_phase(kPhSlice, sl);
+    b.set_phase(kPhPts, p);
+    b.set_phase(kPhEdges, ed);
+    b.set_phase(kPhTris, tr);
+    b.set_phase(kPhBody, bd);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,138 +741,458 @@ static double ms_since(Clock::time_point t0)
     return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-struct IterOut {
-    int result = 0;  // 0 stepped, 1 converged, 2 stall
-    int pcg_iters = 0;
-    int pcg_cap = 0;
-    int halvings = 0;
-    double alpha_ccd = 1.0, alpha = 0.0, energy = NAN, pinf = 0.0;
+// Per-scene control of one step inside a list.
+struct StepCtl {
+    bool active = false;   // still iterating
+    bool failed = false;   // an error ended the step (status < 0)
+    bool stepped = false;  // the last iteration moved x (else it only measured p)
+    int k = 0;             // Newton iterations done
+    int status = IPC_OK;
+    bool pcg_warn = false;
+    ipc_step_stats st{};
+    double alpha = 0.0, alpha0 = 0.0, E0 = 0.0;
 };
 
-// Assemble g and H at x (device pointer): static candidates, active pairs,
-// barrier, incidence, elastic elements, gather.
-static void assemble_at(Scene &s, const double *x, double *ms)
+// scenes that a host phase marked failed leave the list's phases
+static void drop_failed(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on)
+{
+    bool any = false;
+    for (size_t i = 0; i < b.sc.size(); ++i) {
+        if (!b.fail[i] || ctl[i].failed) continue;
+        ctl[i].failed = true;
+        ctl[i].active = false;
+        ctl[i].status = b.fail[i];
+        if (on[i]) {
+            on[i] = 0;
+            any = true;
+        }
+    }
+    if (any) activate(b, on);
+}
+
+// g and H at x for the scenes with on[i]: static candidates, active pairs,
+// barrier, incidence, elastic elements, deterministic gather
+static void assemble_round(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on, double *ms)
 {
     auto t0 = Clock::now();
-    hipEvent_t ev[2];
-    prof_begin(s, kProfBroad, ev);
-    s.n_cand = run_broad_phase(s, x, nullptr, &s.cand, &s.cand_cap);
-    prof_end(s, kProfBroad, ev);
-    ensure_cand_aux(s);
-    prof_begin(s, kProfBarrier, ev);
-    run_narrow_phase(s, x);
-    launch_barrier(s, x);
-    launch_contact_incidence(s);
-    prof_end(s, kProfBarrier, ev);
-    if (ms) ms[1] += ms_since(t0);
+    activate(b, on);
+    run_broad_phase(b, 0);
+    drop_failed(b, ctl, on);
+    run_narrow_phase(b);
+    drop_failed(b, ctl, on);
+    launch_barrier(b);
+    launch_contact_incidence(b);
+    IPC_HIP(hipStreamSynchronize(b.stream));
+    ms[1] += ms_since(t0);
     t0 = Clock::now();
-    prof_begin(s, kProfElastic, ev);
-    launch_elastic_elements(s, x);
-    prof_end(s, kProfElastic, ev);
-    prof_begin(s, kProfAssemble, ev);
-    launch_assemble(s, x);
-    prof_end(s, kProfAssemble, ev);
-    if (ms) {
-        IPC_HIP(hipStreamSynchronize(s.stream));
-        ms[0] += ms_since(t0);
+    launch_elastic_elements(b);
+    launch_assemble(b);
+    IPC_HIP(hipStreamSynchronize(b.stream));
+    ms[0] += ms_since(t0);
+}
+
+// One Newton iteration for every scene with ctl[i].active.
+static void newton_round(Batch &b, std::vector<StepCtl> &ctl)
+{
+    size_t ns = b.sc.size();
+    std::vector<uint8_t> on(ns);
+    for (size_t i = 0; i < ns; ++i) on[i] = ctl[i].active;
+    double ms[8] = {0};
+    assemble_round(b, ctl, on, ms);
+    auto t0 = Clock::now();
+    std::vector<int> iters, caps;
+    run_pcg(b, iters, caps);
+    run_pinf(b);
+    b.read_out();
+    ms[2] += ms_since(t0);
+    std::vector<uint8_t> ls(ns, 0);
+    bool any = false;
+    for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;
+        StepCtl &c = ctl[i];
+        c.st.newton_iters++;
+        c.k++;
+        c.st.pcg_iters += iters[i];
+        c.pcg_warn |= caps[i] != 0;
+        c.st.pinf = b.h_out[i].pinf;
+        c.st.n_candidates = b.h_out[i].n_cand;
+        c.st.n_active = b.h_out[i].n_act;
+        c.stepped = false;
+        if (b.h_out[i].pinf <= b.sc[i]->prm.newton_tol) {
+            c.active = false;  // converged: this iteration only measured p
+        } else {
+            ls[i] = 1;
+            any = true;
+        }
+    }
+    if (any) {
+        t0 = Clock::now();
+        activate(b, ls);
+        run_broad_phase(b, 1);
+        drop_failed(b, ctl, ls);
+        run_ccd(b);
+        run_energy(b, false);
+        b.read_out();
+        ms[3] += ms_since(t0);
+        t0 = Clock::now();
+        for (size_t i = 0; i < ns; ++i)
+            if (ls[i]) {
+                StepCtl &c = ctl[i];
+                c.st.alpha_ccd = b.h_out[i].alpha_ccd;
+                c.alpha = std::min(1.0, b.h_out[i].alpha_ccd);
+                c.alpha0 = c.alpha;
+                c.E0 = b.h_out[i].infeasible ? INFINITY : b.h_out[i].energy;
+            }
+        // Backtracking: every scene halves its own step until its energy does
+        // not increase. The trial count is bounded (a step of 2^-1100 is 0).
+        std::vector<uint8_t> pend = ls;
+        for (int trial = 0; trial < 1100; ++trial) {
+            bool left = false;
+            for (size_t i = 0; i < ns; ++i) {
+                b.h_alpha[i] = pend[i] ? ctl[i].alpha : 0.0;
+                left |= pend[i] != 0;
+            }
+            if (!left) break;
+            IPC_HIP(hipMemcpyAsync(b.d_alpha, b.stage(b.h_alpha.data(), sizeof(double) * ns), sizeof(double) * ns,
+                                   hipMemcpyHostToDevice, b.stream));
+            activate(b, pend);
+            launch_trial(b);
+            run_energy(b, true);
+            b.read_out();
+            std::vector<uint8_t> acc(ns, 0);
+            for (size_t i = 0; i < ns; ++i) {
+                if (!pend[i]) continue;
+                StepCtl &c = ctl[i];
+                double E = b.h_out[i].infeasible ? INFINITY : b.h_out[i].energy;
+                if (E <= c.E0) {
+                    acc[i] = 1;
+                    pend[i] = 0;
+                    c.stepped = true;
+                    c.st.alpha = c.alpha;
+                    c.st.energy = E;
+                } else {
+                    c.alpha *= 0.5;
+                    c.st.ls_halvings++;
+                    if (c.alpha < b.sc[i]->prm.ls_min_ratio * c.alpha0 || !(c.alpha > 0.0)) {
+                        pend[i] = 0;
+                        c.status = IPC_W_LS_STALL;
+                        c.active = false;
+                        c.st.alpha = 0.0;
+                        c.st.energy = c.E0;
+                    }
+                }
+            }
+            activate(b, acc);
+            launch_accept(b);
+        }
+        for (size_t i = 0; i < ns; ++i)
+            if (pend[i]) {  // the bound above was reached
+                ctl[i].status = IPC_W_LS_STALL;
+                ctl[i].active = false;
+                ctl[i].st.alpha = 0.0;
+                ctl[i].st.energy = ctl[i].E0;
+            }
+        ms[4] += ms_since(t0);
+    }
+    for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;
+        for (int k = 0; k < 8; ++k) ctl[i].st.ms_phase[k] += ms[k];
+        if (ctl[i].active && ctl[i].k >= b.sc[i]->prm.max_newton) {
+            ctl[i].active = false;
+            ctl[i].status = IPC_W_NEWTON_MAXITER;
+        }
     }
 }
 
-static IterOut newton_iterate(Scene &s, double *x, double *ms)
+static void set_pose(Scene &s, const double *pose)
 {
-    IterOut o;
-    assemble_at(s, x, ms);
-    auto t0 = Clock::now();
-    o.pcg_iters = run_pcg(s, &o.pcg_cap);
-    o.pinf = run_pinf(s);
-    if (ms) ms[2] += ms_since(t0);
-    if (o.pinf <= s.prm.newton_tol) {
-        o.result = 1;
-        return o;
+    std::memcpy(s.h.pose, pose, sizeof(double) * 12);
+    s.dev_dirty = true;
+}
+
+// predictor and targets of the scenes with on[i] (poses already set)
+static void begin_steps(Batch &b, const std::vector<uint8_t> &on)
+{
+    b.upload_views();
+    activate(b, on);
+    launch_begin_step(b);
+}
+
+// Commit of the scenes with on[i]: v = (x - x^t)/h, target lag, object
+// position, final status. A failed step restores x = x^t (its state is then
+// as before the step).
+static void end_steps(Batch &b, const std::vector<uint8_t> &on, std::vector<StepCtl> &ctl)
+{
+    size_t ns = b.sc.size();
+    std::vector<uint8_t> ok(ns, 0);
+    for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;
+        if (ctl[i].failed) {
+            Scene &s = *b.sc[i];
+            IPC_HIP(hipMemcpyAsync(s.h.x, s.h.xt, sizeof(double) * 3 * s.h.n, hipMemcpyDeviceToDevice, b.stream));
+        } else {
+            ok[i] = 1;
+        }
     }
-    t0 = Clock::now();
-    hipEvent_t ev[2];
-    prof_begin(s, kProfBroad, ev);
-    s.n_cand_sw = run_broad_phase(s, x, s.sol, &s.cand_sw, &s.sw_cap);
-    prof_end(s, kProfBroad, ev);
-    ensure_cand_aux(s);
-    prof_begin(s, kProfCcd, ev);
-    o.alpha_ccd = run_ccd(s, x, s.sol);
-    prof_end(s, kProfCcd, ev);
-    if (ms) ms[3] += ms_since(t0);
-    t0 = Clock::now();
-    double alpha = std::min(1.0, o.alpha_ccd), alpha0 = alpha;
-    int inf = 0;
-    prof_begin(s, kProfEnergy, ev);
-    double E0 = run_energy(s, x, s.cand_sw, s.n_cand_sw, &inf);
-    prof_end(s, kProfEnergy, ev);
+    activate(b, ok);
+    launch_end_step(b);
+    run_lag_and_mean(b);
+    b.read_out();
+    b.prof_collect();
+    for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;
+        StepCtl &c = ctl[i];
+        if (!ok[i]) {
+            c.st.status = c.status;
+            continue;
+        }
+        Scene &s = *b.sc[i];
+        c.st.max_target_lag = b.h_out[i].lag;
+        int status = c.status;
+        if (status == IPC_OK && c.pcg_warn) status = IPC_W_PCG_MAXITER;
+        if (status == IPC_OK && c.st.max_target_lag > 1e-3 * s.prm.dhat) status = IPC_W_TARGET_LAG;
+        c.st.status = status;
+        s.step_index++;
+    }
+}
+
+static void start_ctl(StepCtl &c)
+{
+    c = StepCtl{};
+    c.active = true;
+    c.st.energy = NAN;
+}
+
+// Steps every scene of the list to completion in shared launches.
+static void step_list(Batch &b, const std::vector<const double *> &poses, std::vector<StepCtl> &ctl)
+{
+    size_t ns = b.sc.size();
+    auto t0 = Clock::now();
+    for (size_t i = 0; i < ns; ++i) set_pose(*b.sc[i], poses[i]);
+    ctl.assign(ns, StepCtl{});
+    for (auto &c : ctl) start_ctl(c);
+    std::vector<uint8_t> all(ns, 1);
+    begin_steps(b, all);
     for (;;) {
-        launch_trial(s, x, s.sol, alpha, s.xtrial);
-        prof_begin(s, kProfEnergy, ev);
-        double E = run_energy(s, s.xtrial, s.cand_sw, s.n_cand_sw, &inf);
-        prof_end(s, kProfEnergy, ev);
-        if (E <= E0) {
-            IPC_HIP(hipMemcpyAsync(x, s.xtrial, sizeof(double) * 3 * s.n, hipMemcpyDeviceToDevice, s.stream));
-            o.energy = E;
-            o.alpha = alpha;
-            break;
-        }
-        alpha *= 0.5;
-        o.halvings++;
-        if (alpha < s.prm.ls_min_ratio * alpha0) {
-            o.result = 2;
-            o.energy = E0;
-            o.alpha = 0.0;
-            break;
-        }
+        bool any = false;
+        for (auto &c : ctl) any |= c.active;
+        if (!any) break;
+        newton_round(b, ctl);
     }
-    if (ms) ms[4] += ms_since(t0);
-    return o;
+    end_steps(b, all, ctl);
+    double ms = ms_since(t0);
+    for (auto &c : ctl) c.st.ms_total = ms;
 }
 
-static int32_t step_scene(Scene &s, const ipc_step_req &req, ipc_step_stats *st)
-{
-    auto t_start = Clock::now();
-    ipc_step_stats local;
-    if (!st) st = &local;
-    std::memset(st, 0, sizeof(*st));
-    st->energy = NAN;
-    Pose P;
-    std::memcpy(P.m, req.pose, sizeof(P.m));
-    launch_begin_step(s, P);
-    int status = IPC_OK;
-    int k;
-    bool pcg_warn = false;
-    for (k = 0; k < s.prm.max_newton; ++k) {
-        IterOut o = newton_iterate(s, s.x, st->ms_phase);
-        st->newton_iters++;
-        st->pcg_iters += o.pcg_iters;
-        st->ls_halvings += o.halvings;
-        st->pinf = o.pinf;
-        pcg_warn |= o.pcg_cap != 0;
-        if (o.result == 1) break;
-        st->alpha_ccd = o.alpha_ccd;
-        st->alpha = o.alpha;
-        st->energy = o.energy;
-        if (o.result == 2) {
-            status = IPC_W_LS_STALL;
-            break;
+// ---------------------------------------------------------------------------
+// continuous batching
+// ---------------------------------------------------------------------------
+
+struct Request {
+    Scene *s;
+    ipc_step_req r;
+    ipc_ticket t;
+};
+
+struct Finished {
+    ipc_step_stats st;
+    int32_t status;
+};
+
+// A worker thread keeps one list of in-flight steps per precision and runs
+// Newton rounds over them; requests submitted meanwhile join the list at the
+// next round boundary, finished steps leave it. Admission: the summed device
+// bytes of the scenes in flight stay within mem_budget (if set); a list is
+// never left empty while requests wait.
+class Engine {
+  public:
+    ipc_runtime rt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::unordered_map<ipc_ticket, Finished> done;
+    std::unordered_map<ipc_ticket, int> pending;  // submitted, not yet finished
+    ipc_ticket next = 1;
+    bool stop = false;
+    std::string fatal;  // a device error ends the engine
+    std::thread worker;
+
+    struct Slot {
+        Scene *s;
+        ipc_ticket t;
+        double pose[12];
+        bool fresh;  // admitted this round: begin_step still to run
+        Clock::time_point t0;
+    };
+    struct List {
+        Batch b;
+        std::vector<Slot> slots;
+        std::vector<StepCtl> ctl;
+        bool changed = true;
+    } lists[2];
+
+    ~Engine()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        if (worker.joinable()) worker.join();
+        for (auto &l : lists) {
+            if (stream) (void)hipStreamSynchronize(stream);
+            l.b.stream = nullptr;
+        }
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    int64_t in_flight_bytes() const
+    {
+        int64_t v = 0;
+        for (auto &l : lists)
+            for (auto &sl : l.slots) v += sl.s->arena.used;
+        return v;
+    }
+
+    // move waiting requests into the lists (caller holds mu)
+    void admit()
+    {
+        int64_t bytes = in_flight_bytes();
+        while (!queue.empty()) {
+            Request &q = queue.front();
+            bool empty = lists[0].slots.empty() && lists[1].slots.empty();
+            if (rt.mem_budget > 0 && !empty && bytes + q.s->arena.used > rt.mem_budget) break;
+            List &l = lists[q.s->prm.precision == IPC_MIXED ? 1 : 0];
+            Slot sl{q.s, q.t, {}, true, Clock::now()};
+            std::memcpy(sl.pose, q.r.pose, sizeof(sl.pose));
+            l.slots.push_back(sl);
+            l.ctl.emplace_back();
+            l.changed = true;
+            bytes += q.s->arena.used;
+            queue.pop_front();
         }
     }
-    if (k == s.prm.max_newton) status = IPC_W_NEWTON_MAXITER;
-    if (status == IPC_OK && pcg_warn) status = IPC_W_PCG_MAXITER;
-    st->n_candidates = (int32_t)s.n_cand;
-    st->n_active = (int32_t)s.n_act;
-    launch_end_step(s);
-    st->max_target_lag = run_target_lag(s);
-    if (status == IPC_OK && st->max_target_lag > 1e-3 * s.prm.dhat) status = IPC_W_TARGET_LAG;
-    IPC_HIP(hipStreamSynchronize(s.stream));
-    prof_collect(s);
-    st->status = status;
-    st->ms_total = ms_since(t_start);
-    s.step_index++;
-    return status;
-}
+
+    void finish(List &l, const std::vector<uint8_t> &fin)
+    {
+        std::vector<Slot> keep;
+        std::vector<StepCtl> keepc;
+        std::lock_guard<std::mutex> g(mu);
+        for (size_t i = 0; i < l.slots.size(); ++i) {
+            if (!fin[i]) {
+                keep.push_back(l.slots[i]);
+                keepc.push_back(l.ctl[i]);
+                continue;
+            }
+            Finished f{l.ctl[i].st, l.ctl[i].st.status};
+            f.st.ms_total = ms_since(l.slots[i].t0);
+            done[l.slots[i].t] = f;
+            pending.erase(l.slots[i].t);
+            l.slots[i].s->busy = false;
+            l.changed = true;
+        }
+        l.slots.swap(keep);
+        l.ctl.swap(keepc);
+        cv_done.notify_all();
+    }
+
+    void round(List &l)
+    {
+        size_t ns = l.slots.size();
+        if (!ns) return;
+        if (l.changed) {
+            std::vector<Scene *> sc(ns);
+            for (size_t i = 0; i < ns; ++i) sc[i] = l.slots[i].s;
+            l.b.bind(sc, stream);
+            l.changed = false;
+        } else {
+            l.b.fail.assign(ns, 0);
+        }
+        std::vector<uint8_t> fresh(ns, 0);
+        bool any_fresh = false;
+        for (size_t i = 0; i < ns; ++i)
+            if (l.slots[i].fresh) {
+                Scene &s = *l.slots[i].s;
+                IPC_HIP(hipStreamSynchronize(s.stream));  // earlier work of the scene's own stream
+                set_pose(s, l.slots[i].pose);
+                start_ctl(l.ctl[i]);
+                l.slots[i].fresh = false;
+                fresh[i] = 1;
+                any_fresh = true;
+            }
+        if (any_fresh) begin_steps(l.b, fresh);
+        newton_round(l.b, l.ctl);
+        std::vector<uint8_t> fin(ns, 0);
+        bool any = false;
+        for (size_t i = 0; i < ns; ++i)
+            if (!l.ctl[i].active) {
+                fin[i] = 1;
+                any = true;
+            }
+        if (any) {
+            end_steps(l.b, fin, l.ctl);
+            finish(l, fin);
+        }
+    }
+
+    void fail_all(const std::string &msg)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        fatal = msg;
+        for (auto &l : lists) {
+            for (auto &sl : l.slots) {
+                Finished f{};
+                f.status = IPC_E_DEVICE;
+                f.st.status = IPC_E_DEVICE;
+                done[sl.t] = f;
+                pending.erase(sl.t);
+                sl.s->busy = false;
+            }
+            l.slots.clear();
+            l.ctl.clear();
+            l.changed = true;
+        }
+        for (auto &q : queue) {
+            Finished f{};
+            f.status = IPC_E_DEVICE;
+            f.st.status = IPC_E_DEVICE;
+            done[q.t] = f;
+            pending.erase(q.t);
+            q.s->busy = false;
+        }
+        queue.clear();
+        cv_done.notify_all();
+    }
+
+    void run()
+    {
+        if (hipSetDevice(device) != hipSuccess) {
+            fail_all("engine could not select its device");
+            return;
+        }
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    return stop || !queue.empty() || !lists[0].slots.empty() || !lists[1].slots.empty();
+                });
+                if (stop && queue.empty() && lists[0].slots.empty() && lists[1].slots.empty()) return;
+                admit();
+            }
+            try {
+                for (auto &l : lists) round(l);
+            } catch (const HipError &e) {
+                fail_all(std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+            } catch (...) {
+                fail_all("unexpected error in the batch engine");
+            }
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // C ABI helpers
@@ -606,14 +1224,27 @@ static int32_t guarded(F &&f)
     }
 }
 
+static void set_status_error(int32_t st)
+{
+    switch (st) {
+    case IPC_E_INFEASIBLE: set_error("non-finite or absurd positions in the contact broad phase"); break;
+    case IPC_E_OOM: set_error("device allocation refused (allocator or memory budget)"); break;
+    case IPC_E_CAPACITY: set_error("contact hash table capacity could not be reached"); break;
+    default: break;
+    }
+}
+
 static bool check_desc(const ipc_scene_desc *d)
 {
     if (!d || d->n_verts <= 0 || d->n_tets <= 0 || !d->X || !d->T) return false;
     if (d->n_ind_verts < 0 || d->n_ind_tris < 0) return false;
     if (d->n_ind_verts > 0 && (!d->ind_Y || (d->n_ind_tris > 0 && !d->ind_tris))) return false;
+    if (d->n_ind_verts == 0 && d->n_ind_tris > 0) return false;
     if (!(d->dt > 0) || !(d->dhat > 0) || !(d->kappa > 0) || !(d->E > 0) || !(d->rho > 0)) return false;
     if (!(d->nu > -1.0 && d->nu < 0.5)) return false;
+    if (!(d->newton_tol >= 0) || !(d->pcg_tol >= 0) || !(d->k_target >= 0)) return false;
     if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) return false;
+    if (d->pcg_max_iter < 0 || d->max_newton < 0 || d->ccd_max_iter < 0) return false;
     return true;
 }
 
@@ -644,6 +1275,57 @@ static Params make_params(const ipc_scene_desc &d)
     return p;
 }
 
+// the scene's list of one, bound to its stream
+static Batch &solo(Scene &s)
+{
+    s.solo->bind({&s}, s.stream);
+    return *s.solo;
+}
+
+static size_t rsize(const Scene &s) { return s.prm.precision == IPC_MIXED ? sizeof(float) : sizeof(double); }
+
+// host FP64 vector -> device array of the scene's real type
+static void upload_real(Scene &s, void *dst, const double *src, size_t count)
+{
+    if (s.prm.precision == IPC_MIXED) {
+        std::vector<float> f(src, src + count);
+        IPC_HIP(hipMemcpyAsync(dst, f.data(), sizeof(float) * count, hipMemcpyHostToDevice, s.stream));
+        IPC_HIP(hipStreamSynchronize(s.stream));
+    } else {
+        IPC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyHostToDevice, s.stream));
+    }
+}
+
+static void download_real(Scene &s, double *dst, const void *src, size_t count)
+{
+    if (s.prm.precision == IPC_MIXED) {
+        std::vector<float> f(count);
+        IPC_HIP(hipMemcpyAsync(f.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipStreamSynchronize(s.stream));
+        for (size_t i = 0; i < count; ++i) dst[i] = f[i];
+    } else {
+        IPC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, s.stream));
+        IPC_HIP(hipStreamSynchronize(s.stream));
+    }
+}
+
+// Test hooks evaluate at a given x without changing the scene's state: x is
+// kept in xsave and restored afterwards.
+struct HookState {
+    Scene &s;
+    explicit HookState(Scene &sc, const double *x) : s(sc)
+    {
+        size_t b = sizeof(double) * 3 * s.h.n;
+        IPC_HIP(hipMemcpyAsync(s.xsave, s.h.x, b, hipMemcpyDeviceToDevice, s.stream));
+        if (x) IPC_HIP(hipMemcpyAsync(s.h.x, x, b, hipMemcpyHostToDevice, s.stream));
+    }
+    ~HookState()
+    {
+        (void)hipMemcpyAsync(s.h.x, s.xsave, sizeof(double) * 3 * s.h.n, hipMemcpyDeviceToDevice, s.stream);
+        (void)hipStreamSynchronize(s.stream);
+    }
+};
+
 }  // namespace ipcg
 
 using namespace ipcg;
@@ -651,15 +1333,7 @@ using namespace ipcg;
 struct ipc_scene : public ipcg::Scene {
 };
 
-struct BatchItem {
-    ipc_step_stats st;
-    int32_t status;
-};
-struct ipc_batch {
-    ipc_runtime rt{};
-    std::mutex mu;
-    std::unordered_map<ipc_ticket, BatchItem> done;
-    ipc_ticket next = 1;
+struct ipc_batch : public ipcg::Engine {
 };
 
 extern "C" {
@@ -678,8 +1352,7 @@ int32_t ipc_create_scene(const ipc_scene_desc *d, const ipc_runtime *rt, ipc_sce
         if (rt) s->arena.rt = *rt;
         s->stream = rt ? (hipStream_t)rt->stream : nullptr;
         s->prm = make_params(*d);
-        int32_t r = build_scene(*s, *d);
-        return r;
+        return build_scene(*s, *d);
     });
     if (st != IPC_OK) {
         delete s;
@@ -695,20 +1368,28 @@ int64_t ipc_scene_footprint_bytes(const ipc_scene_desc *d)
 {
     if (!check_desc(d)) return -1;
     int64_t n = (int64_t)d->n_verts + d->n_ind_verts, m = d->n_tets;
-    int64_t per_vertex = 8 * (3 * 14 + 9 + 1) + 4 * 4 + 1;
-    int64_t per_tet = 4 * 4 + 8 * (9 + 1 + 12 + 90) + 4 * 16 + 4 * 4;
-    int64_t bell = n * 16 * (72 + 4 + 4);
+    int64_t rs = d->precision == IPC_MIXED ? 4 : 8;
+    int64_t per_vertex = 8 * (3 * 8 + 1) + rs * (3 * 8 + 9) + 4 * 4 + 1;
+    int64_t per_tet = 4 * 4 + 8 * 10 + rs * (12 + 90) + 4 * 16 + 4 * 4;
+    int64_t bell = n * 16 * (9 * rs + 4 + 4);
     int64_t surf = 4 * (int64_t)std::pow((double)d->n_verts, 2.0 / 3.0) + d->n_ind_verts + 2 * d->n_ind_tris;
-    int64_t contact = surf * (6 * 8 * 3 + 64 * 4 * 3 + 8 * 16);
+    int64_t contact = surf * (6 * 8 * 3 + 64 * 4 * 3 + 8 * 16) + surf / 4 * (rs * 156 + 4 * 9);
     return n * per_vertex + m * per_tet + bell + contact + (8 << 20);
 }
 
 int32_t ipc_step(ipc_scene *s, const ipc_step_req *r, ipc_step_stats *st)
 {
     if (!s || !r) return IPC_E_INVALID_ARG;
-    if (s->busy) return IPC_E_BUSY;
-    s->busy = true;
-    int32_t rc = guarded([&]() -> int32_t { return step_scene(*s, *r, st); });
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
+        Batch &b = solo(*s);
+        std::vector<StepCtl> ctl;
+        step_list(b, {r->pose}, ctl);
+        if (st) *st = ctl[0].st;
+        if (ctl[0].st.status < 0) set_status_error(ctl[0].st.status);
+        return ctl[0].st.status;
+    });
     s->busy = false;
     return rc;
 }
@@ -724,56 +1405,62 @@ int32_t ipc_read_surface(const ipc_scene *cs, double *xyz, int64_t cap, int32_t 
         return IPC_E_INVALID_ARG;
     }
     if (where != IPC_HOST && where != IPC_DEVICE) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
         hipStream_t strm = stream ? (hipStream_t)stream : s->stream;
         IPC_HIP(hipStreamSynchronize(s->stream));
         if (xyz) {
-            double *dst = where == IPC_DEVICE ? xyz : s->yw;
+            double *dst = where == IPC_DEVICE ? xyz : s->ysurf;
             launch_gather_surface(*s, dst, strm);
             if (where == IPC_HOST)
-                IPC_HIP(hipMemcpyAsync(xyz, s->yw, sizeof(double) * need, hipMemcpyDeviceToHost, strm));
+                IPC_HIP(hipMemcpyAsync(xyz, s->ysurf, sizeof(double) * need, hipMemcpyDeviceToHost, strm));
+            IPC_HIP(hipStreamSynchronize(strm));
         }
         if (obj_pos) {
-            double *dm = run_gel_mean(*s, strm);
-            IPC_HIP(hipMemcpyAsync(obj_pos, dm, sizeof(double) * 3, hipMemcpyDeviceToHost, strm));
+            Batch &b = solo(*s);
+            activate(b, {1});
+            run_lag_and_mean(b);
+            b.read_out();
+            for (int c = 0; c < 3; ++c) obj_pos[c] = b.h_out[0].obj[c];
         }
-        IPC_HIP(hipStreamSynchronize(strm));
         return IPC_OK;
     });
+    s->busy = false;
+    return rc;
 }
 
 int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris, int32_t *verts,
                              int64_t vert_cap, int32_t *n_surf_verts)
 {
     if (!s) return IPC_E_INVALID_ARG;
+    if (tris && tri_cap < 3 * (int64_t)s->n_gel_tris) return IPC_E_INVALID_ARG;
+    if (verts && vert_cap < (int64_t)s->h_surf_verts.size()) return IPC_E_INVALID_ARG;
     if (n_tris) *n_tris = s->n_gel_tris;
     if (n_surf_verts) *n_surf_verts = (int32_t)s->h_surf_verts.size();
-    if (tris) {
-        if (tri_cap < 3 * (int64_t)s->n_gel_tris) return IPC_E_INVALID_ARG;
-        std::memcpy(tris, s->h_tris.data(), sizeof(int32_t) * 3 * s->n_gel_tris);
-    }
-    if (verts) {
-        if (vert_cap < (int64_t)s->h_surf_verts.size()) return IPC_E_INVALID_ARG;
-        std::memcpy(verts, s->h_surf_verts.data(), sizeof(int32_t) * s->h_surf_verts.size());
-    }
+    if (tris) std::memcpy(tris, s->h_tris.data(), sizeof(int32_t) * 3 * s->n_gel_tris);
+    if (verts) std::memcpy(verts, s->h_surf_verts.data(), sizeof(int32_t) * s->h_surf_verts.size());
     return IPC_OK;
 }
 
 int32_t ipc_reset(ipc_scene *s)
 {
     if (!s) return IPC_E_INVALID_ARG;
-    if (s->busy) return IPC_E_BUSY;
-    return guarded([&]() -> int32_t {
-        size_t b = sizeof(double) * 3 * s->n;
-        IPC_HIP(hipMemcpyAsync(s->x, s->X0, b, hipMemcpyDeviceToDevice, s->stream));
-        IPC_HIP(hipMemsetAsync(s->v, 0, b, s->stream));
-        IPC_HIP(hipMemcpyAsync(s->xt, s->X0, b, hipMemcpyDeviceToDevice, s->stream));
-        IPC_HIP(hipMemcpyAsync(s->xtilde, s->X0, b, hipMemcpyDeviceToDevice, s->stream));
-        IPC_HIP(hipMemcpyAsync(s->yhat, s->X0, b, hipMemcpyDeviceToDevice, s->stream));
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
+        const SceneDev &H = s->h;
+        size_t b = sizeof(double) * 3 * H.n;
+        for (double *p : {H.x, H.xt, H.xtilde, H.yhat})
+            IPC_HIP(hipMemcpyAsync(p, H.X0, b, hipMemcpyDeviceToDevice, s->stream));
+        IPC_HIP(hipMemsetAsync(H.v, 0, b, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
+        set_pose(*s, s->pose0);
         s->step_index = 0;
         return IPC_OK;
     });
+    s->busy = false;
+    return rc;
 }
 
 static const uint64_t kStateMagic = 0x31657461744370ULL;
@@ -781,23 +1468,27 @@ static const uint64_t kStateMagic = 0x31657461744370ULL;
 int64_t ipc_state_bytes(const ipc_scene *s)
 {
     if (!s) return -1;
-    return 32 + 2 * 3 * (int64_t)s->n * 8;
+    return 32 + 2 * 3 * (int64_t)s->h.n * 8;
 }
 
 int32_t ipc_save_state(const ipc_scene *cs, void *blob, int64_t cap)
 {
     if (!cs || !blob || cap < ipc_state_bytes(cs)) return IPC_E_INVALID_ARG;
     ipc_scene *s = const_cast<ipc_scene *>(cs);
-    return guarded([&]() -> int32_t {
-        uint64_t hdr[4] = {kStateMagic, (uint64_t)s->n, (uint64_t)s->step_index, 0};
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
+        uint64_t hdr[4] = {kStateMagic, (uint64_t)s->h.n, (uint64_t)s->step_index, 0};
         std::memcpy(blob, hdr, sizeof hdr);
         char *p = (char *)blob + 32;
-        size_t b = sizeof(double) * 3 * s->n;
-        IPC_HIP(hipMemcpyAsync(p, s->x, b, hipMemcpyDeviceToHost, s->stream));
-        IPC_HIP(hipMemcpyAsync(p + b, s->v, b, hipMemcpyDeviceToHost, s->stream));
+        size_t b = sizeof(double) * 3 * s->h.n;
+        IPC_HIP(hipMemcpyAsync(p, s->h.x, b, hipMemcpyDeviceToHost, s->stream));
+        IPC_HIP(hipMemcpyAsync(p + b, s->h.v, b, hipMemcpyDeviceToHost, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
         return IPC_OK;
     });
+    s->busy = false;
+    return rc;
 }
 
 int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes)
@@ -805,35 +1496,57 @@ int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes)
     if (!s || !blob || bytes < ipc_state_bytes(s)) return IPC_E_INVALID_ARG;
     uint64_t hdr[4];
     std::memcpy(hdr, blob, sizeof hdr);
-    if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)s->n) {
+    if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)s->h.n) {
         set_error("state blob does not match this scene");
         return IPC_E_INVALID_ARG;
     }
-    return guarded([&]() -> int32_t {
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
         const char *p = (const char *)blob + 32;
-        size_t b = sizeof(double) * 3 * s->n;
-        IPC_HIP(hipMemcpyAsync(s->x, p, b, hipMemcpyHostToDevice, s->stream));
-        IPC_HIP(hipMemcpyAsync(s->v, p + b, b, hipMemcpyHostToDevice, s->stream));
+        size_t b = sizeof(double) * 3 * s->h.n;
+        IPC_HIP(hipMemcpyAsync(s->h.x, p, b, hipMemcpyHostToDevice, s->stream));
+        IPC_HIP(hipMemcpyAsync(s->h.v, p + b, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
         s->step_index = (int)hdr[2];
         return IPC_OK;
     });
+    s->busy = false;
+    return rc;
 }
 
 int32_t ipc_scene_sizes(const ipc_scene *s, int32_t *o)
 {
     if (!s || !o) return IPC_E_INVALID_ARG;
-    o[0] = s->n; o[1] = s->n_gel; o[2] = s->m; o[3] = s->n_pts;
-    o[4] = s->n_edges; o[5] = s->n_tris; o[6] = s->n_ind; o[7] = s->n_gel_tris;
+    const SceneDev &H = s->h;
+    o[0] = H.n; o[1] = H.n_gel; o[2] = H.m; o[3] = H.n_pts;
+    o[4] = H.n_edges; o[5] = H.n_tris; o[6] = H.n_ind; o[7] = s->n_gel_tris;
     return IPC_OK;
 }
 
 int32_t ipc_batch_create(const ipc_runtime *rt, ipc_batch **out)
 {
     if (!out) return IPC_E_INVALID_ARG;
-    *out = new (std::nothrow) ipc_batch();
-    if (!*out) return IPC_E_OOM;
-    if (rt) (*out)->rt = *rt;
+    *out = nullptr;
+    ipc_batch *b = new (std::nothrow) ipc_batch();
+    if (!b) return IPC_E_OOM;
+    int32_t rc = guarded([&]() -> int32_t {
+        if (rt) b->rt = *rt;
+        IPC_HIP(hipGetDevice(&b->device));
+        if (rt && rt->stream) {
+            b->stream = (hipStream_t)rt->stream;
+        } else {
+            IPC_HIP(hipStreamCreate(&b->stream));
+            b->own_stream = true;
+        }
+        b->worker = std::thread([b] { b->run(); });
+        return IPC_OK;
+    });
+    if (rc != IPC_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
     return IPC_OK;
 }
 
@@ -844,18 +1557,31 @@ int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, const ipc
     if (!b || n < 0 || (n > 0 && (!s || !r || !t))) return IPC_E_INVALID_ARG;
     for (int i = 0; i < n; ++i) {
         if (!s[i]) return IPC_E_INVALID_ARG;
-        if (s[i]->busy) return IPC_E_BUSY;
         for (int j = 0; j < i; ++j)
             if (s[j] == s[i]) return IPC_E_BUSY;
     }
+    // claim every scene or none
     for (int i = 0; i < n; ++i) {
-        BatchItem it;
-        std::memset(&it, 0, sizeof it);
-        it.status = ipc_step(s[i], &r[i], &it.st);
-        std::lock_guard<std::mutex> g(b->mu);
-        t[i] = b->next++;
-        b->done[t[i]] = it;
+        bool expect = false;
+        if (!s[i]->busy.compare_exchange_strong(expect, true)) {
+            for (int j = 0; j < i; ++j) s[j]->busy = false;
+            return IPC_E_BUSY;
+        }
     }
+    {
+        std::lock_guard<std::mutex> g(b->mu);
+        if (!b->fatal.empty()) {
+            for (int i = 0; i < n; ++i) s[i]->busy = false;
+            set_error(b->fatal);
+            return IPC_E_DEVICE;
+        }
+        for (int i = 0; i < n; ++i) {
+            t[i] = b->next++;
+            b->queue.push_back(Request{s[i], r[i], t[i]});
+            b->pending[t[i]] = 1;
+        }
+    }
+    b->cv_work.notify_all();
     return IPC_OK;
 }
 
@@ -864,7 +1590,7 @@ int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st)
     if (!b) return IPC_E_INVALID_ARG;
     std::lock_guard<std::mutex> g(b->mu);
     auto it = b->done.find(t);
-    if (it == b->done.end()) return IPC_E_INVALID_ARG;
+    if (it == b->done.end()) return b->pending.count(t) ? 0 : IPC_E_INVALID_ARG;
     if (st) *st = it->second.st;
     return 1;
 }
@@ -872,7 +1598,8 @@ int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st)
 int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st)
 {
     if (!b) return IPC_E_INVALID_ARG;
-    std::lock_guard<std::mutex> g(b->mu);
+    std::unique_lock<std::mutex> lk(b->mu);
+    b->cv_done.wait(lk, [&] { return b->done.count(t) || !b->pending.count(t); });
     auto it = b->done.find(t);
     if (it == b->done.end()) return IPC_E_INVALID_ARG;
     if (st) *st = it->second.st;
@@ -913,80 +1640,86 @@ int32_t ipc_last_error(char *buf, size_t cap)
 
 // ---- test-only ---------------------------------------------------------------
 
-static void upload_vec(ipc_scene *s, double *dst, const double *src)
-{
-    IPC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * 3 * s->n, hipMemcpyHostToDevice, s->stream));
-}
-static void download_vec(ipc_scene *s, double *dst, const double *src)
-{
-    IPC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * 3 * s->n, hipMemcpyDeviceToHost, s->stream));
-    IPC_HIP(hipStreamSynchronize(s->stream));
-}
+#define IPC_HOOK_BEGIN(s)                                            \
+    bool _expect = false;                                            \
+    if (!(s)->busy.compare_exchange_strong(_expect, true)) return IPC_E_BUSY; \
+    int32_t _rc = guarded([&]() -> int32_t {
+#define IPC_HOOK_END(s) \
+    });                 \
+    (s)->busy = false;  \
+    return _rc;
 
 int32_t ipcx_begin_step(ipc_scene *s, const ipc_step_req *r)
 {
     if (!s || !r) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        Pose P;
-        std::memcpy(P.m, r->pose, sizeof(P.m));
-        launch_begin_step(*s, P);
+    IPC_HOOK_BEGIN(s)
+        Batch &b = solo(*s);
+        set_pose(*s, r->pose);
+        begin_steps(b, {1});
         IPC_HIP(hipStreamSynchronize(s->stream));
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
+// one Newton iteration from x_in; returns 0 stepped, 1 converged, 2 stalled
+// (or an error status)
 int32_t ipcx_newton_iterate(ipc_scene *s, const double *x_in, double *x_out, ipc_step_stats *st)
 {
     if (!s || !x_in || !x_out) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x_in);
-        IterOut o = newton_iterate(*s, s->xw, nullptr);
-        download_vec(s, x_out, s->xw);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x_in);
+        Batch &b = solo(*s);
+        std::vector<StepCtl> ctl(1);
+        start_ctl(ctl[0]);
+        newton_round(b, ctl);
+        StepCtl &c = ctl[0];
+        IPC_HIP(hipMemcpyAsync(x_out, s->h.x, sizeof(double) * 3 * s->h.n, hipMemcpyDeviceToHost, s->stream));
+        IPC_HIP(hipStreamSynchronize(s->stream));
+        int32_t res = c.failed ? c.status : (c.stepped ? 0 : (c.status == IPC_W_LS_STALL ? 2 : 1));
+        if (c.failed) set_status_error(c.status);
         if (st) {
-            std::memset(st, 0, sizeof(*st));
-            st->newton_iters = 1;
-            st->pcg_iters = o.pcg_iters;
-            st->ls_halvings = o.halvings;
-            st->n_candidates = (int32_t)s->n_cand;
-            st->n_active = (int32_t)s->n_act;
-            st->alpha_ccd = o.alpha_ccd;
-            st->alpha = o.alpha;
-            st->energy = o.energy;
-            st->pinf = o.pinf;
-            st->status = o.result;
+            *st = c.st;
+            st->status = res;
+            if (!c.stepped) {
+                st->alpha = 0.0;
+                if (res == 1) st->energy = NAN;
+            }
         }
-        return o.result;
-    });
+        return res;
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_candidates(ipc_scene *s, const double *x, const double *p, int32_t *out, int64_t cap, int64_t *count)
 {
     if (!s || !x) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        if (p) upload_vec(s, s->pw, p);
-        int32_t **buf = p ? &s->cand_sw : &s->cand;
-        int64_t *bcap = p ? &s->sw_cap : &s->cand_cap;
-        int64_t nc = run_broad_phase(*s, s->xw, p ? s->pw : nullptr, buf, bcap);
-        if (p)
-            s->n_cand_sw = nc;
-        else
-            s->n_cand = nc;
-        ensure_cand_aux(*s);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        if (p) upload_real(*s, s->h.sol, p, 3 * (size_t)s->h.n);
+        Batch &b = solo(*s);
+        activate(b, {1});
+        int which = p ? 1 : 0;
+        run_broad_phase(b, which);
+        if (b.fail[0]) {
+            set_status_error(b.fail[0]);
+            return b.fail[0];
+        }
+        IPC_HIP(hipStreamSynchronize(s->stream));
+        int64_t nc = which ? b.h_out[0].n_sw : b.h_out[0].n_cand;
+        const int32_t *buf = which ? s->h.cand_sw : s->h.cand;
+        int64_t bcap = which ? s->h.sw_cap : s->h.cand_cap;
         if (count) *count = nc;
         if (out && cap > 0) {
             int64_t w = std::min(cap, nc);
             std::vector<int32_t> h(3 * (size_t)std::max<int64_t>(w, 1));
             for (int c = 0; c < 3; ++c)
-                IPC_HIP(hipMemcpyAsync(h.data() + (size_t)c * w, *buf + (size_t)c * *bcap, sizeof(int32_t) * w,
+                IPC_HIP(hipMemcpyAsync(h.data() + (size_t)c * w, buf + (size_t)c * bcap, sizeof(int32_t) * w,
                                        hipMemcpyDeviceToHost, s->stream));
             IPC_HIP(hipStreamSynchronize(s->stream));
             for (int64_t i = 0; i < w; ++i)
                 for (int c = 0; c < 3; ++c) out[3 * i + c] = h[(size_t)c * w + i];
         }
-        IPC_HIP(hipStreamSynchronize(s->stream));
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_primitives(const ipc_scene *s, int32_t *points, int32_t *edges, int32_t *tris)
@@ -998,80 +1731,116 @@ int32_t ipcx_primitives(const ipc_scene *s, int32_t *points, int32_t *edges, int
     return IPC_OK;
 }
 
+// assemble at the hook's x; returns a failure status or IPC_OK
+static int32_t hook_assemble(Scene &s)
+{
+    Batch &b = solo(s);
+    std::vector<StepCtl> ctl(1);
+    start_ctl(ctl[0]);
+    std::vector<uint8_t> on(1, 1);
+    double ms[8] = {0};
+    assemble_round(b, ctl, on, ms);
+    if (ctl[0].failed) {
+        set_status_error(ctl[0].status);
+        return ctl[0].status;
+    }
+    return IPC_OK;
+}
+
 int32_t ipcx_gradient(ipc_scene *s, const double *x, double *g)
 {
     if (!s || !x || !g) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        assemble_at(*s, s->xw, nullptr);
-        download_vec(s, g, s->grad);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        int32_t r = hook_assemble(*s);
+        if (r != IPC_OK) return r;
+        download_real(*s, g, s->h.grad, 3 * (size_t)s->h.n);
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_hess_apply(ipc_scene *s, const double *x, const double *v, double *y)
 {
     if (!s || !x || !v || !y) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        assemble_at(*s, s->xw, nullptr);
-        upload_vec(s, s->pw, v);
-        launch_hess_apply(*s, s->pw, s->yw);
-        download_vec(s, y, s->yw);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        int32_t r = hook_assemble(*s);
+        if (r != IPC_OK) return r;
+        upload_real(*s, s->h.dB, v, 3 * (size_t)s->h.n);
+        Batch &b = solo(*s);
+        launch_hess_apply(b);
+        download_real(*s, y, s->h.q, 3 * (size_t)s->h.n);
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_pcg(ipc_scene *s, const double *x, double *p, int32_t *iters)
 {
     if (!s || !x || !p) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        assemble_at(*s, s->xw, nullptr);
-        int cap = 0;
-        int it = run_pcg(*s, &cap);
-        if (iters) *iters = cap ? -it : it;
-        download_vec(s, p, s->sol);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        int32_t r = hook_assemble(*s);
+        if (r != IPC_OK) return r;
+        Batch &b = solo(*s);
+        std::vector<int> it, capped;
+        run_pcg(b, it, capped);
+        if (iters) *iters = capped[0] ? -it[0] : it[0];
+        download_real(*s, p, s->h.sol, 3 * (size_t)s->h.n);
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_energy(ipc_scene *s, const double *x, double *E)
 {
     if (!s || !x || !E) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        s->n_cand = run_broad_phase(*s, s->xw, nullptr, &s->cand, &s->cand_cap);
-        ensure_cand_aux(*s);
-        int inf = 0;
-        *E = run_energy(*s, s->xw, s->cand, s->n_cand, &inf);
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        // the energy runs over the swept list; with p = 0 it is the static list at x
+        IPC_HIP(hipMemsetAsync(s->h.sol, 0, 3 * (size_t)s->h.n * rsize(*s), s->stream));
+        Batch &b = solo(*s);
+        activate(b, {1});
+        run_broad_phase(b, 1);
+        if (b.fail[0]) {
+            set_status_error(b.fail[0]);
+            return b.fail[0];
+        }
+        run_energy(b, false);
+        b.read_out();
+        *E = b.h_out[0].infeasible ? INFINITY : b.h_out[0].energy;
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double *alpha)
 {
     if (!s || !x || !p || !alpha) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        upload_vec(s, s->xw, x);
-        upload_vec(s, s->pw, p);
-        s->n_cand_sw = run_broad_phase(*s, s->xw, s->pw, &s->cand_sw, &s->sw_cap);
-        ensure_cand_aux(*s);
-        *alpha = std::min(1.0, run_ccd(*s, s->xw, s->pw));
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        upload_real(*s, s->h.sol, p, 3 * (size_t)s->h.n);
+        Batch &b = solo(*s);
+        activate(b, {1});
+        run_broad_phase(b, 1);
+        if (b.fail[0]) {
+            set_status_error(b.fail[0]);
+            return b.fail[0];
+        }
+        run_ccd(b);
+        b.read_out();
+        *alpha = std::min(1.0, b.h_out[0].alpha_ccd);
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_profile(ipc_scene *s, int32_t enable)
 {
     if (!s) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
+    IPC_HOOK_BEGIN(s)
         IPC_HIP(hipStreamSynchronize(s->stream));
-        prof_collect(*s);
+        s->solo->prof_collect();
         s->prof = enable != 0;
         for (auto &a : s->prof_acc) a = Scene::ProfAcc{};
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches, double *ms_total)
@@ -1086,12 +1855,12 @@ int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
 {
     if (!s || !out) return IPC_E_INVALID_ARG;
     out[0] = s->nnzb;
-    out[1] = (int64_t)s->n_slots * kSlice;
-    out[2] = s->n;
-    out[3] = s->n_act;
-    out[4] = s->m;
-    out[5] = s->n_cand;
-    out[6] = s->n_cand_sw;
+    out[1] = (int64_t)s->h.n_slots * kSlice;
+    out[2] = s->h.n;
+    out[3] = s->last.n_act;
+    out[4] = s->h.m;
+    out[5] = s->last.n_cand;
+    out[6] = s->last.n_sw;
     out[7] = s->n_gather;
     return IPC_OK;
 }
@@ -1099,23 +1868,26 @@ int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
 int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v)
 {
     if (!s) return IPC_E_INVALID_ARG;
-    return guarded([&]() -> int32_t {
-        if (x) upload_vec(s, s->x, x);
-        if (v) upload_vec(s, s->v, v);
+    IPC_HOOK_BEGIN(s)
+        size_t b = sizeof(double) * 3 * s->h.n;
+        if (x) IPC_HIP(hipMemcpyAsync(s->h.x, x, b, hipMemcpyHostToDevice, s->stream));
+        if (v) IPC_HIP(hipMemcpyAsync(s->h.v, v, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 int32_t ipcx_get_state(const ipc_scene *cs, double *x, double *v)
 {
     if (!cs) return IPC_E_INVALID_ARG;
     ipc_scene *s = const_cast<ipc_scene *>(cs);
-    return guarded([&]() -> int32_t {
-        if (x) download_vec(s, x, s->x);
-        if (v) download_vec(s, v, s->v);
+    IPC_HOOK_BEGIN(s)
+        size_t b = sizeof(double) * 3 * s->h.n;
+        if (x) IPC_HIP(hipMemcpyAsync(x, s->h.x, b, hipMemcpyDeviceToHost, s->stream));
+        if (v) IPC_HIP(hipMemcpyAsync(v, s->h.v, b, hipMemcpyDeviceToHost, s->stream));
+        IPC_HIP(hipStreamSynchronize(s->stream));
         return IPC_OK;
-    });
+    IPC_HOOK_END(s)
 }
 
 }  // extern "C"

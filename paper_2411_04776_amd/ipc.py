@@ -426,3 +426,64 @@ class GelScene:
     def v(self, val):
         val = np.ascontiguousarray(val, dtype=np.float64)
         _check(lib().ipcx_set_state(self.ptr, None, _d(val)), "ipcx_set_state")
+
+
+class Batch:
+    """The library's continuous-batching engine (ipc_batch_*).
+
+    submit() queues one step per scene and returns tickets at once; a native
+    worker thread runs every in-flight step in shared launches (one launch per
+    phase for the whole list) and admits newly submitted steps at each Newton
+    iteration boundary. Results are bitwise those of GelScene.step().
+    mem_budget > 0 caps the summed device bytes of the scenes in flight."""
+
+    def __init__(self, stream=None, mem_budget: int = 0):
+        self.rt = ipc_runtime()
+        self.rt.stream = None if stream is None else C.c_void_p(stream.cuda_stream)
+        self.rt.alloc = ALLOC_FN()
+        self.rt.free = FREE_FN()
+        self.rt.user = None
+        self.rt.mem_budget = int(mem_budget)
+        h = C.c_void_p()
+        _check(lib().ipc_batch_create(C.byref(self.rt), C.byref(h)), "ipc_batch_create")
+        self.ptr = h
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().ipc_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, scenes, poses=None):
+        """Queue one step for each GelScene (pose: the scene's next trajectory
+        pose unless given). Returns the tickets."""
+        n = len(scenes)
+        if poses is None:
+            poses = [g.scene.poses[g.step_index + 1] for g in scenes]
+        ptrs = (C.c_void_p * n)(*[g.ptr.value for g in scenes])
+        reqs = (ipc_step_req * n)(*[req_of(p) for p in poses])
+        tk = np.zeros(n, dtype=np.int64)
+        _check(lib().ipc_batch_submit(self.ptr, n, ptrs, reqs, tk.ctypes.data_as(_I64)), "ipc_batch_submit")
+        for g in scenes:
+            g.step_index += 1
+        return [int(t) for t in tk]
+
+    def poll(self, ticket):
+        """(done, stats): done is True once the step has finished."""
+        st = ipc_step_stats()
+        rc = _check(lib().ipc_batch_poll(self.ptr, int(ticket), C.byref(st)), "ipc_batch_poll")
+        return rc == 1, st
+
+    def wait(self, ticket):
+        """Block until the step is done; returns (status, stats). The ticket
+        is consumed."""
+        st = ipc_step_stats()
+        rc = lib().ipc_batch_wait(self.ptr, int(ticket), C.byref(st))
+        if rc < 0:
+            raise IPCError(rc, "ipc_batch_wait")
+        return rc, st

@@ -1,6 +1,7 @@
 import os
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -22,3 +23,29 @@ def pytest_collection_modifyitems(config, items):
 def oracle_lib():
     import oracle
     return oracle.lib()
+
+
+@pytest.fixture(scope="session")
+def c1_oracle_trajectory():
+    """Oracle iterates of config 1: per step, (x^t, v^t, pose, [x_k])."""
+    import oracle
+    from paper_2411_04776_amd import scenes
+    sc = scenes.config1()
+    o = oracle.OracleScene(sc)
+    traj = []
+    for step in range(1, sc.n_steps + 1):
+        pose = sc.poses[step]
+        x0, v0 = o.x, o.v
+        o.begin_step(pose)
+        xs = [x0]
+        x = x0
+        for _ in range(100):
+            r, xn, st = o.newton_iterate(x)
+            if r != 0:
+                break
+            xs.append(xn)
+            x = xn
+        traj.append((x0, v0, pose, xs))
+        o.step(pose)  # commit exactly as the oracle step does (same iterates)
+        assert np.array_equal(o.x, xs[-1])
+    return sc, traj, o.x

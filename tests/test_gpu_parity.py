@@ -124,30 +124,6 @@ def test_pcg_and_ccd_parity(ipc):
     assert abs(ag - ao) <= 1e-12 * max(ao, 1e-30)
 
 
-@pytest.fixture(scope="module")
-def c1_oracle_trajectory():
-    """Oracle iterates of config 1: per step, (x^t, v^t, pose, [x_k])."""
-    sc = S.config1()
-    o = O.OracleScene(sc)
-    traj = []
-    for step in range(1, sc.n_steps + 1):
-        pose = sc.poses[step]
-        x0, v0 = o.x, o.v
-        o.begin_step(pose)
-        xs = [x0]
-        x = x0
-        for _ in range(100):
-            r, xn, st = o.newton_iterate(x)
-            if r != 0:
-                break
-            xs.append(xn)
-            x = xn
-        traj.append((x0, v0, pose, xs))
-        o.step(pose)  # commit exactly as the oracle step does (same iterates)
-        assert np.array_equal(o.x, xs[-1])
-    return sc, traj, o.x
-
-
 def test_teacher_forced_newton_iterates(ipc, c1_oracle_trajectory):
     sc, traj, _ = c1_oracle_trajectory
     L = sc.bbox_diag
