@@ -16,8 +16,9 @@
 //     = one wavefront, padded to its longest row, stored component-major in
 //     the slice (value[(slot*9+c)*64 + lane]); slot 0 of a row is its diagonal;
 //   contact pairs: structure of arrays over active pairs (4 vertex ids, 12
-//     gradient and 144 Hessian components), applied in SpMV through per-vertex
-//     incidence lists sorted by pair index (no float atomics anywhere).
+//     gradient and 144 Hessian components); in SpMV each pair forms its own
+//     H_p d_p and the rows gather those through incidence lists sorted by row
+//     and pair index (no float atomics anywhere).
 // In the mixed form the element Hessians and gradients, matrix values,
 // preconditioner, assembled gradient and PCG vectors are FP32 (dot products
 // accumulate in FP64); positions, Dm^-1, distances, CCD and energies stay FP64.
@@ -37,7 +38,8 @@ namespace ipcg {
 
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
-constexpr int kLanesPerRow = 4;   // SpMV lanes per matrix row
+constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
+constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
 
 // kernels timed by the optional profiler
@@ -82,7 +84,7 @@ struct SceneOut {
 // cast them.
 struct SceneDev {
     int n, n_gel, n_ind, m, n_pts, n_edges, n_tris, n_slices, n_slots, n_surf;
-    int self_contact, ccd_max_iter, precision, nb_vert, pcg_maxit;
+    int self_contact, ccd_max_iter, precision, nb_vert, nb_rows, pcg_maxit;
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
     double pose[12];
     double alpha;      // line-search trial step
@@ -104,17 +106,18 @@ struct SceneDev {
     int32_t *ht_count[2], *ht_start[2];
     int4 *ht_entries[2];
     int32_t ht_bits[2], ht_cap[2];
-    int32_t *q_count, *q_off;
+    int32_t *q_count, *q_off;      // per query primitive (points, then edges): pair counts, offsets
     // candidates: static list and swept list (SoA type, a, b with stride cap)
     int32_t *cand, *cand_sw;
     int64_t cand_cap, sw_cap;
     double *cand_d;
-    int32_t *act_flag;
+    int32_t *act_flag, *act_off;   // active flags of the static list and their exclusive scan
     // active pairs
     int32_t *act_idx, *act_v;
-    void *act_g, *act_H;
+    void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG)
     int64_t act_cap;
-    int32_t *c_ptr, *c_cnt, *c_list;
+    double *pcg_pair;              // per-block d.(H_c d) partials of the pair blocks
+    int32_t *c_ptr, *c_cnt, *c_list, *c_row;
     // PCG
     void *r, *z, *dA, *dB, *q, *sol;
     double *pcg_part;
@@ -238,7 +241,8 @@ enum PhaseKind {
     kPhTet,       // tets (+ vertices for the body energy: kPhBody)
     kPhBody,      // tets + vertices
     kPhEntry,     // stored BELL entries
-    kPhSlice,     // BELL slices (PCG A)
+    kPhSlice,     // SpMV row blocks (kRowsPerBlock rows each)
+    kPhPcgA,      // SpMV row blocks, then pair blocks (PCG A)
     kPhPts, kPhEdges, kPhTris, kPhSurf, kPhInd,
     kPhCand,      // static candidates
     kPhCandSw,    // swept candidates

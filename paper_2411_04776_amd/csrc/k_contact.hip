@@ -463,7 +463,7 @@ __global__ void k_compact(Launch L)
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
-    if (i < L.out[s].n_cand && S.act_flag[i]) S.act_idx[S.q_off[i]] = (int32_t)i;
+    if (i < L.out[s].n_cand && S.act_flag[i]) S.act_idx[S.act_off[i]] = (int32_t)i;
 }
 
 // Shared per-pair data of the distance derivatives at fixed type: residual r,
@@ -711,7 +711,10 @@ __global__ void k_incidence(Launch L)
         int v = S.act_v[(int64_t)a * S.act_cap + k];
         if (S.fixed[v]) continue;
         int pos = atomicAdd(&S.c_cnt[v], 1);
-        if (FILL) S.c_list[S.c_ptr[v] + pos] = (int32_t)(k * 4 + a);
+        if (FILL) {
+            S.c_list[S.c_ptr[v] + pos] = (int32_t)(k * 4 + a);
+            S.c_row[S.c_ptr[v] + pos] = v;
+        }
     }
 }
 

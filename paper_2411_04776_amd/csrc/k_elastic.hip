@@ -20,6 +20,7 @@
 // Element outputs are written SoA (component-major) and summed per matrix
 // block / per vertex by gather kernels in a fixed order: no float atomics.
 #include "device_util.h"
+#include "incidence.h"
 #include "ipc_internal.h"
 
 namespace ipcg {
@@ -286,16 +287,22 @@ __global__ void __launch_bounds__(kBlock) k_elastic_elements(Launch L)
 }
 
 // Gradient gather: one thread per vertex; elastic element gradients in
-// vertex-incidence (tet) order, then inertia / kinematic target, then the
-// active contact pairs in pair order. Sums in FP64, stored in R.
+// vertex-incidence (tet) order, then inertia / kinematic target, then the sum
+// of the vertex's active contact pairs (formed per wavefront). Sums in FP64,
+// stored in R.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_assemble_gradient(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     int i = lb * blockDim.x + threadIdx.x;
-    if (i >= S.n) return;
     const R *eg = as<R>(S.eg), *ag = as<R>(S.act_g);
+    const int64_t cap = S.act_cap;
+    // contact pairs first, for the wavefront's 64 rows together
+    double gc[3] = {0.0, 0.0, 0.0};
+    wave_row_sums<3>(S, i - (int)(threadIdx.x % kWave), (int)(threadIdx.x % kWave),
+                     [&](int p, int a, int c) { return (double)ag[(int64_t)(a * 3 + c) * cap + p]; }, gc);
+    if (i >= S.n) return;
     R *grad = as<R>(S.grad);
     double g[3] = {0.0, 0.0, 0.0};
     if (!S.fixed[i]) {
@@ -309,10 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_gradient(Launch L)
         } else {
             for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
         }
-        for (int k = S.c_ptr[i]; k < S.c_ptr[i + 1]; ++k) {
-            int src = S.c_list[k], p = src >> 2, a = src & 3;
-            for (int c = 0; c < 3; ++c) g[c] += (double)ag[(int64_t)(a * 3 + c) * S.act_cap + p];
-        }
+        for (int c = 0; c < 3; ++c) g[c] += gc[c];
     }
     for (int c = 0; c < 3; ++c) grad[3 * i + c] = (R)g[c];
 }
@@ -341,6 +345,19 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
     int k = (int)(slot - S.slice_ptr[lo]);
     int col = S.bcol[slot_lane];
     const R *eH = as<R>(S.eH), *aH = as<R>(S.act_H);
+    // contact diagonal blocks of the slice's 64 rows (slot 0 is the diagonal;
+    // a wavefront is one slot of one slice, so k is uniform over it)
+    double cd[9];
+    for (int c = 0; c < 9; ++c) cd[c] = 0.0;
+    if (k == 0) {
+        const int64_t cap = S.act_cap;
+        wave_row_sums<9>(S, lo * kSlice, lane,
+                         [&](int p, int a, int c) {
+                             int i = c / 3, j = c % 3;
+                             return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
+                         },
+                         cd);
+    }
     double A[9];
     for (int c = 0; c < 9; ++c) A[c] = 0.0;
     if (col >= 0) {
@@ -361,12 +378,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
             A[0] += dk;
             A[4] += dk;
             A[8] += dk;
-            for (int t = S.c_ptr[row]; t < S.c_ptr[row + 1]; ++t) {
-                int src = S.c_list[t], p = src >> 2, a = src & 3;
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j)
-                        A[i * 3 + j] += (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * S.act_cap + p];
-            }
+            for (int c = 0; c < 9; ++c) A[c] += cd[c];
         }
         if (S.fixed[row] || S.fixed[col]) {
             for (int c = 0; c < 9; ++c) A[c] = 0.0;

@@ -6,11 +6,15 @@
 // kernels with every scalar kept on the device:
 //   A(it): every block of a scene reduces that scene's r.z partials of the
 //          previous iterations in a fixed order (all blocks agree bit for
-//          bit), decides the stop, forms d = z + beta d_prev for its rows and
-//          for the columns it gathers, applies H (BELL blocks + contact
-//          incidence lists, four lanes per row) and writes q = H d and d.q;
+//          bit) and decides the stop; a row block then forms d = z + beta
+//          d_prev for its rows and for the columns it gathers and applies the
+//          elastic BELL matrix (eight lanes per row), a pair block applies
+//          each active pair's off-diagonal blocks to its own four vertices;
+//          both write their d.q partials;
 //   B(it): every block reduces the scene's d.q partials, alpha = rz / dq,
-//          then p += alpha d, r -= alpha q, z = M^-1 r and the r.z partials.
+//          each wavefront adds its rows' incident pair products to q
+//          (segmented over the incidence lists), then p += alpha d,
+//          r -= alpha q, z = M^-1 r and the r.z partials.
 // Kernel boundaries cost ~3 us on MI355X against 8-28 us for a cooperative
 // grid-wide barrier, so an iteration is two launches rather than one
 // persistent kernel. The host launches chunks of iterations and reads the
@@ -19,6 +23,7 @@
 #include <algorithm>
 
 #include "device_util.h"
+#include "incidence.h"
 #include "ipc_internal.h"
 
 namespace ipcg {
@@ -29,11 +34,14 @@ __device__ __forceinline__ R *as(void *p)
     return reinterpret_cast<R *>(p);
 }
 
-// partial-sum layout in pcg_part: [d.q: n_slices][r.z slot 0: nb_vert][slot 1: nb_vert]
+// partial-sum layout in pcg_part: [d.q of the row blocks: nb_rows][r.z slot 0: nb_vert][slot 1: nb_vert];
+// the pair blocks' d.(H_c d) partials live in pcg_pair
 __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 {
-    return S.pcg_part + S.n_slices + (size_t)(it & 1) * S.nb_vert;
+    return S.pcg_part + S.nb_rows + (size_t)(it & 1) * S.nb_vert;
 }
+
+__device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_init(Launch L)
@@ -66,56 +74,82 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(Launch L)
     }
 }
 
+// Partial product of one BELL row: lane `part` of the row's kLanesPerRow
+// lanes takes slots part, part + kLanesPerRow, ... The vector applied is
+// z + beta d_prev (formed at the gathered column) when beta_on, else z.
 template <class R>
-__device__ __forceinline__ void spmv_row_part(const SceneDev &S, int row, int part, const R *__restrict__ z,
+__device__ __forceinline__ void bell_row_part(const SceneDev &S, int row, int part, const R *__restrict__ z,
                                               const R *__restrict__ dold, R beta, bool beta_on, double y[3])
 {
     int sl = row / kSlice, lane = row % kSlice;
     int s0 = S.slice_ptr[sl], s1 = S.slice_ptr[sl + 1];
-    const R *bval = as<R>(S.bval);
+    const R *__restrict__ bval = as<R>(S.bval);
+    const int32_t *__restrict__ bcol = S.bcol;
     R y0 = R(0), y1 = R(0), y2 = R(0);
+#pragma unroll 2
     for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
-        int64_t base = (int64_t)slot * kSlice + lane;
-        int col = S.bcol[base];
-        if (col < 0) break;
-        const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
-        R v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
-        if (beta_on) {
-            v0 += beta * dold[3 * col];
-            v1 += beta * dold[3 * col + 1];
-            v2 += beta * dold[3 * col + 2];
+        int col = bcol[(int64_t)slot * kSlice + lane];
+        if (col >= 0) {
+            const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
+            R v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
+            if (beta_on) {
+                v0 += beta * dold[3 * col];
+                v1 += beta * dold[3 * col + 1];
+                v2 += beta * dold[3 * col + 2];
+            }
+            y0 += A[0 * kSlice] * v0 + A[1 * kSlice] * v1 + A[2 * kSlice] * v2;
+            y1 += A[3 * kSlice] * v0 + A[4 * kSlice] * v1 + A[5 * kSlice] * v2;
+            y2 += A[6 * kSlice] * v0 + A[7 * kSlice] * v1 + A[8 * kSlice] * v2;
         }
-        y0 += A[0 * kSlice] * v0 + A[1 * kSlice] * v1 + A[2 * kSlice] * v2;
-        y1 += A[3 * kSlice] * v0 + A[4 * kSlice] * v1 + A[5 * kSlice] * v2;
-        y2 += A[6 * kSlice] * v0 + A[7 * kSlice] * v1 + A[8 * kSlice] * v2;
     }
     y[0] = y0;
     y[1] = y1;
     y[2] = y2;
 }
 
-// off-diagonal blocks of the active contact pairs incident to `row`
+// One active pair: y_a = sum over b != a of H_ab d_b for its four slots
+// (the diagonal blocks live in the BELL diagonal), stored per pair for the
+// row gather; returns sum_a d_a . y_a.
 template <class R>
-__device__ __forceinline__ void contact_row(const SceneDev &S, int row, const R *__restrict__ z,
-                                            const R *__restrict__ dold, R beta, bool beta_on, double y[3])
+__device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const R *__restrict__ z,
+                                             const R *__restrict__ dold, R beta, bool beta_on)
 {
-    const R *H = as<R>(S.act_H);
-    for (int t = S.c_ptr[row]; t < S.c_ptr[row + 1]; ++t) {
-        int src = S.c_list[t], p = src >> 2, a = src & 3;
+    const int64_t cap = S.act_cap;
+    const R *__restrict__ H = as<R>(S.act_H);
+    R *__restrict__ Y = as<R>(S.act_y);
+    R d[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int v = S.act_v[(int64_t)a * cap + p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[a][c] = beta_on ? z[3 * v + c] + beta * dold[3 * v + c] : z[3 * v + c];
+    }
+    double dy = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
         for (int b = 0; b < 4; ++b) {
-            if (b == a) continue;  // the diagonal block lives in the BELL diagonal
-            int vb = S.act_v[(int64_t)b * S.act_cap + p];
-            R v[3] = {z[3 * vb], z[3 * vb + 1], z[3 * vb + 2]};
-            if (beta_on)
-                for (int c = 0; c < 3; ++c) v[c] += beta * dold[3 * vb + c];
+            if (b == a) continue;
+#pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const R *h = H + (int64_t)((3 * a + i) * 12 + 3 * b) * S.act_cap + p;
-                y[i] += (double)(h[0] * v[0] + h[S.act_cap] * v[1] + h[2 * S.act_cap] * v[2]);
+                const R *h = H + (int64_t)((3 * a + i) * 12 + 3 * b) * cap + p;
+                y[i] += (double)(h[0] * d[b][0] + h[cap] * d[b][1] + h[2 * cap] * d[b][2]);
             }
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            R yv = (R)y[i];
+            Y[(int64_t)(3 * a + i) * cap + p] = yv;
+            dy += (double)d[a][i] * (double)yv;
+        }
     }
+    return dy;
 }
 
+// PCG A(it): stop test and beta from the r.z partials (every block agrees),
+// then either a row block (d = z + beta d_prev for its rows, q = K_el d,
+// d.q partial) or a pair block (H_p d_p per pair, d.(H_c d) partial).
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
 {
@@ -152,33 +186,52 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     }
     const R *z = as<R>(S.z);
     const R *dold = as<R>((it & 1) ? S.dB : S.dA);
-    R *dnew = as<R>((it & 1) ? S.dA : S.dB);
-    R *q = as<R>(S.q);
-    // block = one slice of 64 rows; lanes (4r .. 4r+3) of a wavefront share row r
-    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int row = lb * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
-    int part = lane % kLanesPerRow;
-    double y[3] = {0.0, 0.0, 0.0};
-    bool live = row < S.n;
     R rb = (R)beta;
-    if (live) spmv_row_part<R>(S, row, part, z, dold, rb, it > 1, y);
-    for (int c = 0; c < 3; ++c) {
-        y[c] += __shfl_xor(y[c], 1, kWave);
-        y[c] += __shfl_xor(y[c], 2, kWave);
-    }
+    bool bon = it > 1;
     double dq = 0.0;
-    if (live && part == 0) {
-        contact_row<R>(S, row, z, dold, rb, it > 1, y);
-        for (int c = 0; c < 3; ++c) {
-            R dv = it > 1 ? z[3 * row + c] + rb * dold[3 * row + c] : z[3 * row + c];
-            R qv = (R)y[c];
-            dnew[3 * row + c] = dv;
-            q[3 * row + c] = qv;
-            dq += (double)dv * (double)qv;
+    if (lb < S.nb_rows) {
+        R *dnew = as<R>((it & 1) ? S.dA : S.dB);
+        R *q = as<R>(S.q);
+        // kLanesPerRow consecutive lanes share a row
+        int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+        int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+        int part = lane % kLanesPerRow;
+        double y[3] = {0.0, 0.0, 0.0};
+        bool live = row < S.n;
+        if (live) bell_row_part<R>(S, row, part, z, dold, rb, bon, y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int o = 1; o < kLanesPerRow; o <<= 1) y[c] += __shfl_xor(y[c], o, kWave);
+        if (live && part == 0) {
+            for (int c = 0; c < 3; ++c) {
+                R dv = bon ? z[3 * row + c] + rb * dold[3 * row + c] : z[3 * row + c];
+                R qv = (R)y[c];
+                dnew[3 * row + c] = dv;
+                q[3 * row + c] = qv;
+                dq += (double)dv * (double)qv;
+            }
         }
+        dq = block_sum_all(dq);
+        if (threadIdx.x == 0) S.pcg_part[lb] = dq;
+    } else {
+        int pb = lb - S.nb_rows;
+        int64_t p = (int64_t)pb * blockDim.x + threadIdx.x;
+        if (p < L.out[s].n_act) dq = pair_apply<R>(S, p, z, dold, rb, bon);
+        dq = block_sum_all(dq);
+        if (threadIdx.x == 0) S.pcg_pair[pb] = dq;
     }
-    dq = block_sum_all(dq);
-    if (threadIdx.x == 0) S.pcg_part[lb] = dq;
+}
+
+// q_i = (K_el d)_i + sum of the incident pairs' (H_p d_p)_i
+template <class R>
+__device__ __forceinline__ void contact_rows(const SceneDev &S, int lb, double qc[3])
+{
+    const R *Y = as<R>(S.act_y);
+    const int64_t cap = S.act_cap;
+    int lane = threadIdx.x % kWave;
+    wave_row_sums<3>(S, lb * blockDim.x + (threadIdx.x - lane), lane,
+                     [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
 }
 
 template <class R>
@@ -187,9 +240,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     if (S.pcg->done) return;
-    double dq = reduce_partials(S.pcg_part, S.n_slices);
+    double dq = reduce_partials(S.pcg_part, S.nb_rows) + reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_act));
     double rz_prev = reduce_partials(rz_slot(S, it - 1), S.nb_vert);
     R alpha = (R)(rz_prev / dq);
+    double qc[3] = {0.0, 0.0, 0.0};
+    contact_rows<R>(S, lb, qc);
     const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
     const R *q = as<R>(S.q), *Mi = as<R>(S.Minv);
     R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
@@ -198,8 +253,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
     if (i < S.n) {
         R ri[3];
         for (int c = 0; c < 3; ++c) {
+            R qv = (R)((double)q[3 * i + c] + qc[c]);
             sol[3 * i + c] += alpha * dcur[3 * i + c];
-            ri[c] = r[3 * i + c] - alpha * q[3 * i + c];
+            ri[c] = r[3 * i + c] - alpha * qv;
             r[3 * i + c] = ri[c];
         }
         for (int a = 0; a < 3; ++a) {
@@ -212,28 +268,47 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
     if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
 }
 
-// y = H v for the test hook: v in S.dB, y in S.q
+// y = H v for the test hook (v in S.dB, y in S.q), in the PCG's three parts:
+// pair products, BELL rows, then the incident pair products per row
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_spmv(Launch L)
+__global__ void __launch_bounds__(kBlock) k_spmv_pairs(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (p < L.out[s].n_act) (void)pair_apply<R>(S, p, as<R>(S.dB), nullptr, R(0), false);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_spmv_rows(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     const R *v = as<R>(S.dB);
     R *y = as<R>(S.q);
     int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int row = lb * kSlice + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
     int part = lane % kLanesPerRow;
     double o[3] = {0.0, 0.0, 0.0};
     bool live = row < S.n;
-    if (live) spmv_row_part<R>(S, row, part, v, nullptr, R(0), false, o);
-    for (int c = 0; c < 3; ++c) {
-        o[c] += __shfl_xor(o[c], 1, kWave);
-        o[c] += __shfl_xor(o[c], 2, kWave);
-    }
-    if (live && part == 0) {
-        contact_row<R>(S, row, v, nullptr, R(0), false, o);
+    if (live) bell_row_part<R>(S, row, part, v, nullptr, R(0), false, o);
+    for (int c = 0; c < 3; ++c)
+        for (int k = 1; k < kLanesPerRow; k <<= 1) o[c] += __shfl_xor(o[c], k, kWave);
+    if (live && part == 0)
         for (int c = 0; c < 3; ++c) y[3 * row + c] = (R)o[c];
-    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_spmv_contact(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    double qc[3] = {0.0, 0.0, 0.0};
+    contact_rows<R>(S, lb, qc);
+    int i = lb * blockDim.x + threadIdx.x;
+    R *y = as<R>(S.q);
+    if (i < S.n)
+        for (int c = 0; c < 3; ++c) y[3 * i + c] = (R)((double)y[3 * i + c] + qc[c]);
 }
 
 // ---- per-vertex kernels ------------------------------------------------------
@@ -395,7 +470,7 @@ __device__ __forceinline__ ScanSel scan_sel(const SceneDev &S, const SceneOut &O
     case kScanEdge: return {S.ht_count[1], S.ht_start[1], (int64_t)1 << S.ht_bits[1]};
     case kScanQuery: return {S.q_count, S.q_off, (int64_t)S.n_pts + S.n_edges};
     case kScanContact: return {S.c_cnt, S.c_ptr, (int64_t)S.n};
-    default: return {S.act_flag, S.q_off, (int64_t)O.n_cand};
+    default: return {S.act_flag, S.act_off, (int64_t)O.n_cand};
     }
 }
 
@@ -550,17 +625,28 @@ void run_pinf(Batch &b)
 
 void launch_hess_apply(Batch &b)
 {
-    if (mixed(b))
-        IPC_LAUNCH(b, k_spmv<float>, kPhSlice, kBlock);
-    else
-        IPC_LAUNCH(b, k_spmv<double>, kPhSlice, kBlock);
+    // pair phase as set by the incidence build of the same assembly
+    if (mixed(b)) {
+        IPC_LAUNCH(b, k_spmv_pairs<float>, kPhActT, kBlock);
+        IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kBlock);
+        IPC_LAUNCH(b, k_spmv_contact<float>, kPhVert, kBlock);
+    } else {
+        IPC_LAUNCH(b, k_spmv_pairs<double>, kPhActT, kBlock);
+        IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kBlock);
+        IPC_LAUNCH(b, k_spmv_contact<double>, kPhVert, kBlock);
+    }
 }
 
-// PCG for every scene with blocks in the kPhVert / kPhSlice maps.
+// PCG for every scene with blocks in the kPhVert map (the active-pair counts
+// come from the last read-back of the narrow phase).
 void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
 {
     size_t ns = b.sc.size();
     bool mx = mixed(b);
+    std::vector<int32_t> nab(ns, 0);
+    for (size_t i = 0; i < ns; ++i)
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(b.h_out[i].n_act);
+    b.set_phase(kPhPcgA, nab);
     if (mx)
         IPC_LAUNCH(b, k_pcg_init<float>, kPhVert, kBlock);
     else
@@ -585,9 +671,9 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             bool timed = b.prof() && (it & 3) == 1;  // time one launch in four when profiling
             if (timed) b.prof_begin(kProfPcgA, ev);
             if (mx)
-                IPC_LAUNCH(b, k_pcg_A<float>, kPhSlice, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_A<float>, kPhPcgA, kBlock, it);
             else
-                IPC_LAUNCH(b, k_pcg_A<double>, kPhSlice, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_A<double>, kPhPcgA, kBlock, it);
             if (timed) b.prof_end(kProfPcgA, ev);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)

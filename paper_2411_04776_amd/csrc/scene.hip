@@ -227,13 +227,11 @@ void grow_candidates(Scene &s, int which, int64_t need)
     int64_t &cap = which ? H.sw_cap : H.cand_cap;
     if (buf && need <= cap) return;
     int64_t nc = need + need / 2 + 1024;
-    // q_off doubles as the output of the active-flag scan
-    int64_t q = std::max<int64_t>((int64_t)H.n_pts + H.n_edges, std::max(which ? H.cand_cap : nc, which ? nc : H.sw_cap)) + 1;
     Staged st(s);
     int32_t *nb = st.get<int32_t>(3 * (size_t)nc);
     double *nd = which ? nullptr : st.get<double>(nc);
     int32_t *nf = which ? nullptr : st.get<int32_t>(nc + 1);
-    int32_t *nqc = st.get<int32_t>(q), *nqo = st.get<int32_t>(q);
+    int32_t *no = which ? nullptr : st.get<int32_t>(nc + 1);
     ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max({H.cand_cap, H.sw_cap, nc}));
     st.commit();
     dfree(s, buf);
@@ -242,13 +240,11 @@ void grow_candidates(Scene &s, int which, int64_t need)
     if (!which) {
         dfree(s, H.cand_d);
         dfree(s, H.act_flag);
+        dfree(s, H.act_off);
         H.cand_d = nd;
         H.act_flag = nf;
+        H.act_off = no;
     }
-    dfree(s, H.q_count);
-    dfree(s, H.q_off);
-    H.q_count = nqc;
-    H.q_off = nqo;
     s.dev_dirty = true;
 }
 
@@ -261,18 +257,21 @@ void grow_active(Scene &s, int64_t need)
     Staged st(s);
     int32_t *ni = st.get<int32_t>(nc), *nv = st.get<int32_t>(4 * (size_t)nc);
     void *ng = st.get_bytes(12 * (size_t)nc * rs), *nh = st.get_bytes(144 * (size_t)nc * rs);
-    int32_t *nl = st.get<int32_t>(4 * (size_t)nc);
+    void *ny = st.get_bytes(12 * (size_t)nc * rs);
+    double *npp = st.get<double>((size_t)nblocks(nc) + 1);
+    int32_t *nl = st.get<int32_t>(4 * (size_t)nc), *nr = st.get<int32_t>(4 * (size_t)nc);
     st.commit();
-    dfree(s, H.act_idx);
-    dfree(s, H.act_v);
-    dfree(s, H.act_g);
-    dfree(s, H.act_H);
-    dfree(s, H.c_list);
+    for (void *old : {(void *)H.act_idx, (void *)H.act_v, H.act_g, H.act_H, H.act_y, (void *)H.pcg_pair,
+                      (void *)H.c_list, (void *)H.c_row})
+        dfree(s, old);
     H.act_idx = ni;
     H.act_v = nv;
     H.act_g = ng;
     H.act_H = nh;
+    H.act_y = ny;
+    H.pcg_pair = npp;
     H.c_list = nl;
+    H.c_row = nr;
     H.act_cap = nc;
     s.dev_dirty = true;
 }
@@ -463,6 +462,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     size_t n3 = 3 * (size_t)n;
     H.n_surf = (int)s.h_surf_verts.size();
     H.nb_vert = nblocks(n);
+    H.nb_rows = nblocks(n, kRowsPerBlock);
     H.mu = s.prm.mu;
     H.lam = s.prm.lam;
     H.h = s.prm.dt;
@@ -519,11 +519,13 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     IPC_HIP(hipMemsetAsync(H.c_ptr, 0, sizeof(int32_t) * (n + 1), s.stream));
     for (void **p : {&H.r, &H.z, &H.dA, &H.dB, &H.q, &H.sol}) *p = dalloc_bytes(s, n3 * rs);
     IPC_HIP(hipMemsetAsync(H.sol, 0, n3 * rs, s.stream));
-    H.pcg_part = dalloc<double>(s, (size_t)H.n_slices + 2 * (size_t)H.nb_vert + 8);
+    H.pcg_part = dalloc<double>(s, (size_t)H.nb_rows + 2 * (size_t)H.nb_vert + 8);
     H.pcg = dalloc<PcgState>(s, 1);
     IPC_HIP(hipMemsetAsync(H.pcg, 0, sizeof(PcgState), s.stream));
     grow_table(s, 0, 16 * (int64_t)std::max(H.n_tris, 1));
     grow_table(s, 1, 16 * (int64_t)std::max(H.n_edges, 1));
+    H.q_count = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
+    H.q_off = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     grow_candidates(s, 0, 1024);
     grow_candidates(s, 1, 1024);
     grow_active(s, 256);
@@ -715,7 +717,7 @@ static void activate(Batch &b, const std::vector<uint8_t> &on)
         v[i] = a ? nblocks(H.n) : 0;
         t[i] = a ? nblocks(H.m) : 0;
         e[i] = a ? nblocks((int64_t)H.n_slots * kSlice) : 0;
-        sl[i] = a ? H.n_slices : 0;
+        sl[i] = a ? H.nb_rows : 0;
         p[i] = a ? nblocks(H.n_pts) : 0;
         ed[i] = a ? nblocks(H.n_edges) : 0;
         tr[i] = a ? nblocks(H.n_tris) : 0;

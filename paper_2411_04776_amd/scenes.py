@@ -359,10 +359,19 @@ def config2(seed: int = 0, grid=(40, 50, 8), steps: int = 50) -> Scene:
 def config3_scene(i: int, steps: int = 20) -> Scene:
     """Scene i of the 256-scene batch: grid U{12..40}xU{15..50}xU{3..8}, random
     icosphere/cylinder/box with tilt <= 20 deg, depth U[0.5,2] mm over 20 steps."""
-    rng = np.random.default_rng(1000 + i)
+    return uneven_scene(1000 + i, steps=steps)
+
+
+def uneven_scene(seed: int, steps: int = 20, grid=None, prefix: str = "c3") -> Scene:
+    """A scene of the uneven batch distribution drawn from `seed`; `grid`
+    overrides the drawn resolution (the draws stay the same)."""
+    rng = np.random.default_rng(seed)
     nx = int(rng.integers(12, 41))
     ny = int(rng.integers(15, 51))
     nz = int(rng.integers(3, 9))
+    if grid is not None:
+        nx, ny, nz = grid
+    i = seed - 1000
     X, T, fixed = grid_gel(nx, ny, nz)
     kind = ("icosphere", "cylinder", "box")[int(rng.integers(0, 3))]
     if kind == "icosphere":
@@ -375,8 +384,14 @@ def config3_scene(i: int, steps: int = 20) -> Scene:
     R = rotation(axis, math.radians(float(rng.uniform(0.0, 20.0))))
     depth = float(rng.uniform(0.5e-3, 2e-3))
     poses = _descent_poses(R, Y, GEL_SIZE[2], (GEL_SIZE[0] / 2, GEL_SIZE[1] / 2), depth, steps)
-    return Scene(f"c3_{i}_{nx}x{ny}x{nz}_{kind}", X, T, fixed, Y, F, poses, dt=1e-2,
-                 meta={"i": i, "kind": kind, "depth": depth})
+    return Scene(f"{prefix}_{i}_{nx}x{ny}x{nz}_{kind}", X, T, fixed, Y, F, poses, dt=1e-2,
+                 meta={"i": i, "seed": seed, "kind": kind, "depth": depth})
+
+
+def serving_scene(env: int, large: bool, steps: int = 20) -> Scene:
+    """Environment `env` of the serving workload: the uneven batch
+    distribution from seed 5000 + env, at 80x100x16 for the large ones."""
+    return uneven_scene(5000 + env, steps=steps, grid=(80, 100, 16) if large else None, prefix="c4")
 
 
 def config5(indent_steps: int = 40, slide_steps: int = 160) -> Scene:

@@ -19,7 +19,7 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-MIXED_PCG_TOL = 1e-5  # relative preconditioned residual reachable in FP32 vectors
+MIXED_PCG_TOL = 1e-7  # inner solves converged far enough that the iterate error is the mixed form's, not PCG's
 
 
 def say(*a):
