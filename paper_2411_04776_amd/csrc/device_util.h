@@ -73,6 +73,18 @@ __device__ inline double reduce_partials(const double *partials, int n)
     return block_sum_all(acc);
 }
 
+// The same sum computed by one wavefront alone, without block barriers: lane
+// l adds partials l, l + 64, ... in order, then a fixed shuffle tree. Every
+// wavefront of every block gets the identical value.
+__device__ inline double wave_reduce_partials(const double *partials, int n)
+{
+    int lane = threadIdx.x & (kWave - 1);
+    double acc = 0.0;
+    for (int i = lane; i < n; i += kWave) acc += partials[i];
+    acc = wave_sum(acc);
+    return __shfl(acc, 0, kWave);
+}
+
 // ---- compensated (double-double style) sums for energies ----------------
 struct CSum {
     double s, c;

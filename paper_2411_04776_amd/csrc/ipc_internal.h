@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 #include <memory>
 #include <string>
@@ -41,6 +42,7 @@ constexpr int kBlock = 256;       // threads per block for streaming kernels
 constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
 constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
+constexpr int kHeavyRow = 64;     // incidence rows longer than this get a block of their own
 
 // kernels timed by the optional profiler
 enum ProfKernel {
@@ -59,6 +61,7 @@ struct PcgState {
     int32_t done;
     int32_t iters;
     double stop;
+    double rzv[2];  // r.z of the previous iterations by parity, written once by the SpMV kernel's block 0
 };
 
 // Per-scene values produced on the device and read back once per phase for
@@ -71,7 +74,7 @@ struct SceneOut {
     int32_t bad;          // non-finite positions seen by the broad phase
     int32_t infeasible;   // energy: a tet with J <= 0 or a pair with d <= 0
     int32_t pcg_done, pcg_iters;
-    int32_t pad;
+    int32_t n_heavy;      // incidence rows with more than kHeavyRow entries
     double pinf;          // max |p| over free DOFs
     double alpha_ccd;
     double energy;
@@ -117,7 +120,9 @@ struct SceneDev {
     void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG)
     int64_t act_cap;
     double *pcg_pair;              // per-block d.(H_c d) partials of the pair blocks
-    int32_t *c_ptr, *c_cnt, *c_list, *c_row;
+    int32_t *c_ptr, *c_cnt, *c_list, *c_row, *c_tmp;
+    int32_t *hflag, *heavy_idx, *heavy_rows;  // heavy incidence rows: flag, index (scan), list
+    double *hdiag;                            // 9 contact diagonal sums per heavy row
     // PCG
     void *r, *z, *dA, *dB, *q, *sol;
     double *pcg_part;
@@ -248,6 +253,8 @@ enum PhaseKind {
     kPhCandSw,    // swept candidates
     kPhAct,       // active pairs, one 64-thread block each
     kPhActT,      // active pairs, kBlock threads
+    kPhEnt,       // incidence entries (4 per active pair), kBlock threads
+    kPhVertH,     // vertex blocks, then one block per heavy incidence row
     kPhOne,       // one block per scene
     kPhTilesT, kPhTilesE, kPhTilesQ, kPhTilesC, kPhTilesA,  // scan tiles
     kPhKinds
@@ -320,10 +327,13 @@ void run_energy(Batch &b, bool trial);
 void launch_energy_body(Batch &b, bool trial);
 
 void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap);
+// per-scene upper bound on heavy incidence rows, from the active-pair count
+inline int heavy_bound(int64_t n_act, int n) { return n_act > 0 ? (int)std::min<int64_t>(n, 4 * n_act / (kHeavyRow + 1) + 1) : 0; }
+void set_heavy_phase(Batch &b);  // kPhVertH from the last read-back active-pair counts
 void run_pinf(Batch &b);
 void launch_hess_apply(Batch &b);  // y (S.q) = H v (S.dB)
 
-enum ScanWhich { kScanTri = 0, kScanEdge = 1, kScanQuery = 2, kScanContact = 3, kScanActive = 4 };
+enum ScanWhich { kScanTri = 0, kScanEdge = 1, kScanQuery = 2, kScanContact = 3, kScanActive = 4, kScanHeavy = 5 };
 // len[s] < 0: scene s sits out; query_sw selects the swept-candidate total
 void segmented_scan(Batch &b, ScanWhich which, PhaseKind tiles, const std::vector<int64_t> &len, int query_sw = 0);
 

@@ -700,6 +700,10 @@ __global__ void __launch_bounds__(64) k_barrier(Launch L)
 }
 
 
+// Incidence lists of the active pairs' free vertices: a counting pass, a scan
+// into c_ptr, then a fill in arbitrary order (c_tmp) and a rank pass that
+// puts every row's entries in pair order. Rows with more than kHeavyRow
+// entries are flagged and listed (their sums get a block each).
 template <bool FILL>
 __global__ void k_incidence(Launch L)
 {
@@ -712,29 +716,40 @@ __global__ void k_incidence(Launch L)
         if (S.fixed[v]) continue;
         int pos = atomicAdd(&S.c_cnt[v], 1);
         if (FILL) {
-            S.c_list[S.c_ptr[v] + pos] = (int32_t)(k * 4 + a);
+            S.c_tmp[S.c_ptr[v] + pos] = (int32_t)(k * 4 + a);
             S.c_row[S.c_ptr[v] + pos] = v;
         }
     }
 }
 
-__global__ void k_incidence_sort(Launch L)
+__global__ void k_heavy_flags(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     int i = lb * blockDim.x + threadIdx.x;
-    if (i >= S.n) return;
-    int s0 = S.c_ptr[i], s1 = S.c_ptr[i + 1];
-    int32_t *list = S.c_list;
-    for (int k = s0 + 1; k < s1; ++k) {
-        int key = list[k];
-        int j = k - 1;
-        while (j >= s0 && list[j] > key) {
-            list[j + 1] = list[j];
-            --j;
-        }
-        list[j + 1] = key;
-    }
+    if (i < S.n) S.hflag[i] = S.c_ptr[i + 1] - S.c_ptr[i] > kHeavyRow ? 1 : 0;
+}
+
+__global__ void k_heavy_rows(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i < S.n && S.hflag[i]) S.heavy_rows[S.heavy_idx[i]] = i;
+}
+
+// entry t goes to its row's segment at the rank of its key (pair*4 + slot)
+__global__ void k_incidence_rank(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int t = lb * blockDim.x + threadIdx.x;
+    if (t >= S.c_ptr[S.n]) return;
+    int v = S.c_row[t];
+    int e0 = S.c_ptr[v], e1 = S.c_ptr[v + 1];
+    int key = S.c_tmp[t], rank = 0;
+    for (int u = e0; u < e1; ++u) rank += S.c_tmp[u] < key ? 1 : 0;
+    S.c_list[e0 + rank] = key;
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,23 +1065,41 @@ void launch_barrier(Batch &b)
 void launch_contact_incidence(Batch &b)
 {
     size_t ns = b.sc.size();
-    std::vector<int32_t> na(ns), nz(ns);
+    std::vector<int32_t> na(ns), ne(ns), nz(ns);
     std::vector<int64_t> len(ns, -1);
     for (size_t i = 0; i < ns; ++i) {
         bool on = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
         na[i] = on ? nblocks(b.h_out[i].n_act) : 0;
+        ne[i] = on ? nblocks(4 * (int64_t)b.h_out[i].n_act) : 0;
         nz[i] = on ? nblocks((int64_t)b.sc[i]->h.n + 1) : 0;
         len[i] = on ? b.sc[i]->h.n : -1;
     }
     b.set_phase(kPhActT, na);
+    b.set_phase(kPhEnt, ne);
     b.set_phase(kPhTilesC, nz);
     IPC_LAUNCH(b, k_zero, kPhTilesC, kBlock, 2);
     IPC_LAUNCH(b, k_incidence<false>, kPhActT, kBlock);
     segmented_scan(b, kScanContact, kPhTilesC, len);
+    IPC_LAUNCH(b, k_heavy_flags, kPhVert, kBlock);
+    segmented_scan(b, kScanHeavy, kPhTilesC, len);
+    IPC_LAUNCH(b, k_heavy_rows, kPhVert, kBlock);
     b.set_phase(kPhTilesC, nz);
     IPC_LAUNCH(b, k_zero, kPhTilesC, kBlock, 2);
     IPC_LAUNCH(b, k_incidence<true>, kPhActT, kBlock);
-    IPC_LAUNCH(b, k_incidence_sort, kPhVert, kBlock);
+    IPC_LAUNCH(b, k_incidence_rank, kPhEnt, kBlock);
+    set_heavy_phase(b);
+}
+
+void set_heavy_phase(Batch &b)
+{
+    size_t ns = b.sc.size();
+    std::vector<int32_t> nh(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        bool on = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
+        const SceneDev &H = b.sc[i]->h;
+        nh[i] = on ? H.nb_vert + heavy_bound(b.h_out[i].n_act, H.n) : 0;
+    }
+    b.set_phase(kPhVertH, nh);
 }
 
 void run_ccd(Batch &b)

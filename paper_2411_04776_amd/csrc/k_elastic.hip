@@ -289,36 +289,64 @@ __global__ void __launch_bounds__(kBlock) k_elastic_elements(Launch L)
 // Gradient gather: one thread per vertex; elastic element gradients in
 // vertex-incidence (tet) order, then inertia / kinematic target, then the sum
 // of the vertex's active contact pairs (formed per wavefront). Sums in FP64,
-// stored in R.
+// stored in R. A heavy incidence row gets a block of its own after the vertex
+// blocks, which also sums the contact diagonal blocks of that row (hdiag).
+template <class R>
+__device__ __forceinline__ void vertex_gradient(const SceneDev &S, int i, double g[3])
+{
+    const R *eg = as<R>(S.eg);
+    for (int k = S.vt_ptr[i]; k < S.vt_ptr[i + 1]; ++k) {
+        int src = S.vt_src[k], e = src >> 2, a = src & 3;
+        for (int c = 0; c < 3; ++c) g[c] += (double)eg[(int64_t)(a * 3 + c) * S.m + e];
+    }
+    if (i < S.n_gel) {
+        double kk = S.mass[i] * S.inv_h2;
+        for (int c = 0; c < 3; ++c) g[c] += kk * (S.x[3 * i + c] - S.xtilde[3 * i + c]);
+    } else {
+        for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
+    }
+}
+
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_assemble_gradient(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    int i = lb * blockDim.x + threadIdx.x;
-    const R *eg = as<R>(S.eg), *ag = as<R>(S.act_g);
+    const R *ag = as<R>(S.act_g), *aH = as<R>(S.act_H);
     const int64_t cap = S.act_cap;
-    // contact pairs first, for the wavefront's 64 rows together
-    double gc[3] = {0.0, 0.0, 0.0};
-    wave_row_sums<3>(S, i - (int)(threadIdx.x % kWave), (int)(threadIdx.x % kWave),
-                     [&](int p, int a, int c) { return (double)ag[(int64_t)(a * 3 + c) * cap + p]; }, gc);
-    if (i >= S.n) return;
     R *grad = as<R>(S.grad);
-    double g[3] = {0.0, 0.0, 0.0};
-    if (!S.fixed[i]) {
-        for (int k = S.vt_ptr[i]; k < S.vt_ptr[i + 1]; ++k) {
-            int src = S.vt_src[k], e = src >> 2, a = src & 3;
-            for (int c = 0; c < 3; ++c) g[c] += (double)eg[(int64_t)(a * 3 + c) * S.m + e];
+    if (lb < S.nb_vert) {
+        int i = lb * blockDim.x + threadIdx.x;
+        // contact pairs of the wavefront's 64 (light) rows together
+        double gc[3] = {0.0, 0.0, 0.0};
+        wave_row_sums<3>(S, i - (int)(threadIdx.x % kWave), (int)(threadIdx.x % kWave),
+                         [&](int p, int a, int c) { return (double)ag[(int64_t)(a * 3 + c) * cap + p]; }, gc);
+        if (i >= S.n || S.hflag[i]) return;
+        double g[3] = {0.0, 0.0, 0.0};
+        if (!S.fixed[i]) {
+            vertex_gradient<R>(S, i, g);
+            for (int c = 0; c < 3; ++c) g[c] += gc[c];
         }
-        if (i < S.n_gel) {
-            double kk = S.mass[i] * S.inv_h2;
-            for (int c = 0; c < 3; ++c) g[c] += kk * (S.x[3 * i + c] - S.xtilde[3 * i + c]);
-        } else {
-            for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
+        for (int c = 0; c < 3; ++c) grad[3 * i + c] = (R)g[c];
+    } else {
+        int j = lb - S.nb_vert;
+        if (j >= L.out[s].n_heavy) return;
+        int row = S.heavy_rows[j];  // never a fixed vertex: those have no incidence entries
+        double gc[12];
+        block_row_sums<12>(S, row,
+                           [&](int p, int a, int c) {
+                               if (c < 3) return (double)ag[(int64_t)(a * 3 + c) * cap + p];
+                               int ii = (c - 3) / 3, jj = (c - 3) % 3;
+                               return (double)aH[(int64_t)((3 * a + ii) * 12 + 3 * a + jj) * cap + p];
+                           },
+                           gc);
+        if (threadIdx.x == 0) {
+            double g[3] = {0.0, 0.0, 0.0};
+            vertex_gradient<R>(S, row, g);
+            for (int c = 0; c < 3; ++c) grad[3 * row + c] = (R)(g[c] + gc[c]);
+            for (int c = 0; c < 9; ++c) S.hdiag[9 * (int64_t)j + c] = gc[3 + c];
         }
-        for (int c = 0; c < 3; ++c) g[c] += gc[c];
     }
-    for (int c = 0; c < 3; ++c) grad[3 * i + c] = (R)g[c];
 }
 
 // Matrix gather: one thread per stored BELL block. Sums the element blocks
@@ -357,6 +385,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
                              return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
                          },
                          cd);
+        if (row < S.n && S.hflag[row])  // summed by the row's own block in the gradient kernel
+            for (int c = 0; c < 9; ++c) cd[c] = S.hdiag[9 * (int64_t)S.heavy_idx[row] + c];
     }
     double A[9];
     for (int c = 0; c < 9; ++c) A[c] = 0.0;
@@ -490,10 +520,10 @@ void launch_assemble(Batch &b)
     hipEvent_t ev[2];
     b.prof_begin(kProfAssemble, ev);
     if (mixed(b)) {
-        IPC_LAUNCH(b, k_assemble_gradient<float>, kPhVert, kBlock);
+        IPC_LAUNCH(b, k_assemble_gradient<float>, kPhVertH, kBlock);
         IPC_LAUNCH(b, k_assemble_bell<float>, kPhEntry, kBlock);
     } else {
-        IPC_LAUNCH(b, k_assemble_gradient<double>, kPhVert, kBlock);
+        IPC_LAUNCH(b, k_assemble_gradient<double>, kPhVertH, kBlock);
         IPC_LAUNCH(b, k_assemble_bell<double>, kPhEntry, kBlock);
     }
     b.prof_end(kProfAssemble, ev);

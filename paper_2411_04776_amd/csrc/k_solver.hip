@@ -4,14 +4,15 @@
 // PCG solves H p = -g from p = 0 and stops when the preconditioned residual
 // r^T M^-1 r reaches pcg_tol^2 times its initial value. Each iteration is two
 // kernels with every scalar kept on the device:
-//   A(it): every block of a scene reduces that scene's r.z partials of the
-//          previous iterations in a fixed order (all blocks agree bit for
-//          bit) and decides the stop; a row block then forms d = z + beta
+//   A(it): every wavefront of a scene reduces that scene's r.z partials of
+//          the previous iteration in a fixed order (all agree bit for bit;
+//          no block barrier before the real work) and decides the stop;
+//          block 0 keeps r.z for the next launches; a row block then forms d = z + beta
 //          d_prev for its rows and for the columns it gathers and applies the
 //          elastic BELL matrix (eight lanes per row), a pair block applies
 //          each active pair's off-diagonal blocks to its own four vertices;
 //          both write their d.q partials;
-//   B(it): every block reduces the scene's d.q partials, alpha = rz / dq,
+//   B(it): every wavefront reduces the scene's d.q partials, alpha = rz / dq,
 //          each wavefront adds its rows' incident pair products to q
 //          (segmented over the incidence lists), then p += alpha d,
 //          r -= alpha q, z = M^-1 r and the r.z partials.
@@ -34,11 +35,12 @@ __device__ __forceinline__ R *as(void *p)
     return reinterpret_cast<R *>(p);
 }
 
-// partial-sum layout in pcg_part: [d.q of the row blocks: nb_rows][r.z slot 0: nb_vert][slot 1: nb_vert];
+// partial-sum layout in pcg_part: [d.q of the row blocks: nb_rows][r.z slot 0][r.z slot 1], an
+// r.z slot holding nb_vert vertex-block partials then one per heavy row (n + 1 room);
 // the pair blocks' d.(H_c d) partials live in pcg_pair
 __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 {
-    return S.pcg_part + S.nb_rows + (size_t)(it & 1) * S.nb_vert;
+    return S.pcg_part + S.nb_rows + (size_t)(it & 1) * ((size_t)S.nb_vert + S.n + 1);
 }
 
 __device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = reduce_partials(rz_slot(S, 0), S.nb_vert);
+        double rz0 = wave_reduce_partials(rz_slot(S, 0), S.nb_vert);
         if (!(rz0 > 0.0)) {
             if (lb == 0 && threadIdx.x == 0) {
                 S.pcg->done = 1;
@@ -168,9 +170,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
             }
             return;
         }
-        if (lb == 0 && threadIdx.x == 0) S.pcg->stop = S.pcg_tol2 * rz0;
+        if (lb == 0 && threadIdx.x == 0) {
+            S.pcg->stop = S.pcg_tol2 * rz0;
+            S.pcg->rzv[1] = rz0;
+        }
     } else {
-        double rz_cur = reduce_partials(rz_slot(S, it - 1), S.nb_vert);
+        double rz_cur = wave_reduce_partials(rz_slot(S, it - 1), S.nb_vert + L.out[s].n_heavy);
         bool conv = rz_cur <= S.pcg->stop;
         if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
             if (lb == 0 && threadIdx.x == 0) {
@@ -181,8 +186,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
             }
             return;
         }
-        double rz_prev = reduce_partials(rz_slot(S, it), S.nb_vert);
+        // r.z of iteration it - 2, kept by block 0 of the previous launch
+        double rz_prev = S.pcg->rzv[(it - 1) & 1];
         beta = rz_cur / rz_prev;
+        if (lb == 0 && threadIdx.x == 0) S.pcg->rzv[it & 1] = rz_cur;
     }
     const R *z = as<R>(S.z);
     const R *dold = as<R>((it & 1) ? S.dB : S.dA);
@@ -223,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     }
 }
 
-// q_i = (K_el d)_i + sum of the incident pairs' (H_p d_p)_i
+// q_i = (K_el d)_i + sum of the incident pairs' (H_p d_p)_i, light rows per wavefront
 template <class R>
 __device__ __forceinline__ void contact_rows(const SceneDev &S, int lb, double qc[3])
 {
@@ -234,38 +241,64 @@ __device__ __forceinline__ void contact_rows(const SceneDev &S, int lb, double q
                      [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
 }
 
+// the same sum for one heavy row, by the whole block
+template <class R>
+__device__ __forceinline__ void contact_row_heavy(const SceneDev &S, int row, double qc[3])
+{
+    const R *Y = as<R>(S.act_y);
+    const int64_t cap = S.act_cap;
+    block_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
+}
+
+// one vertex's update: p += alpha d, r -= alpha q, z = M^-1 r; returns r.z
+template <class R>
+__device__ __forceinline__ double pcg_vertex_update(const SceneDev &S, int i, R alpha, const R *dcur, const double qc[3])
+{
+    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv);
+    R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
+    R ri[3];
+    for (int c = 0; c < 3; ++c) {
+        R qv = (R)((double)q[3 * i + c] + qc[c]);
+        sol[3 * i + c] += alpha * dcur[3 * i + c];
+        ri[c] = r[3 * i + c] - alpha * qv;
+        r[3 * i + c] = ri[c];
+    }
+    double rz = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        R za = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
+        z[3 * i + a] = za;
+        rz += (double)ri[a] * (double)za;
+    }
+    return rz;
+}
+
+// PCG B(it) over [vertex blocks | one block per heavy incidence row]
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     if (S.pcg->done) return;
-    double dq = reduce_partials(S.pcg_part, S.nb_rows) + reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_act));
-    double rz_prev = reduce_partials(rz_slot(S, it - 1), S.nb_vert);
+    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_act));
+    double rz_prev = S.pcg->rzv[it & 1];  // r.z of iteration it - 1, stored by A(it)
     R alpha = (R)(rz_prev / dq);
-    double qc[3] = {0.0, 0.0, 0.0};
-    contact_rows<R>(S, lb, qc);
     const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
-    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv);
-    R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
-    int i = lb * blockDim.x + threadIdx.x;
-    double rz = 0.0;
-    if (i < S.n) {
-        R ri[3];
-        for (int c = 0; c < 3; ++c) {
-            R qv = (R)((double)q[3 * i + c] + qc[c]);
-            sol[3 * i + c] += alpha * dcur[3 * i + c];
-            ri[c] = r[3 * i + c] - alpha * qv;
-            r[3 * i + c] = ri[c];
-        }
-        for (int a = 0; a < 3; ++a) {
-            R za = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
-            z[3 * i + a] = za;
-            rz += (double)ri[a] * (double)za;
-        }
+    if (lb < S.nb_vert) {
+        double qc[3] = {0.0, 0.0, 0.0};
+        contact_rows<R>(S, lb, qc);
+        int i = lb * blockDim.x + threadIdx.x;
+        double rz = 0.0;
+        if (i < S.n && !S.hflag[i]) rz = pcg_vertex_update<R>(S, i, alpha, dcur, qc);
+        rz = block_sum_all(rz);
+        if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
+    } else {
+        int j = lb - S.nb_vert;
+        if (j >= L.out[s].n_heavy) return;
+        int row = S.heavy_rows[j];
+        double qc[3];
+        contact_row_heavy<R>(S, row, qc);
+        if (threadIdx.x == 0) rz_slot(S, it)[S.nb_vert + j] = pcg_vertex_update<R>(S, row, alpha, dcur, qc);
     }
-    rz = block_sum_all(rz);
-    if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
 }
 
 // y = H v for the test hook (v in S.dB, y in S.q), in the PCG's three parts:
@@ -303,12 +336,22 @@ __global__ void __launch_bounds__(kBlock) k_spmv_contact(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    double qc[3] = {0.0, 0.0, 0.0};
-    contact_rows<R>(S, lb, qc);
-    int i = lb * blockDim.x + threadIdx.x;
     R *y = as<R>(S.q);
-    if (i < S.n)
-        for (int c = 0; c < 3; ++c) y[3 * i + c] = (R)((double)y[3 * i + c] + qc[c]);
+    if (lb < S.nb_vert) {
+        double qc[3] = {0.0, 0.0, 0.0};
+        contact_rows<R>(S, lb, qc);
+        int i = lb * blockDim.x + threadIdx.x;
+        if (i < S.n && !S.hflag[i])
+            for (int c = 0; c < 3; ++c) y[3 * i + c] = (R)((double)y[3 * i + c] + qc[c]);
+    } else {
+        int j = lb - S.nb_vert;
+        if (j >= L.out[s].n_heavy) return;
+        int row = S.heavy_rows[j];
+        double qc[3];
+        contact_row_heavy<R>(S, row, qc);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) y[3 * row + c] = (R)((double)y[3 * row + c] + qc[c]);
+    }
 }
 
 // ---- per-vertex kernels ------------------------------------------------------
@@ -470,6 +513,7 @@ __device__ __forceinline__ ScanSel scan_sel(const SceneDev &S, const SceneOut &O
     case kScanEdge: return {S.ht_count[1], S.ht_start[1], (int64_t)1 << S.ht_bits[1]};
     case kScanQuery: return {S.q_count, S.q_off, (int64_t)S.n_pts + S.n_edges};
     case kScanContact: return {S.c_cnt, S.c_ptr, (int64_t)S.n};
+    case kScanHeavy: return {S.hflag, S.heavy_idx, (int64_t)S.n};
     default: return {S.act_flag, S.act_off, (int64_t)O.n_cand};
     }
 }
@@ -538,6 +582,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(Launch one, Launch tiles, i
                 O.n_cand = carry;
         }
         if (which == kScanActive) O.n_act = carry;
+        if (which == kScanHeavy) O.n_heavy = carry;
     }
 }
 
@@ -629,11 +674,11 @@ void launch_hess_apply(Batch &b)
     if (mixed(b)) {
         IPC_LAUNCH(b, k_spmv_pairs<float>, kPhActT, kBlock);
         IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kBlock);
-        IPC_LAUNCH(b, k_spmv_contact<float>, kPhVert, kBlock);
+        IPC_LAUNCH(b, k_spmv_contact<float>, kPhVertH, kBlock);
     } else {
         IPC_LAUNCH(b, k_spmv_pairs<double>, kPhActT, kBlock);
         IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kBlock);
-        IPC_LAUNCH(b, k_spmv_contact<double>, kPhVert, kBlock);
+        IPC_LAUNCH(b, k_spmv_contact<double>, kPhVertH, kBlock);
     }
 }
 
@@ -647,6 +692,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     for (size_t i = 0; i < ns; ++i)
         if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(b.h_out[i].n_act);
     b.set_phase(kPhPcgA, nab);
+    set_heavy_phase(b);
     if (mx)
         IPC_LAUNCH(b, k_pcg_init<float>, kPhVert, kBlock);
     else
@@ -677,9 +723,9 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             if (timed) b.prof_end(kProfPcgA, ev);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)
-                IPC_LAUNCH(b, k_pcg_B<float>, kPhVert, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_B<float>, kPhVertH, kBlock, it);
             else
-                IPC_LAUNCH(b, k_pcg_B<double>, kPhVert, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_B<double>, kPhVertH, kBlock, it);
             if (timed) b.prof_end(kProfPcgB, ev);
         }
         b.read_out();

@@ -260,10 +260,12 @@ void grow_active(Scene &s, int64_t need)
     void *ny = st.get_bytes(12 * (size_t)nc * rs);
     double *npp = st.get<double>((size_t)nblocks(nc) + 1);
     int32_t *nl = st.get<int32_t>(4 * (size_t)nc), *nr = st.get<int32_t>(4 * (size_t)nc);
+    int32_t *nt = st.get<int32_t>(4 * (size_t)nc);
     st.commit();
     for (void *old : {(void *)H.act_idx, (void *)H.act_v, H.act_g, H.act_H, H.act_y, (void *)H.pcg_pair,
-                      (void *)H.c_list, (void *)H.c_row})
+                      (void *)H.c_list, (void *)H.c_row, (void *)H.c_tmp})
         dfree(s, old);
+    H.c_tmp = nt;
     H.act_idx = ni;
     H.act_v = nv;
     H.act_g = ng;
@@ -519,7 +521,12 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     IPC_HIP(hipMemsetAsync(H.c_ptr, 0, sizeof(int32_t) * (n + 1), s.stream));
     for (void **p : {&H.r, &H.z, &H.dA, &H.dB, &H.q, &H.sol}) *p = dalloc_bytes(s, n3 * rs);
     IPC_HIP(hipMemsetAsync(H.sol, 0, n3 * rs, s.stream));
-    H.pcg_part = dalloc<double>(s, (size_t)H.nb_rows + 2 * (size_t)H.nb_vert + 8);
+    H.pcg_part = dalloc<double>(s, (size_t)H.nb_rows + 2 * ((size_t)H.nb_vert + n + 1) + 8);
+    H.hflag = dalloc<int32_t>(s, n + 1);
+    H.heavy_idx = dalloc<int32_t>(s, n + 1);
+    H.heavy_rows = dalloc<int32_t>(s, n + 1);
+    H.hdiag = dalloc<double>(s, 9 * ((size_t)n + 1));
+    IPC_HIP(hipMemsetAsync(H.hflag, 0, sizeof(int32_t) * (n + 1), s.stream));
     H.pcg = dalloc<PcgState>(s, 1);
     IPC_HIP(hipMemsetAsync(H.pcg, 0, sizeof(PcgState), s.stream));
     grow_table(s, 0, 16 * (int64_t)std::max(H.n_tris, 1));
