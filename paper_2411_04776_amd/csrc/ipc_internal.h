@@ -113,8 +113,11 @@ struct SceneDev {
     // candidates: static list and swept list (SoA type, a, b with stride cap)
     int32_t *cand, *cand_sw;
     int64_t cand_cap, sw_cap;
+    int64_t n_sw_prev;             // length of the swept list kept from the previous iteration
     double *cand_d;
     int32_t *act_flag, *act_off;   // active flags of the static list and their exclusive scan
+    int32_t *sw_flag, *sw_off;     // swept pairs whose boxes at x overlap, and their scan
+    int32_t *pt_idx;               // surface point index of a vertex (-1: not on the surface)
     // active pairs
     int32_t *act_idx, *act_v;
     void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG)
@@ -198,6 +201,8 @@ class Scene {
     int step_index = 0;
     std::atomic<bool> busy{false};  // a step, read or hook holds the scene
     int last_pcg_iters = 0;
+    bool sw_ok = false;    // the swept list holds every static pair at the current x
+    int64_t sw_n = 0;      // its length
     SceneOut last{};       // last values read back
 
     // optional per-kernel timing with HIP events
@@ -319,6 +324,10 @@ void launch_assemble(Batch &b);
 // finite, or whose tables or lists cannot grow, gets b.fail set and must be
 // dropped from the phase maps by the caller before the next phase.
 void run_broad_phase(Batch &b, int which);
+// Static candidates at x taken from the swept list of the previous iteration
+// (valid when x moved only along that iteration's segment: every pair whose
+// boxes overlap at x is in it); same predicate, same canonical order.
+void run_static_from_swept(Batch &b);
 void run_narrow_phase(Batch &b);
 void launch_barrier(Batch &b);
 void launch_contact_incidence(Batch &b);
@@ -333,7 +342,8 @@ void set_heavy_phase(Batch &b);  // kPhVertH from the last read-back active-pair
 void run_pinf(Batch &b);
 void launch_hess_apply(Batch &b);  // y (S.q) = H v (S.dB)
 
-enum ScanWhich { kScanTri = 0, kScanEdge = 1, kScanQuery = 2, kScanContact = 3, kScanActive = 4, kScanHeavy = 5 };
+enum ScanWhich { kScanTri = 0, kScanEdge = 1, kScanQuery = 2, kScanContact = 3, kScanActive = 4, kScanHeavy = 5,
+                 kScanSwFilter = 6 };
 // len[s] < 0: scene s sits out; query_sw selects the swept-candidate total
 void segmented_scan(Batch &b, ScanWhich which, PhaseKind tiles, const std::vector<int64_t> &len, int query_sw = 0);
 

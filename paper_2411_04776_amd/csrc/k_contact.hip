@@ -394,12 +394,9 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
                     int4 en = entries[k];
                     if (en.x != ix || en.y != iy || en.z != iz) continue;
                     int b = en.w;
-                    if (KIND == 0) {
-                        if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
-                    } else {
-                        if (b <= qa) continue;
-                        if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
-                    }
+                    if (KIND == 1 && b <= qa) continue;
+                    // box test first: most bucket entries fail it, and it
+                    // needs no index loads
                     bool ov = true;
                     double corner[3];
                     for (int c = 0; c < 3; ++c) {
@@ -410,6 +407,11 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
                     if (!ov) continue;
                     if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
                         continue;
+                    if (KIND == 0) {
+                        if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
+                    } else {
+                        if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
+                    }
                     if (!COUNT && o + count < ocap) {
                         out[o + count] = KIND;
                         out[ocap + o + count] = a_id;
@@ -433,6 +435,50 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
             ob[j + 1] = key;
         }
     }
+}
+
+// Static pairs from the swept list: a swept pair is static at x iff the two
+// primitives' boxes at x (the static boxes, from k_boxes) overlap.
+template <bool COMPACT>
+__global__ void k_sw_filter(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (i >= S.n_sw_prev) return;
+    const int64_t cap = S.sw_cap;
+    int type = S.cand_sw[i], a = S.cand_sw[cap + i], b = S.cand_sw[2 * cap + i];
+    if (COMPACT) {
+        if (S.sw_flag[i]) {
+            int64_t o = S.sw_off[i], oc = S.cand_cap;
+            S.cand[o] = type;
+            S.cand[oc + o] = a;
+            S.cand[2 * oc + o] = b;
+        }
+        return;
+    }
+    const double *abox, *bbox;
+    int ia, NA, NB;
+    if (type == 0) {
+        abox = S.pbox;
+        NA = S.n_pts;
+        ia = S.pt_idx[a];
+        bbox = S.tbox;
+        NB = S.n_tris;
+    } else {
+        abox = S.ebox;
+        NA = S.n_edges;
+        ia = a;
+        bbox = S.ebox;
+        NB = S.n_edges;
+    }
+    bool ov = true;
+    for (int c = 0; c < 3; ++c) {
+        double alo = abox[c * NA + ia], ahi = abox[(3 + c) * NA + ia];
+        double blo = bbox[c * NB + b], bhi = bbox[(3 + c) * NB + b];
+        ov = ov && (alo <= bhi) && (blo <= ahi);
+    }
+    S.sw_flag[i] = ov ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,6 +1057,52 @@ void run_broad_phase(Batch &b, int which)
         b.prof_end(kProfBroad, ev);
         return;
     }
+}
+
+void run_static_from_swept(Batch &b)
+{
+    hipEvent_t ev[2];
+    b.prof_begin(kProfBroad, ev);
+    size_t ns = b.sc.size();
+    if (mixed(b)) {
+        IPC_LAUNCH(b, k_boxes<float>, kPhPts, kBlock, 0, 0);
+        IPC_LAUNCH(b, k_boxes<float>, kPhEdges, kBlock, 1, 0);
+        IPC_LAUNCH(b, k_boxes<float>, kPhTris, kBlock, 2, 0);
+    } else {
+        IPC_LAUNCH(b, k_boxes<double>, kPhPts, kBlock, 0, 0);
+        IPC_LAUNCH(b, k_boxes<double>, kPhEdges, kBlock, 1, 0);
+        IPC_LAUNCH(b, k_boxes<double>, kPhTris, kBlock, 2, 0);
+    }
+    std::vector<int32_t> nb(ns, 0);
+    std::vector<int64_t> len(ns, -1);
+    for (size_t i = 0; i < ns; ++i) {
+        if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
+        Scene &sc = *b.sc[i];
+        nb[i] = nblocks(sc.sw_n);
+        len[i] = sc.sw_n;
+        if (sc.h.n_sw_prev != sc.sw_n) {
+            sc.h.n_sw_prev = sc.sw_n;
+            sc.dev_dirty = true;
+        }
+    }
+    b.upload_views();
+    b.set_phase(kPhCandSw, nb);
+    IPC_LAUNCH(b, k_sw_filter<false>, kPhCandSw, kBlock);
+    segmented_scan(b, kScanSwFilter, kPhTilesQ, len);
+    b.read_out();
+    for (size_t i = 0; i < ns; ++i) {
+        if (len[i] < 0) continue;
+        try {
+            grow_candidates(*b.sc[i], 0, b.h_out[i].n_cand);
+        } catch (const OomError &) {
+            b.fail[i] = IPC_E_OOM;
+            nb[i] = 0;
+        }
+    }
+    b.upload_views();
+    b.set_phase(kPhCandSw, nb);
+    IPC_LAUNCH(b, k_sw_filter<true>, kPhCandSw, kBlock);
+    b.prof_end(kProfBroad, ev);
 }
 
 // distances of the static candidates; active = d < dhat, compacted

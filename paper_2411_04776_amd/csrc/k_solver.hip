@@ -514,6 +514,7 @@ __device__ __forceinline__ ScanSel scan_sel(const SceneDev &S, const SceneOut &O
     case kScanQuery: return {S.q_count, S.q_off, (int64_t)S.n_pts + S.n_edges};
     case kScanContact: return {S.c_cnt, S.c_ptr, (int64_t)S.n};
     case kScanHeavy: return {S.hflag, S.heavy_idx, (int64_t)S.n};
+    case kScanSwFilter: return {S.sw_flag, S.sw_off, S.n_sw_prev};
     default: return {S.act_flag, S.act_off, (int64_t)O.n_cand};
     }
 }
@@ -583,6 +584,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(Launch one, Launch tiles, i
         }
         if (which == kScanActive) O.n_act = carry;
         if (which == kScanHeavy) O.n_heavy = carry;
+        if (which == kScanSwFilter) O.n_cand = carry;
     }
 }
 

@@ -230,8 +230,8 @@ void grow_candidates(Scene &s, int which, int64_t need)
     Staged st(s);
     int32_t *nb = st.get<int32_t>(3 * (size_t)nc);
     double *nd = which ? nullptr : st.get<double>(nc);
-    int32_t *nf = which ? nullptr : st.get<int32_t>(nc + 1);
-    int32_t *no = which ? nullptr : st.get<int32_t>(nc + 1);
+    int32_t *nf = st.get<int32_t>(nc + 1);
+    int32_t *no = st.get<int32_t>(nc + 1);
     ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max({H.cand_cap, H.sw_cap, nc}));
     st.commit();
     dfree(s, buf);
@@ -244,6 +244,11 @@ void grow_candidates(Scene &s, int which, int64_t need)
         H.cand_d = nd;
         H.act_flag = nf;
         H.act_off = no;
+    } else {
+        dfree(s, H.sw_flag);
+        dfree(s, H.sw_off);
+        H.sw_flag = nf;
+        H.sw_off = no;
     }
     s.dev_dirty = true;
 }
@@ -511,6 +516,12 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.ev = upload(s, ev);
     H.trv = upload(s, trv);
     H.surf_verts = upload(s, s.h_surf_verts);
+    {
+        std::vector<int32_t> pidx(n, -1);
+        for (size_t k = 0; k < s.h_pts.size(); ++k) pidx[s.h_pts[k]] = (int32_t)k;
+        H.pt_idx = upload(s, pidx);
+        IPC_HIP(hipStreamSynchronize(s.stream));
+    }
     H.edge_rest_sq = upload(s, ers);
     H.pbox = dalloc<double>(s, 6 * (size_t)std::max(H.n_pts, 1));
     H.ebox = dalloc<double>(s, 6 * (size_t)std::max(H.n_edges, 1));
@@ -784,8 +795,30 @@ static void drop_failed(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t
 static void assemble_round(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on, double *ms)
 {
     auto t0 = Clock::now();
+    // static candidates: filtered from the kept swept list where that list is
+    // valid at x, else a hash query
+    size_t ns = b.sc.size();
+    std::vector<uint8_t> on_q(ns, 0), on_f(ns, 0);
+    bool any_q = false, any_f = false;
+    for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;
+        if (b.sc[i]->sw_ok) {
+            on_f[i] = 1;
+            any_f = true;
+        } else {
+            on_q[i] = 1;
+            any_q = true;
+        }
+    }
+    if (any_q) {
+        activate(b, on_q);
+        run_broad_phase(b, 0);
+    }
+    if (any_f) {
+        activate(b, on_f);
+        run_static_from_swept(b);
+    }
     activate(b, on);
-    run_broad_phase(b, 0);
     drop_failed(b, ctl, on);
     run_narrow_phase(b);
     drop_failed(b, ctl, on);
@@ -842,6 +875,13 @@ static void newton_round(Batch &b, std::vector<StepCtl> &ctl)
         run_ccd(b);
         run_energy(b, false);
         b.read_out();
+        for (size_t i = 0; i < ns; ++i)
+            if (ls[i]) {
+                // x only moves along [x, x + p] from here on, so this list
+                // keeps every static pair of the next iterate
+                b.sc[i]->sw_ok = true;
+                b.sc[i]->sw_n = b.h_out[i].n_sw;
+            }
         ms[3] += ms_since(t0);
         t0 = Clock::now();
         for (size_t i = 0; i < ns; ++i)
@@ -938,6 +978,7 @@ static void end_steps(Batch &b, const std::vector<uint8_t> &on, std::vector<Step
         if (!on[i]) continue;
         if (ctl[i].failed) {
             Scene &s = *b.sc[i];
+            s.sw_ok = false;
             IPC_HIP(hipMemcpyAsync(s.h.x, s.h.xt, sizeof(double) * 3 * s.h.n, hipMemcpyDeviceToDevice, b.stream));
         } else {
             ok[i] = 1;
@@ -1324,12 +1365,14 @@ struct HookState {
     Scene &s;
     explicit HookState(Scene &sc, const double *x) : s(sc)
     {
+        s.sw_ok = false;  // hooks move x and rebuild the swept list
         size_t b = sizeof(double) * 3 * s.h.n;
         IPC_HIP(hipMemcpyAsync(s.xsave, s.h.x, b, hipMemcpyDeviceToDevice, s.stream));
         if (x) IPC_HIP(hipMemcpyAsync(s.h.x, x, b, hipMemcpyHostToDevice, s.stream));
     }
     ~HookState()
     {
+        s.sw_ok = false;
         (void)hipMemcpyAsync(s.h.x, s.xsave, sizeof(double) * 3 * s.h.n, hipMemcpyDeviceToDevice, s.stream);
         (void)hipStreamSynchronize(s.stream);
     }
@@ -1466,6 +1509,7 @@ int32_t ipc_reset(ipc_scene *s)
         IPC_HIP(hipStreamSynchronize(s->stream));
         set_pose(*s, s->pose0);
         s->step_index = 0;
+        s->sw_ok = false;
         return IPC_OK;
     });
     s->busy = false;
@@ -1518,6 +1562,7 @@ int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes)
         IPC_HIP(hipMemcpyAsync(s->h.v, p + b, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
         s->step_index = (int)hdr[2];
+        s->sw_ok = false;
         return IPC_OK;
     });
     s->busy = false;
@@ -1882,6 +1927,7 @@ int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v)
         if (x) IPC_HIP(hipMemcpyAsync(s->h.x, x, b, hipMemcpyHostToDevice, s->stream));
         if (v) IPC_HIP(hipMemcpyAsync(s->h.v, v, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
+        if (x) s->sw_ok = false;
         return IPC_OK;
     IPC_HOOK_END(s)
 }
