@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("gravity", C.c_double * 3), ("ccd_s", C.c_double), ("ls_min_ratio", C.c_double),
         ("self_contact", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32),
+        ("mu_fric", C.c_double), ("eps_v", C.c_double),
     ]
 
 
@@ -106,6 +107,11 @@ def lib():
                                        _D, _D]
         L.ora_accd.restype = C.c_double
         L.ora_accd.argtypes = [C.c_int32, _D, _D, C.c_double, C.c_double, C.c_int32]
+        L.ora_friction_f.argtypes = [C.c_double, C.c_double, _D]
+        L.ora_pair_friction.restype = C.c_double
+        L.ora_pair_friction.argtypes = [_D, _D, _D, _D, C.c_double, C.c_double, _D, _D]
+        L.ora_friction_set.restype = C.c_int32
+        L.ora_friction_set.argtypes = [C.c_void_p, _I, _D, _D, _D]
     return _lib
 
 
@@ -208,6 +214,22 @@ def accd(kind, x12, p12, s=0.1, tmax=1.0, max_iter=10000):
     return lib().ora_accd(kind, _d(f64(x12)), _d(f64(p12)), s, tmax, max_iter)
 
 
+def friction_f(y, eps):
+    """(f0, f0', f0'') of the friction smoothing at y for length eps."""
+    f = np.zeros(3)
+    lib().ora_friction_f(float(y), float(eps), _d(f))
+    return f
+
+
+def pair_friction(x12, xt12, c4, nrm, mu_lam, eps):
+    """Lagged friction energy of one pair, its gradient (12) and PSD Hessian (12x12)."""
+    g = np.zeros(12)
+    H = np.zeros(144)
+    D = lib().ora_pair_friction(_d(f64(x12)), _d(f64(xt12)), _d(f64(c4)), _d(f64(nrm)), float(mu_lam),
+                                float(eps), _d(g), _d(H))
+    return D, g, H.reshape(12, 12)
+
+
 # ---------------------------------------------------------------------------
 # scene-level
 # ---------------------------------------------------------------------------
@@ -227,6 +249,9 @@ def default_params(scene, pcg_tol=1e-12, **kw) -> Params:
     p.max_newton = 100
     p.pcg_max_iter = 0
     p.ccd_max_iter = 10000
+    meta = scene.meta or {}
+    p.mu_fric = float(meta.get("mu", 0.0))
+    p.eps_v = float(meta.get("eps_v", 1e-3))
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -276,6 +301,16 @@ class OracleScene:
         mass = np.zeros(self.n)
         lib().ora_scene_rest(self.ptr, _d(vol), _d(mass))
         return vol, mass
+
+    def friction_set(self):
+        """Lagged friction pairs of the current step: (v4, c4, normal, lambda)."""
+        n = lib().ora_friction_set(self.ptr, None, None, None, None)
+        v4 = np.zeros((max(n, 1), 4), dtype=np.int32)
+        c4 = np.zeros((max(n, 1), 4))
+        nrm = np.zeros((max(n, 1), 3))
+        lam = np.zeros(max(n, 1))
+        lib().ora_friction_set(self.ptr, _i(v4), _d(c4), _d(nrm), _d(lam))
+        return v4[:n], c4[:n], nrm[:n], lam[:n]
 
     @property
     def x(self):

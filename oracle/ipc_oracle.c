@@ -735,6 +735,12 @@ struct ora_scene {
     double *x, *v;
     /* step context */
     double *xt, *xtilde, *yhat; /* yhat: 3 per vertex, meaningful for indenter vertices */
+    /* lagged friction set of the step (pairs active at x^t) */
+    int n_fric;
+    int32_t *fric_v;  /* 4 per pair */
+    double *fric_c;   /* 4 per pair: closest-point coefficients at x^t */
+    double *fric_nrm; /* 3 per pair: unit contact normal at x^t */
+    double *fric_lam; /* normal-force magnitude at x^t */
 };
 
 typedef struct {
@@ -967,6 +973,7 @@ void ora_scene_destroy(ora_scene *s)
     free(s->Bm); free(s->vol); free(s->mass);
     free(s->pts); free(s->edges); free(s->tris); free(s->edge_rest_sq);
     free(s->x); free(s->v); free(s->xt); free(s->xtilde); free(s->yhat);
+    free(s->fric_v); free(s->fric_c); free(s->fric_nrm); free(s->fric_lam);
     free(s);
 }
 
@@ -1003,6 +1010,7 @@ void ora_reset(ora_scene *s)
     memcpy(s->xt, s->X, sizeof(double) * 3 * s->n);
     memcpy(s->xtilde, s->X, sizeof(double) * 3 * s->n);
     memcpy(s->yhat, s->X, sizeof(double) * 3 * s->n);
+    s->n_fric = 0;
 }
 
 /* ======================================================================== */
@@ -1160,6 +1168,8 @@ void ora_candidate_distances(const ora_scene *s, const double *x, int32_t nc, co
  * (backward Euler incremental potential divided by h^2; barrier unsquared).
  * Summed with Neumaier compensation in the order: vertices, tets, indenter
  * vertices, candidates. */
+static double friction_energy(const ora_scene *s, const double *x);
+
 static double energy_with(const ora_scene *s, const double *x, const ivec *cand)
 {
     nsum acc = {0.0, 0.0};
@@ -1201,6 +1211,7 @@ static double energy_with(const ora_scene *s, const double *x, const ivec *cand)
         }
         nsum_add(&acc, s->prm.kappa * w * b3[0]);
     }
+    if (s->n_fric) nsum_add(&acc, friction_energy(s, x));
     return nsum_get(&acc);
 }
 
@@ -1214,6 +1225,139 @@ double ora_energy(ora_scene *s, const double *x)
 }
 
 /* ======================================================================== */
+/* lagged friction                                                           */
+/* ======================================================================== */
+/* Frictional contact as in IPC (Li et al. 2020): the dissipative potential
+ * D(x) = sum_c mu lambda_c f0(|u_c|) with one lag per step. For every pair
+ * active at x^t, lambda_c = kappa w |b'(d)| (the barrier's normal force there,
+ * EE mollifier w held fixed), the coefficients c_k of the closest points (the
+ * residual r = sum_k c_k x_k whose length is d) and the unit normal n = r / d
+ * are frozen; the tangential relative displacement is
+ *   u_c = (I - n n^T) sum_k c_k (x_k - x^t_k),
+ * and f0 is IPC's C1 smoothing of |u| over the length e = eps_v h:
+ *   f0(y) = -y^3 / (3 e^2) + y^2 / e + e / 3 for y < e, y otherwise.
+ * Its Hessian is (c c^T) (x) M with M = (f1 / y)(P - uu^T/y^2) + f1' uu^T/y^2
+ * (P = I - nn^T), positive semi-definite (both scalars >= 0); at y = 0 the
+ * limit M = (2 / e) P. */
+
+void ora_friction_f(double y, double eps, double *f3)
+{
+    if (y < eps) {
+        f3[0] = -y * y * y / (3.0 * eps * eps) + y * y / eps + eps / 3.0;
+        f3[1] = -y * y / (eps * eps) + 2.0 * y / eps;
+        f3[2] = -2.0 * y / (eps * eps) + 2.0 / eps;
+    } else {
+        f3[0] = y;
+        f3[1] = 1.0;
+        f3[2] = 0.0;
+    }
+}
+
+double ora_pair_friction(const double *x12, const double *xt12, const double *c4, const double *nrm,
+                         double mu_lam, double eps, double *g12, double *H144)
+{
+    double r[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 3; ++i) r[i] += c4[k] * (x12[3 * k + i] - xt12[3 * k + i]);
+    double rn = dot3(r, nrm);
+    double u[3];
+    for (int i = 0; i < 3; ++i) u[i] = r[i] - rn * nrm[i];
+    double y = sqrt(dot3(u, u));
+    double f[3];
+    ora_friction_f(y, eps, f);
+    /* f1(y) / y, finite at y = 0 */
+    double f1y = y < eps ? 2.0 / eps - y / (eps * eps) : 1.0 / y;
+    if (g12)
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < 3; ++i) g12[3 * k + i] = mu_lam * c4[k] * f1y * u[i];
+    if (H144) {
+        double M[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double P = (i == j ? 1.0 : 0.0) - nrm[i] * nrm[j];
+                if (y > 0.0) {
+                    double uu = u[i] * u[j] / (y * y);
+                    double f2 = f[2] > 0.0 ? f[2] : 0.0;
+                    M[3 * i + j] = f1y * (P - uu) + f2 * uu;
+                } else {
+                    M[3 * i + j] = (2.0 / eps) * P;
+                }
+            }
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l)
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        H144[(3 * k + i) * 12 + 3 * l + j] = mu_lam * c4[k] * c4[l] * M[3 * i + j];
+    }
+    return mu_lam * f[0];
+}
+
+/* the friction set of a step: every static candidate active at x^t */
+static void friction_lag(ora_scene *s)
+{
+    free(s->fric_v); free(s->fric_c); free(s->fric_nrm); free(s->fric_lam);
+    s->fric_v = NULL; s->fric_c = NULL; s->fric_nrm = NULL; s->fric_lam = NULL;
+    s->n_fric = 0;
+    if (!(s->prm.mu_fric > 0.0)) return;
+    ivec cand = {0, 0, 0};
+    candidates_list(s, s->xt, NULL, &cand);
+    int nc = cand.n / 3;
+    s->fric_v = (int32_t *)malloc(sizeof(int32_t) * 4 * (nc + 1));
+    s->fric_c = (double *)malloc(sizeof(double) * 4 * (nc + 1));
+    s->fric_nrm = (double *)malloc(sizeof(double) * 3 * (nc + 1));
+    s->fric_lam = (double *)malloc(sizeof(double) * (nc + 1));
+    for (int i = 0; i < nc; ++i) {
+        const int32_t *c = cand.v + 3 * i;
+        int32_t v[4];
+        double x12[12];
+        cand_verts(s, c, v);
+        gather12(s->xt, v, x12);
+        dist_spec sp = c[0] == 0 ? pt_spec(pt_type(x12)) : ee_spec(ee_type(x12));
+        double r[3], cc[4], uu[2][3], G[2][2];
+        dist_solve(&sp, x12, r, cc, uu, G);
+        double d = sqrt(dot3(r, r));
+        if (!(d < s->prm.dhat) || !(d > 0.0)) continue;
+        double b3[3];
+        ora_barrier_scalar(d, s->prm.dhat, b3);
+        double w = 1.0;
+        if (c[0] == 1) {
+            double m3[3];
+            mollifier(ee_cross_sq(x12, NULL, NULL), cand_eps_x(s, c), m3);
+            w = m3[0];
+        }
+        int k = s->n_fric++;
+        memcpy(s->fric_v + 4 * k, v, sizeof v);
+        memcpy(s->fric_c + 4 * k, cc, sizeof cc);
+        for (int j = 0; j < 3; ++j) s->fric_nrm[3 * k + j] = r[j] / d;
+        s->fric_lam[k] = s->prm.kappa * w * fabs(b3[1]);
+    }
+    free(cand.v);
+}
+
+int32_t ora_friction_set(const ora_scene *s, int32_t *v4, double *c4, double *nrm, double *lam)
+{
+    if (v4) memcpy(v4, s->fric_v, sizeof(int32_t) * 4 * s->n_fric);
+    if (c4) memcpy(c4, s->fric_c, sizeof(double) * 4 * s->n_fric);
+    if (nrm) memcpy(nrm, s->fric_nrm, sizeof(double) * 3 * s->n_fric);
+    if (lam) memcpy(lam, s->fric_lam, sizeof(double) * s->n_fric);
+    return s->n_fric;
+}
+
+static double friction_energy(const ora_scene *s, const double *x)
+{
+    nsum acc = {0.0, 0.0};
+    double eps = s->prm.eps_v * s->prm.h;
+    for (int k = 0; k < s->n_fric; ++k) {
+        double x12[12], xt12[12];
+        gather12(x, s->fric_v + 4 * k, x12);
+        gather12(s->xt, s->fric_v + 4 * k, xt12);
+        nsum_add(&acc, ora_pair_friction(x12, xt12, s->fric_c + 4 * k, s->fric_nrm + 3 * k,
+                                         s->prm.mu_fric * s->fric_lam[k], eps, NULL, NULL));
+    }
+    return nsum_get(&acc);
+}
+
+/* ======================================================================== */
 /* assembly: gradient, element Hessians, contact Hessians                   */
 /* ======================================================================== */
 
@@ -1222,8 +1366,9 @@ typedef struct {
     double *g;     /* 3n */
     double *Hel;   /* 144 per tet */
     int n_c;
-    int32_t *cv;   /* 4 vertex ids per active contact */
-    double *Hc;    /* 144 per active contact */
+    int32_t *cv;   /* 4 vertex ids per active contact, then per friction pair */
+    double *Hc;    /* 144 per active contact, then per friction pair */
+    int n_f;       /* friction pairs (after the n_c contacts) */
     double *diag;  /* 9 per vertex: block diagonal of H */
     int n_cand;
 } assembly;
@@ -1272,8 +1417,8 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
     candidates_list(s, x, NULL, &cand);
     A->n_cand = cand.n / 3;
     A->n_c = 0;
-    A->cv = (int32_t *)malloc(sizeof(int32_t) * 4 * (A->n_cand + 1));
-    A->Hc = (double *)malloc(sizeof(double) * 144 * (A->n_cand + 1));
+    A->cv = (int32_t *)malloc(sizeof(int32_t) * 4 * (A->n_cand + s->n_fric + 1));
+    A->Hc = (double *)malloc(sizeof(double) * 144 * (A->n_cand + s->n_fric + 1));
     for (int i = 0; i < A->n_cand; ++i) {
         const int32_t *c = cand.v + 3 * i;
         int32_t v[4];
@@ -1296,6 +1441,27 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
         A->n_c++;
     }
     free(cand.v);
+    /* lagged friction pairs */
+    A->n_f = 0;
+    double eps = s->prm.eps_v * s->prm.h;
+    for (int k = 0; k < s->n_fric; ++k) {
+        const int32_t *v = s->fric_v + 4 * k;
+        double x12[12], xt12[12], g12[12];
+        gather12(x, v, x12);
+        gather12(s->xt, v, xt12);
+        int slot = A->n_c + A->n_f;
+        double *H = A->Hc + 144 * slot;
+        ora_pair_friction(x12, xt12, s->fric_c + 4 * k, s->fric_nrm + 3 * k, s->prm.mu_fric * s->fric_lam[k], eps,
+                          g12, H);
+        memcpy(A->cv + 4 * slot, v, sizeof(int32_t) * 4);
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) A->g[3 * v[a] + c] += g12[3 * a + c];
+        for (int a = 0; a < 4; ++a)
+            for (int ii = 0; ii < 3; ++ii)
+                for (int jj = 0; jj < 3; ++jj)
+                    A->diag[9 * v[a] + 3 * ii + jj] += H[(3 * a + ii) * 12 + 3 * a + jj];
+        A->n_f++;
+    }
     /* Dirichlet: zero gradient, identity diagonal block */
     for (int i = 0; i < n; ++i)
         if (s->fixed[i]) {
@@ -1327,7 +1493,7 @@ static void hess_apply(const ora_scene *s, const assembly *A, const double *v, d
             }
         }
     }
-    for (int k = 0; k < A->n_c; ++k) {
+    for (int k = 0; k < A->n_c + A->n_f; ++k) {
         const int32_t *cv = A->cv + 4 * k;
         const double *H = A->Hc + 144 * k;
         for (int a = 0; a < 4; ++a) {
@@ -1495,6 +1661,7 @@ void ora_begin_step(ora_scene *s, const double *pose)
         apply_pose(pose, s->Yloc + 3 * j, s->yhat + 3 * (s->n_gel + j));
         for (int c = 0; c < 3; ++c) s->xtilde[3 * (s->n_gel + j) + c] = s->x[3 * (s->n_gel + j) + c];
     }
+    friction_lag(s);
 }
 
 /* One projected-Newton iteration of the incremental potential:

@@ -41,6 +41,8 @@ typedef struct ora_params {
     int32_t max_newton;
     int32_t pcg_max_iter;       /* 0: 10 * (3 n) */
     int32_t ccd_max_iter;
+    double mu_fric;             /* friction coefficient (0: no friction) */
+    double eps_v;               /* friction velocity threshold (m/s); the smoothing length is eps_v h */
 } ora_params;
 
 typedef struct ora_stats {
@@ -123,6 +125,16 @@ double ora_pair_barrier(int32_t kind, const double *x12, double dhat, double kap
                         int32_t project, double *g12, double *H144);
 double ora_accd(int32_t kind, const double *x12, const double *p12, double s, double tmax,
                 int32_t max_iter);
+/* Friction smoothing: f3 = {f0(y), f0'(y), f0''(y)} for the smoothing length eps. */
+void ora_friction_f(double y, double eps, double *f3);
+/* One lagged friction pair: contact coefficients c4 and unit normal nrm from
+ * x^t (xt12), normal-force magnitude folded into mu_lam = mu * lambda.
+ * Returns D; g12 / H144 (PSD) may be NULL. */
+double ora_pair_friction(const double *x12, const double *xt12, const double *c4, const double *nrm,
+                         double mu_lam, double eps, double *g12, double *H144);
+/* Lagged friction set of the current step: count, and per pair (when the
+ * arrays are not NULL) 4 vertex ids, 4 coefficients, the normal, lambda. */
+int32_t ora_friction_set(const ora_scene *s, int32_t *v4, double *c4, double *nrm, double *lam);
 
 #ifdef __cplusplus
 }

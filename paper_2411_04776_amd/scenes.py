@@ -413,3 +413,16 @@ def tiny_scene(grid=(4, 4, 3), radius=2e-3, subdiv=1, depth=0.3e-3, steps=3, dt=
     poses = _descent_poses(np.eye(3), Y, size[2], (size[0] / 2, size[1] / 2), depth, steps)
     return Scene(f"tiny_{grid[0]}x{grid[1]}x{grid[2]}", X, T, fixed, Y, F, poses, dt=dt,
                  self_contact=self_contact)
+
+
+def tiny_slide_scene(mu: float = 0.5, eps_v: float = 1e-3, grid=(6, 5, 4), press_steps=3, slide_steps=4,
+                     slide=0.4e-3) -> Scene:
+    """A small gel pressed 0.3 mm by an icosphere that then slides along +x
+    (lagged friction with coefficient mu, velocity threshold eps_v)."""
+    size = (0.004, 0.004, 0.002)
+    X, T, fixed = grid_gel(*grid, size=size)
+    Y, F = icosphere(2, 1.5e-3)
+    poses = _descent_poses(np.eye(3), Y, size[2], (size[0] / 2 - 0.2e-3, size[1] / 2), 0.3e-3, press_steps,
+                           extra=((1, 0, 0), slide, slide_steps))
+    return Scene(f"tiny_slide_mu{mu}", X, T, fixed, Y, F, poses, dt=1e-2, meta={"mu": mu, "eps_v": eps_v})
+
