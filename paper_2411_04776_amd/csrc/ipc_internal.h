@@ -42,7 +42,7 @@ constexpr int kBlock = 256;       // threads per block for streaming kernels
 constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
 constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
-constexpr int kHeavyRow = 64;     // incidence rows longer than this get a block of their own
+constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
 
 // kernels timed by the optional profiler
 enum ProfKernel {
@@ -75,6 +75,8 @@ struct SceneOut {
     int32_t infeasible;   // energy: a tet with J <= 0 or a pair with d <= 0
     int32_t pcg_done, pcg_iters;
     int32_t n_heavy;      // incidence rows with more than kHeavyRow entries
+    int32_t n_pair;       // pairs in the active arrays: n_act barrier pairs, then the friction pairs
+    int32_t pad2;
     double pinf;          // max |p| over free DOFs
     double alpha_ccd;
     double energy;
@@ -89,6 +91,7 @@ struct SceneDev {
     int n, n_gel, n_ind, m, n_pts, n_edges, n_tris, n_slices, n_slots, n_surf;
     int self_contact, ccd_max_iter, precision, nb_vert, nb_rows, pcg_maxit;
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
+    double mu_fric, eps_fric;  // friction coefficient, smoothing length eps_v h
     double pose[12];
     double alpha;      // line-search trial step
     // state (FP64)
@@ -123,6 +126,12 @@ struct SceneDev {
     void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG)
     int64_t act_cap;
     double *pcg_pair;              // per-block d.(H_c d) partials of the pair blocks
+    // lagged friction set of the step (pairs active at x^t): 4 vertex ids,
+    // closest-point coefficients, unit normal, normal-force magnitude
+    int32_t *fric_v;
+    double *fric_c, *fric_nrm, *fric_lam;
+    int64_t fric_cap;
+    int32_t n_fric;
     int32_t *c_ptr, *c_cnt, *c_list, *c_row, *c_tmp;
     int32_t *hflag, *heavy_idx, *heavy_rows;  // heavy incidence rows: flag, index (scan), list
     double *hdiag;                            // 9 contact diagonal sums per heavy row
@@ -259,6 +268,7 @@ enum PhaseKind {
     kPhAct,       // active pairs, one 64-thread block each
     kPhActT,      // active pairs, kBlock threads
     kPhEnt,       // incidence entries (4 per active pair), kBlock threads
+    kPhFric,      // friction pairs, kBlock threads
     kPhVertH,     // vertex blocks, then one block per heavy incidence row
     kPhOne,       // one block per scene
     kPhTilesT, kPhTilesE, kPhTilesQ, kPhTilesC, kPhTilesA,  // scan tiles
@@ -330,6 +340,10 @@ void run_broad_phase(Batch &b, int which);
 void run_static_from_swept(Batch &b);
 void run_narrow_phase(Batch &b);
 void launch_barrier(Batch &b);
+// friction set from the active pairs at x^t (after the narrow phase at x^t)
+void launch_friction_lag(Batch &b);
+// friction pairs appended after the barrier pairs, then n_pair for every scene
+void launch_friction(Batch &b);
 void launch_contact_incidence(Batch &b);
 void run_ccd(Batch &b);
 void run_energy(Batch &b, bool trial);
@@ -352,5 +366,8 @@ void mark_dirty(Scene &s);
 void grow_table(Scene &s, int table, int64_t entries);
 void grow_candidates(Scene &s, int which, int64_t need);
 void grow_active(Scene &s, int64_t need);
+void grow_friction(Scene &s, int64_t need);
+// barrier + friction pairs of a scene from its last read-back active-pair count
+inline int64_t pair_count(const Scene &s, const SceneOut &o) { return (int64_t)o.n_act + s.h.n_fric; }
 
 }  // namespace ipcg

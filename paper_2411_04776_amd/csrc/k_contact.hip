@@ -756,7 +756,7 @@ __global__ void k_incidence(Launch L)
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
-    if (k >= L.out[s].n_act) return;
+    if (k >= L.out[s].n_pair) return;
     for (int a = 0; a < 4; ++a) {
         int v = S.act_v[(int64_t)a * S.act_cap + k];
         if (S.fixed[v]) continue;
@@ -796,6 +796,144 @@ __global__ void k_incidence_rank(Launch L)
     int key = S.c_tmp[t], rank = 0;
     for (int u = e0; u < e1; ++u) rank += S.c_tmp[u] < key ? 1 : 0;
     S.c_list[e0 + rank] = key;
+}
+
+// ---------------------------------------------------------------------------
+// lagged friction
+// ---------------------------------------------------------------------------
+// Frictional contact as in IPC, one lag per step: each pair active at x^t
+// keeps its normal-force magnitude lambda = kappa w |b'(d)|, the coefficients
+// c_k of its closest points and the unit normal n = r / d. During the step
+// u = (I - n n^T) sum_k c_k (x_k - x^t_k) and D = mu lambda f0(|u|), f0 being
+// IPC's C1 smoothing of |u| over e = eps_v h. Its Hessian (c c^T) (x) M,
+// M = (f1/y)(P - uu^T/y^2) + f0'' uu^T/y^2, is PSD without projection.
+
+// friction set from the active pairs at x (called with x = x^t)
+__global__ void k_friction_lag(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (k >= L.out[s].n_act) return;
+    const int64_t cap = S.cand_cap, fc = S.fric_cap;
+    int ci = S.act_idx[k];
+    int type = S.cand[ci], a = S.cand[cap + ci], b = S.cand[2 * cap + ci];
+    int v[4];
+    double x12[12];
+    cand_vertices(topo_of(S), type, a, b, v);
+    gather12(S.x, v, x12);
+    DistSpec sp = type == 0 ? c_pt_spec[classify_pt(x12)] : c_ee_spec[classify_ee(x12)];
+    double r[3], c[4], u[2][3], G[3];
+    double d = sqrt(dist_residual(sp, x12, r, c, u, G));
+    double bb[3];
+    barrier3(d, S.dhat, bb);
+    double w = 1.0;
+    if (type == 1) {
+        double eps_x = kMollifier * S.edge_rest_sq[a] * S.edge_rest_sq[b];
+        double ea[3] = {x12[3] - x12[0], x12[4] - x12[1], x12[5] - x12[2]};
+        double eb[3] = {x12[9] - x12[6], x12[10] - x12[7], x12[11] - x12[8]};
+        double cr[3] = {ea[1] * eb[2] - ea[2] * eb[1], ea[2] * eb[0] - ea[0] * eb[2], ea[0] * eb[1] - ea[1] * eb[0]};
+        double cv = d3(cr, cr);
+        if (cv < eps_x) w = -cv * cv / (eps_x * eps_x) + 2.0 * cv / eps_x;
+    }
+    for (int q = 0; q < 4; ++q) {
+        S.fric_v[q * fc + k] = v[q];
+        S.fric_c[q * fc + k] = c[q];
+    }
+    for (int i = 0; i < 3; ++i) S.fric_nrm[i * fc + k] = r[i] / d;
+    S.fric_lam[k] = S.kappa * w * fabs(bb[1]);
+}
+
+// tangential displacement u of friction pair j at x and its length
+__device__ __forceinline__ double fric_u(const SceneDev &S, const double *x, int64_t j, int v[4], double c[4],
+                                         double n[3], double u[3])
+{
+    const int64_t fc = S.fric_cap;
+    double r[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q) {
+        v[q] = S.fric_v[q * fc + j];
+        c[q] = S.fric_c[q * fc + j];
+    }
+    for (int i = 0; i < 3; ++i) n[i] = S.fric_nrm[i * fc + j];
+    for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 3; ++i) r[i] += c[q] * (x[3 * v[q] + i] - S.xt[3 * v[q] + i]);
+    double rn = d3(r, n);
+    for (int i = 0; i < 3; ++i) u[i] = r[i] - rn * n[i];
+    return sqrt(d3(u, u));
+}
+
+// friction pair j as active pair n_act + j: gradient and PSD Hessian at x
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_friction(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int64_t j = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (j >= S.n_fric) return;
+    int v[4];
+    double c[4], n[3], u[3];
+    double y = fric_u(S, S.x, j, v, c, n, u);
+    double e = S.eps_fric, ml = S.mu_fric * S.fric_lam[j];
+    double f1y = y < e ? 2.0 / e - y / (e * e) : 1.0 / y;
+    double f2 = y < e ? -2.0 * y / (e * e) + 2.0 / e : 0.0;
+    double M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double P = (i == k ? 1.0 : 0.0) - n[i] * n[k];
+            if (y > 0.0) {
+                double uu = u[i] * u[k] / (y * y);
+                M[3 * i + k] = f1y * (P - uu) + fmax(f2, 0.0) * uu;
+            } else {
+                M[3 * i + k] = (2.0 / e) * P;
+            }
+        }
+    const int64_t cap = S.act_cap, q = L.out[s].n_act + j;
+    R *act_g = as<R>(S.act_g), *act_H = as<R>(S.act_H);
+    bool fx[4];
+    for (int a = 0; a < 4; ++a) {
+        S.act_v[a * cap + q] = v[a];
+        fx[a] = S.fixed[v[a]] != 0;
+        for (int i = 0; i < 3; ++i) act_g[(int64_t)(3 * a + i) * cap + q] = fx[a] ? R(0) : (R)(ml * c[a] * f1y * u[i]);
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 4; ++b)
+                for (int k = 0; k < 3; ++k) {
+                    double h = (fx[a] || fx[b]) ? 0.0 : ml * c[a] * c[b] * M[3 * i + k];
+                    act_H[(int64_t)((3 * a + i) * 12 + 3 * b + k) * cap + q] = (R)h;
+                }
+}
+
+__global__ void k_set_npair(Launch one)
+{
+    int lb, s = scene_of_block(one, lb);
+    const SceneDev &S = *one.sc[s];
+    if (threadIdx.x == 0) one.out[s].n_pair = one.out[s].n_act + S.n_fric;
+}
+
+// friction energy partials, after the body and barrier partials
+__global__ void __launch_bounds__(kBlock) k_energy_fric(Launch L, Launch body, Launch cont, int trial)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const double *x = trial ? S.xtrial : S.x;
+    int64_t j = (int64_t)lb * blockDim.x + threadIdx.x;
+    double val = 0.0;
+    if (j < S.n_fric) {
+        int v[4];
+        double c[4], n[3], u[3];
+        double y = fric_u(S, x, j, v, c, n, u);
+        double e = S.eps_fric;
+        double f0 = y < e ? -y * y * y / (3.0 * e * e) + y * y / e + e / 3.0 : y;
+        val = S.mu_fric * S.fric_lam[j] * f0;
+    }
+    CSum cs = {val, 0.0};
+    cs = block_csum(cs);
+    if (threadIdx.x == 0) {
+        int off = blocks_of(body, s) + blocks_of(cont, s) + lb;
+        S.red[2 * off] = cs.s;
+        S.red[2 * off + 1] = cs.c;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -918,11 +1056,11 @@ __global__ void k_clear_infeasible(Launch one)
 }
 
 // final compensated sum over the body and contact partials of one scene
-__global__ void k_energy_final(Launch one, Launch body, Launch cont)
+__global__ void k_energy_final(Launch one, Launch body, Launch cont, Launch fric)
 {
     int lb, s = scene_of_block(one, lb);
     const SceneDev &S = *one.sc[s];
-    int nb = blocks_of(body, s) + blocks_of(cont, s);
+    int nb = blocks_of(body, s) + blocks_of(cont, s) + blocks_of(fric, s);
     CSum acc = {0.0, 0.0};
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         CSum t = {S.red[2 * i], S.red[2 * i + 1]};
@@ -1126,7 +1264,7 @@ void run_narrow_phase(Batch &b)
     for (size_t i = 0; i < ns; ++i) {
         if (len[i] < 0) continue;
         try {
-            grow_active(*b.sc[i], b.h_out[i].n_act);
+            grow_active(*b.sc[i], pair_count(*b.sc[i], b.h_out[i]));
         } catch (const OomError &) {
             b.fail[i] = IPC_E_OOM;
             nbk[i] = 0;
@@ -1161,8 +1299,8 @@ void launch_contact_incidence(Batch &b)
     std::vector<int64_t> len(ns, -1);
     for (size_t i = 0; i < ns; ++i) {
         bool on = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
-        na[i] = on ? nblocks(b.h_out[i].n_act) : 0;
-        ne[i] = on ? nblocks(4 * (int64_t)b.h_out[i].n_act) : 0;
+        na[i] = on ? nblocks(pair_count(*b.sc[i], b.h_out[i])) : 0;
+        ne[i] = on ? nblocks(4 * pair_count(*b.sc[i], b.h_out[i])) : 0;
         nz[i] = on ? nblocks((int64_t)b.sc[i]->h.n + 1) : 0;
         len[i] = on ? b.sc[i]->h.n : -1;
     }
@@ -1189,9 +1327,30 @@ void set_heavy_phase(Batch &b)
     for (size_t i = 0; i < ns; ++i) {
         bool on = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
         const SceneDev &H = b.sc[i]->h;
-        nh[i] = on ? H.nb_vert + heavy_bound(b.h_out[i].n_act, H.n) : 0;
+        nh[i] = on ? H.nb_vert + heavy_bound(pair_count(*b.sc[i], b.h_out[i]), H.n) : 0;
     }
     b.set_phase(kPhVertH, nh);
+}
+
+void launch_friction_lag(Batch &b)
+{
+    size_t ns = b.sc.size();
+    std::vector<int32_t> na(ns, 0);
+    for (size_t i = 0; i < ns; ++i)
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) na[i] = nblocks(b.h_out[i].n_act);
+    b.set_phase(kPhActT, na);
+    IPC_LAUNCH(b, k_friction_lag, kPhActT, kBlock);
+}
+
+void launch_friction(Batch &b)
+{
+    b.set_phase(kPhFric, per_scene(b, kPhVert, [](const Scene &s) { return nblocks(s.h.n_fric); }));
+    if (mixed(b))
+        IPC_LAUNCH(b, k_friction<float>, kPhFric, kBlock);
+    else
+        IPC_LAUNCH(b, k_friction<double>, kPhFric, kBlock);
+    one_per_active(b, kPhVert);
+    IPC_LAUNCH(b, k_set_npair, kPhOne, 64);
 }
 
 void run_ccd(Batch &b)
@@ -1228,12 +1387,14 @@ void run_energy(Batch &b, bool trial)
     }
     b.set_phase(kPhCandSw, nb);
     b.set_phase(kPhBody, per_scene(b, kPhVert, [](const Scene &s) { return nblocks((int64_t)s.h.m + s.h.n); }));
+    b.set_phase(kPhFric, per_scene(b, kPhVert, [](const Scene &s) { return nblocks(s.h.n_fric); }));
     one_per_active(b, kPhVert);
     IPC_LAUNCH(b, k_clear_infeasible, kPhOne, 64);
     launch_energy_body(b, trial);
     IPC_LAUNCH(b, k_energy_contact, kPhCandSw, kBlock, b.launch(kPhBody), (int)trial);
+    IPC_LAUNCH(b, k_energy_fric, kPhFric, kBlock, b.launch(kPhBody), b.launch(kPhCandSw), (int)trial);
     one_per_active(b, kPhVert);
-    IPC_LAUNCH(b, k_energy_final, kPhOne, kBlock, b.launch(kPhBody), b.launch(kPhCandSw));
+    IPC_LAUNCH(b, k_energy_final, kPhOne, kBlock, b.launch(kPhBody), b.launch(kPhCandSw), b.launch(kPhFric));
     b.prof_end(kProfEnergy, ev);
 }
 

@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_elastic_elements(Launch L)
 
 // Gradient gather: one thread per vertex; elastic element gradients in
 // vertex-incidence (tet) order, then inertia / kinematic target, then the sum
-// of the vertex's active contact pairs (formed per wavefront). Sums in FP64,
+// of the vertex's active contact pairs in pair order. Sums in FP64,
 // stored in R. A heavy incidence row gets a block of its own after the vertex
 // blocks, which also sums the contact diagonal blocks of that row (hdiag).
 template <class R>
@@ -317,13 +317,11 @@ __global__ void __launch_bounds__(kBlock) k_assemble_gradient(Launch L)
     R *grad = as<R>(S.grad);
     if (lb < S.nb_vert) {
         int i = lb * blockDim.x + threadIdx.x;
-        // contact pairs of the wavefront's 64 (light) rows together
-        double gc[3] = {0.0, 0.0, 0.0};
-        wave_row_sums<3>(S, i - (int)(threadIdx.x % kWave), (int)(threadIdx.x % kWave),
-                         [&](int p, int a, int c) { return (double)ag[(int64_t)(a * 3 + c) * cap + p]; }, gc);
         if (i >= S.n || S.hflag[i]) return;
         double g[3] = {0.0, 0.0, 0.0};
         if (!S.fixed[i]) {
+            double gc[3] = {0.0, 0.0, 0.0};
+            thread_row_sums<3>(S, i, [&](int p, int a, int c) { return (double)ag[(int64_t)(a * 3 + c) * cap + p]; }, gc);
             vertex_gradient<R>(S, i, g);
             for (int c = 0; c < 3; ++c) g[c] += gc[c];
         }
@@ -373,20 +371,21 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
     int k = (int)(slot - S.slice_ptr[lo]);
     int col = S.bcol[slot_lane];
     const R *eH = as<R>(S.eH), *aH = as<R>(S.act_H);
-    // contact diagonal blocks of the slice's 64 rows (slot 0 is the diagonal;
-    // a wavefront is one slot of one slice, so k is uniform over it)
+    // contact diagonal blocks (slot 0 is the diagonal)
     double cd[9];
     for (int c = 0; c < 9; ++c) cd[c] = 0.0;
-    if (k == 0) {
+    if (k == 0 && row < S.n) {
         const int64_t cap = S.act_cap;
-        wave_row_sums<9>(S, lo * kSlice, lane,
-                         [&](int p, int a, int c) {
-                             int i = c / 3, j = c % 3;
-                             return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
-                         },
-                         cd);
-        if (row < S.n && S.hflag[row])  // summed by the row's own block in the gradient kernel
+        if (S.hflag[row]) {  // summed by the row's own block in the gradient kernel
             for (int c = 0; c < 9; ++c) cd[c] = S.hdiag[9 * (int64_t)S.heavy_idx[row] + c];
+        } else {
+            thread_row_sums<9>(S, row,
+                               [&](int p, int a, int c) {
+                                   int i = c / 3, j = c % 3;
+                                   return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
+                               },
+                               cd);
+        }
     }
     double A[9];
     for (int c = 0; c < 9; ++c) A[c] = 0.0;

@@ -109,6 +109,45 @@ __device__ __forceinline__ void bell_row_part(const SceneDev &S, int row, int pa
     y[2] = y2;
 }
 
+// The same row with both vectors applied: yz = A z and yd = A d_prev (when
+// two), so that nothing here waits for beta.
+template <class R>
+__device__ __forceinline__ void bell_row_part2(const SceneDev &S, int row, int part, const R *__restrict__ z,
+                                               const R *__restrict__ dold, bool two, double yz[3], double yd[3])
+{
+    int sl = row / kSlice, lane = row % kSlice;
+    int s0 = S.slice_ptr[sl], s1 = S.slice_ptr[sl + 1];
+    const R *__restrict__ bval = as<R>(S.bval);
+    const int32_t *__restrict__ bcol = S.bcol;
+    R a0 = R(0), a1 = R(0), a2 = R(0), b0 = R(0), b1 = R(0), b2 = R(0);
+#pragma unroll 2
+    for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
+        int col = bcol[(int64_t)slot * kSlice + lane];
+        if (col >= 0) {
+            const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
+            R m[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) m[k] = A[k * kSlice];
+            R v0 = z[3 * col], v1 = z[3 * col + 1], v2 = z[3 * col + 2];
+            a0 += m[0] * v0 + m[1] * v1 + m[2] * v2;
+            a1 += m[3] * v0 + m[4] * v1 + m[5] * v2;
+            a2 += m[6] * v0 + m[7] * v1 + m[8] * v2;
+            if (two) {
+                R w0 = dold[3 * col], w1 = dold[3 * col + 1], w2 = dold[3 * col + 2];
+                b0 += m[0] * w0 + m[1] * w1 + m[2] * w2;
+                b1 += m[3] * w0 + m[4] * w1 + m[5] * w2;
+                b2 += m[6] * w0 + m[7] * w1 + m[8] * w2;
+            }
+        }
+    }
+    yz[0] = a0;
+    yz[1] = a1;
+    yz[2] = a2;
+    yd[0] = b0;
+    yd[1] = b1;
+    yd[2] = b2;
+}
+
 // One active pair: y_a = sum over b != a of H_ab d_b for its four slots
 // (the diagonal blocks live in the BELL diagonal), stored per pair for the
 // row gather; returns sum_a d_a . y_a.
@@ -149,14 +188,27 @@ __device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const
     return dy;
 }
 
-// PCG A(it): stop test and beta from the r.z partials (every block agrees),
-// then either a row block (d = z + beta d_prev for its rows, q = K_el d,
-// d.q partial) or a pair block (H_p d_p per pair, d.(H_c d) partial).
+// PCG A(it): a row block first applies the BELL matrix to z and to d_prev
+// (no scalar needed), then every wavefront reduces the r.z partials, decides
+// the stop and forms beta; the row block finishes d = z + beta d_prev and
+// q = K_el d for its rows, a pair block applies each active pair's
+// off-diagonal blocks to its own four vertices; both write d.q partials.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
+    const R *z = as<R>(S.z);
+    const R *dold = as<R>((it & 1) ? S.dB : S.dA);
+    const bool bon = it > 1;
+    // kLanesPerRow consecutive lanes share a row
+    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    int part = lane % kLanesPerRow;
+    bool rows = lb < S.nb_rows;
+    bool live = rows && row < S.n;
+    double yz[3] = {0.0, 0.0, 0.0}, yd[3] = {0.0, 0.0, 0.0};
+    if (live) bell_row_part2<R>(S, row, part, z, dold, bon, yz, yd);
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
@@ -191,25 +243,18 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
         beta = rz_cur / rz_prev;
         if (lb == 0 && threadIdx.x == 0) S.pcg->rzv[it & 1] = rz_cur;
     }
-    const R *z = as<R>(S.z);
-    const R *dold = as<R>((it & 1) ? S.dB : S.dA);
     R rb = (R)beta;
-    bool bon = it > 1;
     double dq = 0.0;
-    if (lb < S.nb_rows) {
+    if (rows) {
         R *dnew = as<R>((it & 1) ? S.dA : S.dB);
         R *q = as<R>(S.q);
-        // kLanesPerRow consecutive lanes share a row
-        int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-        int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
-        int part = lane % kLanesPerRow;
-        double y[3] = {0.0, 0.0, 0.0};
-        bool live = row < S.n;
-        if (live) bell_row_part<R>(S, row, part, z, dold, rb, bon, y);
+        double y[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
+            y[c] = yz[c] + beta * yd[c];
 #pragma unroll
             for (int o = 1; o < kLanesPerRow; o <<= 1) y[c] += __shfl_xor(y[c], o, kWave);
+        }
         if (live && part == 0) {
             for (int c = 0; c < 3; ++c) {
                 R dv = bon ? z[3 * row + c] + rb * dold[3 * row + c] : z[3 * row + c];
@@ -224,21 +269,19 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     } else {
         int pb = lb - S.nb_rows;
         int64_t p = (int64_t)pb * blockDim.x + threadIdx.x;
-        if (p < L.out[s].n_act) dq = pair_apply<R>(S, p, z, dold, rb, bon);
+        if (p < L.out[s].n_pair) dq = pair_apply<R>(S, p, z, dold, rb, bon);
         dq = block_sum_all(dq);
         if (threadIdx.x == 0) S.pcg_pair[pb] = dq;
     }
 }
 
-// q_i = (K_el d)_i + sum of the incident pairs' (H_p d_p)_i, light rows per wavefront
+// the incident pairs' (H_p d_p)_i of a light row, by one thread
 template <class R>
-__device__ __forceinline__ void contact_rows(const SceneDev &S, int lb, double qc[3])
+__device__ __forceinline__ void contact_row_light(const SceneDev &S, int row, double qc[3])
 {
     const R *Y = as<R>(S.act_y);
     const int64_t cap = S.act_cap;
-    int lane = threadIdx.x % kWave;
-    wave_row_sums<3>(S, lb * blockDim.x + (threadIdx.x - lane), lane,
-                     [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
+    thread_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
 }
 
 // the same sum for one heavy row, by the whole block
@@ -250,45 +293,69 @@ __device__ __forceinline__ void contact_row_heavy(const SceneDev &S, int row, do
     block_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
 }
 
-// one vertex's update: p += alpha d, r -= alpha q, z = M^-1 r; returns r.z
+// one vertex's state for the update, loaded before alpha is known
 template <class R>
-__device__ __forceinline__ double pcg_vertex_update(const SceneDev &S, int i, R alpha, const R *dcur, const double qc[3])
+struct VertexPcg {
+    R q[3], d[3], p[3], r[3], M[9];
+};
+
+template <class R>
+__device__ __forceinline__ void pcg_vertex_load(const SceneDev &S, int i, const R *dcur, VertexPcg<R> &v)
 {
-    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv);
+    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv), *sol = as<R>(S.sol), *r = as<R>(S.r);
+    for (int c = 0; c < 3; ++c) {
+        v.q[c] = q[3 * i + c];
+        v.d[c] = dcur[3 * i + c];
+        v.p[c] = sol[3 * i + c];
+        v.r[c] = r[3 * i + c];
+    }
+    for (int k = 0; k < 9; ++k) v.M[k] = Mi[9 * i + k];
+}
+
+// p += alpha d, r -= alpha q (q = K_el d + contact sum), z = M^-1 r; returns r.z
+template <class R>
+__device__ __forceinline__ double pcg_vertex_update(const SceneDev &S, int i, R alpha, const VertexPcg<R> &v,
+                                                    const double qc[3])
+{
     R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
     R ri[3];
     for (int c = 0; c < 3; ++c) {
-        R qv = (R)((double)q[3 * i + c] + qc[c]);
-        sol[3 * i + c] += alpha * dcur[3 * i + c];
-        ri[c] = r[3 * i + c] - alpha * qv;
+        R qv = (R)((double)v.q[c] + qc[c]);
+        sol[3 * i + c] = v.p[c] + alpha * v.d[c];
+        ri[c] = v.r[c] - alpha * qv;
         r[3 * i + c] = ri[c];
     }
     double rz = 0.0;
     for (int a = 0; a < 3; ++a) {
-        R za = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
+        R za = v.M[3 * a] * ri[0] + v.M[3 * a + 1] * ri[1] + v.M[3 * a + 2] * ri[2];
         z[3 * i + a] = za;
         rz += (double)ri[a] * (double)za;
     }
     return rz;
 }
 
-// PCG B(it) over [vertex blocks | one block per heavy incidence row]
+// PCG B(it) over [vertex blocks | one block per heavy incidence row]: the
+// vertex data and contact sums are loaded first, then alpha from the d.q
+// partials, then the update and the r.z partials.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    if (S.pcg->done) return;
-    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_act));
-    double rz_prev = S.pcg->rzv[it & 1];  // r.z of iteration it - 1, stored by A(it)
-    R alpha = (R)(rz_prev / dq);
     const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
     if (lb < S.nb_vert) {
-        double qc[3] = {0.0, 0.0, 0.0};
-        contact_rows<R>(S, lb, qc);
         int i = lb * blockDim.x + threadIdx.x;
-        double rz = 0.0;
-        if (i < S.n && !S.hflag[i]) rz = pcg_vertex_update<R>(S, i, alpha, dcur, qc);
+        bool own = i < S.n && !S.hflag[i];
+        VertexPcg<R> v;
+        double qc[3] = {0.0, 0.0, 0.0};
+        if (own) {
+            pcg_vertex_load<R>(S, i, dcur, v);
+            contact_row_light<R>(S, i, qc);
+        }
+        if (S.pcg->done) return;
+        double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
+        R alpha = (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
+        double rz = own ? pcg_vertex_update<R>(S, i, alpha, v, qc) : 0.0;
         rz = block_sum_all(rz);
         if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
     } else {
@@ -297,7 +364,15 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
         int row = S.heavy_rows[j];
         double qc[3];
         contact_row_heavy<R>(S, row, qc);
-        if (threadIdx.x == 0) rz_slot(S, it)[S.nb_vert + j] = pcg_vertex_update<R>(S, row, alpha, dcur, qc);
+        if (S.pcg->done) return;
+        // every lane of the wavefront takes part in the partial reductions
+        double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
+        R alpha = (R)(S.pcg->rzv[it & 1] / dq);
+        if (threadIdx.x == 0) {
+            VertexPcg<R> v;
+            pcg_vertex_load<R>(S, row, dcur, v);
+            rz_slot(S, it)[S.nb_vert + j] = pcg_vertex_update<R>(S, row, alpha, v, qc);
+        }
     }
 }
 
@@ -309,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_pairs(Launch L)
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
-    if (p < L.out[s].n_act) (void)pair_apply<R>(S, p, as<R>(S.dB), nullptr, R(0), false);
+    if (p < L.out[s].n_pair) (void)pair_apply<R>(S, p, as<R>(S.dB), nullptr, R(0), false);
 }
 
 template <class R>
@@ -338,11 +413,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv_contact(Launch L)
     const SceneDev &S = *L.sc[s];
     R *y = as<R>(S.q);
     if (lb < S.nb_vert) {
-        double qc[3] = {0.0, 0.0, 0.0};
-        contact_rows<R>(S, lb, qc);
         int i = lb * blockDim.x + threadIdx.x;
-        if (i < S.n && !S.hflag[i])
+        if (i < S.n && !S.hflag[i]) {
+            double qc[3] = {0.0, 0.0, 0.0};
+            contact_row_light<R>(S, i, qc);
             for (int c = 0; c < 3; ++c) y[3 * i + c] = (R)((double)y[3 * i + c] + qc[c]);
+        }
     } else {
         int j = lb - S.nb_vert;
         if (j >= L.out[s].n_heavy) return;
@@ -692,7 +768,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     bool mx = mixed(b);
     std::vector<int32_t> nab(ns, 0);
     for (size_t i = 0; i < ns; ++i)
-        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(b.h_out[i].n_act);
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]));
     b.set_phase(kPhPcgA, nab);
     set_heavy_phase(b);
     if (mx)

@@ -171,10 +171,10 @@ struct Staged {
 
 // reduction / scan scratch sized for hash tables of 2^b0 and 2^b1 buckets and
 // candidate lists of cc entries (only ever grows)
-static void ensure_scratch(Scene &s, int b0, int b1, int64_t cc)
+static void ensure_scratch(Scene &s, int b0, int b1, int64_t cc, int64_t fc)
 {
     SceneDev &H = s.h;
-    int64_t red = std::max({2 * ((int64_t)nblocks((int64_t)H.m + H.n) + nblocks(cc)) + 16,
+    int64_t red = std::max({2 * ((int64_t)nblocks((int64_t)H.m + H.n) + nblocks(cc) + nblocks(fc)) + 16,
                             (int64_t)nblocks(H.n_edges) + nblocks(H.n_tris) + 16, 4 * (int64_t)nblocks(H.n) + 16,
                             (int64_t)nblocks(cc) + 16});
     auto tiles = [](int64_t len) { return (len + kScanTile) / kScanTile + 1; };
@@ -207,7 +207,8 @@ void grow_table(Scene &s, int t, int64_t entries)
     Staged st(s);
     int32_t *cnt = st.get<int32_t>(tsize + 1), *start = st.get<int32_t>(tsize + 1);
     int4 *ent = st.get<int4>((size_t)entries);
-    ensure_scratch(s, t == 0 ? bits : H.ht_bits[0], t == 1 ? bits : H.ht_bits[1], std::max(H.cand_cap, H.sw_cap));
+    ensure_scratch(s, t == 0 ? bits : H.ht_bits[0], t == 1 ? bits : H.ht_bits[1], std::max(H.cand_cap, H.sw_cap),
+                   H.fric_cap);
     st.commit();
     dfree(s, H.ht_count[t]);
     dfree(s, H.ht_start[t]);
@@ -232,7 +233,7 @@ void grow_candidates(Scene &s, int which, int64_t need)
     double *nd = which ? nullptr : st.get<double>(nc);
     int32_t *nf = st.get<int32_t>(nc + 1);
     int32_t *no = st.get<int32_t>(nc + 1);
-    ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max({H.cand_cap, H.sw_cap, nc}));
+    ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max({H.cand_cap, H.sw_cap, nc}), H.fric_cap);
     st.commit();
     dfree(s, buf);
     buf = nb;
@@ -250,6 +251,25 @@ void grow_candidates(Scene &s, int which, int64_t need)
         H.sw_flag = nf;
         H.sw_off = no;
     }
+    s.dev_dirty = true;
+}
+
+void grow_friction(Scene &s, int64_t need)
+{
+    SceneDev &H = s.h;
+    if (H.fric_v && need <= H.fric_cap) return;
+    int64_t nc = need + need / 2 + 256;
+    Staged st(s);
+    int32_t *nv = st.get<int32_t>(4 * (size_t)nc);
+    double *ncf = st.get<double>(4 * (size_t)nc), *nn = st.get<double>(3 * (size_t)nc), *nl = st.get<double>(nc);
+    ensure_scratch(s, H.ht_bits[0], H.ht_bits[1], std::max(H.cand_cap, H.sw_cap), nc);
+    st.commit();
+    for (void *old : {(void *)H.fric_v, (void *)H.fric_c, (void *)H.fric_nrm, (void *)H.fric_lam}) dfree(s, old);
+    H.fric_v = nv;
+    H.fric_c = ncf;
+    H.fric_nrm = nn;
+    H.fric_lam = nl;
+    H.fric_cap = nc;
     s.dev_dirty = true;
 }
 
@@ -481,6 +501,9 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     for (int c = 0; c < 3; ++c) H.grav[c] = s.prm.grav[c];
     H.ccd_s = s.prm.ccd_s;
     H.pcg_tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
+    H.mu_fric = s.prm.mu_fric;
+    H.eps_fric = s.prm.eps_v * s.prm.dt;
+    H.n_fric = 0;
     H.self_contact = s.prm.self_contact;
     H.ccd_max_iter = s.prm.ccd_max_iter;
     H.precision = s.prm.precision;
@@ -547,6 +570,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     grow_candidates(s, 0, 1024);
     grow_candidates(s, 1, 1024);
     grow_active(s, 256);
+    grow_friction(s, s.prm.mu_fric > 0.0 ? 256 : 1);
     H.pcg_maxit = s.prm.pcg_max_iter > 0 ? s.prm.pcg_max_iter : 30 * n;
     s.n_gel_tris = n_gel_tris;
     s.xsave = dalloc<double>(s, n3);
@@ -790,13 +814,32 @@ static void drop_failed(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t
     if (any) activate(b, on);
 }
 
+static void static_candidates(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on);
+
 // g and H at x for the scenes with on[i]: static candidates, active pairs,
 // barrier, incidence, elastic elements, deterministic gather
 static void assemble_round(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on, double *ms)
 {
     auto t0 = Clock::now();
-    // static candidates: filtered from the kept swept list where that list is
-    // valid at x, else a hash query
+    static_candidates(b, ctl, on);
+    run_narrow_phase(b);
+    drop_failed(b, ctl, on);
+    launch_barrier(b);
+    launch_friction(b);
+    launch_contact_incidence(b);
+    IPC_HIP(hipStreamSynchronize(b.stream));
+    ms[1] += ms_since(t0);
+    t0 = Clock::now();
+    launch_elastic_elements(b);
+    launch_assemble(b);
+    IPC_HIP(hipStreamSynchronize(b.stream));
+    ms[0] += ms_since(t0);
+}
+
+// static candidates at x for the scenes with on[i]: filtered from the kept
+// swept list where that list is valid at x, else a hash query
+static void static_candidates(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint8_t> &on)
+{
     size_t ns = b.sc.size();
     std::vector<uint8_t> on_q(ns, 0), on_f(ns, 0);
     bool any_q = false, any_f = false;
@@ -820,17 +863,6 @@ static void assemble_round(Batch &b, std::vector<StepCtl> &ctl, std::vector<uint
     }
     activate(b, on);
     drop_failed(b, ctl, on);
-    run_narrow_phase(b);
-    drop_failed(b, ctl, on);
-    launch_barrier(b);
-    launch_contact_incidence(b);
-    IPC_HIP(hipStreamSynchronize(b.stream));
-    ms[1] += ms_since(t0);
-    t0 = Clock::now();
-    launch_elastic_elements(b);
-    launch_assemble(b);
-    IPC_HIP(hipStreamSynchronize(b.stream));
-    ms[0] += ms_since(t0);
 }
 
 // One Newton iteration for every scene with ctl[i].active.
@@ -959,12 +991,46 @@ static void set_pose(Scene &s, const double *pose)
     s.dev_dirty = true;
 }
 
-// predictor and targets of the scenes with on[i] (poses already set)
-static void begin_steps(Batch &b, const std::vector<uint8_t> &on)
+// predictor and targets of the scenes with on[i] (poses already set), and the
+// lagged friction set at x^t of the scenes with friction
+static void begin_steps(Batch &b, const std::vector<uint8_t> &on, std::vector<StepCtl> &ctl)
 {
     b.upload_views();
     activate(b, on);
     launch_begin_step(b);
+    size_t ns = b.sc.size();
+    std::vector<uint8_t> onf(ns, 0);
+    bool any = false;
+    for (size_t i = 0; i < ns; ++i) {
+        Scene &s = *b.sc[i];
+        if (s.h.n_fric) {
+            s.h.n_fric = 0;
+            s.dev_dirty = true;
+        }
+        if (on[i] && s.prm.mu_fric > 0.0) {
+            onf[i] = 1;
+            any = true;
+        }
+    }
+    b.upload_views();
+    if (!any) return;
+    static_candidates(b, ctl, onf);
+    run_narrow_phase(b);
+    drop_failed(b, ctl, onf);
+    for (size_t i = 0; i < ns; ++i) {
+        if (!onf[i]) continue;
+        Scene &s = *b.sc[i];
+        try {
+            grow_friction(s, b.h_out[i].n_act);
+            s.h.n_fric = b.h_out[i].n_act;
+            s.dev_dirty = true;
+        } catch (const OomError &) {
+            b.fail[i] = IPC_E_OOM;
+        }
+    }
+    drop_failed(b, ctl, onf);
+    b.upload_views();
+    launch_friction_lag(b);
 }
 
 // Commit of the scenes with on[i]: v = (x - x^t)/h, target lag, object
@@ -1022,7 +1088,7 @@ static void step_list(Batch &b, const std::vector<const double *> &poses, std::v
     ctl.assign(ns, StepCtl{});
     for (auto &c : ctl) start_ctl(c);
     std::vector<uint8_t> all(ns, 1);
-    begin_steps(b, all);
+    begin_steps(b, all, ctl);
     for (;;) {
         bool any = false;
         for (auto &c : ctl) any |= c.active;
@@ -1174,7 +1240,7 @@ class Engine {
                 fresh[i] = 1;
                 any_fresh = true;
             }
-        if (any_fresh) begin_steps(l.b, fresh);
+        if (any_fresh) begin_steps(l.b, fresh, l.ctl);
         newton_round(l.b, l.ctl);
         std::vector<uint8_t> fin(ns, 0);
         bool any = false;
@@ -1295,6 +1361,7 @@ static bool check_desc(const ipc_scene_desc *d)
     if (!(d->newton_tol >= 0) || !(d->pcg_tol >= 0) || !(d->k_target >= 0)) return false;
     if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) return false;
     if (d->pcg_max_iter < 0 || d->max_newton < 0 || d->ccd_max_iter < 0) return false;
+    if (!(d->mu_friction >= 0.0) || (d->mu_friction > 0.0 && !(d->eps_v > 0.0))) return false;
     return true;
 }
 
@@ -1510,6 +1577,7 @@ int32_t ipc_reset(ipc_scene *s)
         set_pose(*s, s->pose0);
         s->step_index = 0;
         s->sw_ok = false;
+        s->h.n_fric = 0;
         return IPC_OK;
     });
     s->busy = false;
@@ -1563,6 +1631,8 @@ int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes)
         IPC_HIP(hipStreamSynchronize(s->stream));
         s->step_index = (int)hdr[2];
         s->sw_ok = false;
+        s->h.n_fric = 0;
+        s->dev_dirty = true;
         return IPC_OK;
     });
     s->busy = false;
@@ -1709,8 +1779,15 @@ int32_t ipcx_begin_step(ipc_scene *s, const ipc_step_req *r)
     IPC_HOOK_BEGIN(s)
         Batch &b = solo(*s);
         set_pose(*s, r->pose);
-        begin_steps(b, {1});
+        std::vector<StepCtl> ctl(1);
+        start_ctl(ctl[0]);
+        std::vector<uint8_t> on(1, 1);
+        begin_steps(b, on, ctl);
         IPC_HIP(hipStreamSynchronize(s->stream));
+        if (ctl[0].failed) {
+            set_status_error(ctl[0].status);
+            return ctl[0].status;
+        }
         return IPC_OK;
     IPC_HOOK_END(s)
 }
