@@ -43,6 +43,12 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="scenes of the batched uneven-scene leg (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=4)
+    ap.add_argument("--serve", type=int, default=64, help="environments of the serving leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="only copy a buffer of this many MiB with torch (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -60,6 +66,15 @@ def main():
     from paper_2411_04776_amd import ipc, scenes
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
+        return
     sc = scenes.config2(args.seed)
     g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol)
     for _ in range(args.warmup):
@@ -78,7 +93,8 @@ def main():
         pcg += st.pcg_iters
         active.append(st.n_active)
         print(f"step {g.step_index}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
-              f"active={st.n_active} ms={st.ms_total:.1f}", file=sys.stderr, flush=True)
+              f"active={st.n_active} alpha_ccd={st.alpha_ccd:.3g} halvings={st.ls_halvings} "
+              f"ms={st.ms_total:.1f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -122,10 +138,104 @@ def main():
         "roofline": roofline,
     }
 
+    g.close()
+    if args.batch > 0:
+        line["batch"] = batch_leg(args, ipc, scenes, torch)
+    if args.serve > 0:
+        line["serving"] = serving_leg(args, ipc, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, x_start, v_start, args, newton / args.steps)
 
     print(json.dumps(line), flush=True)
+
+
+def batch_leg(args, ipc, scenes, torch):
+    """Uneven scenes (grid U{12..40}xU{15..50}xU{3..8}, random indenters)
+    stepped together through the continuous-batching engine, mixed precision:
+    every Newton phase is one launch for the whole list. Also the same first
+    16 scenes stepped one at a time (ipc_step) for the batching gain."""
+    rt = ipc.TorchRuntime()
+    t0 = time.perf_counter()
+    scs = [scenes.config3_scene(i) for i in range(args.batch)]
+    gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol) for sc in scs]
+    build_s = time.perf_counter() - t0
+    nv = sum(len(sc.X) for sc in scs)
+    nt = sum(len(sc.T) for sc in scs)
+    eng = ipc.Batch()
+
+    def list_step():
+        tks = eng.submit(gs)
+        newton = 0
+        for t in tks:
+            rc, st = eng.wait(t)
+            if rc < 0:
+                raise RuntimeError(f"batched step failed: {rc}")
+            newton += st.newton_iters
+        return newton
+
+    list_step()  # warm-up: first contact, buffer growth
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = 0
+    for _ in range(args.batch_steps):
+        newton += list_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    eng.close()
+    # the same scenes one at a time, from the same states
+    k = min(16, len(gs))
+    states = [g.save_state() for g in gs[:k]]
+    t0 = time.perf_counter()
+    alone_steps = 0
+    for g in gs[:k]:
+        for _ in range(args.batch_steps):
+            g.step()
+            alone_steps += 1
+    torch.cuda.synchronize()
+    el_alone = time.perf_counter() - t0
+    for g, b in zip(gs[:k], states):
+        g.load_state(b)
+    for g in gs:
+        g.close()
+    steps = args.batch_steps * len(gs)
+    print(f"batch leg: {len(gs)} scenes, {steps} env-steps in {el:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": f"{len(gs)} uneven scenes ({nv} v, {nt} tets in total), seeds 1000-{999 + len(gs)}, "
+                        f"steps 2-{1 + args.batch_steps}, mixed precision, continuous-batching engine",
+            "env_steps_per_s": round(steps / el, 2), "newton_iters_per_s": round(newton / el, 1),
+            "ms_per_list_step": round(1e3 * el / args.batch_steps, 2), "scene_build_s": round(build_s, 2),
+            "alone_env_steps_per_s": round(alone_steps / el_alone, 2), "alone_scenes": k}
+
+
+def serving_leg(args, ipc, torch):
+    """Request loop: Poisson arrivals over environments whose scenes stay
+    resident in HBM, at most one request in flight per environment, each
+    handed to the continuous-batching engine; latency = completion - arrival."""
+    from paper_2411_04776_amd import serve
+    envs = serve.serving_envs(args.serve, large_frac=0.0)
+    srv = serve.Server(envs, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol)
+    # warm every scene once (contact set-up, buffer growth), then the closed-loop
+    # capacity with every environment in flight; the open loop offers 70% of it
+    def closed_round():
+        tks = srv.engine.submit(srv.envs, [srv.next_pose(g) for g in srv.envs])
+        for t in tks:
+            srv.engine.wait(t)
+
+    closed_round()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        closed_round()
+    capacity = 2 * len(srv.envs) / (time.perf_counter() - t0)
+    rate = 0.7 * capacity
+    res = srv.run(rate_hz=rate, n_requests=args.serve_requests, seed=7, time_limit_s=60.0)
+    srv.close()
+    return {"workload": f"{args.serve} environments (uneven scenes, seeds 5000-{4999 + args.serve}), "
+                        f"Poisson arrivals at {rate:.0f} req/s, mixed precision",
+            "closed_loop_env_steps_per_s": round(capacity, 2),
+            "completed": res.completed, "env_steps_per_s": round(res.env_steps_per_s, 2),
+            "newton_iters_per_s": round(res.newton_iters_per_s, 1),
+            "latency_ms": {"p50": round(res.latency_ms_p50, 2), "p99": round(res.latency_ms_p99, 2)},
+            "admitted": res.admitted, "refused": res.refused, "footprint_gib": round(res.footprint_gb, 3),
+            "statuses": {str(k): v for k, v in res.statuses.items()}}
 
 
 def cpu_baseline(sc, x0, v0, args, newton_per_step):

@@ -80,7 +80,7 @@ typedef struct ipc_scene_desc {
     double newton_tol;        /* converged when max |p_i| over free DOFs <= newton_tol (m) */
     double pcg_tol;           /* PCG stops at r^T M^-1 r <= pcg_tol^2 r0^T M^-1 r0 */
     double gravity[3];
-    double mu_friction, eps_v;/* lagged friction (0 = off) */
+    double mu_friction, eps_v;/* lagged IPC friction: coefficient (0 = off), velocity threshold (m/s, > 0 when on) */
     double ccd_s;             /* ACCD keep-gap fraction (0.1) */
     double ls_min_ratio;      /* line search stall ratio (2^-30) */
     int32_t self_contact;     /* 1: gel-gel PT/EE pairs take part */
@@ -151,14 +151,28 @@ IPC_API int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes);
 /* Sizes: out[0..7] = n_all, n_gel, n_tets, n_points, n_edges, n_tris, n_ind, n_gel_tris. */
 IPC_API int32_t ipc_scene_sizes(const ipc_scene *s, int32_t *out);
 
-/* Batched asynchronous stepping. Every scene of a submit must be idle (else
- * IPC_E_BUSY, nothing queued). ipc_step == submit of one + wait. */
+/* Batched asynchronous stepping with continuous batching. A batch owns a
+ * worker thread that keeps one list of in-flight steps per precision and runs
+ * Newton iterations over each list with one kernel launch per phase for all
+ * of its scenes; a step submitted while others are mid-step joins the list at
+ * the next iteration boundary, a finished step leaves it. Each scene's
+ * results are bitwise those of ipc_step (a scene's blocks, partial sums and
+ * reduction order depend on that scene alone).
+ * rt->stream: stream of the batch's launches (NULL: a stream of its own);
+ * rt->mem_budget > 0: the summed device bytes of the scenes in flight stay
+ * within it (one scene is always admitted); alloc/free are not used.
+ * submit: every scene must be idle and appear once (else IPC_E_BUSY, nothing
+ * queued); returns at once with one ticket per scene. A scene with a pending
+ * ticket must not be stepped, read, reset or destroyed (calls on it return
+ * IPC_E_BUSY; destroying it is undefined). A HIP error inside the worker ends
+ * every pending ticket with IPC_E_DEVICE. destroy waits for pending steps. */
 IPC_API int32_t ipc_batch_create(const ipc_runtime *rt, ipc_batch **out);
 IPC_API void ipc_batch_destroy(ipc_batch *b);
 IPC_API int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, const ipc_step_req *r,
                          ipc_ticket *t);
-/* 1 if done (stats filled), 0 if pending, < 0 on error. */
+/* 1 if done (stats filled), 0 if pending, < 0 on error (unknown ticket). */
 IPC_API int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
+/* Blocks until the step is done; returns its status and consumes the ticket. */
 IPC_API int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
 
 IPC_API const char *ipc_status_str(int32_t status);
