@@ -25,6 +25,41 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+PCG_SOURCES = ("paper_2411_04776_amd/csrc/k_solver.hip", "paper_2411_04776_amd/csrc/incidence.h",
+               "paper_2411_04776_amd/csrc/device_util.h", "paper_2411_04776_amd/csrc/ipc_internal.h")
+TRAFFIC_PROFILE = "profiles/k_pcg_A_c2_fp64_pmc.md"
+
+
+def pcg_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PCG_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_pcg_A launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size), or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != pcg_source_hash():
+        return None
+    try:
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def spmv_bytes_per_launch(info, n_active):
     """Algorithmic bytes of one PCG SpMV launch (FP64): each stored 3x3 block
     (72 B values + 4 B column) once, per vertex the z and d gathers and the d,
@@ -112,7 +147,7 @@ def main():
     roofline = {
         "kernel": "k_pcg_A (PCG SpMV + direction update)",
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "traffic_source": TRAFFIC_PROFILE,
         "bytes_per_launch": int(bytes_launch), "timed_launches": int(n_launch), "timing": "HIP events around 1 in 4 launches in the timed region",
         "avg_launch_us": round(avg_s * 1e6, 3),
         "share_of_event_time": {k: round(v[1] / max(sum(w[1] for w in prof.values()), 1e-12), 4)

@@ -6,9 +6,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-namespace ipcg {
+#include "ipc_internal.h"
 
-constexpr int kWave = 64;
+namespace ipcg {
 
 __device__ __forceinline__ double wave_sum(double v)
 {

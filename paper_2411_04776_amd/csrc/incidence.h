@@ -29,14 +29,20 @@ __device__ __forceinline__ void thread_row_sums(const SceneDev &S, int row, F va
     }
 }
 
-// Vector sum over a block of kBlock threads in a fixed order (all threads get it).
+// Vector sum over the block (blockDim.x a multiple of 64, at most kBlock) in
+// a fixed order; every thread gets the result.
 template <int NC>
 __device__ __forceinline__ void block_sum_vec(double v[NC])
 {
     __shared__ double sh[kBlock / kWave][NC];
-    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = wave_sum(v[c]);
+    if (nw == 1) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = __shfl(v[c], 0, kWave);
+        return;
+    }
     if (lane == 0)
 #pragma unroll
         for (int c = 0; c < NC; ++c) sh[w][c] = v[c];
@@ -44,21 +50,21 @@ __device__ __forceinline__ void block_sum_vec(double v[NC])
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double t = 0.0;
-        for (int k = 0; k < kBlock / kWave; ++k) t += sh[k][c];
+        for (int k = 0; k < nw; ++k) t += sh[k][c];
         v[c] = t;
     }
     __syncthreads();
 }
 
 // Sum over the entries of one (heavy) row by a whole block: thread t takes
-// entries t, t + kBlock, ... in order, then a fixed-order block sum.
+// entries t, t + blockDim, ... in order, then a fixed-order block sum.
 template <int NC, class F>
 __device__ __forceinline__ void block_row_sums(const SceneDev &S, int row, F val, double out[NC])
 {
     int e0 = S.c_ptr[row], e1 = S.c_ptr[row + 1];
 #pragma unroll
     for (int c = 0; c < NC; ++c) out[c] = 0.0;
-    for (int t = e0 + (int)threadIdx.x; t < e1; t += kBlock) {
+    for (int t = e0 + (int)threadIdx.x; t < e1; t += (int)blockDim.x) {
         int src = S.c_list[t];
         int p = src >> 2, a = src & 3;
 #pragma unroll

@@ -37,6 +37,7 @@
 
 namespace ipcg {
 
+constexpr int kWave = 64;         // wavefront width on gfx950
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
 constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
