@@ -30,6 +30,11 @@ PCG_SOURCES = ("paper_2411_04776_amd/csrc/k_solver.hip", "paper_2411_04776_amd/c
 TRAFFIC_PROFILE = "profiles/k_pcg_A_c2_fp64_pmc.md"
 
 
+def precond_code(args):
+    from paper_2411_04776_amd import ipc
+    return ipc.IPC_PRECOND_JACOBI if args.precond == "jacobi" else ipc.IPC_PRECOND_MULTILEVEL
+
+
 def pcg_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -76,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
+    ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel",
+                    help="PCG preconditioner: additive multilevel aggregates or block-Jacobi")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="scenes of the batched uneven-scene leg (0: skip)")
@@ -111,7 +118,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
         return
     sc = scenes.config2(args.seed)
-    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol)
+    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args))
     for _ in range(args.warmup):
         rc, st = g.step()
         print(f"warmup step {g.step_index}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
@@ -168,7 +175,7 @@ def main():
         "config": {"workload": f"40x50x8 gel (16000 v, 80262 tets), {sc.meta['kind']} indenter seed "
                                f"{args.seed}, 1.5 mm over 50 steps, dt 5e-3 s, FP64, steps "
                                f"{args.warmup + 1}-{args.warmup + args.steps}",
-                   "precision": "fp64", "pcg_tol": args.pcg_tol, "newton_tol_m": sc.newton_tol,
+                   "precision": "fp64", "pcg_tol": args.pcg_tol, "precond": args.precond, "newton_tol_m": sc.newton_tol,
                    "dhat_m": sc.dhat, "kappa": sc.kappa},
         "roofline": roofline,
     }
@@ -192,7 +199,8 @@ def batch_leg(args, ipc, scenes, torch):
     rt = ipc.TorchRuntime()
     t0 = time.perf_counter()
     scs = [scenes.config3_scene(i) for i in range(args.batch)]
-    gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol) for sc in scs]
+    gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol,
+                         precond=precond_code(args)) for sc in scs]
     build_s = time.perf_counter() - t0
     nv = sum(len(sc.X) for sc in scs)
     nt = sum(len(sc.T) for sc in scs)
@@ -247,7 +255,7 @@ def serving_leg(args, ipc, torch):
     handed to the continuous-batching engine; latency = completion - arrival."""
     from paper_2411_04776_amd import serve
     envs = serve.serving_envs(args.serve, large_frac=0.0)
-    srv = serve.Server(envs, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol)
+    srv = serve.Server(envs, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol, precond=precond_code(args))
     # warm every scene once (contact set-up, buffer growth), then the closed-loop
     # capacity with every environment in flight; the open loop offers 70% of it
     def closed_round():

@@ -52,6 +52,11 @@ extern "C" {
 #define IPC_FP64 0   /* every stage in FP64 */
 #define IPC_MIXED 1  /* FP32 assembly/SpMV/PCG vectors, FP64 dots, distances, CCD, energies */
 
+/* PCG preconditioner: 3x3 block Jacobi plus additive corrections on nested
+ * aggregates of free gel vertices (default), or 3x3 block Jacobi alone. */
+#define IPC_PRECOND_MULTILEVEL 0
+#define IPC_PRECOND_JACOBI 1
+
 #define IPC_HOST 0
 #define IPC_DEVICE 1
 
@@ -88,6 +93,7 @@ typedef struct ipc_scene_desc {
     int32_t max_newton;       /* 0: 100 */
     int32_t pcg_max_iter;     /* 0: 10 * 3 * (all vertices) */
     int32_t ccd_max_iter;     /* 0: 10000 */
+    int32_t precond;          /* IPC_PRECOND_MULTILEVEL (0) or IPC_PRECOND_JACOBI */
 } ipc_scene_desc;
 
 /* Device memory and stream plumbing. alloc/free may be NULL (then hipMalloc /

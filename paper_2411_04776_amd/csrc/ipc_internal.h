@@ -44,6 +44,7 @@ constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
 constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
+constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
 
 // kernels timed by the optional profiler
 enum ProfKernel {
@@ -136,6 +137,20 @@ struct SceneDev {
     int32_t *c_ptr, *c_cnt, *c_list, *c_row, *c_tmp;
     int32_t *hflag, *heavy_idx, *heavy_rows;  // heavy incidence rows: flag, index (scan), list
     double *hdiag;                            // 9 contact diagonal sums per heavy row
+    // multilevel additive preconditioner: nested aggregates of the free gel
+    // vertices (level 0 = cells of twice the mean edge, doubling per level);
+    // aggregates are numbered level-major (global id = mas_off[l] + local id)
+    int mas_levels;                  // 0: block Jacobi only
+    int mas_n[kMasLevels];           // aggregates per level
+    int mas_off[kMasLevels + 1];
+    int mas_nb1;                     // restriction blocks of level 0 (a thread per aggregate)
+    int mas_nblk;                    // restriction blocks in total (then a block per aggregate)
+    int32_t *mas_anc;                // level-major ancestor: mas_anc[l * n + i] (-1 outside)
+    int32_t *mas_mb, *mas_me, *mas_mem;  // members of aggregate g: mas_mem[mas_mb[g] .. mas_me[g])
+    int32_t *mas_dptr, *mas_dsrc;    // BELL entries summed into aggregate g's 3x3 block
+    void *mas_dinv;                  // 9 per aggregate (R)
+    void *mas_e;                     // 3 per aggregate (R): coarse corrections of the iteration
+    double *mas_part;                // r.e partials, two parity slots of mas_nblk
     // PCG
     void *r, *z, *dA, *dB, *q, *sol;
     double *pcg_part;
@@ -175,7 +190,7 @@ struct Params {
     double grav[3];
     double mu_fric, eps_v;
     double ccd_s, ls_min_ratio;
-    int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter;
+    int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter, precond;
 };
 
 // Device allocation through the runtime's callbacks (PyTorch's caching
@@ -271,6 +286,8 @@ enum PhaseKind {
     kPhEnt,       // incidence entries (4 per active pair), kBlock threads
     kPhFric,      // friction pairs, kBlock threads
     kPhVertH,     // vertex blocks, then one block per heavy incidence row
+    kPhMas,       // preconditioner aggregates: level-0 blocks, then a block per coarser aggregate
+    kPhMasV,      // vertex blocks of the scenes with the multilevel preconditioner
     kPhOne,       // one block per scene
     kPhTilesT, kPhTilesE, kPhTilesQ, kPhTilesC, kPhTilesA,  // scan tiles
     kPhKinds
@@ -330,6 +347,7 @@ void launch_gather_surface(Scene &s, double *dst, hipStream_t strm);
 
 void launch_elastic_elements(Batch &b);
 void launch_assemble(Batch &b);
+void launch_mas_diag(Batch &b);  // 3x3 aggregate blocks of the assembled matrix, inverted
 
 // 0: static at x, 1: swept over [x, x + p]. A scene whose positions are not
 // finite, or whose tables or lists cannot grow, gets b.fail set and must be

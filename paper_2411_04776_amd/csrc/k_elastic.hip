@@ -525,6 +525,7 @@ void launch_assemble(Batch &b)
         IPC_LAUNCH(b, k_assemble_gradient<double>, kPhVertH, kBlock);
         IPC_LAUNCH(b, k_assemble_bell<double>, kPhEntry, kBlock);
     }
+    launch_mas_diag(b);
     b.prof_end(kProfAssemble, ev);
 }
 

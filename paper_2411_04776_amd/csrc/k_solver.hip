@@ -45,6 +45,21 @@ __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 
 __device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// coarse-level r.e partials of iteration it (two parity slots)
+__device__ __forceinline__ double *mas_slot(const SceneDev &S, int it)
+{
+    return S.mas_part + (size_t)(it & 1) * S.mas_nblk;
+}
+
+// r.z of iteration it: the block-Jacobi part of the vertex blocks (and heavy
+// rows), plus the aggregate corrections' part
+__device__ __forceinline__ double rz_total(const SceneDev &S, int it, int n_vert_part)
+{
+    double v = wave_reduce_partials(rz_slot(S, it), n_vert_part);
+    if (S.mas_levels > 0) v += wave_reduce_partials(mas_slot(S, it), S.mas_nblk);
+    return v;
+}
+
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pcg_init(Launch L)
 {
@@ -212,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = wave_reduce_partials(rz_slot(S, 0), S.nb_vert);
+        double rz0 = rz_total(S, 0, S.nb_vert);
         if (!(rz0 > 0.0)) {
             if (lb == 0 && threadIdx.x == 0) {
                 S.pcg->done = 1;
@@ -227,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
             S.pcg->rzv[1] = rz0;
         }
     } else {
-        double rz_cur = wave_reduce_partials(rz_slot(S, it - 1), S.nb_vert + L.out[s].n_heavy);
+        double rz_cur = rz_total(S, it - 1, S.nb_vert + L.out[s].n_heavy);
         bool conv = rz_cur <= S.pcg->stop;
         if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
             if (lb == 0 && threadIdx.x == 0) {
@@ -374,6 +389,105 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
             rz_slot(S, it)[S.nb_vert + j] = pcg_vertex_update<R>(S, row, alpha, v, qc);
         }
     }
+}
+
+// ---- multilevel additive preconditioner ----------------------------------
+// z = D0^-1 r + sum over levels l of P_l E_l^-1 P_l^T r, with P_l the
+// piecewise-constant injection of level-l aggregates of free gel vertices and
+// E_l the 3x3 block of the assembled matrix summed over each aggregate
+// (translation of the aggregate as a whole). Symmetric positive definite, so
+// PCG keeps its guarantees; every sum runs in a fixed order. Level 0 has a
+// thread per aggregate, coarser levels a block per aggregate.
+
+// which aggregate a block (and thread) of a kPhMas launch serves; -1: none
+__device__ __forceinline__ int mas_agg_of(const SceneDev &S, int lb, bool &per_block)
+{
+    if (lb < S.mas_nb1) {
+        per_block = false;
+        int a = lb * kBlock + threadIdx.x;
+        return a < S.mas_n[0] ? a : -1;
+    }
+    per_block = true;
+    return S.mas_n[0] + (lb - S.mas_nb1);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_mas_diag(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    bool pb;
+    int g = mas_agg_of(S, lb, pb);
+    const R *bval = as<R>(S.bval);
+    double A[9];
+    for (int c = 0; c < 9; ++c) A[c] = 0.0;
+    int e0 = g >= 0 ? S.mas_dptr[g] : 0, e1 = g >= 0 ? S.mas_dptr[g + 1] : 0;
+    int t0 = pb ? e0 + (int)threadIdx.x : e0, dt = pb ? (int)blockDim.x : 1;
+    for (int t = t0; t < e1; t += dt) {
+        int64_t e = S.mas_dsrc[t];
+        int64_t slot = e / kSlice, lane = e % kSlice;
+        for (int c = 0; c < 9; ++c) A[c] += (double)bval[(slot * 9 + c) * kSlice + lane];
+    }
+    if (pb) block_sum_vec<9>(A);
+    if (g < 0 || (pb && threadIdx.x != 0)) return;
+    double Inv[9];
+    inverse3(A, Inv);
+    R *Di = as<R>(S.mas_dinv);
+    for (int c = 0; c < 9; ++c) Di[9 * (int64_t)g + c] = (R)Inv[c];
+}
+
+// restriction of r to every aggregate, e = E^-1 r_agg, and the r.e partials
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_mas_restrict(Launch L, int it)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    if (S.pcg->done) return;
+    bool pb;
+    int g = mas_agg_of(S, lb, pb);
+    const R *r = as<R>(S.r);
+    double ra[3] = {0.0, 0.0, 0.0};
+    int m0 = g >= 0 ? S.mas_mb[g] : 0, m1 = g >= 0 ? S.mas_me[g] : 0;
+    int t0 = pb ? m0 + (int)threadIdx.x : m0, dt = pb ? (int)blockDim.x : 1;
+    for (int t = t0; t < m1; t += dt) {
+        int i = S.mas_mem[t];
+        for (int c = 0; c < 3; ++c) ra[c] += (double)r[3 * i + c];
+    }
+    if (pb) block_sum_vec<3>(ra);
+    double re = 0.0;
+    if (g >= 0 && (!pb || threadIdx.x == 0)) {
+        const R *Di = as<R>(S.mas_dinv);
+        R *E = as<R>(S.mas_e);
+        for (int a = 0; a < 3; ++a) {
+            R ea = (R)(Di[9 * (int64_t)g + 3 * a] * (R)ra[0] + Di[9 * (int64_t)g + 3 * a + 1] * (R)ra[1] +
+                       Di[9 * (int64_t)g + 3 * a + 2] * (R)ra[2]);
+            E[3 * (int64_t)g + a] = ea;
+            re += ra[a] * (double)ea;
+        }
+    }
+    if (!pb) re = block_sum_all(re);
+    if (threadIdx.x == 0) mas_slot(S, it)[lb] = re;
+}
+
+// z_i += sum over levels of the corrections of i's aggregates
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_mas_prolong(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    if (S.pcg->done) return;
+    int i = lb * blockDim.x + threadIdx.x;
+    if (i >= S.n || S.mas_levels == 0) return;
+    int g0 = S.mas_anc[i];
+    if (g0 < 0) return;
+    const R *E = as<R>(S.mas_e);
+    R *z = as<R>(S.z);
+    double zi[3] = {(double)z[3 * i], (double)z[3 * i + 1], (double)z[3 * i + 2]};
+    for (int l = 0; l < S.mas_levels; ++l) {
+        int g = S.mas_anc[(int64_t)l * S.n + i];
+        for (int c = 0; c < 3; ++c) zi[c] += (double)E[3 * (int64_t)g + c];
+    }
+    for (int c = 0; c < 3; ++c) z[3 * i + c] = (R)zi[c];
 }
 
 // y = H v for the test hook (v in S.dB, y in S.q), in the PCG's three parts:
@@ -746,6 +860,14 @@ void run_pinf(Batch &b)
     IPC_LAUNCH(b, k_final_pinf, kPhOne, kBlock, b.launch(kPhVert));
 }
 
+void launch_mas_diag(Batch &b)
+{
+    if (mixed(b))
+        IPC_LAUNCH(b, k_mas_diag<float>, kPhMas, kBlock);
+    else
+        IPC_LAUNCH(b, k_mas_diag<double>, kPhMas, kBlock);
+}
+
 void launch_hess_apply(Batch &b)
 {
     // pair phase as set by the incidence build of the same assembly
@@ -771,10 +893,24 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]));
     b.set_phase(kPhPcgA, nab);
     set_heavy_phase(b);
+    std::vector<int32_t> mv(ns, 0);
+    for (size_t i = 0; i < ns; ++i)
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && b.sc[i]->h.mas_levels > 0) mv[i] = b.sc[i]->h.nb_vert;
+    b.set_phase(kPhMasV, mv);
     if (mx)
         IPC_LAUNCH(b, k_pcg_init<float>, kPhVert, kBlock);
     else
         IPC_LAUNCH(b, k_pcg_init<double>, kPhVert, kBlock);
+    auto precondition = [&](int it) {  // aggregate corrections of z for the scenes that use them
+        if (mx) {
+            IPC_LAUNCH(b, k_mas_restrict<float>, kPhMas, kBlock, it);
+            IPC_LAUNCH(b, k_mas_prolong<float>, kPhMasV, kBlock);
+        } else {
+            IPC_LAUNCH(b, k_mas_restrict<double>, kPhMas, kBlock, it);
+            IPC_LAUNCH(b, k_mas_prolong<double>, kPhMasV, kBlock);
+        }
+    };
+    precondition(0);
     int maxit = 0, last = 0;
     for (size_t i = 0; i < ns; ++i) {
         if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
@@ -804,6 +940,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
                 IPC_LAUNCH(b, k_pcg_B<float>, kPhVertH, kBlock, it);
             else
                 IPC_LAUNCH(b, k_pcg_B<double>, kPhVertH, kBlock, it);
+            precondition(it);
             if (timed) b.prof_end(kProfPcgB, ev);
         }
         b.read_out();

@@ -460,6 +460,86 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     }
     s.n_gather = (int64_t)g_src.size();
 
+    // ---- multilevel aggregates of the free gel vertices (preconditioner)
+    std::vector<int32_t> mas_anc, mas_mb, mas_me, mas_mem, mas_dptr, mas_dsrc;
+    s.h.mas_levels = 0;
+    if (s.prm.precond == IPC_PRECOND_MULTILEVEL) {
+        std::vector<int32_t> freev;
+        for (int i = 0; i < ng; ++i)
+            if (!(d.fixed && d.fixed[i])) freev.push_back(i);
+        double h0 = 0.0, org[3] = {INFINITY, INFINITY, INFINITY};
+        for (int e = 0; e < m; ++e) {
+            const double *a = d.X + 3 * d.T[4 * e], *b = d.X + 3 * d.T[4 * e + 1];
+            h0 += std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]));
+        }
+        h0 /= m;
+        for (int i = 0; i < ng; ++i)
+            for (int c = 0; c < 3; ++c) org[c] = std::min(org[c], d.X[3 * i + c]);
+        // finest cell key, coarser keys by integer halving (exactly nested)
+        size_t nf = freev.size();
+        std::vector<std::array<int64_t, 3>> key0(nf);
+        for (size_t k = 0; k < nf; ++k)
+            for (int c = 0; c < 3; ++c) key0[k][c] = (int64_t)std::floor((d.X[3 * freev[k] + c] - org[c]) / (2.0 * h0));
+        auto key_at = [&](size_t k, int l) {
+            std::array<int64_t, 3> q = key0[k];
+            for (int t = 0; t < l; ++t)
+                for (int c = 0; c < 3; ++c) q[c] = q[c] >= 0 ? q[c] / 2 : -((-q[c] + 1) / 2);
+            return q;
+        };
+        std::vector<size_t> ord(nf);
+        for (size_t k = 0; k < nf; ++k) ord[k] = k;
+        std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            for (int l = kMasLevels - 1; l >= 0; --l) {
+                auto ka = key_at(a, l), kb = key_at(b, l);
+                if (ka != kb) return ka < kb;
+            }
+            return freev[a] < freev[b];
+        });
+        for (size_t k = 0; k < nf; ++k) mas_mem.push_back(freev[ord[k]]);
+        mas_anc.assign((size_t)kMasLevels * n, -1);
+        int total = 0, prev = (int)nf;
+        for (int l = 0; l < kMasLevels; ++l) {
+            // runs of equal level-l keys in the sorted order are the aggregates
+            std::vector<int32_t> beg;
+            for (size_t k = 0; k < nf; ++k)
+                if (k == 0 || key_at(ord[k], l) != key_at(ord[k - 1], l)) beg.push_back((int32_t)k);
+            int na = (int)beg.size();
+            if (na < 2 || na >= prev) break;  // no further coarsening
+            s.h.mas_off[l] = total;
+            s.h.mas_n[l] = na;
+            for (int a = 0; a < na; ++a) {
+                int32_t b0 = beg[a], b1 = a + 1 < na ? beg[a + 1] : (int32_t)nf;
+                mas_mb.push_back(b0);
+                mas_me.push_back(b1);
+                for (int32_t k = b0; k < b1; ++k) mas_anc[(size_t)l * n + mas_mem[k]] = total + a;
+            }
+            total += na;
+            prev = na;
+            s.h.mas_levels = l + 1;
+        }
+        s.h.mas_off[s.h.mas_levels] = total;
+        // BELL entries inside each aggregate
+        mas_dptr.push_back(0);
+        for (int l = 0; l < s.h.mas_levels; ++l)
+            for (int a = 0; a < s.h.mas_n[l]; ++a) {
+                int g = s.h.mas_off[l] + a;
+                for (int32_t k = mas_mb[g]; k < mas_me[g]; ++k) {
+                    int row = mas_mem[k];
+                    int sl = row / kSlice, ln = row % kSlice;
+                    for (int slot = slice_ptr[sl]; slot < slice_ptr[sl + 1]; ++slot) {
+                        size_t e = (size_t)slot * kSlice + ln;
+                        int col = bcol[e];
+                        if (col >= 0 && mas_anc[(size_t)l * n + col] == g) mas_dsrc.push_back((int32_t)e);
+                    }
+                }
+                mas_dptr.push_back((int32_t)mas_dsrc.size());
+            }
+        if (s.h.mas_levels > 0) {
+            s.h.mas_nb1 = nblocks(s.h.mas_n[0]);
+            s.h.mas_nblk = s.h.mas_nb1 + (total - s.h.mas_n[0]);
+        }
+    }
+
     // ---- SoA tets, surface arrays
     std::vector<int32_t> tv(4 * (size_t)m);
     for (int e = 0; e < m; ++e)
@@ -561,6 +641,19 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.heavy_rows = dalloc<int32_t>(s, n + 1);
     H.hdiag = dalloc<double>(s, 9 * ((size_t)n + 1));
     IPC_HIP(hipMemsetAsync(H.hflag, 0, sizeof(int32_t) * (n + 1), s.stream));
+    if (H.mas_levels > 0) {
+        int total = H.mas_off[H.mas_levels];
+        H.mas_anc = upload(s, mas_anc);
+        H.mas_mb = upload(s, mas_mb);
+        H.mas_me = upload(s, mas_me);
+        H.mas_mem = upload(s, mas_mem);
+        H.mas_dptr = upload(s, mas_dptr);
+        H.mas_dsrc = upload(s, mas_dsrc);
+        H.mas_dinv = dalloc_bytes(s, 9 * (size_t)total * rs);
+        H.mas_e = dalloc_bytes(s, 3 * (size_t)total * rs);
+        H.mas_part = dalloc<double>(s, 2 * (size_t)H.mas_nblk + 2);
+        IPC_HIP(hipStreamSynchronize(s.stream));  // host vectors above are locals
+    }
     H.pcg = dalloc<PcgState>(s, 1);
     IPC_HIP(hipMemsetAsync(H.pcg, 0, sizeof(PcgState), s.stream));
     grow_table(s, 0, 16 * (int64_t)std::max(H.n_tris, 1));
@@ -773,6 +866,9 @@ static void activate(Batch &b, const std::vector<uint8_t> &on)
     b.set_phase(kPhEdges, ed);
     b.set_phase(kPhTris, tr);
     b.set_phase(kPhBody, bd);
+    std::vector<int32_t> ms(ns);
+    for (size_t i = 0; i < ns; ++i) ms[i] = on[i] ? b.sc[i]->h.mas_nblk : 0;
+    b.set_phase(kPhMas, ms);
 }
 
 // ---------------------------------------------------------------------------
@@ -1362,6 +1458,7 @@ static bool check_desc(const ipc_scene_desc *d)
     if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) return false;
     if (d->pcg_max_iter < 0 || d->max_newton < 0 || d->ccd_max_iter < 0) return false;
     if (!(d->mu_friction >= 0.0) || (d->mu_friction > 0.0 && !(d->eps_v > 0.0))) return false;
+    if (d->precond != IPC_PRECOND_MULTILEVEL && d->precond != IPC_PRECOND_JACOBI) return false;
     return true;
 }
 
@@ -1389,6 +1486,7 @@ static Params make_params(const ipc_scene_desc &d)
     p.max_newton = d.max_newton > 0 ? d.max_newton : 100;
     p.pcg_max_iter = d.pcg_max_iter;
     p.ccd_max_iter = d.ccd_max_iter > 0 ? d.ccd_max_iter : 10000;
+    p.precond = d.precond;
     return p;
 }
 

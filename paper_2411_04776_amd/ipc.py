@@ -31,6 +31,8 @@ IPC_FP64 = 0
 IPC_MIXED = 1
 IPC_HOST = 0
 IPC_DEVICE = 1
+IPC_PRECOND_MULTILEVEL = 0
+IPC_PRECOND_JACOBI = 1
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
@@ -52,7 +54,7 @@ class ipc_scene_desc(C.Structure):
         ("mu_friction", C.c_double), ("eps_v", C.c_double), ("ccd_s", C.c_double),
         ("ls_min_ratio", C.c_double),
         ("self_contact", C.c_int32), ("precision", C.c_int32), ("max_newton", C.c_int32),
-        ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32),
+        ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32), ("precond", C.c_int32),
     ]
 
 
@@ -203,7 +205,8 @@ class TorchRuntime:
         self.torch.cuda.caching_allocator_delete(int(ptr))
 
 
-def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=None) -> ipc_scene_desc:
+def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=None,
+              precond=IPC_PRECOND_MULTILEVEL) -> ipc_scene_desc:
     """ipc_scene_desc of a scenes.Scene; `keep` collects the numpy arrays that
     must outlive the create call."""
     X = np.ascontiguousarray(scene.X, dtype=np.float64)
@@ -235,6 +238,7 @@ def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=Non
     d.max_newton = max_newton
     d.pcg_max_iter = 0
     d.ccd_max_iter = 10000
+    d.precond = precond
     return d
 
 
@@ -249,11 +253,11 @@ class GelScene:
     """One library scene built from a scenes.Scene."""
 
     def __init__(self, scene, runtime: TorchRuntime | None = None, precision=IPC_FP64, pcg_tol=1e-12,
-                 max_newton=100):
+                 max_newton=100, precond=IPC_PRECOND_MULTILEVEL):
         self.scene = scene
         self.runtime = runtime or TorchRuntime()
         keep = []
-        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep)
+        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep, precond)
         self._keep = keep
         h = C.c_void_p()
         _check(lib().ipc_create_scene(C.byref(self.desc), C.byref(self.runtime.rt), C.byref(h)),

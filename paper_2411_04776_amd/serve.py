@@ -45,8 +45,8 @@ def footprint(scene, precision) -> int:
 class Server:
     """Admitted environments and the engine that steps them."""
 
-    def __init__(self, env_scenes, precision=ipc.IPC_MIXED, pcg_tol=1e-5, mem_budget_bytes=200 << 30,
-                 runtime=None):
+    def __init__(self, env_scenes, precision=ipc.IPC_MIXED, pcg_tol=1e-5, precond=ipc.IPC_PRECOND_MULTILEVEL,
+                 mem_budget_bytes=200 << 30, runtime=None):
         self.precision = precision
         self.envs = []
         self.refused = 0
@@ -57,7 +57,7 @@ class Server:
             if used + need > mem_budget_bytes:
                 self.refused += 1
                 continue
-            self.envs.append(ipc.GelScene(sc, runtime=rt, precision=precision, pcg_tol=pcg_tol))
+            self.envs.append(ipc.GelScene(sc, runtime=rt, precision=precision, pcg_tol=pcg_tol, precond=precond))
             used += need
         self.footprint = used
         self.engine = ipc.Batch()
