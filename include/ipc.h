@@ -210,6 +210,11 @@ IPC_API int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *l
 /* out[0..7] = stored elastic blocks, stored BELL entries incl. padding, vertices,
  * active pairs, tets, static candidates, swept candidates, gather entries. */
 IPC_API int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out);
+/* Multilevel preconditioner of the scene: out[0] levels (0: block-Jacobi only),
+ * out[1] groups (blocks of the preconditioner kernel), out[2..4] aggregates
+ * of levels 0..2, out[5] the largest group's members, out[6] the largest
+ * group's aggregates, out[7] members (free gel vertices). */
+IPC_API int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out);
 IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);
 IPC_API int32_t ipcx_get_state(const ipc_scene *s, double *x, double *v);
 

@@ -45,6 +45,9 @@ constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV bl
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
 constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
+constexpr int kMasCapM = 512;     // members of a preconditioner group (one block, held in LDS)
+constexpr int kMasCapA = 512;     // aggregates of all levels in a group
+constexpr int kMasTarget = 256;   // groups are packed with top-level aggregates up to this many members
 
 // kernels timed by the optional profiler
 enum ProfKernel {
@@ -139,18 +142,27 @@ struct SceneDev {
     double *hdiag;                            // 9 contact diagonal sums per heavy row
     // multilevel additive preconditioner: nested aggregates of the free gel
     // vertices (level 0 = cells of twice the mean edge, doubling per level);
-    // aggregates are numbered level-major (global id = mas_off[l] + local id)
+    // aggregates are numbered level-major (global id = mas_off[l] + local id).
+    // The members (free gel vertices) are ordered so that every aggregate of
+    // every level is a contiguous range of positions; a group is a run of
+    // top-level aggregates handled by one block.
     int mas_levels;                  // 0: block Jacobi only
     int mas_n[kMasLevels];           // aggregates per level
     int mas_off[kMasLevels + 1];
-    int mas_nb1;                     // restriction blocks of level 0 (a thread per aggregate)
-    int mas_nblk;                    // restriction blocks in total (then a block per aggregate)
-    int32_t *mas_anc;                // level-major ancestor: mas_anc[l * n + i] (-1 outside)
-    int32_t *mas_mb, *mas_me, *mas_mem;  // members of aggregate g: mas_mem[mas_mb[g] .. mas_me[g])
-    int32_t *mas_dptr, *mas_dsrc;    // BELL entries summed into aggregate g's 3x3 block
+    int mas_nf;                      // members
+    int mas_ng;                      // groups
+    int mas_nd0;                     // diagonal blocks of level 0 (a wavefront per aggregate)
+    int32_t *mas_mem;                // vertex of member position k
+    int32_t *mas_manc;               // level-local aggregate of member position k: mas_manc[l * nf + k]
+    int32_t *mas_mb, *mas_me;        // per global aggregate: member positions (level 0) or child ids (level l-1)
+    int32_t *mas_gofs;               // (levels + 1) rows of ng + 1: member offsets, then per-level aggregate offsets
+    int32_t *mas_dptr, *mas_dsrc;    // BELL entries first shared at aggregate g's level, per global aggregate
+    double *mas_ex;                  // 9 per aggregate: those entries' sum, then the aggregate's whole block
     void *mas_dinv;                  // 9 per aggregate (R)
-    void *mas_e;                     // 3 per aggregate (R): coarse corrections of the iteration
-    double *mas_part;                // r.e partials, two parity slots of mas_nblk
+    int mas_nother;                  // vertices outside the aggregates (fixed gel, indenter)
+    int32_t *mas_other;              // their ids, ascending
+    int32_t *mas_vpos;               // member position of each vertex, -1 outside
+    int pcg_nvp;                     // PCG update blocks before the heavy rows (and their r.z partials)
     // PCG
     void *r, *z, *dA, *dB, *q, *sol;
     double *pcg_part;
@@ -217,6 +229,7 @@ class Scene {
 
     int64_t nnzb = 0, n_gather = 0;
     int n_gel_tris = 0;
+    int mas_max_members = 0, mas_max_aggs = 0;  // largest preconditioner group
     double *xsave = nullptr;   // test hooks: the state x kept across a hook call
     double *ysurf = nullptr;   // staging for surface read-back to the host
     std::unique_ptr<Batch> solo;  // the list of one used by ipc_step and the hooks
@@ -286,8 +299,9 @@ enum PhaseKind {
     kPhEnt,       // incidence entries (4 per active pair), kBlock threads
     kPhFric,      // friction pairs, kBlock threads
     kPhVertH,     // vertex blocks, then one block per heavy incidence row
-    kPhMas,       // preconditioner aggregates: level-0 blocks, then a block per coarser aggregate
-    kPhMasV,      // vertex blocks of the scenes with the multilevel preconditioner
+    kPhMas,       // preconditioner diagonal: a wavefront per level-0 aggregate, a block per coarser one
+    kPhMasG,      // preconditioner groups (a block each)
+    kPhPcgB,      // PCG update: groups, vertex blocks, then a block per heavy incidence row
     kPhOne,       // one block per scene
     kPhTilesT, kPhTilesE, kPhTilesQ, kPhTilesC, kPhTilesA,  // scan tiles
     kPhKinds

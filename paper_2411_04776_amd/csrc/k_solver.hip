@@ -36,60 +36,14 @@ __device__ __forceinline__ R *as(void *p)
 }
 
 // partial-sum layout in pcg_part: [d.q of the row blocks: nb_rows][r.z slot 0][r.z slot 1], an
-// r.z slot holding nb_vert vertex-block partials then one per heavy row (n + 1 room);
+// r.z slot holding the pcg_nvp update-block partials then one per heavy row (n + 1 room);
 // the pair blocks' d.(H_c d) partials live in pcg_pair
 __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 {
-    return S.pcg_part + S.nb_rows + (size_t)(it & 1) * ((size_t)S.nb_vert + S.n + 1);
+    return S.pcg_part + S.nb_rows + (size_t)(it & 1) * ((size_t)S.pcg_nvp + S.n + 1);
 }
 
 __device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
-
-// coarse-level r.e partials of iteration it (two parity slots)
-__device__ __forceinline__ double *mas_slot(const SceneDev &S, int it)
-{
-    return S.mas_part + (size_t)(it & 1) * S.mas_nblk;
-}
-
-// r.z of iteration it: the block-Jacobi part of the vertex blocks (and heavy
-// rows), plus the aggregate corrections' part
-__device__ __forceinline__ double rz_total(const SceneDev &S, int it, int n_vert_part)
-{
-    double v = wave_reduce_partials(rz_slot(S, it), n_vert_part);
-    if (S.mas_levels > 0) v += wave_reduce_partials(mas_slot(S, it), S.mas_nblk);
-    return v;
-}
-
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_pcg_init(Launch L)
-{
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
-    int i = lb * blockDim.x + threadIdx.x;
-    R *r = as<R>(S.r), *z = as<R>(S.z), *sol = as<R>(S.sol);
-    const R *g = as<R>(S.grad), *Mi = as<R>(S.Minv);
-    double rz = 0.0;
-    if (i < S.n) {
-        R ri[3], zi[3];
-        for (int c = 0; c < 3; ++c) ri[c] = -g[3 * i + c];
-        for (int a = 0; a < 3; ++a) zi[a] = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
-        for (int c = 0; c < 3; ++c) {
-            r[3 * i + c] = ri[c];
-            z[3 * i + c] = zi[c];
-            sol[3 * i + c] = R(0);
-            rz += (double)ri[c] * (double)zi[c];
-        }
-    }
-    rz = block_sum_all(rz);
-    if (threadIdx.x == 0) rz_slot(S, 0)[lb] = rz;
-    if (i == 0) {
-        S.pcg->done = 0;
-        S.pcg->iters = 0;
-        S.pcg->stop = 0.0;
-        L.out[s].pcg_done = 0;
-        L.out[s].pcg_iters = 0;
-    }
-}
 
 // Partial product of one BELL row: lane `part` of the row's kLanesPerRow
 // lanes takes slots part, part + kLanesPerRow, ... The vector applied is
@@ -227,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = rz_total(S, 0, S.nb_vert);
+        double rz0 = wave_reduce_partials(rz_slot(S, 0), S.pcg_nvp + L.out[s].n_heavy);
         if (!(rz0 > 0.0)) {
             if (lb == 0 && threadIdx.x == 0) {
                 S.pcg->done = 1;
@@ -242,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
             S.pcg->rzv[1] = rz0;
         }
     } else {
-        double rz_cur = rz_total(S, it - 1, S.nb_vert + L.out[s].n_heavy);
+        double rz_cur = wave_reduce_partials(rz_slot(S, it - 1), S.pcg_nvp + L.out[s].n_heavy);
         bool conv = rz_cur <= S.pcg->stop;
         if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
             if (lb == 0 && threadIdx.x == 0) {
@@ -349,18 +303,149 @@ __device__ __forceinline__ double pcg_vertex_update(const SceneDev &S, int i, R 
     return rz;
 }
 
-// PCG B(it) over [vertex blocks | one block per heavy incidence row]: the
-// vertex data and contact sums are loaded first, then alpha from the d.q
-// partials, then the update and the r.z partials.
+// ---- multilevel additive preconditioner ----------------------------------
+// z = D^-1 r + sum over levels l of P_l E_l^-1 P_l^T r: D the 3x3 diagonal
+// blocks, P_l the piecewise-constant injection of the level-l aggregates of
+// free gel vertices, E_l = P_l^T A P_l (the assembled block matrix summed over
+// each aggregate: the aggregate translating as a whole). Symmetric positive
+// definite, so PCG keeps its guarantees. Aggregates nest and a group of
+// top-level aggregates is one block, so restriction, the coarse solves and
+// prolongation of a group happen in LDS with no grid-wide dependency; every
+// sum runs in a fixed order.
+
+// k_mas_diag: each aggregate's own entries (those first shared at its level):
+// a wavefront per level-0 aggregate, a block per coarser aggregate
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
+__global__ void __launch_bounds__(kBlock) k_mas_diag(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
-    if (lb < S.nb_vert) {
-        int i = lb * blockDim.x + threadIdx.x;
-        bool own = i < S.n && !S.hflag[i];
+    int g, t0, dt;
+    bool per_block = lb >= S.mas_nd0;
+    if (!per_block) {
+        g = lb * (kBlock / kWave) + (int)threadIdx.x / kWave;
+        t0 = (int)threadIdx.x % kWave;
+        dt = kWave;
+        if (g >= S.mas_n[0]) return;  // whole wavefronts leave
+    } else {
+        g = S.mas_n[0] + (lb - S.mas_nd0);
+        t0 = (int)threadIdx.x;
+        dt = (int)blockDim.x;
+    }
+    const R *bval = as<R>(S.bval);
+    double A[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A[c] = 0.0;
+    for (int t = S.mas_dptr[g] + t0; t < S.mas_dptr[g + 1]; t += dt) {
+        int64_t e = S.mas_dsrc[t];
+        int64_t slot = e / kSlice, lane = e % kSlice;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) A[c] += (double)bval[(slot * 9 + c) * kSlice + lane];
+    }
+    if (per_block)
+        block_sum_vec<9>(A);
+    else
+#pragma unroll
+        for (int c = 0; c < 9; ++c) A[c] = wave_sum(A[c]);
+    if (t0 == 0)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) S.mas_ex[9 * (int64_t)g + c] = A[c];
+}
+
+// group's level-l aggregate range [a0, a1) (level-local ids); l = -1: members
+__device__ __forceinline__ void mas_group_range(const SceneDev &S, int grp, int l, int &a0, int &a1)
+{
+    const int32_t *row = S.mas_gofs + (size_t)(l + 1) * (S.mas_ng + 1);
+    a0 = row[grp];
+    a1 = row[grp + 1];
+}
+
+// k_mas_invert: per group, level by level, E(g) = own entries + the children's
+// blocks (in child order), then its inverse
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_mas_invert(Launch L)
+{
+    int grp, s = scene_of_block(L, grp);
+    const SceneDev &S = *L.sc[s];
+    R *Di = as<R>(S.mas_dinv);
+    for (int l = 0; l < S.mas_levels; ++l) {
+        int a0, a1;
+        mas_group_range(S, grp, l, a0, a1);
+        for (int a = a0 + (int)threadIdx.x; a < a1; a += blockDim.x) {
+            int64_t g = S.mas_off[l] + a;
+            double E[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) E[c] = S.mas_ex[9 * g + c];
+            if (l > 0)
+                for (int ch = S.mas_mb[g]; ch < S.mas_me[g]; ++ch) {
+                    int64_t gc = S.mas_off[l - 1] + ch;
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) E[c] += S.mas_ex[9 * gc + c];
+                }
+            if (l + 1 < S.mas_levels)  // the parent level reads the whole block
+#pragma unroll
+                for (int c = 0; c < 9; ++c) S.mas_ex[9 * g + c] = E[c];
+            double Inv[9];
+            inverse3(E, Inv);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) Di[9 * g + c] = (R)Inv[c];
+        }
+        __syncthreads();  // the next level reads these blocks
+    }
+}
+
+// ---- PCG B(it) --------------------------------------------------------------
+// Blocks of a scene: [preconditioner groups | vertex blocks | a block per heavy
+// incidence row]. With the multilevel preconditioner the vertex blocks cover
+// the vertices outside the aggregates; without it, every vertex. Every block
+// loads its vertices' data and contact sums first, then alpha from the d.q
+// partials, then p += alpha d, r -= alpha q, z = D^-1 r (plus, in a group,
+// the aggregate corrections) and its r.z partial. B(0) starts the solve
+// from p = 0, r = -g instead.
+
+// alpha = r.z / d.q for iteration it (every lane of the wavefront takes part)
+template <class R>
+__device__ __forceinline__ R pcg_alpha(const Launch &L, const SceneDev &S, int s, int it)
+{
+    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
+    return (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
+}
+
+// start of the solve for vertex i: r = -g, p = 0, z = D^-1 r; returns r.z
+template <class R>
+__device__ __forceinline__ double pcg_vertex_start(const SceneDev &S, int i, R zo[3], R ri[3])
+{
+    R *r = as<R>(S.r), *sol = as<R>(S.sol);
+    const R *g = as<R>(S.grad), *Mi = as<R>(S.Minv);
+    for (int c = 0; c < 3; ++c) ri[c] = -g[3 * i + c];
+    double rz = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        zo[a] = Mi[9 * i + 3 * a] * ri[0] + Mi[9 * i + 3 * a + 1] * ri[1] + Mi[9 * i + 3 * a + 2] * ri[2];
+        rz += (double)ri[a] * (double)zo[a];
+    }
+    for (int c = 0; c < 3; ++c) {
+        r[3 * i + c] = ri[c];
+        sol[3 * i + c] = R(0);
+    }
+    return rz;
+}
+
+template <class R>
+__device__ void pcg_B_vertices(const Launch &L, const SceneDev &S, int s, int vb, int it, int lb)
+{
+    int k = vb * blockDim.x + threadIdx.x;
+    int i = S.mas_levels > 0 ? (k < S.mas_nother ? S.mas_other[k] : -1) : (k < S.n ? k : -1);
+    double rz = 0.0;
+    if (it == 0) {
+        if (i >= 0) {
+            R zo[3], ri[3];
+            rz = pcg_vertex_start<R>(S, i, zo, ri);
+            R *z = as<R>(S.z);
+            for (int c = 0; c < 3; ++c) z[3 * i + c] = zo[c];
+        }
+    } else {
+        const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
+        bool own = i >= 0 && !S.hflag[i];
         VertexPcg<R> v;
         double qc[3] = {0.0, 0.0, 0.0};
         if (own) {
@@ -368,126 +453,216 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
             contact_row_light<R>(S, i, qc);
         }
         if (S.pcg->done) return;
-        double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
-        R alpha = (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
-        double rz = own ? pcg_vertex_update<R>(S, i, alpha, v, qc) : 0.0;
-        rz = block_sum_all(rz);
-        if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
+        R alpha = pcg_alpha<R>(L, S, s, it);
+        if (own) rz = pcg_vertex_update<R>(S, i, alpha, v, qc);
+    }
+    rz = block_sum_all(rz);
+    if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
+}
+
+template <class R>
+__device__ void pcg_B_heavy(const Launch &L, const SceneDev &S, int s, int j, int it)
+{
+    if (j >= L.out[s].n_heavy) return;
+    int row = S.heavy_rows[j];
+    // B(0) and the aggregate members (updated by their group) leave a zero partial
+    if (it == 0 || (S.mas_levels > 0 && S.mas_vpos[row] >= 0)) {
+        if (threadIdx.x == 0) rz_slot(S, it)[S.pcg_nvp + j] = 0.0;
+        return;
+    }
+    const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
+    double qc[3];
+    contact_row_heavy<R>(S, row, qc);
+    if (S.pcg->done) return;
+    R alpha = pcg_alpha<R>(L, S, s, it);
+    if (threadIdx.x == 0) {
+        VertexPcg<R> v;
+        pcg_vertex_load<R>(S, row, dcur, v);
+        rz_slot(S, it)[S.pcg_nvp + j] = pcg_vertex_update<R>(S, row, alpha, v, qc);
+    }
+}
+
+static_assert(kMasCapA <= kMasCapM, "corrections reuse the members' LDS rows");
+static_assert(kMasCapM % kBlock == 0, "members per thread");
+constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group block
+
+// One group: the members' update, then restriction of the new r to every
+// aggregate (members, then children, in order), e = E^-1 r_agg per aggregate,
+// and z = D^-1 r + the corrections of the member's aggregates. The r.z
+// partial is r.D^-1 r + sum over the group's aggregates of r_agg.e.
+template <class R>
+__device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it)
+{
+    __shared__ double rm[kMasCapM][3];  // heavy members' contact sums, the members' r, then the corrections
+    __shared__ double ra[kMasCapA][3];  // aggregate sums of r
+    __shared__ int32_t hlist[kMasCapM];
+    __shared__ int32_t hcount;
+    const int nl = S.mas_levels;
+    int k0, k1;
+    mas_group_range(S, grp, -1, k0, k1);
+    int vid[kMasSlots];
+    R zo[kMasSlots][3];
+    double rz = 0.0;
+    if (it == 0) {
+#pragma unroll
+        for (int j = 0; j < kMasSlots; ++j) {
+            int k = k0 + (int)threadIdx.x + j * kBlock;
+            vid[j] = k < k1 ? S.mas_mem[k] : -1;
+            if (vid[j] >= 0) {
+                R ri[3];
+                rz += pcg_vertex_start<R>(S, vid[j], zo[j], ri);
+                for (int c = 0; c < 3; ++c) rm[k - k0][c] = (double)ri[c];
+            }
+        }
     } else {
-        int j = lb - S.nb_vert;
-        if (j >= L.out[s].n_heavy) return;
-        int row = S.heavy_rows[j];
-        double qc[3];
-        contact_row_heavy<R>(S, row, qc);
+        if (threadIdx.x == 0) hcount = 0;
+        const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
+        VertexPcg<R> v[kMasSlots];
+        double qc[kMasSlots][3];
+        bool heavy[kMasSlots];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMasSlots; ++j) {
+            int k = k0 + (int)threadIdx.x + j * kBlock;
+            vid[j] = k < k1 ? S.mas_mem[k] : -1;
+            heavy[j] = false;
+            qc[j][0] = qc[j][1] = qc[j][2] = 0.0;
+            if (vid[j] >= 0) {
+                pcg_vertex_load<R>(S, vid[j], dcur, v[j]);
+                heavy[j] = S.hflag[vid[j]] != 0;
+                if (!heavy[j])
+                    contact_row_light<R>(S, vid[j], qc[j]);
+                else
+                    hlist[atomicAdd(&hcount, 1)] = k - k0;
+            }
+        }
         if (S.pcg->done) return;
-        // every lane of the wavefront takes part in the partial reductions
-        double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
-        R alpha = (R)(S.pcg->rzv[it & 1] / dq);
-        if (threadIdx.x == 0) {
-            VertexPcg<R> v;
-            pcg_vertex_load<R>(S, row, dcur, v);
-            rz_slot(S, it)[S.nb_vert + j] = pcg_vertex_update<R>(S, row, alpha, v, qc);
+        __syncthreads();
+        // heavy members: the whole block sums each one's incidence row
+        const int nh = hcount;
+        for (int h = 0; h < nh; ++h) {
+            int pos = hlist[h];
+            double q3[3];
+            contact_row_heavy<R>(S, S.mas_mem[k0 + pos], q3);
+            if (threadIdx.x == 0)
+                for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
+        }
+        __syncthreads();
+        R alpha = pcg_alpha<R>(L, S, s, it);
+        R *sol = as<R>(S.sol), *r = as<R>(S.r);
+#pragma unroll
+        for (int j = 0; j < kMasSlots; ++j) {
+            if (vid[j] < 0) continue;
+            int i = vid[j], pos = k0 + (int)threadIdx.x + j * kBlock - k0;
+            if (heavy[j])
+                for (int c = 0; c < 3; ++c) qc[j][c] = rm[pos][c];
+            R ri[3];
+            for (int c = 0; c < 3; ++c) {
+                R qv = (R)((double)v[j].q[c] + qc[j][c]);
+                sol[3 * i + c] = v[j].p[c] + alpha * v[j].d[c];
+                ri[c] = v[j].r[c] - alpha * qv;
+                r[3 * i + c] = ri[c];
+            }
+            for (int a = 0; a < 3; ++a) {
+                zo[j][a] = v[j].M[3 * a] * ri[0] + v[j].M[3 * a + 1] * ri[1] + v[j].M[3 * a + 2] * ri[2];
+                rz += (double)ri[a] * (double)zo[j][a];
+            }
+            for (int c = 0; c < 3; ++c) rm[pos][c] = (double)ri[c];
         }
     }
-}
-
-// ---- multilevel additive preconditioner ----------------------------------
-// z = D0^-1 r + sum over levels l of P_l E_l^-1 P_l^T r, with P_l the
-// piecewise-constant injection of level-l aggregates of free gel vertices and
-// E_l the 3x3 block of the assembled matrix summed over each aggregate
-// (translation of the aggregate as a whole). Symmetric positive definite, so
-// PCG keeps its guarantees; every sum runs in a fixed order. Level 0 has a
-// thread per aggregate, coarser levels a block per aggregate.
-
-// which aggregate a block (and thread) of a kPhMas launch serves; -1: none
-__device__ __forceinline__ int mas_agg_of(const SceneDev &S, int lb, bool &per_block)
-{
-    if (lb < S.mas_nb1) {
-        per_block = false;
-        int a = lb * kBlock + threadIdx.x;
-        return a < S.mas_n[0] ? a : -1;
-    }
-    per_block = true;
-    return S.mas_n[0] + (lb - S.mas_nb1);
-}
-
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_mas_diag(Launch L)
-{
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
-    bool pb;
-    int g = mas_agg_of(S, lb, pb);
-    const R *bval = as<R>(S.bval);
-    double A[9];
-    for (int c = 0; c < 9; ++c) A[c] = 0.0;
-    int e0 = g >= 0 ? S.mas_dptr[g] : 0, e1 = g >= 0 ? S.mas_dptr[g + 1] : 0;
-    int t0 = pb ? e0 + (int)threadIdx.x : e0, dt = pb ? (int)blockDim.x : 1;
-    for (int t = t0; t < e1; t += dt) {
-        int64_t e = S.mas_dsrc[t];
-        int64_t slot = e / kSlice, lane = e % kSlice;
-        for (int c = 0; c < 9; ++c) A[c] += (double)bval[(slot * 9 + c) * kSlice + lane];
-    }
-    if (pb) block_sum_vec<9>(A);
-    if (g < 0 || (pb && threadIdx.x != 0)) return;
-    double Inv[9];
-    inverse3(A, Inv);
-    R *Di = as<R>(S.mas_dinv);
-    for (int c = 0; c < 9; ++c) Di[9 * (int64_t)g + c] = (R)Inv[c];
-}
-
-// restriction of r to every aggregate, e = E^-1 r_agg, and the r.e partials
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_mas_restrict(Launch L, int it)
-{
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
-    if (S.pcg->done) return;
-    bool pb;
-    int g = mas_agg_of(S, lb, pb);
-    const R *r = as<R>(S.r);
-    double ra[3] = {0.0, 0.0, 0.0};
-    int m0 = g >= 0 ? S.mas_mb[g] : 0, m1 = g >= 0 ? S.mas_me[g] : 0;
-    int t0 = pb ? m0 + (int)threadIdx.x : m0, dt = pb ? (int)blockDim.x : 1;
-    for (int t = t0; t < m1; t += dt) {
-        int i = S.mas_mem[t];
-        for (int c = 0; c < 3; ++c) ra[c] += (double)r[3 * i + c];
-    }
-    if (pb) block_sum_vec<3>(ra);
-    double re = 0.0;
-    if (g >= 0 && (!pb || threadIdx.x == 0)) {
-        const R *Di = as<R>(S.mas_dinv);
-        R *E = as<R>(S.mas_e);
-        for (int a = 0; a < 3; ++a) {
-            R ea = (R)(Di[9 * (int64_t)g + 3 * a] * (R)ra[0] + Di[9 * (int64_t)g + 3 * a + 1] * (R)ra[1] +
-                       Di[9 * (int64_t)g + 3 * a + 2] * (R)ra[2]);
-            E[3 * (int64_t)g + a] = ea;
-            re += ra[a] * (double)ea;
+    __syncthreads();
+    // restriction, coarse solves: level l's corrections are formed while level
+    // l + 1 sums (a barrier between levels)
+    const R *Di = as<R>(S.mas_dinv);
+    int base_prev = 0, a0_prev = 0, base = 0;
+    for (int l = 0; l <= nl; ++l) {
+        int a0 = 0, a1 = 0;
+        if (l < nl) mas_group_range(S, grp, l, a0, a1);
+        if (l > 0) {
+            int pa0 = a0_prev, pa1 = a0_prev + (base - base_prev);
+            for (int a = pa0 + (int)threadIdx.x; a < pa1; a += blockDim.x) {
+                int loc = base_prev + a - pa0;
+                const R *D = Di + 9 * ((int64_t)S.mas_off[l - 1] + a);
+                R sa[3] = {(R)ra[loc][0], (R)ra[loc][1], (R)ra[loc][2]};
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    R e = D[3 * q] * sa[0] + D[3 * q + 1] * sa[1] + D[3 * q + 2] * sa[2];
+                    rm[loc][q] = (double)e;
+                    rz += ra[loc][q] * (double)e;
+                }
+            }
+        }
+        for (int a = a0 + (int)threadIdx.x; a < a1; a += blockDim.x) {
+            int64_t g = S.mas_off[l] + a;
+            double acc[3] = {0.0, 0.0, 0.0};
+            int j0 = S.mas_mb[g], j1 = S.mas_me[g];
+            for (int j = j0; j < j1; ++j) {
+                const double *src = l == 0 ? rm[j - k0] : ra[base_prev + j - a0_prev];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] += src[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ra[base + a - a0][c] = acc[c];
+        }
+        __syncthreads();
+        if (l < nl) {
+            base_prev = base;
+            a0_prev = a0;
+            base += a1 - a0;
         }
     }
-    if (!pb) re = block_sum_all(re);
-    if (threadIdx.x == 0) mas_slot(S, it)[lb] = re;
-}
-
-// z_i += sum over levels of the corrections of i's aggregates
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_mas_prolong(Launch L)
-{
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
-    if (S.pcg->done) return;
-    int i = lb * blockDim.x + threadIdx.x;
-    if (i >= S.n || S.mas_levels == 0) return;
-    int g0 = S.mas_anc[i];
-    if (g0 < 0) return;
-    const R *E = as<R>(S.mas_e);
+    // prolongation: z = D^-1 r + the corrections of the member's aggregates
+    int ga0[kMasLevels], gbase[kMasLevels];
+    {
+        int bsum = 0;
+#pragma unroll
+        for (int l = 0; l < kMasLevels; ++l) {
+            int a0 = 0, a1 = 0;
+            if (l < nl) mas_group_range(S, grp, l, a0, a1);
+            ga0[l] = a0;
+            gbase[l] = bsum;
+            bsum += a1 - a0;
+        }
+    }
     R *z = as<R>(S.z);
-    double zi[3] = {(double)z[3 * i], (double)z[3 * i + 1], (double)z[3 * i + 2]};
-    for (int l = 0; l < S.mas_levels; ++l) {
-        int g = S.mas_anc[(int64_t)l * S.n + i];
-        for (int c = 0; c < 3; ++c) zi[c] += (double)E[3 * (int64_t)g + c];
+#pragma unroll
+    for (int j = 0; j < kMasSlots; ++j) {
+        if (vid[j] < 0) continue;
+        int k = k0 + (int)threadIdx.x + j * kBlock;
+        double zi[3] = {(double)zo[j][0], (double)zo[j][1], (double)zo[j][2]};
+#pragma unroll
+        for (int l = 0; l < kMasLevels; ++l) {
+            if (l >= nl) break;
+            int loc = gbase[l] + S.mas_manc[(int64_t)l * S.mas_nf + k] - ga0[l];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) zi[c] += rm[loc][c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) z[3 * vid[j] + c] = (R)zi[c];
     }
-    for (int c = 0; c < 3; ++c) z[3 * i + c] = (R)zi[c];
+    rz = block_sum_all(rz);
+    if (threadIdx.x == 0) rz_slot(S, it)[grp] = rz;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    if (it == 0 && lb == 0 && threadIdx.x == 0) {  // a new solve
+        S.pcg->done = 0;
+        S.pcg->iters = 0;
+        S.pcg->stop = 0.0;
+        L.out[s].pcg_done = 0;
+        L.out[s].pcg_iters = 0;
+    }
+    const int ngrp = S.mas_levels > 0 ? S.mas_ng : 0;
+    if (lb < ngrp)
+        pcg_B_group<R>(L, S, s, lb, it);
+    else if (lb < S.pcg_nvp)
+        pcg_B_vertices<R>(L, S, s, lb - ngrp, it, lb);
+    else
+        pcg_B_heavy<R>(L, S, s, lb - S.pcg_nvp, it);
 }
 
 // y = H v for the test hook (v in S.dB, y in S.q), in the PCG's three parts:
@@ -862,10 +1037,13 @@ void run_pinf(Batch &b)
 
 void launch_mas_diag(Batch &b)
 {
-    if (mixed(b))
+    if (mixed(b)) {
         IPC_LAUNCH(b, k_mas_diag<float>, kPhMas, kBlock);
-    else
+        IPC_LAUNCH(b, k_mas_invert<float>, kPhMasG, kBlock);
+    } else {
         IPC_LAUNCH(b, k_mas_diag<double>, kPhMas, kBlock);
+        IPC_LAUNCH(b, k_mas_invert<double>, kPhMasG, kBlock);
+    }
 }
 
 void launch_hess_apply(Batch &b)
@@ -893,24 +1071,14 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]));
     b.set_phase(kPhPcgA, nab);
     set_heavy_phase(b);
-    std::vector<int32_t> mv(ns, 0);
+    std::vector<int32_t> nbb(ns, 0);
     for (size_t i = 0; i < ns; ++i)
-        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && b.sc[i]->h.mas_levels > 0) mv[i] = b.sc[i]->h.nb_vert;
-    b.set_phase(kPhMasV, mv);
+        if (nab[i] > 0) nbb[i] = b.sc[i]->h.pcg_nvp + heavy_bound(pair_count(*b.sc[i], b.h_out[i]), b.sc[i]->h.n);
+    b.set_phase(kPhPcgB, nbb);
     if (mx)
-        IPC_LAUNCH(b, k_pcg_init<float>, kPhVert, kBlock);
+        IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, 0);
     else
-        IPC_LAUNCH(b, k_pcg_init<double>, kPhVert, kBlock);
-    auto precondition = [&](int it) {  // aggregate corrections of z for the scenes that use them
-        if (mx) {
-            IPC_LAUNCH(b, k_mas_restrict<float>, kPhMas, kBlock, it);
-            IPC_LAUNCH(b, k_mas_prolong<float>, kPhMasV, kBlock);
-        } else {
-            IPC_LAUNCH(b, k_mas_restrict<double>, kPhMas, kBlock, it);
-            IPC_LAUNCH(b, k_mas_prolong<double>, kPhMasV, kBlock);
-        }
-    };
-    precondition(0);
+        IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, 0);
     int maxit = 0, last = 0;
     for (size_t i = 0; i < ns; ++i) {
         if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
@@ -937,10 +1105,9 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             if (timed) b.prof_end(kProfPcgA, ev);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)
-                IPC_LAUNCH(b, k_pcg_B<float>, kPhVertH, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it);
             else
-                IPC_LAUNCH(b, k_pcg_B<double>, kPhVertH, kBlock, it);
-            precondition(it);
+                IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, it);
             if (timed) b.prof_end(kProfPcgB, ev);
         }
         b.read_out();

@@ -305,6 +305,189 @@ void grow_active(Scene &s, int64_t need)
 
 static void activate(Batch &b, const std::vector<uint8_t> &on);
 
+// Host image of the multilevel preconditioner's index arrays (layouts as in SceneDev).
+struct MasHost {
+    std::vector<int32_t> mem, manc, mb, me, gofs, dptr, dsrc, other, vpos;
+};
+
+// Nested aggregates of the free gel vertices. Level 0 bins the rest positions
+// into cubic cells of edge twice the mean tet edge; level l + 1 merges the
+// 2x2x2 cells of level l (integer halving of the cell key, so levels nest
+// exactly). Members are sorted by (top cell, ..., level-0 cell, vertex), so
+// every aggregate is a contiguous run of member positions. A run is split at
+// child boundaries wherever it would exceed kMasCapM members or kMasCapA
+// aggregates in its subtree (any partition keeps the preconditioner SPD),
+// which lets a group of top-level aggregates live in one block's LDS. A level
+// that does not coarsen ends the hierarchy. The diagonal lists hold, for each
+// aggregate, the BELL entries whose row and column first share an aggregate
+// at its level, so the block of the aggregate is its list plus its children's
+// blocks.
+static void build_multilevel(SceneDev &H, const ipc_scene_desc &d, const std::vector<int32_t> &slice_ptr,
+                             const std::vector<int32_t> &bcol, MasHost &M)
+{
+    const int ng = d.n_verts, m = d.n_tets, n = H.n;
+    H.mas_levels = 0;
+    H.mas_ng = 0;
+    H.mas_nf = 0;
+    H.mas_nd0 = 0;
+    H.mas_nother = 0;
+    std::vector<int32_t> freev;
+    for (int i = 0; i < ng; ++i)
+        if (!(d.fixed && d.fixed[i])) freev.push_back(i);
+    const size_t nf = freev.size();
+    if (nf < 2 || m == 0) return;
+    double h0 = 0.0, org[3] = {INFINITY, INFINITY, INFINITY};
+    for (int e = 0; e < m; ++e) {
+        const double *a = d.X + 3 * d.T[4 * e], *b = d.X + 3 * d.T[4 * e + 1];
+        h0 += std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]));
+    }
+    h0 /= m;
+    for (int i = 0; i < ng; ++i)
+        for (int c = 0; c < 3; ++c) org[c] = std::min(org[c], d.X[3 * i + c]);
+    std::vector<std::array<int64_t, 3>> key0(nf);
+    for (size_t k = 0; k < nf; ++k)
+        for (int c = 0; c < 3; ++c) key0[k][c] = (int64_t)std::floor((d.X[3 * freev[k] + c] - org[c]) / (2.0 * h0));
+    auto key_at = [&](size_t k, int l) {
+        std::array<int64_t, 3> q = key0[k];
+        for (int t = 0; t < l; ++t)
+            for (int c = 0; c < 3; ++c) q[c] = q[c] >= 0 ? q[c] / 2 : -((-q[c] + 1) / 2);
+        return q;
+    };
+    std::vector<size_t> ord(nf);
+    for (size_t k = 0; k < nf; ++k) ord[k] = k;
+    std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        for (int l = kMasLevels - 1; l >= 0; --l) {
+            auto ka = key_at(a, l), kb = key_at(b, l);
+            if (ka != kb) return ka < kb;
+        }
+        return freev[a] < freev[b];
+    });
+    // aggregates of one level: [b, e) member positions (level 0) or child ids,
+    // first member position, members and aggregates in the subtree
+    struct Agg {
+        int32_t b, e, fm, subm, suba;
+    };
+    std::vector<std::vector<Agg>> lv;
+    {
+        std::vector<Agg> a0;
+        for (size_t k = 0; k < nf; ++k) {
+            bool brk = a0.empty() || key_at(ord[k], 0) != key_at(ord[k - 1], 0) || a0.back().subm >= kMasCapM;
+            if (brk)
+                a0.push_back({(int32_t)k, (int32_t)k + 1, (int32_t)k, 1, 1});
+            else {
+                a0.back().e = (int32_t)k + 1;
+                a0.back().subm++;
+            }
+        }
+        if (a0.size() >= nf) return;  // cells hold single vertices: nothing to aggregate
+        lv.push_back(std::move(a0));
+    }
+    for (int l = 1; l < kMasLevels; ++l) {
+        const std::vector<Agg> &pr = lv.back();
+        const int capA = kMasCapA - (kMasLevels - 1 - l);
+        std::vector<Agg> nx;
+        for (size_t c = 0; c < pr.size(); ++c) {
+            const Agg &ch = pr[c];
+            bool brk = nx.empty() || key_at(ord[ch.fm], l) != key_at(ord[pr[nx.back().b].fm], l) ||
+                       nx.back().subm + ch.subm > kMasCapM || nx.back().suba + ch.suba > capA;
+            if (brk)
+                nx.push_back({(int32_t)c, (int32_t)c + 1, ch.fm, ch.subm, 1 + ch.suba});
+            else {
+                nx.back().e = (int32_t)c + 1;
+                nx.back().subm += ch.subm;
+                nx.back().suba += ch.suba;
+            }
+        }
+        if (nx.size() >= pr.size()) break;
+        lv.push_back(std::move(nx));
+    }
+    const int L = (int)lv.size();
+    H.mas_levels = L;
+    H.mas_nf = (int)nf;
+    int total = 0;
+    for (int l = 0; l < L; ++l) {
+        H.mas_off[l] = total;
+        H.mas_n[l] = (int)lv[l].size();
+        total += H.mas_n[l];
+    }
+    H.mas_off[L] = total;
+    H.mas_nd0 = (H.mas_n[0] + kBlock / kWave - 1) / (kBlock / kWave);
+    M.mem.resize(nf);
+    for (size_t k = 0; k < nf; ++k) M.mem[k] = freev[ord[k]];
+    M.mb.clear();
+    M.me.clear();
+    for (int l = 0; l < L; ++l)
+        for (auto &a : lv[l]) {
+            M.mb.push_back(a.b);
+            M.me.push_back(a.e);
+        }
+    // level-local aggregate of every member position, and of every vertex
+    M.manc.assign((size_t)L * nf, -1);
+    for (int a = 0; a < H.mas_n[0]; ++a)
+        for (int32_t k = lv[0][a].b; k < lv[0][a].e; ++k) M.manc[k] = a;
+    for (int l = 1; l < L; ++l) {
+        std::vector<int32_t> par(lv[l - 1].size());
+        for (int a = 0; a < H.mas_n[l]; ++a)
+            for (int32_t c = lv[l][a].b; c < lv[l][a].e; ++c) par[c] = a;
+        for (size_t k = 0; k < nf; ++k) M.manc[(size_t)l * nf + k] = par[M.manc[(size_t)(l - 1) * nf + k]];
+    }
+    M.vpos.assign(n, -1);
+    for (size_t k = 0; k < nf; ++k) M.vpos[M.mem[k]] = (int32_t)k;
+    M.other.clear();
+    for (int i = 0; i < n; ++i)
+        if (M.vpos[i] < 0) M.other.push_back(i);
+    H.mas_nother = (int)M.other.size();
+    std::vector<int32_t> vanc((size_t)L * n, -1);
+    for (int l = 0; l < L; ++l)
+        for (size_t k = 0; k < nf; ++k) vanc[(size_t)l * n + M.mem[k]] = M.manc[(size_t)l * nf + k];
+    // groups: runs of top-level aggregates
+    const std::vector<Agg> &top = lv[L - 1];
+    std::vector<int32_t> gstart;  // first top aggregate of each group
+    {
+        int cm = 0, ca = 0;
+        for (size_t t = 0; t < top.size(); ++t) {
+            if (gstart.empty() || cm + top[t].subm > kMasTarget || ca + top[t].suba > kMasCapA) {
+                gstart.push_back((int32_t)t);
+                cm = ca = 0;
+            }
+            cm += top[t].subm;
+            ca += top[t].suba;
+        }
+    }
+    const int G = (int)gstart.size();
+    H.mas_ng = G;
+    M.gofs.assign((size_t)(L + 1) * (G + 1), 0);
+    for (int g = 0; g <= G; ++g) {
+        int32_t pos = g < G ? top[gstart[g]].fm : (int32_t)nf;
+        M.gofs[g] = pos;
+        for (int l = 0; l < L; ++l) {
+            // level-l aggregates that start before member position pos
+            auto it = std::lower_bound(lv[l].begin(), lv[l].end(), pos,
+                                       [](const Agg &a, int32_t p) { return a.fm < p; });
+            M.gofs[(size_t)(l + 1) * (G + 1) + g] = (int32_t)(it - lv[l].begin());
+        }
+    }
+    // diagonal lists
+    M.dptr.assign(1, 0);
+    M.dsrc.clear();
+    for (int l = 0; l < L; ++l)
+        for (int a = 0; a < H.mas_n[l]; ++a) {
+            const Agg &A = lv[l][a];
+            for (int32_t k = A.fm; k < A.fm + A.subm; ++k) {
+                int row = M.mem[k];
+                int sl = row / kSlice, ln = row % kSlice;
+                for (int slot = slice_ptr[sl]; slot < slice_ptr[sl + 1]; ++slot) {
+                    size_t e = (size_t)slot * kSlice + ln;
+                    int col = bcol[e];
+                    if (col < 0 || vanc[(size_t)l * n + col] != a) continue;
+                    if (l > 0 && vanc[(size_t)(l - 1) * n + col] == vanc[(size_t)(l - 1) * n + row]) continue;
+                    M.dsrc.push_back((int32_t)e);
+                }
+            }
+            M.dptr.push_back((int32_t)M.dsrc.size());
+        }
+}
+
 static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
 {
     int n_gel_tris = 0, n_gel_edges = 0;
@@ -461,83 +644,16 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     s.n_gather = (int64_t)g_src.size();
 
     // ---- multilevel aggregates of the free gel vertices (preconditioner)
-    std::vector<int32_t> mas_anc, mas_mb, mas_me, mas_mem, mas_dptr, mas_dsrc;
+    MasHost mas;
     s.h.mas_levels = 0;
-    if (s.prm.precond == IPC_PRECOND_MULTILEVEL) {
-        std::vector<int32_t> freev;
-        for (int i = 0; i < ng; ++i)
-            if (!(d.fixed && d.fixed[i])) freev.push_back(i);
-        double h0 = 0.0, org[3] = {INFINITY, INFINITY, INFINITY};
-        for (int e = 0; e < m; ++e) {
-            const double *a = d.X + 3 * d.T[4 * e], *b = d.X + 3 * d.T[4 * e + 1];
-            h0 += std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]));
-        }
-        h0 /= m;
-        for (int i = 0; i < ng; ++i)
-            for (int c = 0; c < 3; ++c) org[c] = std::min(org[c], d.X[3 * i + c]);
-        // finest cell key, coarser keys by integer halving (exactly nested)
-        size_t nf = freev.size();
-        std::vector<std::array<int64_t, 3>> key0(nf);
-        for (size_t k = 0; k < nf; ++k)
-            for (int c = 0; c < 3; ++c) key0[k][c] = (int64_t)std::floor((d.X[3 * freev[k] + c] - org[c]) / (2.0 * h0));
-        auto key_at = [&](size_t k, int l) {
-            std::array<int64_t, 3> q = key0[k];
-            for (int t = 0; t < l; ++t)
-                for (int c = 0; c < 3; ++c) q[c] = q[c] >= 0 ? q[c] / 2 : -((-q[c] + 1) / 2);
-            return q;
-        };
-        std::vector<size_t> ord(nf);
-        for (size_t k = 0; k < nf; ++k) ord[k] = k;
-        std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-            for (int l = kMasLevels - 1; l >= 0; --l) {
-                auto ka = key_at(a, l), kb = key_at(b, l);
-                if (ka != kb) return ka < kb;
-            }
-            return freev[a] < freev[b];
-        });
-        for (size_t k = 0; k < nf; ++k) mas_mem.push_back(freev[ord[k]]);
-        mas_anc.assign((size_t)kMasLevels * n, -1);
-        int total = 0, prev = (int)nf;
-        for (int l = 0; l < kMasLevels; ++l) {
-            // runs of equal level-l keys in the sorted order are the aggregates
-            std::vector<int32_t> beg;
-            for (size_t k = 0; k < nf; ++k)
-                if (k == 0 || key_at(ord[k], l) != key_at(ord[k - 1], l)) beg.push_back((int32_t)k);
-            int na = (int)beg.size();
-            if (na < 2 || na >= prev) break;  // no further coarsening
-            s.h.mas_off[l] = total;
-            s.h.mas_n[l] = na;
-            for (int a = 0; a < na; ++a) {
-                int32_t b0 = beg[a], b1 = a + 1 < na ? beg[a + 1] : (int32_t)nf;
-                mas_mb.push_back(b0);
-                mas_me.push_back(b1);
-                for (int32_t k = b0; k < b1; ++k) mas_anc[(size_t)l * n + mas_mem[k]] = total + a;
-            }
-            total += na;
-            prev = na;
-            s.h.mas_levels = l + 1;
-        }
-        s.h.mas_off[s.h.mas_levels] = total;
-        // BELL entries inside each aggregate
-        mas_dptr.push_back(0);
-        for (int l = 0; l < s.h.mas_levels; ++l)
-            for (int a = 0; a < s.h.mas_n[l]; ++a) {
-                int g = s.h.mas_off[l] + a;
-                for (int32_t k = mas_mb[g]; k < mas_me[g]; ++k) {
-                    int row = mas_mem[k];
-                    int sl = row / kSlice, ln = row % kSlice;
-                    for (int slot = slice_ptr[sl]; slot < slice_ptr[sl + 1]; ++slot) {
-                        size_t e = (size_t)slot * kSlice + ln;
-                        int col = bcol[e];
-                        if (col >= 0 && mas_anc[(size_t)l * n + col] == g) mas_dsrc.push_back((int32_t)e);
-                    }
-                }
-                mas_dptr.push_back((int32_t)mas_dsrc.size());
-            }
-        if (s.h.mas_levels > 0) {
-            s.h.mas_nb1 = nblocks(s.h.mas_n[0]);
-            s.h.mas_nblk = s.h.mas_nb1 + (total - s.h.mas_n[0]);
-        }
+    if (s.prm.precond == IPC_PRECOND_MULTILEVEL) build_multilevel(s.h, d, slice_ptr, bcol, mas);
+    s.mas_max_members = s.mas_max_aggs = 0;
+    for (int g = 0; g < s.h.mas_ng; ++g) {
+        const int G1 = s.h.mas_ng + 1;
+        int aggs = 0;
+        for (int l = 0; l < s.h.mas_levels; ++l) aggs += mas.gofs[(size_t)(l + 1) * G1 + g + 1] - mas.gofs[(size_t)(l + 1) * G1 + g];
+        s.mas_max_members = std::max(s.mas_max_members, mas.gofs[g + 1] - mas.gofs[g]);
+        s.mas_max_aggs = std::max(s.mas_max_aggs, aggs);
     }
 
     // ---- SoA tets, surface arrays
@@ -635,7 +751,8 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     IPC_HIP(hipMemsetAsync(H.c_ptr, 0, sizeof(int32_t) * (n + 1), s.stream));
     for (void **p : {&H.r, &H.z, &H.dA, &H.dB, &H.q, &H.sol}) *p = dalloc_bytes(s, n3 * rs);
     IPC_HIP(hipMemsetAsync(H.sol, 0, n3 * rs, s.stream));
-    H.pcg_part = dalloc<double>(s, (size_t)H.nb_rows + 2 * ((size_t)H.nb_vert + n + 1) + 8);
+    H.pcg_nvp = H.mas_levels > 0 ? H.mas_ng + nblocks(H.mas_nother) : H.nb_vert;
+    H.pcg_part = dalloc<double>(s, (size_t)H.nb_rows + 2 * ((size_t)H.pcg_nvp + n + 1) + 8);
     H.hflag = dalloc<int32_t>(s, n + 1);
     H.heavy_idx = dalloc<int32_t>(s, n + 1);
     H.heavy_rows = dalloc<int32_t>(s, n + 1);
@@ -643,15 +760,17 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     IPC_HIP(hipMemsetAsync(H.hflag, 0, sizeof(int32_t) * (n + 1), s.stream));
     if (H.mas_levels > 0) {
         int total = H.mas_off[H.mas_levels];
-        H.mas_anc = upload(s, mas_anc);
-        H.mas_mb = upload(s, mas_mb);
-        H.mas_me = upload(s, mas_me);
-        H.mas_mem = upload(s, mas_mem);
-        H.mas_dptr = upload(s, mas_dptr);
-        H.mas_dsrc = upload(s, mas_dsrc);
+        H.mas_mem = upload(s, mas.mem);
+        H.mas_manc = upload(s, mas.manc);
+        H.mas_mb = upload(s, mas.mb);
+        H.mas_me = upload(s, mas.me);
+        H.mas_gofs = upload(s, mas.gofs);
+        H.mas_dptr = upload(s, mas.dptr);
+        H.mas_dsrc = upload(s, mas.dsrc);
+        H.mas_ex = dalloc<double>(s, 9 * (size_t)total);
         H.mas_dinv = dalloc_bytes(s, 9 * (size_t)total * rs);
-        H.mas_e = dalloc_bytes(s, 3 * (size_t)total * rs);
-        H.mas_part = dalloc<double>(s, 2 * (size_t)H.mas_nblk + 2);
+        H.mas_other = upload(s, mas.other);
+        H.mas_vpos = upload(s, mas.vpos);
         IPC_HIP(hipStreamSynchronize(s.stream));  // host vectors above are locals
     }
     H.pcg = dalloc<PcgState>(s, 1);
@@ -866,9 +985,15 @@ static void activate(Batch &b, const std::vector<uint8_t> &on)
     b.set_phase(kPhEdges, ed);
     b.set_phase(kPhTris, tr);
     b.set_phase(kPhBody, bd);
-    std::vector<int32_t> ms(ns);
-    for (size_t i = 0; i < ns; ++i) ms[i] = on[i] ? b.sc[i]->h.mas_nblk : 0;
+    std::vector<int32_t> ms(ns), mg(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const SceneDev &h = b.sc[i]->h;
+        bool ml = on[i] && h.mas_levels > 0;
+        ms[i] = ml ? h.mas_nd0 + (h.mas_off[h.mas_levels] - h.mas_n[0]) : 0;
+        mg[i] = ml ? h.mas_ng : 0;
+    }
     b.set_phase(kPhMas, ms);
+    b.set_phase(kPhMasG, mg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2091,6 +2216,20 @@ int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
     out[5] = s->last.n_cand;
     out[6] = s->last.n_sw;
     out[7] = s->n_gather;
+    return IPC_OK;
+}
+
+int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out)
+{
+    if (!s || !out) return IPC_E_INVALID_ARG;
+    for (int k = 0; k < 8; ++k) out[k] = 0;
+    const SceneDev &h = s->h;
+    out[0] = h.mas_levels;
+    out[1] = h.mas_ng;
+    for (int l = 0; l < h.mas_levels; ++l) out[2 + l] = h.mas_n[l];
+    out[5] = s->mas_max_members;
+    out[6] = s->mas_max_aggs;
+    out[7] = h.mas_nf;
     return IPC_OK;
 }
 

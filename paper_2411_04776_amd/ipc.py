@@ -112,6 +112,7 @@ _SIGS = {
     "ipcx_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "ipcx_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipcx_matrix_info": (C.c_int32, [C.c_void_p, _I64]),
+    "ipcx_precond_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_set_state": (C.c_int32, [C.c_void_p, _D, _D]),
     "ipcx_get_state": (C.c_int32, [C.c_void_p, _D, _D]),
 }
@@ -407,6 +408,12 @@ class GelScene:
         o = np.zeros(8, dtype=np.int64)
         lib().ipcx_matrix_info(self.ptr, o.ctypes.data_as(_I64))
         keys = ("nnzb", "bell_entries", "n", "n_active", "n_tets", "n_cand", "n_cand_swept", "n_gather")
+        return dict(zip(keys, map(int, o)))
+
+    def precond_info(self):
+        o = np.zeros(8, dtype=np.int64)
+        _check(lib().ipcx_precond_info(self.ptr, o.ctypes.data_as(_I64)), "ipcx_precond_info")
+        keys = ("levels", "groups", "aggs0", "aggs1", "aggs2", "max_group_members", "max_group_aggs", "members")
         return dict(zip(keys, map(int, o)))
 
     @property
