@@ -44,6 +44,7 @@ constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
 constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
+constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its cells)
 constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
 constexpr int kMasCapM = 512;     // members of a preconditioner group (one block, held in LDS)
 constexpr int kMasCapA = 512;     // aggregates of all levels in a group
@@ -118,6 +119,7 @@ struct SceneDev {
     int4 *ht_entries[2];
     int32_t ht_bits[2], ht_cap[2];
     int32_t *q_count, *q_off;      // per query primitive (points, then edges): pair counts, offsets
+    int32_t *q_lane;               // kLanesQ per query primitive: each lane's pair count
     // candidates: static list and swept list (SoA type, a, b with stride cap)
     int32_t *cand, *cand_sw;
     int64_t cand_cap, sw_cap;
@@ -292,6 +294,7 @@ enum PhaseKind {
     kPhSlice,     // SpMV row blocks (kRowsPerBlock rows each)
     kPhPcgA,      // SpMV row blocks, then pair blocks (PCG A)
     kPhPts, kPhEdges, kPhTris, kPhSurf, kPhInd,
+    kPhQPts, kPhQEdges,  // broad-phase queries: kLanesQ threads per point / edge
     kPhCand,      // static candidates
     kPhCandSw,    // swept candidates
     kPhAct,       // active pairs, one 64-thread block each

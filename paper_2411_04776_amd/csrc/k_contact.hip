@@ -339,9 +339,12 @@ __device__ __forceinline__ bool ee_admissible(const SceneDev &S, int a0, int a1,
     return true;
 }
 
-// One thread per query primitive (PT: surface point index, EE: edge index).
-// COUNT: per-query number of accepted pairs. Else write them at q_off and
-// sort the query's segment by b. swept selects the output list.
+// kLanesQ lanes per query primitive (PT: surface point index, EE: edge
+// index) split the cells its box spans. COUNT: each lane's number of
+// accepted pairs, and the query's total. Else each lane writes its pairs at
+// q_off plus the counts of the lanes before it, and lane 0 sorts the query's
+// segment by b (each pair is found in exactly one cell, so the sorted segment
+// does not depend on the split). swept selects the output list.
 template <int KIND, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
 {
@@ -349,8 +352,9 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
     const SceneDev &S = *L.sc[s];
     int NA = KIND == 0 ? S.n_pts : S.n_edges;
     int NB = KIND == 0 ? S.n_tris : S.n_edges;
-    int qa = lb * blockDim.x + threadIdx.x;
-    if (qa >= NA) return;
+    int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
+    int qa = (int)(gt / kLanesQ), lane = (int)(gt % kLanesQ);
+    const bool live = qa < NA;  // whole lane groups
     const double *abox = KIND == 0 ? S.pbox : S.ebox;
     const double *bbox = KIND == 0 ? S.tbox : S.ebox;
     const int table = KIND == 0 ? 0 : 1;
@@ -362,77 +366,99 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
     double h = *S.cell_h;
     double alo[3], ahi[3];
     int clo[3], chi[3];
-    for (int c = 0; c < 3; ++c) {
+    bool ok = live;
+    for (int c = 0; c < 3 && ok; ++c) {
         alo[c] = abox[c * NA + qa];
         ahi[c] = abox[(3 + c) * NA + qa];
         if (!(alo[c] <= ahi[c]) || !((ahi[c] - alo[c]) / h < (double)kMaxSpan)) {
-            if (COUNT) S.q_count[qidx] = 0;
-            return;
+            ok = false;
+            break;
         }
         clo[c] = cell_of(alo[c], h);
         chi[c] = cell_of(ahi[c], h);
     }
-    int va0, va1 = -1, a_id;
-    if (KIND == 0) {
-        va0 = S.pts[qa];
-        a_id = va0;
-    } else {
-        va0 = S.ev[qa];
-        va1 = S.ev[S.n_edges + qa];
-        a_id = qa;
+    int va0 = -1, va1 = -1, a_id = -1;
+    if (ok) {
+        if (KIND == 0) {
+            va0 = S.pts[qa];
+            a_id = va0;
+        } else {
+            va0 = S.ev[qa];
+            va1 = S.ev[S.n_edges + qa];
+            a_id = qa;
+        }
     }
     int32_t *out = swept ? S.cand_sw : S.cand;
     int64_t ocap = swept ? S.sw_cap : S.cand_cap;
+    int64_t o0 = 0, o = 0;
+    if (!COUNT && ok) {
+        o0 = S.q_off[qidx];
+        o = o0;
+        for (int j = 0; j < lane; ++j) o += S.q_lane[(int64_t)kLanesQ * qidx + j];
+    }
     int count = 0;
-    int64_t o = COUNT ? 0 : (int64_t)S.q_off[qidx];
-    for (int iz = clo[2]; iz <= chi[2]; ++iz)
-        for (int iy = clo[1]; iy <= chi[1]; ++iy)
-            for (int ix = clo[0]; ix <= chi[0]; ++ix) {
-                uint32_t bkt = cell_hash(ix, iy, iz, mask);
-                int kend = min(start[bkt + 1], cap);
-                for (int k = start[bkt]; k < kend; ++k) {
-                    int4 en = entries[k];
-                    if (en.x != ix || en.y != iy || en.z != iz) continue;
-                    int b = en.w;
-                    if (KIND == 1 && b <= qa) continue;
-                    // box test first: most bucket entries fail it, and it
-                    // needs no index loads
-                    bool ov = true;
-                    double corner[3];
-                    for (int c = 0; c < 3; ++c) {
-                        double blo = bbox[c * NB + b], bhi = bbox[(3 + c) * NB + b];
-                        ov = ov && (alo[c] <= bhi) && (blo <= ahi[c]);
-                        corner[c] = fmax(alo[c], blo);
-                    }
-                    if (!ov) continue;
-                    if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
-                        continue;
-                    if (KIND == 0) {
-                        if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
-                    } else {
-                        if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
-                    }
-                    if (!COUNT && o + count < ocap) {
-                        out[o + count] = KIND;
-                        out[ocap + o + count] = a_id;
-                        out[2 * ocap + o + count] = b;
-                    }
-                    ++count;
+    if (ok) {
+        const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1, ncz = chi[2] - clo[2] + 1;
+        const int64_t ncell = (int64_t)ncx * ncy * ncz;
+        for (int64_t cc = lane; cc < ncell; cc += kLanesQ) {
+            const int ix = clo[0] + (int)(cc % ncx);
+            const int64_t t = cc / ncx;
+            const int iy = clo[1] + (int)(t % ncy), iz = clo[2] + (int)(t / ncy);
+            uint32_t bkt = cell_hash(ix, iy, iz, mask);
+            int kend = min(start[bkt + 1], cap);
+            for (int k = start[bkt]; k < kend; ++k) {
+                int4 en = entries[k];
+                if (en.x != ix || en.y != iy || en.z != iz) continue;
+                int b = en.w;
+                if (KIND == 1 && b <= qa) continue;
+                // box test first: most bucket entries fail it, and it
+                // needs no index loads
+                bool ov = true;
+                double corner[3];
+                for (int c = 0; c < 3; ++c) {
+                    double blo = bbox[c * NB + b], bhi = bbox[(3 + c) * NB + b];
+                    ov = ov && (alo[c] <= bhi) && (blo <= ahi[c]);
+                    corner[c] = fmax(alo[c], blo);
                 }
+                if (!ov) continue;
+                if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
+                    continue;
+                if (KIND == 0) {
+                    if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
+                } else {
+                    if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
+                }
+                if (!COUNT && o + count < ocap) {
+                    out[o + count] = KIND;
+                    out[ocap + o + count] = a_id;
+                    out[2 * ocap + o + count] = b;
+                }
+                ++count;
             }
+        }
+    }
+    // the query's total over its lanes (every lane of the wavefront takes part)
+    int tot = count;
+    for (int m = 1; m < kLanesQ; m <<= 1) tot += __shfl_xor(tot, m, kWave);
     if (COUNT) {
-        S.q_count[qidx] = count;
+        if (live) {
+            S.q_lane[(int64_t)kLanesQ * qidx + lane] = count;
+            if (lane == 0) S.q_count[qidx] = tot;
+        }
     } else {
-        int32_t *ob = out + 2 * ocap + o;
-        int len = (int)min((int64_t)count, ocap - o);  // equal to count once the list has grown
-        for (int i = 1; i < len; ++i) {
-            int key = ob[i];
-            int j = i - 1;
-            while (j >= 0 && ob[j] > key) {
-                ob[j + 1] = ob[j];
-                --j;
+        __syncthreads();  // the lanes' writes are visible to lane 0
+        if (ok && lane == 0) {
+            int32_t *ob = out + 2 * ocap + o0;
+            int len = (int)min((int64_t)tot, ocap - o0);  // equal to tot once the list has grown
+            for (int i = 1; i < len; ++i) {
+                int key = ob[i];
+                int j = i - 1;
+                while (j >= 0 && ob[j] > key) {
+                    ob[j + 1] = ob[j];
+                    --j;
+                }
+                ob[j + 1] = key;
             }
-            ob[j + 1] = key;
         }
     }
 }
@@ -1143,8 +1169,8 @@ void run_broad_phase(Batch &b, int which)
         IPC_LAUNCH(b, k_zero, kPhTilesE, kBlock, 1);
         IPC_LAUNCH(b, k_hash_insert<true>, kPhTris, kBlock, 0);
         IPC_LAUNCH(b, k_hash_insert<true>, kPhEdges, kBlock, 1);
-        IPC_LAUNCH(b, (k_query<0, true>), kPhPts, kBlock, which);
-        IPC_LAUNCH(b, (k_query<1, true>), kPhEdges, kBlock, which);
+        IPC_LAUNCH(b, (k_query<0, true>), kPhQPts, kBlock, which);
+        IPC_LAUNCH(b, (k_query<1, true>), kPhQEdges, kBlock, which);
         segmented_scan(b, kScanQuery, kPhTilesQ, lq, which);
         b.read_out();
         bool any_redo = false;
@@ -1190,8 +1216,8 @@ void run_broad_phase(Batch &b, int which)
         b.upload_views();
         // failed scenes still run the fill pass: every write is bounded by
         // their list capacity, and the caller drops them afterwards
-        IPC_LAUNCH(b, (k_query<0, false>), kPhPts, kBlock, which);
-        IPC_LAUNCH(b, (k_query<1, false>), kPhEdges, kBlock, which);
+        IPC_LAUNCH(b, (k_query<0, false>), kPhQPts, kBlock, which);
+        IPC_LAUNCH(b, (k_query<1, false>), kPhQEdges, kBlock, which);
         b.prof_end(kProfBroad, ev);
         return;
     }

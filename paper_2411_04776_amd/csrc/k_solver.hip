@@ -489,7 +489,9 @@ constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group b
 // One group: the members' update, then restriction of the new r to every
 // aggregate (members, then children, in order), e = E^-1 r_agg per aggregate,
 // and z = D^-1 r + the corrections of the member's aggregates. The r.z
-// partial is r.D^-1 r + sum over the group's aggregates of r_agg.e.
+// partial is r.D^-1 r + sum over the group's aggregates of r_agg.e. The
+// group's index data and the inverses of the first kBlock aggregates of each
+// level are loaded at the start, beside the members' vertex data.
 template <class R>
 __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it)
 {
@@ -498,24 +500,56 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
     __shared__ int32_t hlist[kMasCapM];
     __shared__ int32_t hcount;
     const int nl = S.mas_levels;
+    const int tid = (int)threadIdx.x;
     int k0, k1;
     mas_group_range(S, grp, -1, k0, k1);
-    int vid[kMasSlots];
+    // level ranges, LDS bases, this thread's first aggregate per level
+    int ga0[kMasLevels], ga1[kMasLevels], gbase[kMasLevels];
+    int amb[kMasLevels], ame[kMasLevels];
+    R dinv[kMasLevels][9];
+    const R *Di = as<R>(S.mas_dinv);
+    {
+        int bsum = 0;
+#pragma unroll
+        for (int l = 0; l < kMasLevels; ++l) {
+            int a0 = 0, a1 = 0;
+            if (l < nl) mas_group_range(S, grp, l, a0, a1);
+            ga0[l] = a0;
+            ga1[l] = a1;
+            gbase[l] = bsum;
+            bsum += a1 - a0;
+            amb[l] = ame[l] = 0;
+            int a = a0 + tid;
+            if (a < a1) {
+                int64_t g = S.mas_off[l] + a;
+                amb[l] = S.mas_mb[g];
+                ame[l] = S.mas_me[g];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) dinv[l][c] = Di[9 * g + c];
+            }
+        }
+    }
+    int vid[kMasSlots], loc[kMasSlots][kMasLevels];
     R zo[kMasSlots][3];
     double rz = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMasSlots; ++j) {
+        int k = k0 + tid + j * kBlock;
+        vid[j] = k < k1 ? S.mas_mem[k] : -1;
+#pragma unroll
+        for (int l = 0; l < kMasLevels; ++l)
+            loc[j][l] = (vid[j] >= 0 && l < nl) ? gbase[l] + S.mas_manc[(int64_t)l * S.mas_nf + k] - ga0[l] : 0;
+    }
     if (it == 0) {
 #pragma unroll
-        for (int j = 0; j < kMasSlots; ++j) {
-            int k = k0 + (int)threadIdx.x + j * kBlock;
-            vid[j] = k < k1 ? S.mas_mem[k] : -1;
+        for (int j = 0; j < kMasSlots; ++j)
             if (vid[j] >= 0) {
                 R ri[3];
                 rz += pcg_vertex_start<R>(S, vid[j], zo[j], ri);
-                for (int c = 0; c < 3; ++c) rm[k - k0][c] = (double)ri[c];
+                for (int c = 0; c < 3; ++c) rm[tid + j * kBlock][c] = (double)ri[c];
             }
-        }
     } else {
-        if (threadIdx.x == 0) hcount = 0;
+        if (tid == 0) hcount = 0;
         const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
         VertexPcg<R> v[kMasSlots];
         double qc[kMasSlots][3];
@@ -523,8 +557,6 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kMasSlots; ++j) {
-            int k = k0 + (int)threadIdx.x + j * kBlock;
-            vid[j] = k < k1 ? S.mas_mem[k] : -1;
             heavy[j] = false;
             qc[j][0] = qc[j][1] = qc[j][2] = 0.0;
             if (vid[j] >= 0) {
@@ -533,7 +565,7 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                 if (!heavy[j])
                     contact_row_light<R>(S, vid[j], qc[j]);
                 else
-                    hlist[atomicAdd(&hcount, 1)] = k - k0;
+                    hlist[atomicAdd(&hcount, 1)] = tid + j * kBlock;
             }
         }
         if (S.pcg->done) return;
@@ -544,7 +576,7 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             int pos = hlist[h];
             double q3[3];
             contact_row_heavy<R>(S, S.mas_mem[k0 + pos], q3);
-            if (threadIdx.x == 0)
+            if (tid == 0)
                 for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
         }
         __syncthreads();
@@ -553,7 +585,7 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
 #pragma unroll
         for (int j = 0; j < kMasSlots; ++j) {
             if (vid[j] < 0) continue;
-            int i = vid[j], pos = k0 + (int)threadIdx.x + j * kBlock - k0;
+            int i = vid[j], pos = tid + j * kBlock;
             if (heavy[j])
                 for (int c = 0; c < 3; ++c) qc[j][c] = rm[pos][c];
             R ri[3];
@@ -571,77 +603,72 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
         }
     }
     __syncthreads();
-    // restriction, coarse solves: level l's corrections are formed while level
-    // l + 1 sums (a barrier between levels)
-    const R *Di = as<R>(S.mas_dinv);
-    int base_prev = 0, a0_prev = 0, base = 0;
-    for (int l = 0; l <= nl; ++l) {
-        int a0 = 0, a1 = 0;
-        if (l < nl) mas_group_range(S, grp, l, a0, a1);
+    // restriction and coarse solves, a barrier per level: the sums of level l
+    // are formed while the corrections of level l - 1 are
+#pragma unroll
+    for (int l = 0; l <= kMasLevels; ++l) {
+        if (l > nl) break;
         if (l > 0) {
-            int pa0 = a0_prev, pa1 = a0_prev + (base - base_prev);
-            for (int a = pa0 + (int)threadIdx.x; a < pa1; a += blockDim.x) {
-                int loc = base_prev + a - pa0;
-                const R *D = Di + 9 * ((int64_t)S.mas_off[l - 1] + a);
-                R sa[3] = {(R)ra[loc][0], (R)ra[loc][1], (R)ra[loc][2]};
+            const int pl = l - 1;
+            for (int a = ga0[pl] + tid; a < ga1[pl]; a += kBlock) {
+                int lc = gbase[pl] + a - ga0[pl];
+                R D[9];
+                if (a == ga0[pl] + tid) {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) D[c] = dinv[pl][c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) D[c] = Di[9 * ((int64_t)S.mas_off[pl] + a) + c];
+                }
+                R sa[3] = {(R)ra[lc][0], (R)ra[lc][1], (R)ra[lc][2]};
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     R e = D[3 * q] * sa[0] + D[3 * q + 1] * sa[1] + D[3 * q + 2] * sa[2];
-                    rm[loc][q] = (double)e;
-                    rz += ra[loc][q] * (double)e;
+                    rm[lc][q] = (double)e;
+                    rz += ra[lc][q] * (double)e;
                 }
             }
         }
-        for (int a = a0 + (int)threadIdx.x; a < a1; a += blockDim.x) {
-            int64_t g = S.mas_off[l] + a;
-            double acc[3] = {0.0, 0.0, 0.0};
-            int j0 = S.mas_mb[g], j1 = S.mas_me[g];
-            for (int j = j0; j < j1; ++j) {
-                const double *src = l == 0 ? rm[j - k0] : ra[base_prev + j - a0_prev];
+        if (l < nl) {
+            for (int a = ga0[l] + tid; a < ga1[l]; a += kBlock) {
+                int j0, j1;
+                if (a == ga0[l] + tid) {
+                    j0 = amb[l];
+                    j1 = ame[l];
+                } else {
+                    int64_t g = S.mas_off[l] + a;
+                    j0 = S.mas_mb[g];
+                    j1 = S.mas_me[g];
+                }
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int j = j0; j < j1; ++j) {
+                    const double *src = l == 0 ? rm[j - k0] : ra[gbase[l - 1] + j - ga0[l - 1]];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) acc[c] += src[c];
+                    for (int c = 0; c < 3; ++c) acc[c] += src[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ra[gbase[l] + a - ga0[l]][c] = acc[c];
             }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ra[base + a - a0][c] = acc[c];
         }
         __syncthreads();
-        if (l < nl) {
-            base_prev = base;
-            a0_prev = a0;
-            base += a1 - a0;
-        }
     }
     // prolongation: z = D^-1 r + the corrections of the member's aggregates
-    int ga0[kMasLevels], gbase[kMasLevels];
-    {
-        int bsum = 0;
-#pragma unroll
-        for (int l = 0; l < kMasLevels; ++l) {
-            int a0 = 0, a1 = 0;
-            if (l < nl) mas_group_range(S, grp, l, a0, a1);
-            ga0[l] = a0;
-            gbase[l] = bsum;
-            bsum += a1 - a0;
-        }
-    }
     R *z = as<R>(S.z);
 #pragma unroll
     for (int j = 0; j < kMasSlots; ++j) {
         if (vid[j] < 0) continue;
-        int k = k0 + (int)threadIdx.x + j * kBlock;
         double zi[3] = {(double)zo[j][0], (double)zo[j][1], (double)zo[j][2]};
 #pragma unroll
         for (int l = 0; l < kMasLevels; ++l) {
             if (l >= nl) break;
-            int loc = gbase[l] + S.mas_manc[(int64_t)l * S.mas_nf + k] - ga0[l];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) zi[c] += rm[loc][c];
+            for (int c = 0; c < 3; ++c) zi[c] += rm[loc[j][l]][c];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) z[3 * vid[j] + c] = (R)zi[c];
     }
     rz = block_sum_all(rz);
-    if (threadIdx.x == 0) rz_slot(S, it)[grp] = rz;
+    if (tid == 0) rz_slot(S, it)[grp] = rz;
 }
 
 template <class R>

@@ -779,6 +779,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     grow_table(s, 1, 16 * (int64_t)std::max(H.n_edges, 1));
     H.q_count = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     H.q_off = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
+    H.q_lane = dalloc<int32_t>(s, (size_t)kLanesQ * ((size_t)H.n_pts + H.n_edges) + 1);
     grow_candidates(s, 0, 1024);
     grow_candidates(s, 1, 1024);
     grow_active(s, 256);
@@ -985,6 +986,13 @@ static void activate(Batch &b, const std::vector<uint8_t> &on)
     b.set_phase(kPhEdges, ed);
     b.set_phase(kPhTris, tr);
     b.set_phase(kPhBody, bd);
+    for (size_t i = 0; i < ns; ++i) {
+        const SceneDev &H = b.sc[i]->h;
+        p[i] = on[i] ? nblocks((int64_t)H.n_pts * kLanesQ) : 0;
+        ed[i] = on[i] ? nblocks((int64_t)H.n_edges * kLanesQ) : 0;
+    }
+    b.set_phase(kPhQPts, p);
+    b.set_phase(kPhQEdges, ed);
     std::vector<int32_t> ms(ns), mg(ns);
     for (size_t i = 0; i < ns; ++i) {
         const SceneDev &h = b.sc[i]->h;
