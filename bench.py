@@ -224,7 +224,21 @@ def batch_leg(args, ipc, scenes, torch):
         newton += list_step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # one more list step with the engine's HIP-event timing of the SpMV (kernel
+    # class 0): achieved = algorithmic bytes of the timed launches / their time
+    eng.profile(True)
+    list_step()
+    n_a, ms_a, by_a = eng.profile_read(0)
+    eng.profile(False)
     eng.close()
+    spmv = None
+    if n_a and ms_a > 0:
+        gbs = by_a / (ms_a * 1e-3) / 1e9
+        spmv = {"kernel": "k_pcg_A over the list (PCG SpMV + direction update)", "bound": "hbm",
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "timed_launches": n_a, "avg_launch_us": round(1e3 * ms_a / n_a, 2),
+                "bytes_per_launch": int(by_a / n_a),
+                "timing": "engine HIP events around 1 in 4 launches of one list step"}
     # the same scenes one at a time, from the same states
     k = min(16, len(gs))
     states = [g.save_state() for g in gs[:k]]
@@ -246,7 +260,8 @@ def batch_leg(args, ipc, scenes, torch):
                         f"steps 2-{1 + args.batch_steps}, mixed precision, continuous-batching engine",
             "env_steps_per_s": round(steps / el, 2), "newton_iters_per_s": round(newton / el, 1),
             "ms_per_list_step": round(1e3 * el / args.batch_steps, 2), "scene_build_s": round(build_s, 2),
-            "alone_env_steps_per_s": round(alone_steps / el_alone, 2), "alone_scenes": k}
+            "alone_env_steps_per_s": round(alone_steps / el_alone, 2), "alone_scenes": k,
+            "pcg_spmv_roofline": spmv}
 
 
 def serving_leg(args, ipc, torch):

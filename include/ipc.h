@@ -180,6 +180,18 @@ IPC_API int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, c
 IPC_API int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
 /* Blocks until the step is done; returns its status and consumes the ticket. */
 IPC_API int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
+/* Kernel timing inside the engine: enable (1) or disable (0) resets the
+ * totals; from the next Newton round on, one launch in four of each kernel
+ * class is bracketed by HIP events on the engine's stream (same classes as
+ * ipcx_profile). profile_read returns the timed launches, their summed
+ * milliseconds and, for class 0 (PCG SpMV), the summed algorithmic bytes of
+ * those launches over every scene of the list: per stored 3x3 block its
+ * values and column index, per vertex the z and d gathers, the d and q writes
+ * and the row pointer, per contact pair its off-diagonal blocks and vertex
+ * ids (4- or 8-byte reals by the list's precision). */
+IPC_API int32_t ipc_batch_profile(ipc_batch *b, int32_t enable);
+IPC_API int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total,
+                                       double *bytes_total);
 
 IPC_API const char *ipc_status_str(int32_t status);
 /* Last error message of the calling thread; returns its length. */

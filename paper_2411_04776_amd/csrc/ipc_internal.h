@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -40,8 +41,9 @@ namespace ipcg {
 constexpr int kWave = 64;         // wavefront width on gfx950
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
-constexpr int kLanesPerRow = 8;   // SpMV lanes per matrix row
-constexpr int kRowsPerBlock = kBlock / kLanesPerRow;  // matrix rows per SpMV block
+constexpr int kLanesPerRow = 2;   // SpMV lanes per matrix row
+constexpr int kPcgABlock = 128;   // threads per SpMV block (PCG A)
+constexpr int kRowsPerBlock = kPcgABlock / kLanesPerRow;  // matrix rows per SpMV block
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
 constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its cells)
@@ -218,6 +220,20 @@ struct DeviceArena {
 
 class Batch;
 
+// timed launches of one kernel class: count, summed event milliseconds and
+// summed algorithmic bytes (counted for the PCG SpMV)
+struct ProfAcc {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+
+// accumulators shared by the lists of a batch engine
+struct ProfSink {
+    std::mutex mu;
+    ProfAcc acc[kProfKernels];
+};
+
 class Scene {
   public:
     Params prm{};
@@ -247,10 +263,7 @@ class Scene {
 
     // optional per-kernel timing with HIP events
     bool prof = false;
-    struct ProfAcc {
-        int64_t launches = 0;
-        double ms = 0.0;
-    } prof_acc[kProfKernels];
+    ProfAcc prof_acc[kProfKernels];
 
     ~Scene();
 };
@@ -329,7 +342,13 @@ class Batch {
     size_t stage_cap = 0, stage_used = 0;
     void *stage(const void *src, size_t bytes);
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    struct PendingEv {
+        int kernel;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<PendingEv> ev_pending;
+    ProfSink *sink = nullptr;  // engine lists: timings go here (any list size)
 
     ~Batch();
     void bind(const std::vector<Scene *> &scenes, hipStream_t strm);
@@ -340,7 +359,7 @@ class Batch {
     void read_out();
     bool prof() const;
     void prof_begin(int kernel, hipEvent_t *pair);
-    void prof_end(int kernel, hipEvent_t *pair);
+    void prof_end(int kernel, hipEvent_t *pair, double bytes = 0.0);
     void prof_collect();
 };
 

@@ -43,7 +43,8 @@ __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
     return S.pcg_part + S.nb_rows + (size_t)(it & 1) * ((size_t)S.pcg_nvp + S.n + 1);
 }
 
-__device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+// pair blocks of PCG A for n pairs
+__device__ __forceinline__ int pair_blocks(int64_t n) { return (int)((n + kPcgABlock - 1) / kPcgABlock); }
 
 // Partial product of one BELL row: lane `part` of the row's kLanesPerRow
 // lanes takes slots part, part + kLanesPerRow, ... The vector applied is
@@ -163,7 +164,7 @@ __device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const
 // q = K_el d for its rows, a pair block applies each active pair's
 // off-diagonal blocks to its own four vertices; both write d.q partials.
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_pcg_A(Launch L, int it)
+__global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
@@ -407,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_mas_invert(Launch L)
 template <class R>
 __device__ __forceinline__ R pcg_alpha(const Launch &L, const SceneDev &S, int s, int it)
 {
-    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, blocks_for(L.out[s].n_pair));
+    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, pair_blocks(L.out[s].n_pair));
     return (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
 }
 
@@ -1078,11 +1079,11 @@ void launch_hess_apply(Batch &b)
     // pair phase as set by the incidence build of the same assembly
     if (mixed(b)) {
         IPC_LAUNCH(b, k_spmv_pairs<float>, kPhActT, kBlock);
-        IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kBlock);
+        IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kPcgABlock);
         IPC_LAUNCH(b, k_spmv_contact<float>, kPhVertH, kBlock);
     } else {
         IPC_LAUNCH(b, k_spmv_pairs<double>, kPhActT, kBlock);
-        IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kBlock);
+        IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kPcgABlock);
         IPC_LAUNCH(b, k_spmv_contact<double>, kPhVertH, kBlock);
     }
 }
@@ -1095,7 +1096,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     bool mx = mixed(b);
     std::vector<int32_t> nab(ns, 0);
     for (size_t i = 0; i < ns; ++i)
-        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]));
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]), kPcgABlock);
     b.set_phase(kPhPcgA, nab);
     set_heavy_phase(b);
     std::vector<int32_t> nbb(ns, 0);
@@ -1115,6 +1116,21 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     }
     iters.assign(ns, 0);
     hit_cap.assign(ns, 0);
+    // algorithmic bytes of one A launch over the list: every stored 3x3 block
+    // (values and column) once; per vertex the z and d gathers, the d and q
+    // writes and its row pointer; per pair its off-diagonal blocks and ids
+    auto spmv_bytes = [&]() {
+        double v = 0.0;
+        const double rs = mx ? 4.0 : 8.0;
+        for (size_t i = 0; i < ns; ++i) {
+            if (nab[i] == 0) continue;
+            const Scene &s = *b.sc[i];
+            v += (9 * rs + 4) * (double)s.nnzb + (12 * rs + 4) * (double)s.h.n +
+                 (108 * rs + 16) * (double)pair_count(s, b.h_out[i]);
+        }
+        return v;
+    };
+    double a_bytes = b.prof() ? spmv_bytes() : 0.0;
     int it = 1;
     int chunk = last > 16 ? (last * 7) / 8 : 8;
     hipEvent_t ev[2];
@@ -1126,10 +1142,10 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             bool timed = b.prof() && (it & 3) == 1;  // time one launch in four when profiling
             if (timed) b.prof_begin(kProfPcgA, ev);
             if (mx)
-                IPC_LAUNCH(b, k_pcg_A<float>, kPhPcgA, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_A<float>, kPhPcgA, kPcgABlock, it);
             else
-                IPC_LAUNCH(b, k_pcg_A<double>, kPhPcgA, kBlock, it);
-            if (timed) b.prof_end(kProfPcgA, ev);
+                IPC_LAUNCH(b, k_pcg_A<double>, kPhPcgA, kPcgABlock, it);
+            if (timed) b.prof_end(kProfPcgA, ev, a_bytes);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)
                 IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it);
@@ -1144,6 +1160,18 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && !b.h_out[i].pcg_done) all = false;
         if (all) break;
         chunk = 8;
+        // scenes that finished leave the remaining launches of the list
+        bool shrink = false;
+        for (size_t i = 0; i < ns; ++i)
+            if (nab[i] > 0 && b.h_out[i].pcg_done) {
+                nab[i] = nbb[i] = 0;
+                shrink = true;
+            }
+        if (shrink) {
+            b.set_phase(kPhPcgA, nab);
+            b.set_phase(kPhPcgB, nbb);
+            if (b.prof()) a_bytes = spmv_bytes();
+        }
     }
     for (size_t i = 0; i < ns; ++i) {
         if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;

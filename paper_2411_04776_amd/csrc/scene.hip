@@ -283,7 +283,7 @@ void grow_active(Scene &s, int64_t need)
     int32_t *ni = st.get<int32_t>(nc), *nv = st.get<int32_t>(4 * (size_t)nc);
     void *ng = st.get_bytes(12 * (size_t)nc * rs), *nh = st.get_bytes(144 * (size_t)nc * rs);
     void *ny = st.get_bytes(12 * (size_t)nc * rs);
-    double *npp = st.get<double>((size_t)nblocks(nc) + 1);
+    double *npp = st.get<double>((size_t)nblocks(nc, kPcgABlock) + 1);
     int32_t *nl = st.get<int32_t>(4 * (size_t)nc), *nr = st.get<int32_t>(4 * (size_t)nc);
     int32_t *nt = st.get<int32_t>(4 * (size_t)nc);
     st.commit();
@@ -809,8 +809,8 @@ Batch::~Batch()
 {
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto &p : ev_pending) {
-        ev_pool.push_back(p.second.first);
-        ev_pool.push_back(p.second.second);
+        ev_pool.push_back(p.a);
+        ev_pool.push_back(p.b);
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(d_list);
@@ -918,7 +918,7 @@ void Batch::read_out()
     for (size_t i = 0; i < sc.size(); ++i) sc[i]->last = h_out[i];
 }
 
-bool Batch::prof() const { return sc.size() == 1 && sc[0]->prof; }
+bool Batch::prof() const { return sink || (sc.size() == 1 && sc[0]->prof); }
 
 void Batch::prof_begin(int kernel, hipEvent_t *pair)
 {
@@ -936,11 +936,11 @@ void Batch::prof_begin(int kernel, hipEvent_t *pair)
     IPC_HIP(hipEventRecord(pair[0], stream));
 }
 
-void Batch::prof_end(int kernel, hipEvent_t *pair)
+void Batch::prof_end(int kernel, hipEvent_t *pair, double bytes)
 {
     if (!prof()) return;
     IPC_HIP(hipEventRecord(pair[1], stream));
-    ev_pending.push_back({kernel, {pair[0], pair[1]}});
+    ev_pending.push_back({kernel, pair[0], pair[1], bytes});
 }
 
 void Batch::prof_collect()
@@ -948,14 +948,23 @@ void Batch::prof_collect()
     if (ev_pending.empty()) return;
     for (auto &p : ev_pending) {
         float ms = 0.f;
-        IPC_HIP(hipEventSynchronize(p.second.second));
-        IPC_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
-        if (!sc.empty()) {
-            sc[0]->prof_acc[p.first].launches++;
-            sc[0]->prof_acc[p.first].ms += ms;
+        IPC_HIP(hipEventSynchronize(p.b));
+        IPC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        ProfAcc *acc = nullptr;
+        std::unique_lock<std::mutex> lk;
+        if (sink) {
+            lk = std::unique_lock<std::mutex>(sink->mu);
+            acc = &sink->acc[p.kernel];
+        } else if (!sc.empty()) {
+            acc = &sc[0]->prof_acc[p.kernel];
         }
-        ev_pool.push_back(p.second.first);
-        ev_pool.push_back(p.second.second);
+        if (acc) {
+            acc->launches++;
+            acc->ms += ms;
+            acc->bytes += p.bytes;
+        }
+        ev_pool.push_back(p.a);
+        ev_pool.push_back(p.b);
     }
     ev_pending.clear();
 }
@@ -1379,6 +1388,8 @@ class Engine {
         std::vector<StepCtl> ctl;
         bool changed = true;
     } lists[2];
+    ProfSink prof;
+    std::atomic<bool> prof_on{false};
 
     ~Engine()
     {
@@ -1449,6 +1460,7 @@ class Engine {
     {
         size_t ns = l.slots.size();
         if (!ns) return;
+        l.b.sink = prof_on.load() ? &prof : nullptr;
         if (l.changed) {
             std::vector<Scene *> sc(ns);
             for (size_t i = 0; i < ns; ++i) sc[i] = l.slots[i].s;
@@ -1963,6 +1975,25 @@ int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st)
     return rc;
 }
 
+int32_t ipc_batch_profile(ipc_batch *b, int32_t enable)
+{
+    if (!b) return IPC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(b->prof.mu);
+    for (auto &a : b->prof.acc) a = ProfAcc{};
+    b->prof_on = enable != 0;
+    return IPC_OK;
+}
+
+int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total, double *bytes_total)
+{
+    if (!b || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(b->prof.mu);
+    if (launches) *launches = b->prof.acc[kernel].launches;
+    if (ms_total) *ms_total = b->prof.acc[kernel].ms;
+    if (bytes_total) *bytes_total = b->prof.acc[kernel].bytes;
+    return IPC_OK;
+}
+
 const char *ipc_status_str(int32_t s)
 {
     switch (s) {
@@ -2200,7 +2231,7 @@ int32_t ipcx_profile(ipc_scene *s, int32_t enable)
         IPC_HIP(hipStreamSynchronize(s->stream));
         s->solo->prof_collect();
         s->prof = enable != 0;
-        for (auto &a : s->prof_acc) a = Scene::ProfAcc{};
+        for (auto &a : s->prof_acc) a = ProfAcc{};
         return IPC_OK;
     IPC_HOOK_END(s)
 }

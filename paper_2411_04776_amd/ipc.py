@@ -98,6 +98,8 @@ _SIGS = {
     "ipc_batch_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(ipc_step_req), _I64]),
     "ipc_batch_poll": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(ipc_step_stats)]),
     "ipc_batch_wait": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(ipc_step_stats)]),
+    "ipc_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "ipc_batch_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D, _D]),
     "ipc_status_str": (C.c_char_p, [C.c_int32]),
     "ipc_last_error": (C.c_int32, [C.c_char_p, C.c_size_t]),
     "ipcx_begin_step": (C.c_int32, [C.c_void_p, C.POINTER(ipc_step_req)]),
@@ -498,3 +500,15 @@ class Batch:
         if rc < 0:
             raise IPCError(rc, "ipc_batch_wait")
         return rc, st
+
+    def profile(self, enable=True):
+        _check(lib().ipc_batch_profile(self.ptr, int(bool(enable))), "ipc_batch_profile")
+
+    def profile_read(self, kernel):
+        """(timed launches, summed ms, summed algorithmic bytes) of a kernel class."""
+        n = np.zeros(1, dtype=np.int64)
+        ms = np.zeros(1)
+        by = np.zeros(1)
+        _check(lib().ipc_batch_profile_read(self.ptr, int(kernel), n.ctypes.data_as(_I64), _d(ms), _d(by)),
+               "ipc_batch_profile_read")
+        return int(n[0]), float(ms[0]), float(by[0])

@@ -134,3 +134,24 @@ def test_busy_scene_rejected(ipc):
     rc, st = g2.step()  # idle again: a plain step works
     assert rc in (0, 4)
     b.close()
+
+
+def test_engine_profile_counts(ipc):
+    """The engine's kernel timing: timed SpMV launches, positive time and the
+    algorithmic bytes of the list (at least every stored block once per
+    timed launch); disabling resets nothing until enabled again."""
+    scs = mix()[:3]
+    gs = [ipc.GelScene(sc, precision=1, pcg_tol=PCG_TOL[1]) for sc in scs]
+    b = ipc.Batch()
+    b.profile(True)
+    for t in b.submit(gs):
+        rc, _ = b.wait(t)
+        assert rc == 0
+    n, ms, by = b.profile_read(0)
+    say(f"  engine SpMV: {n} timed launches, {ms:.3f} ms, {by / max(n, 1):.0f} B per launch")
+    assert n > 0 and ms > 0
+    min_bytes = min(40 * g.matrix_info()["nnzb"] for g in gs)
+    assert by >= n * min_bytes
+    b.profile(False)
+    assert b.profile_read(0)[0] == 0
+    b.close()
