@@ -41,9 +41,10 @@ namespace ipcg {
 constexpr int kWave = 64;         // wavefront width on gfx950
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
-constexpr int kLanesPerRow = 2;   // SpMV lanes per matrix row
-constexpr int kPcgABlock = 128;   // threads per SpMV block (PCG A)
-constexpr int kRowsPerBlock = kPcgABlock / kLanesPerRow;  // matrix rows per SpMV block
+constexpr int kSpmvStreams = 2;   // partial sums per SpMV row (slots k, k + 2, ...), added in stream order
+constexpr int kRowsPerBlock = 64; // matrix rows per SpMV block (PCG A), a thread or two lanes each
+constexpr int kPairsPerBlock = 64;  // contact pairs per pair block of PCG A
+constexpr int64_t kSpmvOneLaneRows = 65536;  // lists with at least this many rows: one thread per row
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
 constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its cells)

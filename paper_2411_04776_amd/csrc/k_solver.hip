@@ -44,10 +44,10 @@ __device__ __forceinline__ double *rz_slot(const SceneDev &S, int it)
 }
 
 // pair blocks of PCG A for n pairs
-__device__ __forceinline__ int pair_blocks(int64_t n) { return (int)((n + kPcgABlock - 1) / kPcgABlock); }
+__device__ __forceinline__ int pair_blocks(int64_t n) { return (int)((n + kPairsPerBlock - 1) / kPairsPerBlock); }
 
-// Partial product of one BELL row: lane `part` of the row's kLanesPerRow
-// lanes takes slots part, part + kLanesPerRow, ... The vector applied is
+// Partial product of one BELL row: stream `part` of the row's kSpmvStreams
+// takes slots part, part + kSpmvStreams, ... The vector applied is
 // z + beta d_prev (formed at the gathered column) when beta_on, else z.
 template <class R>
 __device__ __forceinline__ void bell_row_part(const SceneDev &S, int row, int part, const R *__restrict__ z,
@@ -59,7 +59,7 @@ __device__ __forceinline__ void bell_row_part(const SceneDev &S, int row, int pa
     const int32_t *__restrict__ bcol = S.bcol;
     R y0 = R(0), y1 = R(0), y2 = R(0);
 #pragma unroll 2
-    for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
+    for (int slot = s0 + part; slot < s1; slot += kSpmvStreams) {
         int col = bcol[(int64_t)slot * kSlice + lane];
         if (col >= 0) {
             const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void bell_row_part2(const SceneDev &S, int row, int p
     const int32_t *__restrict__ bcol = S.bcol;
     R a0 = R(0), a1 = R(0), a2 = R(0), b0 = R(0), b1 = R(0), b2 = R(0);
 #pragma unroll 2
-    for (int slot = s0 + part; slot < s1; slot += kLanesPerRow) {
+    for (int slot = s0 + part; slot < s1; slot += kSpmvStreams) {
         int col = bcol[(int64_t)slot * kSlice + lane];
         if (col >= 0) {
             const R *A = bval + (int64_t)slot * 9 * kSlice + lane;
@@ -163,28 +163,38 @@ __device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const
 // the stop and forms beta; the row block finishes d = z + beta d_prev and
 // q = K_el d for its rows, a pair block applies each active pair's
 // off-diagonal blocks to its own four vertices; both write d.q partials.
-template <class R>
-__global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
+// LPR lanes per row (1: a thread runs both slot streams, for coalesced rows in
+// large lists; 2: a lane per stream, for latency): the arithmetic is the same
+// (streams added in order, the block's d.q summed by one wavefront over its 64
+// rows or pairs), so a scene gets the same bits in either form.
+template <class R, int LPR>
+__global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it)
 {
+    constexpr int NP = kSpmvStreams / LPR;  // streams per thread
+    __shared__ double sdq[kRowsPerBlock];
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     const R *z = as<R>(S.z);
     const R *dold = as<R>((it & 1) ? S.dB : S.dA);
     const bool bon = it > 1;
-    // kLanesPerRow consecutive lanes share a row
-    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
-    int part = lane % kLanesPerRow;
+    const int t = (int)threadIdx.x, rloc = t / LPR, part0 = t % LPR;
+    int row = lb * kRowsPerBlock + rloc;
     bool rows = lb < S.nb_rows;
     bool live = rows && row < S.n;
-    double yz[3] = {0.0, 0.0, 0.0}, yd[3] = {0.0, 0.0, 0.0};
-    if (live) bell_row_part2<R>(S, row, part, z, dold, bon, yz, yd);
+    double yz[NP][3], yd[NP][3];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) yz[q][c] = yd[q][c] = 0.0;
+    if (live)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) bell_row_part2<R>(S, row, part0 + q, z, dold, bon, yz[q], yd[q]);
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
         double rz0 = wave_reduce_partials(rz_slot(S, 0), S.pcg_nvp + L.out[s].n_heavy);
         if (!(rz0 > 0.0)) {
-            if (lb == 0 && threadIdx.x == 0) {
+            if (lb == 0 && t == 0) {
                 S.pcg->done = 1;
                 S.pcg->iters = 0;
                 L.out[s].pcg_done = 1;
@@ -192,7 +202,7 @@ __global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
             }
             return;
         }
-        if (lb == 0 && threadIdx.x == 0) {
+        if (lb == 0 && t == 0) {
             S.pcg->stop = S.pcg_tol2 * rz0;
             S.pcg->rzv[1] = rz0;
         }
@@ -200,7 +210,7 @@ __global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
         double rz_cur = wave_reduce_partials(rz_slot(S, it - 1), S.pcg_nvp + L.out[s].n_heavy);
         bool conv = rz_cur <= S.pcg->stop;
         if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
-            if (lb == 0 && threadIdx.x == 0) {
+            if (lb == 0 && t == 0) {
                 S.pcg->done = 1;
                 S.pcg->iters = it - 1;
                 L.out[s].pcg_done = conv ? 1 : 2;
@@ -211,7 +221,7 @@ __global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
         // r.z of iteration it - 2, kept by block 0 of the previous launch
         double rz_prev = S.pcg->rzv[(it - 1) & 1];
         beta = rz_cur / rz_prev;
-        if (lb == 0 && threadIdx.x == 0) S.pcg->rzv[it & 1] = rz_cur;
+        if (lb == 0 && t == 0) S.pcg->rzv[it & 1] = rz_cur;
     }
     R rb = (R)beta;
     double dq = 0.0;
@@ -221,11 +231,12 @@ __global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
         double y[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            y[c] = yz[c] + beta * yd[c];
+            y[c] = yz[0][c] + beta * yd[0][c];
 #pragma unroll
-            for (int o = 1; o < kLanesPerRow; o <<= 1) y[c] += __shfl_xor(y[c], o, kWave);
+            for (int k = 1; k < NP; ++k) y[c] += yz[k][c] + beta * yd[k][c];
+            if (LPR == 2) y[c] += __shfl_xor(y[c], 1, kWave);
         }
-        if (live && part == 0) {
+        if (live && part0 == 0) {
             for (int c = 0; c < 3; ++c) {
                 R dv = bon ? z[3 * row + c] + rb * dold[3 * row + c] : z[3 * row + c];
                 R qv = (R)y[c];
@@ -234,14 +245,23 @@ __global__ void __launch_bounds__(kPcgABlock) k_pcg_A(Launch L, int it)
                 dq += (double)dv * (double)qv;
             }
         }
-        dq = block_sum_all(dq);
-        if (threadIdx.x == 0) S.pcg_part[lb] = dq;
+        if (LPR == 2) {
+            if (part0 == 0) sdq[rloc] = dq;
+            __syncthreads();
+            if (t < kWave) dq = sdq[t];
+        }
+        if (t < kWave) {
+            dq = wave_sum(dq);
+            if (t == 0) S.pcg_part[lb] = dq;
+        }
     } else {
         int pb = lb - S.nb_rows;
-        int64_t p = (int64_t)pb * blockDim.x + threadIdx.x;
-        if (p < L.out[s].n_pair) dq = pair_apply<R>(S, p, z, dold, rb, bon);
-        dq = block_sum_all(dq);
-        if (threadIdx.x == 0) S.pcg_pair[pb] = dq;
+        int64_t p = (int64_t)pb * kPairsPerBlock + t;
+        if (t < kPairsPerBlock && p < L.out[s].n_pair) dq = pair_apply<R>(S, p, z, dold, rb, bon);
+        if (t < kWave) {
+            dq = wave_sum(dq);
+            if (t == 0) S.pcg_pair[pb] = dq;
+        }
     }
 }
 
@@ -711,16 +731,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv_rows(Launch L)
     const SceneDev &S = *L.sc[s];
     const R *v = as<R>(S.dB);
     R *y = as<R>(S.q);
-    int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int row = lb * kRowsPerBlock + wave * (kWave / kLanesPerRow) + lane / kLanesPerRow;
-    int part = lane % kLanesPerRow;
-    double o[3] = {0.0, 0.0, 0.0};
-    bool live = row < S.n;
-    if (live) bell_row_part<R>(S, row, part, v, nullptr, R(0), false, o);
-    for (int c = 0; c < 3; ++c)
-        for (int k = 1; k < kLanesPerRow; k <<= 1) o[c] += __shfl_xor(o[c], k, kWave);
-    if (live && part == 0)
-        for (int c = 0; c < 3; ++c) y[3 * row + c] = (R)o[c];
+    int row = lb * kRowsPerBlock + (int)threadIdx.x;  // a thread per row, both slot streams
+    if (row >= S.n) return;
+    double o[3] = {0.0, 0.0, 0.0}, o1[3];
+    bell_row_part<R>(S, row, 0, v, nullptr, R(0), false, o);
+    bell_row_part<R>(S, row, 1, v, nullptr, R(0), false, o1);
+    for (int c = 0; c < 3; ++c) y[3 * row + c] = (R)(o[c] + o1[c]);
 }
 
 template <class R>
@@ -1079,11 +1095,11 @@ void launch_hess_apply(Batch &b)
     // pair phase as set by the incidence build of the same assembly
     if (mixed(b)) {
         IPC_LAUNCH(b, k_spmv_pairs<float>, kPhActT, kBlock);
-        IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kPcgABlock);
+        IPC_LAUNCH(b, k_spmv_rows<float>, kPhSlice, kRowsPerBlock);
         IPC_LAUNCH(b, k_spmv_contact<float>, kPhVertH, kBlock);
     } else {
         IPC_LAUNCH(b, k_spmv_pairs<double>, kPhActT, kBlock);
-        IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kPcgABlock);
+        IPC_LAUNCH(b, k_spmv_rows<double>, kPhSlice, kRowsPerBlock);
         IPC_LAUNCH(b, k_spmv_contact<double>, kPhVertH, kBlock);
     }
 }
@@ -1096,7 +1112,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     bool mx = mixed(b);
     std::vector<int32_t> nab(ns, 0);
     for (size_t i = 0; i < ns; ++i)
-        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]), kPcgABlock);
+        if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i]) nab[i] = b.sc[i]->h.nb_rows + nblocks(pair_count(*b.sc[i], b.h_out[i]), kPairsPerBlock);
     b.set_phase(kPhPcgA, nab);
     set_heavy_phase(b);
     std::vector<int32_t> nbb(ns, 0);
@@ -1131,6 +1147,11 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         return v;
     };
     double a_bytes = b.prof() ? spmv_bytes() : 0.0;
+    // large lists are bandwidth-bound: a thread per row reads the slices fully coalesced
+    int64_t rows_total = 0;
+    for (size_t i = 0; i < ns; ++i)
+        if (nab[i] > 0) rows_total += b.sc[i]->h.n;
+    const bool one_lane = rows_total >= kSpmvOneLaneRows;
     int it = 1;
     int chunk = last > 16 ? (last * 7) / 8 : 8;
     hipEvent_t ev[2];
@@ -1141,10 +1162,17 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         for (int j = 0; j < c; ++j, ++it) {
             bool timed = b.prof() && (it & 3) == 1;  // time one launch in four when profiling
             if (timed) b.prof_begin(kProfPcgA, ev);
-            if (mx)
-                IPC_LAUNCH(b, k_pcg_A<float>, kPhPcgA, kPcgABlock, it);
-            else
-                IPC_LAUNCH(b, k_pcg_A<double>, kPhPcgA, kPcgABlock, it);
+            if (one_lane) {
+                if (mx)
+                    IPC_LAUNCH(b, (k_pcg_A<float, 1>), kPhPcgA, kRowsPerBlock, it);
+                else
+                    IPC_LAUNCH(b, (k_pcg_A<double, 1>), kPhPcgA, kRowsPerBlock, it);
+            } else {
+                if (mx)
+                    IPC_LAUNCH(b, (k_pcg_A<float, 2>), kPhPcgA, 2 * kRowsPerBlock, it);
+                else
+                    IPC_LAUNCH(b, (k_pcg_A<double, 2>), kPhPcgA, 2 * kRowsPerBlock, it);
+            }
             if (timed) b.prof_end(kProfPcgA, ev, a_bytes);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)

@@ -283,7 +283,7 @@ void grow_active(Scene &s, int64_t need)
     int32_t *ni = st.get<int32_t>(nc), *nv = st.get<int32_t>(4 * (size_t)nc);
     void *ng = st.get_bytes(12 * (size_t)nc * rs), *nh = st.get_bytes(144 * (size_t)nc * rs);
     void *ny = st.get_bytes(12 * (size_t)nc * rs);
-    double *npp = st.get<double>((size_t)nblocks(nc, kPcgABlock) + 1);
+    double *npp = st.get<double>((size_t)nblocks(nc, kPairsPerBlock) + 1);
     int32_t *nl = st.get<int32_t>(4 * (size_t)nc), *nr = st.get<int32_t>(4 * (size_t)nc);
     int32_t *nt = st.get<int32_t>(4 * (size_t)nc);
     st.commit();

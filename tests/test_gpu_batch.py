@@ -155,3 +155,25 @@ def test_engine_profile_counts(ipc):
     b.profile(False)
     assert b.profile_read(0)[0] == 0
     b.close()
+
+
+def test_large_list_bitwise_equals_alone(ipc):
+    """A list above 65536 matrix rows runs the SpMV with a thread per row,
+    a scene alone with two lanes per row; both forms give the same bits."""
+    scs = [S.uneven_scene(6000 + k, steps=2) for k in range(16)]
+    rows = sum(len(sc.X) + len(sc.Y) for sc in scs)
+    say(f"  list rows {rows}")
+    assert rows >= 65536
+    ref = []
+    for sc in scs:
+        g = ipc.GelScene(sc, precision=1, pcg_tol=PCG_TOL[1])
+        rc, st = g.step()
+        ref.append((rc, st.newton_iters, st.pcg_iters, g.x))
+        g.close()
+    gs = [ipc.GelScene(sc, precision=1, pcg_tol=PCG_TOL[1]) for sc in scs]
+    b = ipc.Batch()
+    for i, t in enumerate(b.submit(gs)):
+        rc, st = b.wait(t)
+        assert (rc, st.newton_iters, st.pcg_iters) == ref[i][:3]
+        assert np.array_equal(gs[i].x, ref[i][3])
+    b.close()
