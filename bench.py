@@ -35,6 +35,11 @@ def precond_code(args):
     return ipc.IPC_PRECOND_JACOBI if args.precond == "jacobi" else ipc.IPC_PRECOND_MULTILEVEL
 
 
+def barrier_code(args):
+    from paper_2411_04776_amd import ipc
+    return ipc.IPC_BARRIER_GAUSS_NEWTON if args.barrier_hessian == "gauss-newton" else ipc.IPC_BARRIER_PROJECTED
+
+
 def pcg_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -83,6 +88,8 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
     ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel",
                     help="PCG preconditioner: additive multilevel aggregates or block-Jacobi")
+    ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected",
+                    help="pair barrier Hessian: PSD-projected exact Hessian or the Gauss-Newton form")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="scenes of the batched uneven-scene leg (0: skip)")
@@ -95,8 +102,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (scenes shard across GPUs "
-              "without communication; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (scenes are independent and "
+              "would shard across GPUs without communication). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.warmup + args.steps > 50:
         print("warmup + steps must fit the 50-step trajectory", file=sys.stderr)
@@ -118,7 +125,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
         return
     sc = scenes.config2(args.seed)
-    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args))
+    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args),
+                     barrier_hessian=barrier_code(args))
     for _ in range(args.warmup):
         rc, st = g.step()
         print(f"warmup step {g.step_index}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
@@ -175,7 +183,8 @@ def main():
         "config": {"workload": f"40x50x8 gel (16000 v, 80262 tets), {sc.meta['kind']} indenter seed "
                                f"{args.seed}, 1.5 mm over 50 steps, dt 5e-3 s, FP64, steps "
                                f"{args.warmup + 1}-{args.warmup + args.steps}",
-                   "precision": "fp64", "pcg_tol": args.pcg_tol, "precond": args.precond, "newton_tol_m": sc.newton_tol,
+                   "precision": "fp64", "pcg_tol": args.pcg_tol, "precond": args.precond,
+                   "barrier_hessian": args.barrier_hessian, "newton_tol_m": sc.newton_tol,
                    "dhat_m": sc.dhat, "kappa": sc.kappa},
         "roofline": roofline,
     }
@@ -200,7 +209,7 @@ def batch_leg(args, ipc, scenes, torch):
     t0 = time.perf_counter()
     scs = [scenes.config3_scene(i) for i in range(args.batch)]
     gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol,
-                         precond=precond_code(args)) for sc in scs]
+                         precond=precond_code(args), barrier_hessian=barrier_code(args)) for sc in scs]
     build_s = time.perf_counter() - t0
     nv = sum(len(sc.X) for sc in scs)
     nt = sum(len(sc.T) for sc in scs)

@@ -57,6 +57,16 @@ extern "C" {
 #define IPC_PRECOND_MULTILEVEL 0
 #define IPC_PRECOND_JACOBI 1
 
+/* Pair barrier Hessian. PROJECTED: the exact Hessian of kappa w b(d) with its
+ * negative eigenvalues clamped to zero (12x12 per pair). GAUSS_NEWTON: the
+ * form kappa w b''(d) grad d grad d^T, PSD and rank one by construction (no
+ * eigen-decomposition). The paper names GIPC's Gauss-Newton treatment of the
+ * barrier only by its title; this form is the library's reading of it: the
+ * only term of the exact Hessian that is an outer product of first
+ * derivatives with a non-negative weight. The gradient is exact in both. */
+#define IPC_BARRIER_PROJECTED 0
+#define IPC_BARRIER_GAUSS_NEWTON 1
+
 #define IPC_HOST 0
 #define IPC_DEVICE 1
 
@@ -94,6 +104,7 @@ typedef struct ipc_scene_desc {
     int32_t pcg_max_iter;     /* 0: 10 * 3 * (all vertices) */
     int32_t ccd_max_iter;     /* 0: 10000 */
     int32_t precond;          /* IPC_PRECOND_MULTILEVEL (0) or IPC_PRECOND_JACOBI */
+    int32_t barrier_hessian;  /* IPC_BARRIER_PROJECTED (0) or IPC_BARRIER_GAUSS_NEWTON */
 } ipc_scene_desc;
 
 /* Device memory and stream plumbing. alloc/free may be NULL (then hipMalloc /

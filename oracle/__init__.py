@@ -21,7 +21,8 @@ CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast
 
 
 def build(force: bool = False) -> str:
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "ipc_oracle.h")))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", _LIB, "-lm"])
     return _LIB
 
@@ -34,7 +35,7 @@ class Params(C.Structure):
         ("gravity", C.c_double * 3), ("ccd_s", C.c_double), ("ls_min_ratio", C.c_double),
         ("self_contact", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32),
-        ("mu_fric", C.c_double), ("eps_v", C.c_double),
+        ("mu_fric", C.c_double), ("eps_v", C.c_double), ("barrier_hessian", C.c_int32),
     ]
 
 
@@ -204,6 +205,7 @@ def barrier_scalar(d, dhat):
 
 
 def pair_barrier(kind, x12, dhat, kappa, eps_x, project=True):
+    """project: False/0 exact Hessian, True/1 PSD-projected, 2 Gauss-Newton form."""
     g = np.zeros(12)
     H = np.zeros(144)
     E = lib().ora_pair_barrier(kind, _d(f64(x12)), dhat, kappa, eps_x, int(project), _d(g), _d(H))

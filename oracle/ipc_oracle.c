@@ -10,14 +10,14 @@
  * same way as the GPU path's FP64 contact code.
  *
  * The paper (TacEx) integrates GIPC, a GPU variant of the IPC model it cites in
- * "Choice of the Simulation Methods"; one GIPC step computes new positions of
- * all soft vertices after the attachment targets are set ("General GIPC
- * Simulation Pipeline", "GIPC Attachments"). The paper prints no formulas for
- * that step, so every formula here is the standard IPC formulation of the cited
- * IPC work (Li et al. 2020): incremental potential with a log barrier on
- * unsigned point-triangle / edge-edge distances, PSD-projected Newton, CCD-
- * filtered backtracking line search. Choices the paper leaves open are listed
- * in the design doc as readings.
+ * "Choice of the Simulation Methods"; one GIPC step updates every soft vertex
+ * once the attachment targets are in place ("General GIPC Simulation
+ * Pipeline", "GIPC Attachments"). The paper prints no formulas for that step,
+ * so every formula here is the standard IPC formulation of the cited IPC work
+ * (Li et al. 2020): incremental potential with a log barrier on unsigned
+ * point-triangle / edge-edge distances, PSD-projected Newton, CCD-filtered
+ * backtracking line search. Where the paper leaves a choice open, the choice
+ * taken is stated at the place it is made.
  */
 #include "ipc_oracle.h"
 
@@ -622,8 +622,16 @@ static double ee_cross_sq(const double *x12, double *gc, double *Hc)
     return c;
 }
 
-/* kappa * w * b(d) for one pair with gradient and (optionally projected)
- * Hessian. w = 1 for PT; w = mollifier for EE. Returns the energy. */
+/* kappa * w * b(d) for one pair with gradient and Hessian. w = 1 for PT;
+ * w = mollifier for EE. project: 0 the exact Hessian, 1 its PSD projection,
+ * 2 the Gauss-Newton form kappa w b''(d) grad d grad d^T. The paper names
+ * GIPC's Gauss-Newton treatment of the barrier only by its title, so this form
+ * is a reading: of the exact Hessian it keeps the one term that is an outer
+ * product of first derivatives with a non-negative weight (b'' > 0 on
+ * (0, dhat), w >= 0) and drops the distance curvature b' grad^2 d, the
+ * mollifier's own curvature and the mollifier-distance cross terms; it is PSD
+ * with rank one by construction. The gradient is exact in every mode.
+ * Returns the energy. */
 double ora_pair_barrier(int32_t kind, const double *x12, double dhat, double kappa, double eps_x,
                         int32_t project, double *g12, double *H144)
 {
@@ -650,7 +658,10 @@ double ora_pair_barrier(int32_t kind, const double *x12, double dhat, double kap
             if (kind == 1) v += b3[0] * m3[1] * gc[a];
             g12[a] = kappa * v;
         }
-    if (H144) {
+    if (H144 && project == 2) {
+        for (int a = 0; a < 12; ++a)
+            for (int b = 0; b < 12; ++b) H144[a * 12 + b] = kappa * (w * b3[2] * gd[a] * gd[b]);
+    } else if (H144) {
         for (int a = 0; a < 12; ++a)
             for (int b = 0; b < 12; ++b) {
                 double v = w * (b3[2] * gd[a] * gd[b] + b3[1] * Hd[a * 12 + b]);
@@ -1430,7 +1441,7 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
         double g12[12];
         double eps_x = c[0] == 1 ? cand_eps_x(s, c) : 0.0;
         double *H = A->Hc + 144 * A->n_c;
-        ora_pair_barrier(c[0], x12, s->prm.dhat, s->prm.kappa, eps_x, 1, g12, H);
+        ora_pair_barrier(c[0], x12, s->prm.dhat, s->prm.kappa, eps_x, s->prm.barrier_hessian == 1 ? 2 : 1, g12, H);
         memcpy(A->cv + 4 * A->n_c, v, sizeof v);
         for (int a = 0; a < 4; ++a)
             for (int k = 0; k < 3; ++k) A->g[3 * v[a] + k] += g12[3 * a + k];

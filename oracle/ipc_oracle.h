@@ -9,11 +9,12 @@
  *
  * What it follows: the paper integrates the IPC soft-body model (cited in its
  * "Choice of the Simulation Methods" section: intersection- and inversion-free,
- * any material parameters) through GIPC, whose step "computes new positions"
- * of all soft vertices after attachment targets are set (section "General
- * GIPC Simulation Pipeline"). The paper prints no formula for that step, so the
- * energy, barrier, distances, CCD, PCG and line search below are the standard
- * formulation of the cited IPC work; each reading is listed in the design doc.
+ * any material parameters) through GIPC, whose step updates every soft vertex
+ * once the attachment targets are in place (section "General GIPC Simulation
+ * Pipeline"). The paper prints no formula for that step, so the energy,
+ * barrier, distances, CCD, PCG and line search below are the standard
+ * formulation of the cited IPC work; where the paper leaves a choice open, the
+ * choice taken is stated at the place it is made.
  *
  * Conventions shared with the product library by *specification only* (no
  * shared code): vertex ids = gel vertices then indenter vertices; primitive
@@ -43,6 +44,7 @@ typedef struct ora_params {
     int32_t ccd_max_iter;
     double mu_fric;             /* friction coefficient (0: no friction) */
     double eps_v;               /* friction velocity threshold (m/s); the smoothing length is eps_v h */
+    int32_t barrier_hessian;    /* 0: PSD-projected pair Hessians, 1: Gauss-Newton form (ora_pair_barrier) */
 } ora_params;
 
 typedef struct ora_stats {
@@ -120,7 +122,8 @@ double ora_ee_distance(const double *x12, int32_t *type);
 /* kind 0 = PT, 1 = EE; grad/hess of the unsigned distance, unprojected */
 double ora_distance_derivs(int32_t kind, const double *x12, double *g12, double *H144);
 void ora_barrier_scalar(double d, double dhat, double *b3);
-/* pair barrier energy (kappa * w * b), gradient and Hessian; project = apply PSD projection */
+/* pair barrier energy (kappa * w * b), gradient and Hessian; project: 0 exact,
+ * 1 PSD-projected, 2 Gauss-Newton kappa w b'' grad d grad d^T */
 double ora_pair_barrier(int32_t kind, const double *x12, double dhat, double kappa, double eps_x,
                         int32_t project, double *g12, double *H144);
 double ora_accd(int32_t kind, const double *x12, const double *p12, double s, double tmax,

@@ -101,6 +101,7 @@ struct SceneDev {
     int self_contact, ccd_max_iter, precision, nb_vert, nb_rows, pcg_maxit;
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
     double mu_fric, eps_fric;  // friction coefficient, smoothing length eps_v h
+    int barrier_gn;            // 1: Gauss-Newton pair Hessians kappa w b'' grad d grad d^T
     double pose[12];
     double alpha;      // line-search trial step
     // state (FP64)
@@ -207,7 +208,7 @@ struct Params {
     double grav[3];
     double mu_fric, eps_v;
     double ccd_s, ls_min_ratio;
-    int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter, precond;
+    int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter, precond, barrier_hessian;
 };
 
 // Device allocation through the runtime's callbacks (PyTorch's caching

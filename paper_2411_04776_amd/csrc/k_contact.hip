@@ -592,11 +592,12 @@ __device__ __forceinline__ void rr_pair(int round, int i, int &p, int &q)
     q = a < b ? b : a;
 }
 
-// kappa * w * b(d) for each active pair: gradient and PSD-projected Hessian.
-// One wavefront per pair: lanes evaluate Hessian entries, then a parallel
-// cyclic Jacobi (six disjoint rotations per round) diagonalises the 12x12 in
-// LDS and negative eigenvalues are clamped to zero. Matrices that are already
-// PSD are kept as assembled.
+// kappa * w * b(d) for each active pair: gradient and PSD Hessian.
+// One wavefront per pair. Projected form: lanes evaluate Hessian entries, then
+// a parallel cyclic Jacobi (six disjoint rotations per round) diagonalises the
+// 12x12 in LDS and negative eigenvalues are clamped to zero; matrices that are
+// already PSD are kept as assembled. Gauss-Newton form (S.barrier_gn): the
+// entries kappa w b''(d) gd_p gd_q, PSD and rank one as they are.
 template <class R>
 __global__ void __launch_bounds__(64) k_barrier(Launch L)
 {
@@ -658,6 +659,22 @@ __global__ void __launch_bounds__(64) k_barrier(Launch L)
         double gb = 2.0 * aa * eb[i] - 2.0 * ab * ea[i];
         return sa[kk] * ga + sb[kk] * gb;
     };
+    if (S.barrier_gn) {
+        double wb2 = kappa * w * bb[2];
+        if (lane < 12) {
+            double gv = w * bb[1] * gs_of(lane) * inv2d;
+            if (moll) gv += bb[0] * m1 * gc_of(lane);
+            act_g[(int64_t)lane * act_cap + k] = fixed[v[lane / 3]] ? R(0) : (R)(kappa * gv);
+        }
+        if (lane < 4) act_v[(int64_t)lane * act_cap + k] = v[lane];
+        for (int e = lane; e < 144; e += 64) {
+            int p = e / 12, q = e % 12;
+            double val = wb2 * (gs_of(p) * inv2d) * (gs_of(q) * inv2d);
+            if (fixed[v[p / 3]] || fixed[v[q / 3]]) val = 0.0;
+            act_H[(int64_t)e * act_cap + k] = (R)val;
+        }
+        return;
+    }
     // entries of the unprojected pair Hessian
     for (int e = lane; e < 144; e += 64) {
         int p = e / 12, q = e % 12;

@@ -698,6 +698,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.ccd_s = s.prm.ccd_s;
     H.pcg_tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
     H.mu_fric = s.prm.mu_fric;
+    H.barrier_gn = s.prm.barrier_hessian == IPC_BARRIER_GAUSS_NEWTON;
     H.eps_fric = s.prm.eps_v * s.prm.dt;
     H.n_fric = 0;
     H.self_contact = s.prm.self_contact;
@@ -1604,6 +1605,7 @@ static bool check_desc(const ipc_scene_desc *d)
     if (d->pcg_max_iter < 0 || d->max_newton < 0 || d->ccd_max_iter < 0) return false;
     if (!(d->mu_friction >= 0.0) || (d->mu_friction > 0.0 && !(d->eps_v > 0.0))) return false;
     if (d->precond != IPC_PRECOND_MULTILEVEL && d->precond != IPC_PRECOND_JACOBI) return false;
+    if (d->barrier_hessian != IPC_BARRIER_PROJECTED && d->barrier_hessian != IPC_BARRIER_GAUSS_NEWTON) return false;
     return true;
 }
 
@@ -1632,6 +1634,7 @@ static Params make_params(const ipc_scene_desc &d)
     p.pcg_max_iter = d.pcg_max_iter;
     p.ccd_max_iter = d.ccd_max_iter > 0 ? d.ccd_max_iter : 10000;
     p.precond = d.precond;
+    p.barrier_hessian = d.barrier_hessian;
     return p;
 }
 

@@ -33,6 +33,8 @@ IPC_HOST = 0
 IPC_DEVICE = 1
 IPC_PRECOND_MULTILEVEL = 0
 IPC_PRECOND_JACOBI = 1
+IPC_BARRIER_PROJECTED = 0
+IPC_BARRIER_GAUSS_NEWTON = 1
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
@@ -55,6 +57,7 @@ class ipc_scene_desc(C.Structure):
         ("ls_min_ratio", C.c_double),
         ("self_contact", C.c_int32), ("precision", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32), ("precond", C.c_int32),
+        ("barrier_hessian", C.c_int32),
     ]
 
 
@@ -209,7 +212,7 @@ class TorchRuntime:
 
 
 def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=None,
-              precond=IPC_PRECOND_MULTILEVEL) -> ipc_scene_desc:
+              precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED) -> ipc_scene_desc:
     """ipc_scene_desc of a scenes.Scene; `keep` collects the numpy arrays that
     must outlive the create call."""
     X = np.ascontiguousarray(scene.X, dtype=np.float64)
@@ -242,6 +245,7 @@ def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=Non
     d.pcg_max_iter = 0
     d.ccd_max_iter = 10000
     d.precond = precond
+    d.barrier_hessian = barrier_hessian
     return d
 
 
@@ -256,11 +260,11 @@ class GelScene:
     """One library scene built from a scenes.Scene."""
 
     def __init__(self, scene, runtime: TorchRuntime | None = None, precision=IPC_FP64, pcg_tol=1e-12,
-                 max_newton=100, precond=IPC_PRECOND_MULTILEVEL):
+                 max_newton=100, precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED):
         self.scene = scene
         self.runtime = runtime or TorchRuntime()
         keep = []
-        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep, precond)
+        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep, precond, barrier_hessian)
         self._keep = keep
         h = C.c_void_p()
         _check(lib().ipc_create_scene(C.byref(self.desc), C.byref(self.runtime.rt), C.byref(h)),

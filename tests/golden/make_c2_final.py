@@ -1,9 +1,9 @@
 """Writes c2_seed0_final.txt: the FP64 oracle's positions after the full
 50-step trajectory of the 40x50x8 gel / cylinder (seed 0) workload, sampled
-at every 97th vertex plus all indenter vertices of the last ring, for the
-fixed-error check of the benchmarked configuration (R23: max error / L).
+at every 97th vertex, for the fixed-error check of the benchmarked
+configuration (max over the samples of |x - x_oracle| / L).
 
-Calls only the oracle. Takes about 15 minutes on one core."""
+Calls only the oracle. Takes about two hours on one core."""
 import os
 import sys
 import time

@@ -1,0 +1,121 @@
+"""Gauss-Newton pair barrier Hessians (IPC_BARRIER_GAUSS_NEWTON) through the
+C ABI against the oracle run with the same form (barrier_hessian = 1).
+
+Tolerances as for the projected form: H v 1e-11 of the largest entry,
+teacher-forced Newton iterates 1e-9 L, the free-running config-1 trajectory
+1e-8 L (both sides take the same Newton steps), mixed precision 1e-4 L.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_04776_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ipc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2411_04776_amd import ipc as I
+    I.lib()
+    return I
+
+
+@pytest.fixture(scope="module")
+def gn_trajectory():
+    """Oracle iterates of config 1 with Gauss-Newton pair Hessians."""
+    sc = S.config1()
+    o = O.OracleScene(sc, barrier_hessian=1)
+    traj = []
+    for step in range(1, sc.n_steps + 1):
+        pose = sc.poses[step]
+        x0, v0 = o.x, o.v
+        o.begin_step(pose)
+        xs = [x0]
+        x = x0
+        for _ in range(100):
+            r, xn, st = o.newton_iterate(x)
+            if r != 0:
+                break
+            xs.append(xn)
+            x = xn
+        traj.append((x0, v0, pose, xs))
+        o.step(pose)
+        assert np.array_equal(o.x, xs[-1])
+    return sc, traj, o.x
+
+
+def pressed(x, n_gel, fixed, dhat, frac=0.85, seed=2, jiggle=0.05):
+    x = x.copy()
+    x[n_gel:] -= np.array([0, 0, frac * dhat])
+    rng = np.random.default_rng(seed)
+    x[:n_gel] += rng.normal(0, jiggle * dhat, (n_gel, 3)) * (1 - fixed[:, None])
+    return x
+
+
+def test_gn_hess_apply_parity(ipc):
+    sc = S.config1()
+    g = ipc.GelScene(sc, barrier_hessian=ipc.IPC_BARRIER_GAUSS_NEWTON)
+    o = O.OracleScene(sc, barrier_hessian=1)
+    g.begin_step(sc.poses[1])
+    o.begin_step(sc.poses[1])
+    x = pressed(o.x, o.n_gel, sc.fixed, sc.dhat)
+    c = o.candidates(x)
+    assert (o.candidate_distances(x, c)[0] < sc.dhat).sum() > 0
+    gg, go = g.gradient(x), o.gradient(x)
+    assert np.abs(gg - go).max() <= 1e-11 * np.abs(go).max()
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.normal(size=x.shape)
+        yg, yo = g.hess_apply(x, v), o.hess_apply(x, v)
+        assert np.abs(yg - yo).max() <= 1e-11 * np.abs(yo).max()
+    # the projected form differs at this state (the forms are not the same matrix)
+    p = O.OracleScene(sc)
+    p.begin_step(sc.poses[1])
+    v = rng.normal(size=x.shape)
+    assert np.abs(p.hess_apply(x, v) - o.hess_apply(x, v)).max() > 1e-6 * np.abs(yo).max()
+
+
+def test_gn_teacher_forced_newton_iterates(ipc, gn_trajectory):
+    sc, traj, _ = gn_trajectory
+    L = sc.bbox_diag
+    g = ipc.GelScene(sc, barrier_hessian=ipc.IPC_BARRIER_GAUSS_NEWTON)
+    checked = 0
+    for step, (x0, v0, pose, xs) in enumerate(traj):
+        if step not in (0, 3, 6, 9):
+            continue
+        g.x = x0
+        g.v = v0
+        g.begin_step(pose)
+        for k in range(min(len(xs) - 1, 4)):
+            rc, xg, st = g.newton_iterate(xs[k])
+            assert rc == 0
+            err = np.abs(xg - xs[k + 1]).max() / L
+            checked += 1
+            say(f"  step {step} iterate {k}: err/L = {err:.3e} pcg={st.pcg_iters}")
+            assert err <= 1e-9
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gn_free_running_trajectory(ipc, gn_trajectory, precision):
+    sc, traj, x_final = gn_trajectory
+    L = sc.bbox_diag
+    g = ipc.GelScene(sc, precision=precision, pcg_tol=1e-12 if precision == 0 else 1e-7,
+                     barrier_hessian=ipc.IPC_BARRIER_GAUSS_NEWTON)
+    for step in range(1, sc.n_steps + 1):
+        rc, st = g.step()
+        say(f"  prec {precision} step {step}: rc={rc} newton={st.newton_iters} (oracle {len(traj[step - 1][3]) - 1})")
+        assert rc in (0, 4)
+    err = np.abs(g.x - x_final).max() / L
+    say("  final-step error / L", err)
+    assert err <= (1e-8 if precision == 0 else 1e-4)
