@@ -156,6 +156,26 @@ IPC_API int32_t ipc_read_surface(const ipc_scene *s, double *xyz, int64_t cap, i
                          double obj_pos[3]);
 /* Surface topology: gel surface triangles (outward, vertex ids) and the
  * ascending list of gel surface vertex ids. Either pointer may be NULL. */
+/* Height map of the deformed gel surface (the input of optical tactile
+ * renderers, which the paper feeds from the gel's sensing surface). Pixel
+ * (i, j), 0 <= i < nx, 0 <= j < ny, has its centre at (x0 + i dx, y0 + j dy)
+ * in the gel frame; out[j nx + i] = z_ref - (the largest z at which the
+ * vertical line through the centre meets an upward-facing gel surface
+ * triangle, i.e. one with positive signed area in xy), or 0 where it meets
+ * none: the indentation depth below z_ref (the rest top surface for a tactile
+ * image). A centre on a triangle's edge counts as inside. out holds
+ * nx ny doubles (cap >= nx ny), in host (IPC_HOST) or device (IPC_DEVICE)
+ * memory; stream as for ipc_read_surface. The scratch of nx ny 8-byte keys
+ * is taken from the scene's allocator on the first call and kept for later
+ * calls of the same or smaller size. */
+typedef struct ipc_height_map_spec {
+    double x0, y0;   /* centre of pixel (0, 0) (m) */
+    double dx, dy;   /* pixel pitch (m), > 0 */
+    double z_ref;    /* reference height (m) */
+    int32_t nx, ny;  /* pixels per row, rows (> 0) */
+} ipc_height_map_spec;
+IPC_API int32_t ipc_height_map(const ipc_scene *s, const ipc_height_map_spec *spec, double *out, int64_t cap,
+                               int32_t where, void *stream);
 IPC_API int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris,
                              int32_t *verts, int64_t vert_cap, int32_t *n_surf_verts);
 /* Reset: positions to rest, velocities to zero, indenter to its initial pose

@@ -250,6 +250,9 @@ class Scene {
     int64_t nnzb = 0, n_gather = 0;
     int n_gel_tris = 0;
     int mas_max_members = 0, mas_max_aggs = 0;  // largest preconditioner group
+    unsigned long long *hm_key = nullptr;       // height-map scratch (hm_cap keys)
+    int64_t hm_cap = 0;
+    double *hm_out = nullptr;                   // staging of a host-bound height map (hm_cap doubles)
     double *xsave = nullptr;   // test hooks: the state x kept across a hook call
     double *ysurf = nullptr;   // staging for surface read-back to the host
     std::unique_ptr<Batch> solo;  // the list of one used by ipc_step and the hooks
@@ -382,6 +385,12 @@ void launch_accept(Batch &b);
 void launch_rest_precompute(Batch &b);
 void run_lag_and_mean(Batch &b);
 void launch_gather_surface(Scene &s, double *dst, hipStream_t strm);
+// pixel grid of a height map (mirrors ipc_height_map_spec)
+struct HeightSpec {
+    double x0, y0, dx, dy, z_ref;
+    int nx, ny;
+};
+void launch_height_map(Scene &s, const HeightSpec &hs, unsigned long long *key, double *out, hipStream_t strm);
 
 void launch_elastic_elements(Batch &b);
 void launch_assemble(Batch &b);

@@ -1795,6 +1795,49 @@ int32_t ipc_read_surface(const ipc_scene *cs, double *xyz, int64_t cap, int32_t 
     return rc;
 }
 
+int32_t ipc_height_map(const ipc_scene *cs, const ipc_height_map_spec *spec, double *out, int64_t cap,
+                       int32_t where, void *stream)
+{
+    if (!cs || !spec || !out) return IPC_E_INVALID_ARG;
+    if (spec->nx <= 0 || spec->ny <= 0 || !(spec->dx > 0.0) || !(spec->dy > 0.0) || !std::isfinite(spec->x0) ||
+        !std::isfinite(spec->y0) || !std::isfinite(spec->z_ref)) {
+        set_error("invalid height map grid");
+        return IPC_E_INVALID_ARG;
+    }
+    int64_t np = (int64_t)spec->nx * spec->ny;
+    if (cap < np) {
+        set_error("height map buffer too small");
+        return IPC_E_INVALID_ARG;
+    }
+    if (where != IPC_HOST && where != IPC_DEVICE) return IPC_E_INVALID_ARG;
+    ipc_scene *s = const_cast<ipc_scene *>(cs);
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
+        hipStream_t strm = stream ? (hipStream_t)stream : s->stream;
+        IPC_HIP(hipStreamSynchronize(s->stream));
+        if (s->hm_cap < np) {
+            Staged st(*s);
+            auto *nk = st.get<unsigned long long>((size_t)np);
+            double *no = st.get<double>((size_t)np);
+            st.commit();
+            dfree(*s, s->hm_key);
+            dfree(*s, s->hm_out);
+            s->hm_key = nk;
+            s->hm_out = no;
+            s->hm_cap = np;
+        }
+        HeightSpec hs{spec->x0, spec->y0, spec->dx, spec->dy, spec->z_ref, spec->nx, spec->ny};
+        double *dst = where == IPC_DEVICE ? out : s->hm_out;
+        launch_height_map(*s, hs, s->hm_key, dst, strm);
+        if (where == IPC_HOST) IPC_HIP(hipMemcpyAsync(out, s->hm_out, sizeof(double) * np, hipMemcpyDeviceToHost, strm));
+        IPC_HIP(hipStreamSynchronize(strm));
+        return IPC_OK;
+    });
+    s->busy = false;
+    return rc;
+}
+
 int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris, int32_t *verts,
                              int64_t vert_cap, int32_t *n_surf_verts)
 {

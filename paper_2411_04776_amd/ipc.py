@@ -70,6 +70,11 @@ class ipc_step_req(C.Structure):
     _fields_ = [("pose", C.c_double * 12)]
 
 
+class ipc_height_map_spec(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
+                ("z_ref", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
 class ipc_step_stats(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("newton_iters", C.c_int32), ("pcg_iters", C.c_int32),
@@ -91,6 +96,8 @@ _SIGS = {
     "ipc_step": (C.c_int32, [C.c_void_p, C.POINTER(ipc_step_req), C.POINTER(ipc_step_stats)]),
     "ipc_read_surface": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, _D]),
     "ipc_surface_topology": (C.c_int32, [C.c_void_p, _I, C.c_int64, _I, _I, C.c_int64, _I]),
+    "ipc_height_map": (C.c_int32, [C.c_void_p, C.POINTER(ipc_height_map_spec), C.c_void_p, C.c_int64, C.c_int32,
+                                   C.c_void_p]),
     "ipc_reset": (C.c_int32, [C.c_void_p]),
     "ipc_state_bytes": (C.c_int64, [C.c_void_p]),
     "ipc_save_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -294,6 +301,20 @@ class GelScene:
         rc = _check(lib().ipc_step(self.ptr, C.byref(req_of(pose)), C.byref(st)), "ipc_step")
         self.step_index += 1
         return rc, st
+
+    def height_map(self, x0, y0, dx, dy, nx, ny, z_ref, device_out=None):
+        """Indentation depth below z_ref of the deformed gel surface on an
+        nx x ny pixel grid (row j, column i at (x0 + i dx, y0 + j dy)); host
+        (ny, nx) array, or written into a device tensor of nx ny doubles."""
+        sp = ipc_height_map_spec(float(x0), float(y0), float(dx), float(dy), float(z_ref), int(nx), int(ny))
+        if device_out is not None:
+            _check(lib().ipc_height_map(self.ptr, C.byref(sp), C.c_void_p(device_out.data_ptr()), device_out.numel(),
+                                        IPC_DEVICE, None), "ipc_height_map")
+            return device_out
+        out = np.zeros((int(ny), int(nx)))
+        _check(lib().ipc_height_map(self.ptr, C.byref(sp), out.ctypes.data_as(C.c_void_p), out.size, IPC_HOST, None),
+               "ipc_height_map")
+        return out
 
     def read_surface(self, device_out=None):
         """Surface positions (host numpy, or into a device tensor) and the
