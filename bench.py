@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="scenes of the batched uneven-scene leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--serve", type=int, default=64, help="environments of the serving leg (0: skip)")
+    ap.add_argument("--no-soft-ball", action="store_true", help="skip the soft-ball leg")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only copy a buffer of this many MiB with torch (HBM counter calibration) and exit")
@@ -194,6 +195,8 @@ def main():
         line["batch"] = batch_leg(args, ipc, scenes, torch)
     if args.serve > 0:
         line["serving"] = serving_leg(args, ipc, torch)
+    if not args.no_soft_ball:
+        line["soft_ball"] = soft_ball_leg(args, ipc, scenes, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, x_start, v_start, args, newton / args.steps)
 
@@ -271,6 +274,38 @@ def batch_leg(args, ipc, scenes, torch):
             "ms_per_list_step": round(1e3 * el / args.batch_steps, 2), "scene_build_s": round(build_s, 2),
             "alone_env_steps_per_s": round(alone_steps / el_alone, 2), "alone_scenes": k,
             "pcg_spmv_roofline": spmv}
+
+
+# GIPC ms per frame of the paper's timing table (soft ball, RTX 3080 Ti; context only)
+PAPER_SOFT_BALL_MS = {"small": 24.95, "medium": 110.47, "large": 221.61}
+
+
+def soft_ball_leg(args, ipc, scenes, torch):
+    """Gel pad + soft ball squeezed by a rigid plate at the three mesh sizes
+    of the paper's GIPC timing table (gel + ball vertex/tet counts), FP64,
+    20 steps each after one untimed step; ms per step beside the paper's
+    per-frame times on its own hardware (a different scene: context)."""
+    out = {}
+    for size in ("small", "medium", "large"):
+        sc = scenes.soft_ball_scene(size, steps=21)
+        g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args),
+                         barrier_hessian=barrier_code(args))
+        g.step()
+        torch.cuda.synchronize()
+        newton, pcg, t = 0, 0, []
+        for _ in range(sc.n_steps - 1):
+            t0 = time.perf_counter()
+            rc, st = g.step()
+            t.append(time.perf_counter() - t0)
+            newton += st.newton_iters
+            pcg += st.pcg_iters
+        g.close()
+        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "ms_per_step": round(1e3 * sum(t) / len(t), 2),
+                     "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
+                     "newton_per_step": round(newton / len(t), 2), "pcg_per_newton": round(pcg / max(newton, 1), 1),
+                     "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
+        print(f"soft ball {size}: {out[size]}", file=sys.stderr, flush=True)
+    return out
 
 
 def serving_leg(args, ipc, torch):

@@ -311,9 +311,9 @@ struct MasHost {
 };
 
 // Nested aggregates of the free gel vertices. Level 0 bins the rest positions
-// into cubic cells of edge twice the mean tet edge; level l + 1 merges the
-// 2x2x2 cells of level l (integer halving of the cell key, so levels nest
-// exactly). Members are sorted by (top cell, ..., level-0 cell, vertex), so
+// into cubic cells of edge twice the mean tet edge, separately for every
+// connected body of the mesh; level l + 1 merges the 2x2x2 cells of level l
+// (integer halving of the cell key, so levels nest exactly). Members are sorted by (top cell, ..., level-0 cell, vertex), so
 // every aggregate is a contiguous run of member positions. A run is split at
 // child boundaries wherever it would exceed kMasCapM members or kMasCapA
 // aggregates in its subtree (any partition keeps the preconditioner SPD),
@@ -344,13 +344,28 @@ static void build_multilevel(SceneDev &H, const ipc_scene_desc &d, const std::ve
     h0 /= m;
     for (int i = 0; i < ng; ++i)
         for (int c = 0; c < 3; ++c) org[c] = std::min(org[c], d.X[3 * i + c]);
-    std::vector<std::array<int64_t, 3>> key0(nf);
-    for (size_t k = 0; k < nf; ++k)
-        for (int c = 0; c < 3; ++c) key0[k][c] = (int64_t)std::floor((d.X[3 * freev[k] + c] - org[c]) / (2.0 * h0));
+    // connected bodies of the tet mesh: an aggregate never spans two of them
+    std::vector<int32_t> comp(ng);
+    for (int i = 0; i < ng; ++i) comp[i] = i;
+    auto root = [&](int32_t i) {
+        while (comp[i] != i) i = comp[i] = comp[comp[i]];
+        return i;
+    };
+    for (int e = 0; e < m; ++e)
+        for (int a = 1; a < 4; ++a) {
+            int32_t r0 = root(d.T[4 * e]), r1 = root(d.T[4 * e + a]);
+            if (r0 != r1) comp[std::max(r0, r1)] = std::min(r0, r1);
+        }
+    // key = (body, cell): level-0 cells of edge 2 h0, integer halving per level
+    std::vector<std::array<int64_t, 4>> key0(nf);
+    for (size_t k = 0; k < nf; ++k) {
+        key0[k][0] = root(freev[k]);
+        for (int c = 0; c < 3; ++c) key0[k][1 + c] = (int64_t)std::floor((d.X[3 * freev[k] + c] - org[c]) / (2.0 * h0));
+    }
     auto key_at = [&](size_t k, int l) {
-        std::array<int64_t, 3> q = key0[k];
+        std::array<int64_t, 4> q = key0[k];
         for (int t = 0; t < l; ++t)
-            for (int c = 0; c < 3; ++c) q[c] = q[c] >= 0 ? q[c] / 2 : -((-q[c] + 1) / 2);
+            for (int c = 1; c < 4; ++c) q[c] = q[c] >= 0 ? q[c] / 2 : -((-q[c] + 1) / 2);
         return q;
     };
     std::vector<size_t> ord(nf);

@@ -79,6 +79,21 @@ def grid_gel(nx: int, ny: int, nz: int, size=GEL_SIZE):
     return X, T, fixed
 
 
+def soft_ball(n: int, radius: float, center):
+    """Tet mesh of a ball: the n^3 Kuhn grid of the cube [-r, r]^3 mapped
+    radially onto the ball, p -> p |p|_inf / |p|_2 (cube surface onto the
+    sphere; the map scales each ray by a positive factor constant along it, so
+    its Jacobian determinant is that factor cubed and no tet turns over).
+    Returns X (n^3, 3), T (6 (n-1)^3, 4)."""
+    X, T, _ = grid_gel(n, n, n, size=(2 * radius, 2 * radius, 2 * radius))
+    P = X - radius
+    inf = np.abs(P).max(axis=1)
+    two = np.linalg.norm(P, axis=1)
+    scale = np.where(two > 0, inf / np.where(two > 0, two, 1.0), 1.0)
+    X = P * scale[:, None] + np.asarray(center, dtype=np.float64)
+    return X, T
+
+
 # ----------------------------------------------------------------------------
 # Indenter shapes (closed or open triangle meshes in a local frame)
 # ----------------------------------------------------------------------------
@@ -402,6 +417,46 @@ def config5(indent_steps: int = 40, slide_steps: int = 160) -> Scene:
                            1e-3, indent_steps, extra=((1, 0, 0), 5e-3, slide_steps))
     return Scene("c5_80x100x16_icosphere4", X, T, fixed, Y, F, poses, dt=1e-2,
                  meta={"mu": 0.5, "eps_v": 1e-3})
+
+
+# Soft-ball workloads at the mesh sizes of the paper's GIPC timing table
+# (Table 3: 1029/3717, 7900/40370, 12509/66563 vertices/tets), counted here
+# as gel + ball: (gel grid, ball grid points per axis).
+SOFT_BALL_SIZES = {
+    "tiny": ((6, 6, 3), 5),        # 233 v, 918 t (parity tests)
+    "small": ((12, 13, 3), 8),     # 980 v, 3642 t
+    "medium": ((28, 28, 4), 17),   # 8049 v, 37698 t
+    "large": ((30, 30, 5), 20),    # 12500 v, 61338 t
+}
+
+
+def soft_ball_scene(size: str = "small", radius: float = 5e-3, depth: float = 2.0e-3, steps: int = 20,
+                    slide: float = 0.0, slide_steps: int = 0, mu: float = 0.0, dt: float = 1e-2) -> Scene:
+    """Two deformable bodies in contact: the gel pad (bottom fixed) and a soft
+    ball resting dhat/2 above its centre (inside the barrier's range, so the
+    gel holds it from the first step), squeezed by a rigid plate (a box
+    indenter dhat/2 above the ball) that descends `depth` over `steps`; with
+    `slide` > 0 the plate then moves along +x over `slide_steps` (with
+    friction mu the ball rolls on the gel). Gel-ball contact is self-contact
+    of the deformable set."""
+    (gx, gy, gz), nb = SOFT_BALL_SIZES[size]
+    Xg, Tg, fixed = grid_gel(gx, gy, gz)
+    top = GEL_SIZE[2]
+    c = np.array([GEL_SIZE[0] / 2, GEL_SIZE[1] / 2, top + radius])
+    Xb, Tb = soft_ball(nb, radius, c)
+    Xb[:, 2] += top + 0.5 * DHAT - Xb[:, 2].min()
+    X = np.concatenate([Xg, Xb])
+    T = np.concatenate([Tg, Tb + len(Xg)]).astype(np.int32)
+    fixed = np.concatenate([fixed, np.zeros(len(Xb), dtype=np.uint8)])
+    Y, F = box(4 * radius, target_edge=radius / 2)
+    ball_top = Xb[:, 2].max()
+    R = np.eye(3)
+    extra = ((1, 0, 0), slide, slide_steps) if slide > 0 else None
+    poses = _descent_poses(R, Y, ball_top - 0.5 * DHAT, (c[0], c[1]), depth, steps, extra=extra)
+    meta = {"kind": "soft_ball", "size": size, "n_gel": len(Xg), "n_ball": len(Xb)}
+    if mu > 0:
+        meta.update({"mu": mu, "eps_v": 1e-3})
+    return Scene(f"soft_ball_{size}", X, T, fixed, Y, F, poses, dt=dt, meta=meta)
 
 
 def tiny_scene(grid=(4, 4, 3), radius=2e-3, subdiv=1, depth=0.3e-3, steps=3, dt=1e-2,
