@@ -105,6 +105,12 @@ typedef struct ipc_scene_desc {
     int32_t ccd_max_iter;     /* 0: 10000 */
     int32_t precond;          /* IPC_PRECOND_MULTILEVEL (0) or IPC_PRECOND_JACOBI */
     int32_t barrier_hessian;  /* IPC_BARRIER_PROJECTED (0) or IPC_BARRIER_GAUSS_NEWTON */
+    /* Attachment (the paper's GIPC attachments: gel vertices held by the
+     * sensor case move with it). n_verts bytes, 1 = attached, or NULL. An
+     * attached free gel vertex i gets k_target/2 |x_i - P X_i|^2 on top of its
+     * inertia and elasticity, P the case pose of the step request, X_i its
+     * rest position; fixed vertices stay fixed. Copied at creation. */
+    const uint8_t *attached;
 } ipc_scene_desc;
 
 /* Device memory and stream plumbing. alloc/free may be NULL (then hipMalloc /
@@ -120,9 +126,15 @@ typedef struct ipc_runtime {
     int64_t mem_budget;
 } ipc_runtime;
 
-/* One step request: the indenter's target pose at t+1 (row-major 3x4). */
+/* One step request: the indenter's target pose at t+1 (row-major 3x4) and,
+ * when case_pose_set is 1, the sensor case's pose at t+1 (row-major 3x4):
+ * attached gel vertices (ipc_scene_desc.attached) are pulled to it applied to
+ * their rest positions from this step on. With case_pose_set 0 the case keeps
+ * its last pose (identity after creation and after ipc_reset). */
 typedef struct ipc_step_req {
     double pose[12];
+    double case_pose[12];
+    int32_t case_pose_set;
 } ipc_step_req;
 
 typedef struct ipc_step_stats {

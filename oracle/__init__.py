@@ -73,6 +73,10 @@ def lib():
         for f in ("ora_get_x", "ora_set_x", "ora_get_v", "ora_set_v", "ora_begin_step"):
             getattr(L, f).argtypes = [C.c_void_p, _D]
         L.ora_reset.argtypes = [C.c_void_p]
+        L.ora_set_attachment.restype = None
+        L.ora_set_attachment.argtypes = [C.c_void_p, _U8]
+        L.ora_set_case_pose.restype = None
+        L.ora_set_case_pose.argtypes = [C.c_void_p, _D]
         L.ora_newton_iterate.restype = C.c_int32
         L.ora_newton_iterate.argtypes = [C.c_void_p, _D, _D, C.POINTER(Stats)]
         L.ora_step.restype = C.c_int32
@@ -284,6 +288,13 @@ class OracleScene:
         (self.n, self.n_gel, self.n_tet, self.n_pts, self.n_edges, self.n_tris, self.n_ind,
          self.n_gel_tris) = map(int, sz)
         self.step_index = 0
+        at = getattr(scene, "attached", None)
+        if at is not None:
+            self._attached = np.ascontiguousarray(at, dtype=np.uint8)
+            lib().ora_set_attachment(self.ptr, self._attached.ctypes.data_as(_U8))
+
+    def set_case_pose(self, pose):
+        lib().ora_set_case_pose(self.ptr, _d(f64(pose)))
 
     def __del__(self):
         if getattr(self, "ptr", None):
@@ -338,7 +349,9 @@ class OracleScene:
         lib().ora_reset(self.ptr)
         self.step_index = 0
 
-    def begin_step(self, pose):
+    def begin_step(self, pose, case_pose=None):
+        if case_pose is not None:
+            self.set_case_pose(case_pose)
         lib().ora_begin_step(self.ptr, _d(f64(pose)))
 
     def newton_iterate(self, x_in):
@@ -347,9 +360,14 @@ class OracleScene:
         r = lib().ora_newton_iterate(self.ptr, _d(f64(x_in)), _d(out), C.byref(st))
         return int(r), out, st
 
-    def step(self, pose=None):
+    def step(self, pose=None, case_pose=None):
         if pose is None:
             pose = self.scene.poses[self.step_index + 1]
+        cp = getattr(self.scene, "case_poses", None)
+        if case_pose is None and cp is not None:
+            case_pose = cp[self.step_index + 1]
+        if case_pose is not None:
+            self.set_case_pose(case_pose)
         st = Stats()
         r = lib().ora_step(self.ptr, _d(f64(pose)), C.byref(st))
         self.step_index += 1

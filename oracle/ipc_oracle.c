@@ -752,7 +752,12 @@ struct ora_scene {
     double *fric_c;   /* 4 per pair: closest-point coefficients at x^t */
     double *fric_nrm; /* 3 per pair: unit contact normal at x^t */
     double *fric_lam; /* normal-force magnitude at x^t */
+    /* attachment: free gel vertices pulled to case pose o rest position */
+    uint8_t *attached; /* per gel vertex, NULL: none */
+    double case_pose[12];
 };
+
+static int is_attached(const ora_scene *s, int i);
 
 typedef struct {
     int32_t a, b, c, src;
@@ -862,6 +867,7 @@ ora_scene *ora_scene_create(int32_t n_gel, const double *X, int32_t n_tet, const
     s->Yloc = (double *)malloc(sizeof(double) * 3 * (n_ind > 0 ? n_ind : 1));
     s->pose0 = (double *)malloc(sizeof(double) * 12);
     memcpy(s->pose0, pose0, sizeof(double) * 12);
+    for (int k = 0; k < 12; ++k) s->case_pose[k] = (k % 5 == 0) ? 1.0 : 0.0; /* identity */
     memcpy(s->X, X, sizeof(double) * 3 * n_gel);
     if (n_ind) memcpy(s->Yloc, Y_local, sizeof(double) * 3 * n_ind);
     for (int j = 0; j < n_ind; ++j) apply_pose(pose0, Y_local + 3 * j, s->X + 3 * (n_gel + j));
@@ -984,6 +990,7 @@ void ora_scene_destroy(ora_scene *s)
     free(s->Bm); free(s->vol); free(s->mass);
     free(s->pts); free(s->edges); free(s->tris); free(s->edge_rest_sq);
     free(s->x); free(s->v); free(s->xt); free(s->xtilde); free(s->yhat);
+    free(s->attached);
     free(s->fric_v); free(s->fric_c); free(s->fric_nrm); free(s->fric_lam);
     free(s);
 }
@@ -1022,6 +1029,7 @@ void ora_reset(ora_scene *s)
     memcpy(s->xtilde, s->X, sizeof(double) * 3 * s->n);
     memcpy(s->yhat, s->X, sizeof(double) * 3 * s->n);
     s->n_fric = 0;
+    for (int k = 0; k < 12; ++k) s->case_pose[k] = (k % 5 == 0) ? 1.0 : 0.0;
 }
 
 /* ======================================================================== */
@@ -1201,6 +1209,12 @@ static double energy_with(const ora_scene *s, const double *x, const ivec *cand)
     for (int j = s->n_gel; j < s->n; ++j) {
         double d[3];
         sub3(x + 3 * j, s->yhat + 3 * j, d);
+        nsum_add(&acc, 0.5 * s->prm.k_target * dot3(d, d));
+    }
+    for (int i = 0; i < s->n_gel; ++i) {
+        if (!is_attached(s, i)) continue;
+        double d[3];
+        sub3(x + 3 * i, s->yhat + 3 * i, d);
         nsum_add(&acc, 0.5 * s->prm.k_target * dot3(d, d));
     }
     for (int i = 0; i < cand->n / 3; ++i) {
@@ -1410,6 +1424,12 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
             A->g[3 * j + c] += s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]);
             A->diag[9 * j + 4 * c] += s->prm.k_target;
         }
+    for (int i = 0; i < s->n_gel; ++i)
+        if (is_attached(s, i))
+            for (int c = 0; c < 3; ++c) {
+                A->g[3 * i + c] += s->prm.k_target * (x[3 * i + c] - s->yhat[3 * i + c]);
+                A->diag[9 * i + 4 * c] += s->prm.k_target;
+            }
     /* elasticity */
     for (int e = 0; e < s->n_tet; ++e) {
         const int32_t *t = s->T + 4 * e;
@@ -1491,6 +1511,9 @@ static void hess_apply(const ora_scene *s, const assembly *A, const double *v, d
         for (int c = 0; c < 3; ++c) y[3 * i + c] += s->mass[i] / h2 * v[3 * i + c];
     for (int j = s->n_gel; j < n; ++j)
         for (int c = 0; c < 3; ++c) y[3 * j + c] += s->prm.k_target * v[3 * j + c];
+    for (int i = 0; i < s->n_gel; ++i)
+        if (is_attached(s, i))
+            for (int c = 0; c < 3; ++c) y[3 * i + c] += s->prm.k_target * v[3 * i + c];
     for (int e = 0; e < s->n_tet; ++e) {
         const int32_t *t = s->T + 4 * e;
         const double *H = A->Hel + 144 * e;
@@ -1655,6 +1678,29 @@ double ora_ccd(ora_scene *s, const double *x, const double *p)
 /* ======================================================================== */
 /* Newton                                                                    */
 /* ======================================================================== */
+/* attachment                                                                */
+/* ======================================================================== */
+/* The paper's GIPC attachments move the gel with the sensor case: gel
+ * vertices inside the case keep fixed offsets in the case frame and get the
+ * case pose applied to them as target values before each solve ("GIPC
+ * Attachments"). Here an attached free gel vertex i is pulled to its target
+ * yhat_i = case pose applied to its rest position by the same penalty
+ * k_t/2 |x_i - yhat_i|^2 that drives the indenter (on top of its inertia and
+ * elasticity). Fixed vertices stay fixed. */
+static int is_attached(const ora_scene *s, int i) { return s->attached && s->attached[i] && !s->fixed[i]; }
+
+void ora_set_attachment(ora_scene *s, const uint8_t *mask)
+{
+    free(s->attached);
+    s->attached = NULL;
+    if (!mask) return;
+    s->attached = (uint8_t *)malloc((size_t)s->n_gel);
+    memcpy(s->attached, mask, (size_t)s->n_gel);
+}
+
+void ora_set_case_pose(ora_scene *s, const double *pose) { memcpy(s->case_pose, pose, sizeof(double) * 12); }
+
+/* ======================================================================== */
 
 void ora_begin_step(ora_scene *s, const double *pose)
 {
@@ -1672,6 +1718,8 @@ void ora_begin_step(ora_scene *s, const double *pose)
         apply_pose(pose, s->Yloc + 3 * j, s->yhat + 3 * (s->n_gel + j));
         for (int c = 0; c < 3; ++c) s->xtilde[3 * (s->n_gel + j) + c] = s->x[3 * (s->n_gel + j) + c];
     }
+    for (int i = 0; i < s->n_gel; ++i)
+        if (is_attached(s, i)) apply_pose(s->case_pose, s->X + 3 * i, s->yhat + 3 * i);
     friction_lag(s);
 }
 

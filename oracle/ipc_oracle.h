@@ -78,6 +78,12 @@ void ora_set_x(ora_scene *s, const double *x);
 void ora_get_v(const ora_scene *s, double *v);
 void ora_set_v(ora_scene *s, const double *v);
 void ora_reset(ora_scene *s);
+/* Attachment: mask (n_gel bytes, NULL: none) of free gel vertices pulled by
+ * k_target/2 |x_i - P_case X_i|^2 to the case pose applied to their rest
+ * position; the case pose (3x4 row-major, identity at creation) is read by
+ * ora_begin_step. */
+void ora_set_attachment(ora_scene *s, const uint8_t *mask);
+void ora_set_case_pose(ora_scene *s, const double *pose);
 
 /* Start a step toward indenter pose `pose` (row-major 3x4): stores x^t, the
  * inertial predictor and the indenter targets. */

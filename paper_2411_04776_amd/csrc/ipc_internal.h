@@ -102,6 +102,8 @@ struct SceneDev {
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
     double mu_fric, eps_fric;  // friction coefficient, smoothing length eps_v h
     int barrier_gn;            // 1: Gauss-Newton pair Hessians kappa w b'' grad d grad d^T
+    uint8_t *attached;         // per gel vertex: pulled to case_pose X0 by k_target (NULL: none)
+    double case_pose[12];
     double pose[12];
     double alpha;      // line-search trial step
     // state (FP64)

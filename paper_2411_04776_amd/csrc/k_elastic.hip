@@ -302,6 +302,8 @@ __device__ __forceinline__ void vertex_gradient(const SceneDev &S, int i, double
     if (i < S.n_gel) {
         double kk = S.mass[i] * S.inv_h2;
         for (int c = 0; c < 3; ++c) g[c] += kk * (S.x[3 * i + c] - S.xtilde[3 * i + c]);
+        if (S.attached && S.attached[i])
+            for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
     } else {
         for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
     }
@@ -404,6 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
         }
         if (k == 0) {
             double dk = row < S.n_gel ? S.mass[row] * S.inv_h2 : S.k_target;
+            if (row < S.n_gel && S.attached && S.attached[row]) dk += S.k_target;
             A[0] += dk;
             A[4] += dk;
             A[8] += dk;
@@ -485,6 +488,11 @@ __global__ void __launch_bounds__(kBlock) k_energy_body(Launch L, int trial)
                 double d0 = x[3 * i] - S.xtilde[3 * i], d1 = x[3 * i + 1] - S.xtilde[3 * i + 1],
                        d2 = x[3 * i + 2] - S.xtilde[3 * i + 2];
                 val = S.mass[i] * (0.5 * S.inv_h2) * (d0 * d0 + d1 * d1 + d2 * d2);
+                if (S.attached && S.attached[i]) {
+                    double e0 = x[3 * i] - S.yhat[3 * i], e1 = x[3 * i + 1] - S.yhat[3 * i + 1],
+                           e2 = x[3 * i + 2] - S.yhat[3 * i + 2];
+                    val += 0.5 * S.k_target * (e0 * e0 + e1 * e1 + e2 * e2);
+                }
             }
         } else {
             double d0 = x[3 * i] - S.yhat[3 * i], d1 = x[3 * i + 1] - S.yhat[3 * i + 1], d2 = x[3 * i + 2] - S.yhat[3 * i + 2];

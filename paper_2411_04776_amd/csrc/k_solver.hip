@@ -815,7 +815,8 @@ __global__ void k_accept(Launch L)
 }
 
 // step start: keep x^t, inertial predictor for free gel vertices, indenter
-// targets from the scene's pose
+// targets from the scene's pose, attached gel vertices' targets from the case
+// pose
 __global__ void k_begin_step(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
@@ -829,6 +830,11 @@ __global__ void k_begin_step(Launch L)
             double xv = S.x[3 * i + c];
             S.xtilde[3 * i + c] = S.fixed[i] ? xv : xv + h * S.v[3 * i + c] + h * h * S.grav[c];
             S.yhat[3 * i + c] = xv;
+        }
+        if (S.attached && S.attached[i]) {  // the case pose applied to the rest position
+            const double *X = S.X0 + 3 * i, *P = S.case_pose;
+            for (int c = 0; c < 3; ++c)
+                S.yhat[3 * i + c] = P[c * 4 + 0] * X[0] + P[c * 4 + 1] * X[1] + P[c * 4 + 2] * X[2] + P[c * 4 + 3];
         }
     } else {
         const double *y = S.Yloc + 3 * (i - S.n_gel);

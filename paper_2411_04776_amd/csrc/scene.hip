@@ -36,6 +36,8 @@
 
 namespace ipcg {
 
+static const double kIdentityPose[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+
 static thread_local std::string g_last_error;
 void set_error(const std::string &m) { g_last_error = m; }
 
@@ -714,6 +716,17 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.pcg_tol2 = s.prm.pcg_tol * s.prm.pcg_tol;
     H.mu_fric = s.prm.mu_fric;
     H.barrier_gn = s.prm.barrier_hessian == IPC_BARRIER_GAUSS_NEWTON;
+    std::memcpy(H.case_pose, kIdentityPose, sizeof(kIdentityPose));
+    H.attached = nullptr;
+    if (d.attached) {
+        std::vector<uint8_t> at(ng, 0);
+        bool any = false;
+        for (int i = 0; i < ng; ++i) {
+            at[i] = (d.attached[i] && !(d.fixed && d.fixed[i])) ? 1 : 0;
+            any |= at[i] != 0;
+        }
+        if (any) H.attached = upload(s, at);
+    }
     H.eps_fric = s.prm.eps_v * s.prm.dt;
     H.n_fric = 0;
     H.self_contact = s.prm.self_contact;
@@ -1245,6 +1258,20 @@ static void set_pose(Scene &s, const double *pose)
     s.dev_dirty = true;
 }
 
+static void set_case_pose(Scene &s, const double *pose)
+{
+    std::memcpy(s.h.case_pose, pose, sizeof(double) * 12);
+    s.dev_dirty = true;
+}
+
+// the poses of one step request
+static void set_request(Scene &s, const ipc_step_req &r)
+{
+    set_pose(s, r.pose);
+    if (r.case_pose_set) set_case_pose(s, r.case_pose);
+}
+
+
 // predictor and targets of the scenes with on[i] (poses already set), and the
 // lagged friction set at x^t of the scenes with friction
 static void begin_steps(Batch &b, const std::vector<uint8_t> &on, std::vector<StepCtl> &ctl)
@@ -1334,11 +1361,11 @@ static void start_ctl(StepCtl &c)
 }
 
 // Steps every scene of the list to completion in shared launches.
-static void step_list(Batch &b, const std::vector<const double *> &poses, std::vector<StepCtl> &ctl)
+static void step_list(Batch &b, const std::vector<const ipc_step_req *> &reqs, std::vector<StepCtl> &ctl)
 {
     size_t ns = b.sc.size();
     auto t0 = Clock::now();
-    for (size_t i = 0; i < ns; ++i) set_pose(*b.sc[i], poses[i]);
+    for (size_t i = 0; i < ns; ++i) set_request(*b.sc[i], *reqs[i]);
     ctl.assign(ns, StepCtl{});
     for (auto &c : ctl) start_ctl(c);
     std::vector<uint8_t> all(ns, 1);
@@ -1394,7 +1421,7 @@ class Engine {
     struct Slot {
         Scene *s;
         ipc_ticket t;
-        double pose[12];
+        ipc_step_req req;
         bool fresh;  // admitted this round: begin_step still to run
         Clock::time_point t0;
     };
@@ -1440,7 +1467,7 @@ class Engine {
             if (rt.mem_budget > 0 && !empty && bytes + q.s->arena.used > rt.mem_budget) break;
             List &l = lists[q.s->prm.precision == IPC_MIXED ? 1 : 0];
             Slot sl{q.s, q.t, {}, true, Clock::now()};
-            std::memcpy(sl.pose, q.r.pose, sizeof(sl.pose));
+            sl.req = q.r;
             l.slots.push_back(sl);
             l.ctl.emplace_back();
             l.changed = true;
@@ -1491,7 +1518,7 @@ class Engine {
             if (l.slots[i].fresh) {
                 Scene &s = *l.slots[i].s;
                 IPC_HIP(hipStreamSynchronize(s.stream));  // earlier work of the scene's own stream
-                set_pose(s, l.slots[i].pose);
+                set_request(s, l.slots[i].req);
                 start_ctl(l.ctl[i]);
                 l.slots[i].fresh = false;
                 fresh[i] = 1;
@@ -1765,7 +1792,7 @@ int32_t ipc_step(ipc_scene *s, const ipc_step_req *r, ipc_step_stats *st)
     int32_t rc = guarded([&]() -> int32_t {
         Batch &b = solo(*s);
         std::vector<StepCtl> ctl;
-        step_list(b, {r->pose}, ctl);
+        step_list(b, {r}, ctl);
         if (st) *st = ctl[0].st;
         if (ctl[0].st.status < 0) set_status_error(ctl[0].st.status);
         return ctl[0].st.status;
@@ -1879,6 +1906,7 @@ int32_t ipc_reset(ipc_scene *s)
         IPC_HIP(hipMemsetAsync(H.v, 0, b, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
         set_pose(*s, s->pose0);
+        set_case_pose(*s, kIdentityPose);
         s->step_index = 0;
         s->sw_ok = false;
         s->h.n_fric = 0;
@@ -2101,7 +2129,7 @@ int32_t ipcx_begin_step(ipc_scene *s, const ipc_step_req *r)
     if (!s || !r) return IPC_E_INVALID_ARG;
     IPC_HOOK_BEGIN(s)
         Batch &b = solo(*s);
-        set_pose(*s, r->pose);
+        set_request(*s, *r);
         std::vector<StepCtl> ctl(1);
         start_ctl(ctl[0]);
         std::vector<uint8_t> on(1, 1);

@@ -57,7 +57,7 @@ class ipc_scene_desc(C.Structure):
         ("ls_min_ratio", C.c_double),
         ("self_contact", C.c_int32), ("precision", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32), ("precond", C.c_int32),
-        ("barrier_hessian", C.c_int32),
+        ("barrier_hessian", C.c_int32), ("attached", _U8),
     ]
 
 
@@ -67,7 +67,7 @@ class ipc_runtime(C.Structure):
 
 
 class ipc_step_req(C.Structure):
-    _fields_ = [("pose", C.c_double * 12)]
+    _fields_ = [("pose", C.c_double * 12), ("case_pose", C.c_double * 12), ("case_pose_set", C.c_int32)]
 
 
 class ipc_height_map_spec(C.Structure):
@@ -253,14 +253,30 @@ def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=Non
     d.ccd_max_iter = 10000
     d.precond = precond
     d.barrier_hessian = barrier_hessian
+    at = getattr(scene, "attached", None)
+    if at is not None:
+        at = np.ascontiguousarray(at, dtype=np.uint8)
+        if keep is not None:
+            keep.append(at)
+        d.attached = at.ctypes.data_as(_U8)
     return d
 
 
-def req_of(pose) -> ipc_step_req:
+def req_of(pose, case_pose=None) -> ipc_step_req:
     r = ipc_step_req()
     for k, v in enumerate(np.asarray(pose, dtype=np.float64).ravel()):
         r.pose[k] = v
+    if case_pose is not None:
+        for k, v in enumerate(np.asarray(case_pose, dtype=np.float64).ravel()):
+            r.case_pose[k] = v
+        r.case_pose_set = 1
     return r
+
+
+def scene_case_pose(scene, step):
+    """The scene's case pose for `step` (None when the scene has none)."""
+    cp = getattr(scene, "case_poses", None)
+    return None if cp is None else cp[step]
 
 
 class GelScene:
@@ -294,11 +310,13 @@ class GelScene:
         except Exception:
             pass
 
-    def step(self, pose=None):
+    def step(self, pose=None, case_pose=None):
         if pose is None:
             pose = self.scene.poses[self.step_index + 1]
+        if case_pose is None:
+            case_pose = scene_case_pose(self.scene, self.step_index + 1)
         st = ipc_step_stats()
-        rc = _check(lib().ipc_step(self.ptr, C.byref(req_of(pose)), C.byref(st)), "ipc_step")
+        rc = _check(lib().ipc_step(self.ptr, C.byref(req_of(pose, case_pose)), C.byref(st)), "ipc_step")
         self.step_index += 1
         return rc, st
 
@@ -356,8 +374,8 @@ class GelScene:
         _check(lib().ipc_load_state(self.ptr, buf, len(blob)), "ipc_load_state")
 
     # ---- test-only hooks ----
-    def begin_step(self, pose):
-        _check(lib().ipcx_begin_step(self.ptr, C.byref(req_of(pose))), "ipcx_begin_step")
+    def begin_step(self, pose, case_pose=None):
+        _check(lib().ipcx_begin_step(self.ptr, C.byref(req_of(pose, case_pose))), "ipcx_begin_step")
 
     def newton_iterate(self, x_in):
         x_in = np.ascontiguousarray(x_in, dtype=np.float64)
@@ -504,7 +522,8 @@ class Batch:
         if poses is None:
             poses = [g.scene.poses[g.step_index + 1] for g in scenes]
         ptrs = (C.c_void_p * n)(*[g.ptr.value for g in scenes])
-        reqs = (ipc_step_req * n)(*[req_of(p) for p in poses])
+        reqs = (ipc_step_req * n)(*[req_of(p, scene_case_pose(g.scene, g.step_index + 1))
+                                     for p, g in zip(poses, scenes)])
         tk = np.zeros(n, dtype=np.int64)
         _check(lib().ipc_batch_submit(self.ptr, n, ptrs, reqs, tk.ctypes.data_as(_I64)), "ipc_batch_submit")
         for g in scenes:

@@ -302,6 +302,8 @@ class Scene:
     gravity: tuple = (0.0, 0.0, 0.0)
     self_contact: bool = True
     meta: dict = field(default_factory=dict)
+    attached: np.ndarray | None = None    # (n,) uint8: gel vertices held by the sensor case
+    case_poses: np.ndarray | None = None  # (steps+1, 3, 4): case pose per step
 
     @property
     def n_steps(self) -> int:
@@ -457,6 +459,34 @@ def soft_ball_scene(size: str = "small", radius: float = 5e-3, depth: float = 2.
     if mu > 0:
         meta.update({"mu": mu, "eps_v": 1e-3})
     return Scene(f"soft_ball_{size}", X, T, fixed, Y, F, poses, dt=dt, meta=meta)
+
+
+def attached_scene(grid=(16, 20, 4), depth: float = 1.0e-3, steps: int = 10, tilt_deg: float = 0.0,
+                   radius: float = 5e-3, dt: float = 1e-2) -> Scene:
+    """The sensor moves, the object stays: the gel's bottom layer is held by
+    the sensor case (attached, not fixed) and the case lifts the gel by
+    `depth` over `steps` (tilting by `tilt_deg` about the x axis through the
+    bottom centre along the way) into a static icosphere whose lowest point
+    starts dhat above the gel top. The indenter keeps its initial pose."""
+    X, T, bottom = grid_gel(*grid)
+    fixed = np.zeros(len(X), dtype=np.uint8)
+    Y, F = icosphere(2, radius)
+    R = np.eye(3)
+    # the sphere hangs above the gel centre with its lowest point dhat above the top
+    c = np.array([GEL_SIZE[0] / 2, GEL_SIZE[1] / 2, GEL_SIZE[2] + DHAT - Y[:, 2].min()])
+    P0 = pose_matrix(R, c)
+    poses = np.stack([P0] * (steps + 1))
+    # the case: the gel moves up towards the sphere (the sensor pressed onto it)
+    cases = []
+    for t in range(steps + 1):
+        a = math.radians(tilt_deg) * t / steps
+        Rc = rotation((1, 0, 0), a)
+        ctr = np.array([GEL_SIZE[0] / 2, GEL_SIZE[1] / 2, 0.0])
+        # rotate about the bottom centre, then lift
+        off = ctr - Rc @ ctr + np.array([0, 0, depth * t / steps])
+        cases.append(pose_matrix(Rc, off))
+    return Scene(f"attached_{grid[0]}x{grid[1]}x{grid[2]}", X, T, fixed, Y, F, poses, dt=dt,
+                 attached=bottom.copy(), case_poses=np.stack(cases), meta={"kind": "attached"})
 
 
 def tiny_scene(grid=(4, 4, 3), radius=2e-3, subdiv=1, depth=0.3e-3, steps=3, dt=1e-2,
