@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 PCG_SOURCES = ("paper_2411_04776_amd/csrc/k_solver.hip", "paper_2411_04776_amd/csrc/incidence.h",
                "paper_2411_04776_amd/csrc/device_util.h", "paper_2411_04776_amd/csrc/ipc_internal.h")
-TRAFFIC_PROFILE = "profiles/k_pcg_A_c2_fp64_pmc.md"
+TRAFFIC_PROFILES = {"k_pcg_A": "profiles/k_pcg_A_c2_fp64_pmc.md", "k_pcg_B": "profiles/k_pcg_B_c2_fp64_pmc.md"}
 
 
 def precond_code(args):
@@ -49,11 +49,11 @@ def pcg_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_pcg_A launch from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size), or None
-    when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+def measured_traffic(kernel):
+    """HBM bytes per launch of a PCG kernel from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size),
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILES[kernel])
     if not os.path.exists(path):
         return None
     vals = {}
@@ -68,6 +68,16 @@ def measured_traffic():
         return int(float(vals["traffic_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
+
+
+def update_bytes_per_launch(info, n_active, members):
+    """Algorithmic bytes of one PCG update launch (k_pcg_B, FP64): per vertex
+    q, d, p, r and the 3x3 inverse read (21 values) and p, r, z written (9),
+    per incidence entry (4 per active pair) its index and 3 pair-product
+    values, per preconditioner member its vertex id and three level ids, and
+    the SpMV blocks' d.q partials once."""
+    n = info["n"]
+    return 240 * n + 28 * 4 * n_active + 16 * members + 8 * ((n + 63) // 64)
 
 
 def spmv_bytes_per_launch(info, n_active):
@@ -153,23 +163,36 @@ def main():
     info = g.matrix_info()
     g.profile(False)
 
-    # dominant kernel: the one with the largest summed event time
-    dom = max(prof, key=lambda k: prof[k][1])
-    n_launch, ms = prof["pcg_spmv"]
-    avg_s = ms / 1e3 / max(n_launch, 1)
+    # the two PCG kernels (the dominant launches): achieved = algorithmic
+    # bytes per launch / mean event-timed launch duration
     n_act_mean = float(np.mean(active)) if active else 0.0
-    bytes_launch = spmv_bytes_per_launch(info, n_act_mean)
-    achieved = bytes_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-    roofline = {
-        "kernel": "k_pcg_A (PCG SpMV + direction update)",
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "traffic_source": TRAFFIC_PROFILE,
-        "bytes_per_launch": int(bytes_launch), "timed_launches": int(n_launch), "timing": "HIP events around 1 in 4 launches in the timed region",
-        "avg_launch_us": round(avg_s * 1e6, 3),
-        "share_of_event_time": {k: round(v[1] / max(sum(w[1] for w in prof.values()), 1e-12), 4)
-                                for k, v in prof.items()},
-        "dominant_by_event_time": dom,
-    }
+    members = g.precond_info()["members"]
+    pcg_k = {}
+    for cls, kname, what, nbytes in (
+            ("pcg_spmv", "k_pcg_A", "PCG SpMV + direction update", spmv_bytes_per_launch(info, n_act_mean)),
+            ("pcg_update", "k_pcg_B", "PCG update + multilevel preconditioner", update_bytes_per_launch(info, n_act_mean, members))):
+        n_launch, ms = prof[cls]
+        avg_s = ms / 1e3 / max(n_launch, 1)
+        achieved = nbytes / avg_s / 1e9 if avg_s > 0 else 0.0
+        pcg_k[kname] = {
+            "kernel": f"{kname} ({what})", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
+            "traffic_source": TRAFFIC_PROFILES[kname], "bytes_per_launch": int(nbytes), "timed_launches": int(n_launch),
+            "timing": "HIP events around 1 in 16 launches in the timed region", "avg_launch_us": round(avg_s * 1e6, 3),
+            "event_ms": round(ms, 3)}
+    dom_k = max(pcg_k, key=lambda k: pcg_k[k]["event_ms"])
+    other = [k for k in pcg_k if k != dom_k][0]
+    roofline = dict(pcg_k[dom_k])
+    # PCG classes time one launch in sixteen: scale them to all pcg iterations
+    est = {k: v[1] for k, v in prof.items()}
+    for cls in ("pcg_spmv", "pcg_update"):
+        if prof[cls][0] > 0:
+            est[cls] = prof[cls][1] / prof[cls][0] * pcg
+    roofline["share_of_event_time"] = {k: round(v / max(sum(est.values()), 1e-12), 4) for k, v in est.items()}
+    roofline["dominant_by_event_time"] = max(est, key=est.get)
+    roofline["other_pcg_kernel"] = pcg_k[other]
+    roofline["note"] = ("one 16k-vertex scene is latency-bound (a chain of dependent loads and block barriers per "
+                        "launch, ~250 blocks for 256 CUs); the batch leg's pcg_spmv_roofline is the bandwidth case")
 
     line = {
         "metric": "env-steps/sec", "value": round(args.steps / elapsed, 4), "unit": "env-steps/s",
@@ -250,7 +273,7 @@ def batch_leg(args, ipc, scenes, torch):
                 "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "timed_launches": n_a, "avg_launch_us": round(1e3 * ms_a / n_a, 2),
                 "bytes_per_launch": int(by_a / n_a),
-                "timing": "engine HIP events around 1 in 4 launches of one list step"}
+                "timing": "engine HIP events around 1 in 16 launches of one list step"}
     # the same scenes one at a time, from the same states
     k = min(16, len(gs))
     states = [g.save_state() for g in gs[:k]]

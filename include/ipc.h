@@ -149,7 +149,8 @@ typedef struct ipc_step_stats {
     double pinf;              /* last |p|_inf */
     double max_target_lag;    /* max |y_j - yhat_j| over indenter vertices (m) */
     double ms_total;          /* wall time of the step on the host (ms) */
-    double ms_phase[8];       /* assemble, contact, pcg, ccd, line search, other */
+    double ms_phase[8];       /* host wall time per phase: assemble, contact, pcg, ccd, line search,
+                                 other (the device work of a phase may finish in a later one) */
 } ipc_step_stats;
 
 /* Create a scene. Validates the mesh (indices, rest volumes > 0, manifold
@@ -224,8 +225,8 @@ IPC_API int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
 /* Blocks until the step is done; returns its status and consumes the ticket. */
 IPC_API int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
 /* Kernel timing inside the engine: enable (1) or disable (0) resets the
- * totals; from the next Newton round on, one launch in four of each kernel
- * class is bracketed by HIP events on the engine's stream (same classes as
+ * totals; from the next Newton round on, each phase launch and one PCG
+ * launch in sixteen is bracketed by HIP events on the engine's stream (same classes as
  * ipcx_profile). profile_read returns the timed launches, their summed
  * milliseconds and, for class 0 (PCG SpMV), the summed algorithmic bytes of
  * those launches over every scene of the list: per stored 3x3 block its

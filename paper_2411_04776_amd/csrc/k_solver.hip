@@ -168,12 +168,13 @@ __device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const
 // (streams added in order, the block's d.q summed by one wavefront over its 64
 // rows or pairs), so a scene gets the same bits in either form.
 template <class R, int LPR>
-__global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it)
+__global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it, int early)
 {
     constexpr int NP = kSpmvStreams / LPR;  // streams per thread
     __shared__ double sdq[kRowsPerBlock];
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
+    if (early && S.pcg->done) return;  // launches past the expected count: a finished solve costs nothing
     const R *z = as<R>(S.z);
     const R *dold = as<R>((it & 1) ? S.dB : S.dA);
     const bool bon = it > 1;
@@ -570,12 +571,13 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                 for (int c = 0; c < 3; ++c) rm[tid + j * kBlock][c] = (double)ri[c];
             }
     } else {
+        const bool any_heavy = L.out[s].n_heavy > 0;  // the same for the whole scene
         if (tid == 0) hcount = 0;
         const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
         VertexPcg<R> v[kMasSlots];
         double qc[kMasSlots][3];
         bool heavy[kMasSlots];
-        __syncthreads();
+        if (any_heavy) __syncthreads();
 #pragma unroll
         for (int j = 0; j < kMasSlots; ++j) {
             heavy[j] = false;
@@ -590,17 +592,19 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             }
         }
         if (S.pcg->done) return;
-        __syncthreads();
-        // heavy members: the whole block sums each one's incidence row
-        const int nh = hcount;
-        for (int h = 0; h < nh; ++h) {
-            int pos = hlist[h];
-            double q3[3];
-            contact_row_heavy<R>(S, S.mas_mem[k0 + pos], q3);
-            if (tid == 0)
-                for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
+        if (any_heavy) {
+            __syncthreads();
+            // heavy members: the whole block sums each one's incidence row
+            const int nh = hcount;
+            for (int h = 0; h < nh; ++h) {
+                int pos = hlist[h];
+                double q3[3];
+                contact_row_heavy<R>(S, S.mas_mem[k0 + pos], q3);
+                if (tid == 0)
+                    for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         R alpha = pcg_alpha<R>(L, S, s, it);
         R *sol = as<R>(S.sol), *r = as<R>(S.r);
 #pragma unroll
@@ -693,10 +697,11 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it)
+__global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it, int early)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
+    if (early && it > 0 && S.pcg->done) return;
     if (it == 0 && lb == 0 && threadIdx.x == 0) {  // a new solve
         S.pcg->done = 0;
         S.pcg->iters = 0;
@@ -1126,9 +1131,9 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         if (nab[i] > 0) nbb[i] = b.sc[i]->h.pcg_nvp + heavy_bound(pair_count(*b.sc[i], b.h_out[i]), b.sc[i]->h.n);
     b.set_phase(kPhPcgB, nbb);
     if (mx)
-        IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, 0);
+        IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, 0, 0);
     else
-        IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, 0);
+        IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, 0, 0);
     int maxit = 0, last = 0;
     for (size_t i = 0; i < ns; ++i) {
         if (b.h_off[kPhVert][i + 1] == b.h_off[kPhVert][i]) continue;
@@ -1159,41 +1164,47 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         if (nab[i] > 0) rows_total += b.sc[i]->h.n;
     const bool one_lane = rows_total >= kSpmvOneLaneRows;
     int it = 1;
+    // the first chunk stops short of the previous solve's count; later
+    // launches check the done flag first, so overshooting them is cheap
     int chunk = last > 16 ? (last * 7) / 8 : 8;
+    int early = 0;
     hipEvent_t ev[2];
     // launch it = maxit + 1 too: its A kernel records the cap of the scenes
     // that did not converge
     while (it <= maxit + 1) {
         int c = std::min(chunk, maxit + 2 - it);
         for (int j = 0; j < c; ++j, ++it) {
-            bool timed = b.prof() && (it & 3) == 1;  // time one launch in four when profiling
+            // time one launch in sixteen when profiling (not the early-exit launches)
+            bool timed = b.prof() && (it & 15) == 1 && !early;
             if (timed) b.prof_begin(kProfPcgA, ev);
             if (one_lane) {
                 if (mx)
-                    IPC_LAUNCH(b, (k_pcg_A<float, 1>), kPhPcgA, kRowsPerBlock, it);
+                    IPC_LAUNCH(b, (k_pcg_A<float, 1>), kPhPcgA, kRowsPerBlock, it, early);
                 else
-                    IPC_LAUNCH(b, (k_pcg_A<double, 1>), kPhPcgA, kRowsPerBlock, it);
+                    IPC_LAUNCH(b, (k_pcg_A<double, 1>), kPhPcgA, kRowsPerBlock, it, early);
             } else {
                 if (mx)
-                    IPC_LAUNCH(b, (k_pcg_A<float, 2>), kPhPcgA, 2 * kRowsPerBlock, it);
+                    IPC_LAUNCH(b, (k_pcg_A<float, 2>), kPhPcgA, 2 * kRowsPerBlock, it, early);
                 else
-                    IPC_LAUNCH(b, (k_pcg_A<double, 2>), kPhPcgA, 2 * kRowsPerBlock, it);
+                    IPC_LAUNCH(b, (k_pcg_A<double, 2>), kPhPcgA, 2 * kRowsPerBlock, it, early);
             }
             if (timed) b.prof_end(kProfPcgA, ev, a_bytes);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)
-                IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it, early);
             else
-                IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, it);
+                IPC_LAUNCH(b, k_pcg_B<double>, kPhPcgB, kBlock, it, early);
             if (timed) b.prof_end(kProfPcgB, ev);
         }
+        run_pinf(b);  // |p|_inf of the scenes done so far comes back with their flags
         b.read_out();
         b.prof_collect();
         bool all = true;
         for (size_t i = 0; i < ns; ++i)
             if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && !b.h_out[i].pcg_done) all = false;
         if (all) break;
-        chunk = 8;
+        chunk = early ? 8 : std::max(8, last / 4);
+        early = 1;
         // scenes that finished leave the remaining launches of the list
         bool shrink = false;
         for (size_t i = 0; i < ns; ++i)
