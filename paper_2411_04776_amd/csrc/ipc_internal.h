@@ -315,6 +315,10 @@ enum PhaseKind {
     kPhPcgA,      // SpMV row blocks, then pair blocks (PCG A)
     kPhPts, kPhEdges, kPhTris, kPhSurf, kPhInd,
     kPhQPts, kPhQEdges,  // broad-phase queries: kLanesQ threads per point / edge
+    kPhPrims,     // point, then edge, then triangle blocks
+    kPhTE,        // triangle, then edge blocks
+    kPhQAll,      // point-query, then edge-query blocks
+    kPhTilesTE,   // both hash tables' bucket blocks
     kPhCand,      // static candidates
     kPhCandSw,    // swept candidates
     kPhAct,       // active pairs, one 64-thread block each

@@ -202,10 +202,8 @@ __device__ __forceinline__ R *as(void *p)
 // box over the primitive's vertex positions at x (and x + p for the swept
 // set), inflated by dhat/2. kind 0 points, 1 edges, 2 triangles.
 template <class R>
-__global__ void k_boxes(Launch L, int kind, int swept)
+__device__ void boxes_body(const SceneDev &S, int lb, int kind, int swept)
 {
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
     int N = kind == 0 ? S.n_pts : (kind == 1 ? S.n_edges : S.n_tris);
     int i = lb * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -235,30 +233,38 @@ __global__ void k_boxes(Launch L, int kind, int swept)
     }
 }
 
-// per-block sums of the largest axis extent of each box (edges at
-// red[0..nbe), triangles after them)
-__global__ void k_box_extent(Launch L, int kind, Launch edges)
+__device__ __forceinline__ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// Boxes of points, edges and triangles in one launch (blocks in that order);
+// with `extent`, the edge and triangle blocks also write the per-block sums
+// of their boxes' largest axis extent (edges at red[0..nbe), triangles after).
+template <class R>
+__global__ void k_boxes_all(Launch L, int swept, int extent)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
+    const int np = blocks_for(S.n_pts), ne = blocks_for(S.n_edges);
+    int kind = lb < np ? 0 : (lb < np + ne ? 1 : 2);
+    int kb = kind == 0 ? lb : (kind == 1 ? lb - np : lb - np - ne);
+    boxes_body<R>(S, kb, kind, swept);
+    if (!extent || kind == 0) return;  // uniform over the block
     int N = kind == 1 ? S.n_edges : S.n_tris;
     const double *box = kind == 1 ? S.ebox : S.tbox;
-    int i = lb * blockDim.x + threadIdx.x;
+    int i = kb * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < N)
         for (int c = 0; c < 3; ++c) e = fmax(e, box[(3 + c) * N + i] - box[c * N + i]);
     e = block_sum_all(e);
-    int off = kind == 1 ? 0 : blocks_of(edges, s);
-    if (threadIdx.x == 0) S.red[off + lb] = e;
+    if (threadIdx.x == 0) S.red[(kind == 1 ? 0 : ne) + kb] = e;
 }
 
 // cell size = mean extent of the edge and triangle boxes (never below the
 // inflation dhat): most primitives span 1-3 cells per axis, large ones more
-__global__ void k_cell_size(Launch one, Launch edges, Launch tris)
+__global__ void k_cell_size(Launch one)
 {
     int lb, s = scene_of_block(one, lb);
     const SceneDev &S = *one.sc[s];
-    int nb = blocks_of(edges, s) + blocks_of(tris, s);
+    int nb = blocks_for(S.n_edges) + blocks_for(S.n_tris);
     double v = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) v += S.red[i];
     v = block_sum_all(v);
@@ -286,11 +292,22 @@ __global__ void k_zero(Launch L, int which)
         a[i] = 0;
 }
 
-template <bool FILL>
-__global__ void k_hash_insert(Launch L, int table)
+// zero both hash tables' bucket counts in one launch (table 0's blocks first)
+__global__ void k_zero_tables(Launch L)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
+    const int64_t len0 = ((int64_t)1 << S.ht_bits[0]) + 1;
+    const int n0 = blocks_for(len0);
+    int t = lb < n0 ? 0 : 1;
+    int64_t len = t == 0 ? len0 : ((int64_t)1 << S.ht_bits[1]) + 1;
+    int64_t i = (int64_t)(t == 0 ? lb : lb - n0) * blockDim.x + threadIdx.x;
+    if (i < len) S.ht_count[t][i] = 0;
+}
+
+template <bool FILL>
+__device__ void hash_insert_body(const Launch &L, int s, const SceneDev &S, int lb, int table)
+{
     int N = table == 0 ? S.n_tris : S.n_edges;
     const double *box = table == 0 ? S.tbox : S.ebox;
     int i = lb * blockDim.x + threadIdx.x;
@@ -320,6 +337,19 @@ __global__ void k_hash_insert(Launch L, int table)
             }
 }
 
+// triangles into table 0, then edges into table 1, in one launch
+template <bool FILL>
+__global__ void k_hash_insert_all(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const int nt = blocks_for(S.n_tris);
+    if (lb < nt)
+        hash_insert_body<FILL>(L, s, S, lb, 0);
+    else
+        hash_insert_body<FILL>(L, s, S, lb - nt, 1);
+}
+
 __device__ __forceinline__ bool pt_admissible(const SceneDev &S, int a, int t0, int t1, int t2)
 {
     if (a == t0 || a == t1 || a == t2) return false;
@@ -346,10 +376,8 @@ __device__ __forceinline__ bool ee_admissible(const SceneDev &S, int a0, int a1,
 // segment by b (each pair is found in exactly one cell, so the sorted segment
 // does not depend on the split). swept selects the output list.
 template <int KIND, bool COUNT>
-__global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
+__device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, int swept)
 {
-    int lb, s = scene_of_block(L, lb);
-    const SceneDev &S = *L.sc[s];
     int NA = KIND == 0 ? S.n_pts : S.n_edges;
     int NB = KIND == 0 ? S.n_tris : S.n_edges;
     int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
@@ -461,6 +489,19 @@ __global__ void __launch_bounds__(kBlock) k_query(Launch L, int swept)
             }
         }
     }
+}
+
+// point queries, then edge queries, in one launch
+template <bool COUNT>
+__global__ void __launch_bounds__(kBlock) k_query_all(Launch L, int swept)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    const int np = blocks_for((int64_t)S.n_pts * kLanesQ);
+    if (lb < np)
+        query_body<0, COUNT>(L, s, S, lb, swept);
+    else
+        query_body<1, COUNT>(L, s, S, lb - np, swept);
 }
 
 // Static pairs from the swept list: a swept pair is static at x iff the two
@@ -1140,19 +1181,12 @@ void run_broad_phase(Batch &b, int which)
     hipEvent_t ev[2];
     b.prof_begin(kProfBroad, ev);
     bool mx = mixed(b);
-    if (mx) {
-        IPC_LAUNCH(b, k_boxes<float>, kPhPts, kBlock, 0, which);
-        IPC_LAUNCH(b, k_boxes<float>, kPhEdges, kBlock, 1, which);
-        IPC_LAUNCH(b, k_boxes<float>, kPhTris, kBlock, 2, which);
-    } else {
-        IPC_LAUNCH(b, k_boxes<double>, kPhPts, kBlock, 0, which);
-        IPC_LAUNCH(b, k_boxes<double>, kPhEdges, kBlock, 1, which);
-        IPC_LAUNCH(b, k_boxes<double>, kPhTris, kBlock, 2, which);
-    }
-    IPC_LAUNCH(b, k_box_extent, kPhEdges, kBlock, 1, b.launch(kPhEdges));
-    IPC_LAUNCH(b, k_box_extent, kPhTris, kBlock, 2, b.launch(kPhEdges));
+    if (mx)
+        IPC_LAUNCH(b, k_boxes_all<float>, kPhPrims, kBlock, which, 1);
+    else
+        IPC_LAUNCH(b, k_boxes_all<double>, kPhPrims, kBlock, which, 1);
     one_per_active(b, kPhVert);
-    IPC_LAUNCH(b, k_cell_size, kPhOne, kBlock, b.launch(kPhEdges), b.launch(kPhTris));
+    IPC_LAUNCH(b, k_cell_size, kPhOne, kBlock);
     size_t ns = b.sc.size();
     std::vector<uint8_t> redo(ns, 0), live(ns, 0);
     for (size_t i = 0; i < ns; ++i) live[i] = b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i];
@@ -1172,22 +1206,16 @@ void run_broad_phase(Batch &b, int which)
             lq[i] = (int64_t)S.n_pts + S.n_edges;
         }
         // zero the buckets, count, scan, zero again, fill; then count queries
-        b.set_phase(kPhTilesT, tiles_of(0));
-        b.set_phase(kPhTilesE, tiles_of(1));
-        IPC_LAUNCH(b, k_zero, kPhTilesT, kBlock, 0);
-        IPC_LAUNCH(b, k_zero, kPhTilesE, kBlock, 1);
-        IPC_LAUNCH(b, k_hash_insert<false>, kPhTris, kBlock, 0);
-        IPC_LAUNCH(b, k_hash_insert<false>, kPhEdges, kBlock, 1);
+        std::vector<int32_t> zt = tiles_of(0), ze = tiles_of(1);
+        for (size_t i = 0; i < ns; ++i) zt[i] += ze[i];
+        b.set_phase(kPhTilesTE, zt);
+        IPC_LAUNCH(b, k_zero_tables, kPhTilesTE, kBlock);
+        IPC_LAUNCH(b, k_hash_insert_all<false>, kPhTE, kBlock);
         segmented_scan(b, kScanTri, kPhTilesT, lt);
         segmented_scan(b, kScanEdge, kPhTilesE, le);
-        b.set_phase(kPhTilesT, tiles_of(0));
-        b.set_phase(kPhTilesE, tiles_of(1));
-        IPC_LAUNCH(b, k_zero, kPhTilesT, kBlock, 0);
-        IPC_LAUNCH(b, k_zero, kPhTilesE, kBlock, 1);
-        IPC_LAUNCH(b, k_hash_insert<true>, kPhTris, kBlock, 0);
-        IPC_LAUNCH(b, k_hash_insert<true>, kPhEdges, kBlock, 1);
-        IPC_LAUNCH(b, (k_query<0, true>), kPhQPts, kBlock, which);
-        IPC_LAUNCH(b, (k_query<1, true>), kPhQEdges, kBlock, which);
+        IPC_LAUNCH(b, k_zero_tables, kPhTilesTE, kBlock);
+        IPC_LAUNCH(b, k_hash_insert_all<true>, kPhTE, kBlock);
+        IPC_LAUNCH(b, k_query_all<true>, kPhQAll, kBlock, which);
         segmented_scan(b, kScanQuery, kPhTilesQ, lq, which);
         b.read_out();
         bool any_redo = false;
@@ -1233,8 +1261,7 @@ void run_broad_phase(Batch &b, int which)
         b.upload_views();
         // failed scenes still run the fill pass: every write is bounded by
         // their list capacity, and the caller drops them afterwards
-        IPC_LAUNCH(b, (k_query<0, false>), kPhQPts, kBlock, which);
-        IPC_LAUNCH(b, (k_query<1, false>), kPhQEdges, kBlock, which);
+        IPC_LAUNCH(b, k_query_all<false>, kPhQAll, kBlock, which);
         b.prof_end(kProfBroad, ev);
         return;
     }
@@ -1245,15 +1272,10 @@ void run_static_from_swept(Batch &b)
     hipEvent_t ev[2];
     b.prof_begin(kProfBroad, ev);
     size_t ns = b.sc.size();
-    if (mixed(b)) {
-        IPC_LAUNCH(b, k_boxes<float>, kPhPts, kBlock, 0, 0);
-        IPC_LAUNCH(b, k_boxes<float>, kPhEdges, kBlock, 1, 0);
-        IPC_LAUNCH(b, k_boxes<float>, kPhTris, kBlock, 2, 0);
-    } else {
-        IPC_LAUNCH(b, k_boxes<double>, kPhPts, kBlock, 0, 0);
-        IPC_LAUNCH(b, k_boxes<double>, kPhEdges, kBlock, 1, 0);
-        IPC_LAUNCH(b, k_boxes<double>, kPhTris, kBlock, 2, 0);
-    }
+    if (mixed(b))
+        IPC_LAUNCH(b, k_boxes_all<float>, kPhPrims, kBlock, 0, 0);
+    else
+        IPC_LAUNCH(b, k_boxes_all<double>, kPhPrims, kBlock, 0, 0);
     std::vector<int32_t> nb(ns, 0);
     std::vector<int64_t> len(ns, -1);
     for (size_t i = 0; i < ns; ++i) {

@@ -1031,6 +1031,16 @@ static void activate(Batch &b, const std::vector<uint8_t> &on)
     }
     b.set_phase(kPhQPts, p);
     b.set_phase(kPhQEdges, ed);
+    std::vector<int32_t> pr(ns), te(ns), qa(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const SceneDev &H = b.sc[i]->h;
+        pr[i] = on[i] ? nblocks(H.n_pts) + nblocks(H.n_edges) + nblocks(H.n_tris) : 0;
+        te[i] = on[i] ? nblocks(H.n_tris) + nblocks(H.n_edges) : 0;
+        qa[i] = on[i] ? nblocks((int64_t)H.n_pts * kLanesQ) + nblocks((int64_t)H.n_edges * kLanesQ) : 0;
+    }
+    b.set_phase(kPhPrims, pr);
+    b.set_phase(kPhTE, te);
+    b.set_phase(kPhQAll, qa);
     std::vector<int32_t> ms(ns), mg(ns);
     for (size_t i = 0; i < ns; ++i) {
         const SceneDev &h = b.sc[i]->h;
