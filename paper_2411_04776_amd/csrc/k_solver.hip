@@ -118,6 +118,52 @@ __device__ __forceinline__ void bell_row_part2(const SceneDev &S, int row, int p
     yd[2] = b2;
 }
 
+// Both slot streams of one row by one thread, interleaved (two independent
+// chains of loads in flight); each stream accumulates its slots in the same
+// order and with the same expressions as bell_row_part2, so the partial sums
+// are bit-identical to the two-lane form.
+template <class R>
+__device__ __forceinline__ void bell_row_both(const SceneDev &S, int row, const R *__restrict__ z,
+                                              const R *__restrict__ dold, bool two, double yz[2][3], double yd[2][3])
+{
+    int sl = row / kSlice, lane = row % kSlice;
+    int s0 = S.slice_ptr[sl], s1 = S.slice_ptr[sl + 1];
+    const R *__restrict__ bval = as<R>(S.bval);
+    const int32_t *__restrict__ bcol = S.bcol;
+    R a[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}}, c[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+#pragma unroll 2
+    for (int slot = s0; slot < s1; slot += 2) {
+        int col[2];
+        col[0] = bcol[(int64_t)slot * kSlice + lane];
+        col[1] = slot + 1 < s1 ? bcol[(int64_t)(slot + 1) * kSlice + lane] : -1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (col[k] < 0) continue;
+            const R *A = bval + (int64_t)(slot + k) * 9 * kSlice + lane;
+            R m[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) m[e] = A[e * kSlice];
+            R v0 = z[3 * col[k]], v1 = z[3 * col[k] + 1], v2 = z[3 * col[k] + 2];
+            a[k][0] += m[0] * v0 + m[1] * v1 + m[2] * v2;
+            a[k][1] += m[3] * v0 + m[4] * v1 + m[5] * v2;
+            a[k][2] += m[6] * v0 + m[7] * v1 + m[8] * v2;
+            if (two) {
+                R w0 = dold[3 * col[k]], w1 = dold[3 * col[k] + 1], w2 = dold[3 * col[k] + 2];
+                c[k][0] += m[0] * w0 + m[1] * w1 + m[2] * w2;
+                c[k][1] += m[3] * w0 + m[4] * w1 + m[5] * w2;
+                c[k][2] += m[6] * w0 + m[7] * w1 + m[8] * w2;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            yz[k][e] = a[k][e];
+            yd[k][e] = c[k][e];
+        }
+}
+
 // One active pair: y_a = sum over b != a of H_ab d_b for its four slots
 // (the diagonal blocks live in the BELL diagonal), stored per pair for the
 // row gather; returns sum_a d_a . y_a.
@@ -187,9 +233,12 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
     for (int q = 0; q < NP; ++q)
 #pragma unroll
         for (int c = 0; c < 3; ++c) yz[q][c] = yd[q][c] = 0.0;
-    if (live)
-#pragma unroll
-        for (int q = 0; q < NP; ++q) bell_row_part2<R>(S, row, part0 + q, z, dold, bon, yz[q], yd[q]);
+    if (live) {
+        if constexpr (NP == 2)
+            bell_row_both<R>(S, row, z, dold, bon, yz, yd);
+        else
+            bell_row_part2<R>(S, row, part0, z, dold, bon, yz[0], yd[0]);
+    }
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
