@@ -121,7 +121,9 @@ __device__ __forceinline__ void bell_row_part2(const SceneDev &S, int row, int p
 // Both slot streams of one row by one thread, interleaved (two independent
 // chains of loads in flight); each stream accumulates its slots in the same
 // order and with the same expressions as bell_row_part2, so the partial sums
-// are bit-identical to the two-lane form.
+// are bit-identical to the two-lane form. Used for large lists, whose matrix
+// exceeds the caches: its values are streamed with non-temporal loads so the
+// gathered vectors keep the cache.
 template <class R>
 __device__ __forceinline__ void bell_row_both(const SceneDev &S, int row, const R *__restrict__ z,
                                               const R *__restrict__ dold, bool two, double yz[2][3], double yd[2][3])
@@ -142,7 +144,7 @@ __device__ __forceinline__ void bell_row_both(const SceneDev &S, int row, const 
             const R *A = bval + (int64_t)(slot + k) * 9 * kSlice + lane;
             R m[9];
 #pragma unroll
-            for (int e = 0; e < 9; ++e) m[e] = A[e * kSlice];
+            for (int e = 0; e < 9; ++e) m[e] = __builtin_nontemporal_load(A + e * kSlice);  // read once per launch
             R v0 = z[3 * col[k]], v1 = z[3 * col[k] + 1], v2 = z[3 * col[k] + 2];
             a[k][0] += m[0] * v0 + m[1] * v1 + m[2] * v2;
             a[k][1] += m[3] * v0 + m[4] * v1 + m[5] * v2;
