@@ -95,7 +95,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--pcg-tol", type=float, default=1e-4)
+    # PCG tolerance of the timed runs: the loosest that keeps the final error of
+    # config 2 far inside 1e-4 L (tests/test_gpu_fixed_error.py: 8e-6 L)
+    ap.add_argument("--pcg-tol", type=float, default=1e-3)
     ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel",
                     help="PCG preconditioner: additive multilevel aggregates or block-Jacobi")
     ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected",

@@ -31,7 +31,7 @@ def main():
         f.write(f"# written by tests/golden/make_c2_final.py; L = {sc.bbox_diag!r}\n")
         f.write("# vertex x y z (m)\n")
         for i in idx:
-            f.write(f"{i} {x[i, 0]!r} {x[i, 1]!r} {x[i, 2]!r}\n")
+            f.write(f"{i} {float(x[i, 0])!r} {float(x[i, 1])!r} {float(x[i, 2])!r}\n")
 
 
 if __name__ == "__main__":
