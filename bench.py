@@ -313,7 +313,9 @@ def soft_ball_leg(args, ipc, scenes, torch):
     out = {}
     for size in ("small", "medium", "large"):
         sc = scenes.soft_ball_scene(size, steps=21)
-        g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args),
+        # the floating ball's near-rigid modes make Newton sensitive to inexact
+        # steps: this leg solves PCG to 1e-4 (fewer Newton iterations than 1e-3)
+        g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
                          barrier_hessian=barrier_code(args))
         g.step()
         torch.cuda.synchronize()
@@ -328,7 +330,7 @@ def soft_ball_leg(args, ipc, scenes, torch):
         out[size] = {"verts": len(sc.X), "tets": len(sc.T), "ms_per_step": round(1e3 * sum(t) / len(t), 2),
                      "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
                      "newton_per_step": round(newton / len(t), 2), "pcg_per_newton": round(pcg / max(newton, 1), 1),
-                     "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
+                     "pcg_tol": min(args.pcg_tol, 1e-4), "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
         print(f"soft ball {size}: {out[size]}", file=sys.stderr, flush=True)
     return out
 
