@@ -1225,8 +1225,10 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     while (it <= maxit + 1) {
         int c = std::min(chunk, maxit + 2 - it);
         for (int j = 0; j < c; ++j, ++it) {
-            // time one launch in sixteen when profiling (not the early-exit launches)
-            bool timed = b.prof() && (it & 15) == 1 && !early;
+            // time one launch in sixteen when profiling: iterations 2, 18, 34, ...
+            // of the first chunk (the first iteration applies the matrix to one
+            // vector only; later chunks may skip finished scenes early)
+            bool timed = b.prof() && (it & 15) == 2 && !early;
             if (timed) b.prof_begin(kProfPcgA, ev);
             if (one_lane) {
                 if (mx)
