@@ -85,6 +85,46 @@ __device__ inline double wave_reduce_partials(const double *partials, int n)
     return __shfl(acc, 0, kWave);
 }
 
+// The same sum in two parts, for a kernel that can issue the loads before
+// other dependent loads: wave_partials_load fetches a lane's first U entries,
+// wave_partials_sum adds them and the rest (four loads ahead of the adds) in
+// the same order, so the value is bit-identical to wave_reduce_partials. The
+// PCG update kernel keeps the plain loop, which measured faster there.
+template <int U>
+__device__ __forceinline__ void wave_partials_load(const double *partials, int n, double (&a)[U])
+{
+    int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int i = lane + u * kWave;
+        a[u] = i < n ? partials[i] : 0.0;
+    }
+}
+
+template <int U>
+__device__ __forceinline__ double wave_partials_sum(const double *partials, int n, const double (&a)[U])
+{
+    constexpr int kU = 4;
+    int lane = threadIdx.x & (kWave - 1);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (lane + u * kWave < n) acc += a[u];
+    for (int base = lane + U * kWave; base < n; base += kU * kWave) {
+        double b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            int i = base + u * kWave;
+            b[u] = i < n ? partials[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (base + u * kWave < n) acc += b[u];
+    }
+    acc = wave_sum(acc);
+    return __shfl(acc, 0, kWave);
+}
+
 // ---- compensated (double-double style) sums for energies ----------------
 struct CSum {
     double s, c;

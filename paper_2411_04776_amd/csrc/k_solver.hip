@@ -223,6 +223,10 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
     if (early && S.pcg->done) return;  // launches past the expected count: a finished solve costs nothing
+    // the previous launch's r.z partials load before the matrix rows
+    const int nrz = S.pcg_nvp + L.out[s].n_heavy;
+    double rzp[2];
+    wave_partials_load<2>(rz_slot(S, it - 1), nrz, rzp);
     const R *z = as<R>(S.z);
     const R *dold = as<R>((it & 1) ? S.dB : S.dA);
     const bool bon = it > 1;
@@ -244,7 +248,7 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
     if (S.pcg->done) return;
     double beta = 0.0;
     if (it == 1) {
-        double rz0 = wave_reduce_partials(rz_slot(S, 0), S.pcg_nvp + L.out[s].n_heavy);
+        double rz0 = wave_partials_sum<2>(rz_slot(S, 0), nrz, rzp);
         if (!(rz0 > 0.0)) {
             if (lb == 0 && t == 0) {
                 S.pcg->done = 1;
@@ -259,7 +263,7 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
             S.pcg->rzv[1] = rz0;
         }
     } else {
-        double rz_cur = wave_reduce_partials(rz_slot(S, it - 1), S.pcg_nvp + L.out[s].n_heavy);
+        double rz_cur = wave_partials_sum<2>(rz_slot(S, it - 1), nrz, rzp);
         bool conv = rz_cur <= S.pcg->stop;
         if (conv || it > S.pcg_maxit) {  // converged, or the scene's iteration cap is spent
             if (lb == 0 && t == 0) {
