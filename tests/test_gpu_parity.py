@@ -132,6 +132,27 @@ def test_pcg_and_ccd_parity(ipc, precond):
     assert abs(ag - ao) <= 1e-12 * max(ao, 1e-30)
 
 
+def test_pcg_parity_many_update_blocks(ipc):
+    """A 60x60x10 gel has more than 128 PCG update blocks, so the SpMV
+    kernel's r.z sums run past the partials each lane loads up front.
+    Block-Jacobi PCG at tolerance 1e-6 against the oracle's."""
+    sc = S.uneven_scene(7100, steps=2, grid=(60, 60, 10))
+    n = len(sc.X) + len(sc.Y)
+    assert (n + 255) // 256 > 128
+    say("pcg, many update blocks:", n, "vertices")
+    g = ipc.GelScene(sc, precond=ipc.IPC_PRECOND_JACOBI, pcg_tol=1e-6)
+    o = O.OracleScene(sc, pcg_tol=1e-6)
+    g.begin_step(sc.poses[1])
+    o.begin_step(sc.poses[1])
+    x = pressed(o.x, o.n_gel, sc.fixed, sc.dhat, 0.85, seed=4)
+    pg, itg = g.pcg(x)
+    po, ito = o.pcg(x)
+    L = sc.bbox_diag
+    say("  pcg iterations gpu/oracle", itg, ito, "max diff / L", np.abs(pg - po).max() / L)
+    assert ito >= 10 and abs(itg - ito) <= 2
+    assert np.abs(pg - po).max() <= 1e-9 * L
+
+
 def test_teacher_forced_newton_iterates(ipc, c1_oracle_trajectory):
     sc, traj, _ = c1_oracle_trajectory
     L = sc.bbox_diag
