@@ -133,10 +133,13 @@ def test_pcg_and_ccd_parity(ipc, precond):
 
 
 def test_pcg_parity_many_update_blocks(ipc):
-    """A 60x60x10 gel has more than 128 PCG update blocks, so the SpMV
+    """A 60x60x12 gel has more than 128 PCG update blocks, so the SpMV
     kernel's r.z sums run past the partials each lane loads up front.
-    Block-Jacobi PCG at tolerance 1e-6 against the oracle's."""
-    sc = S.uneven_scene(7100, steps=2, grid=(60, 60, 10))
+    Block-Jacobi PCG at tolerance 1e-6 follows the oracle's iteration by
+    iteration. (The multilevel form is not compared here: on this thin,
+    ill-conditioned gel two preconditioners stopped at the same relative
+    tolerance give solutions that differ by ~1e-6 of |p|.)"""
+    sc = S.uneven_scene(7100, steps=2, grid=(60, 60, 12))
     n = len(sc.X) + len(sc.Y)
     assert (n + 255) // 256 > 128
     say("pcg, many update blocks:", n, "vertices")
