@@ -308,29 +308,34 @@ PAPER_SOFT_BALL_MS = {"small": 24.95, "medium": 110.47, "large": 221.61}
 def soft_ball_leg(args, ipc, scenes, torch):
     """Gel pad + soft ball squeezed by a rigid plate at the three mesh sizes
     of the paper's GIPC timing table (gel + ball vertex/tet counts), FP64,
-    20 steps each after one untimed step; ms per step beside the paper's
-    per-frame times on its own hardware (a different scene: context)."""
+    20 steps each after one untimed step, with both pair-Hessian forms (the
+    projected one and the Gauss-Newton one GIPC uses); ms per step beside the
+    paper's per-frame times on its own hardware (a different scene: context)."""
     out = {}
+    forms = (("projected", ipc.IPC_BARRIER_PROJECTED), ("gauss_newton", ipc.IPC_BARRIER_GAUSS_NEWTON))
     for size in ("small", "medium", "large"):
         sc = scenes.soft_ball_scene(size, steps=21)
-        # the floating ball's near-rigid modes make Newton sensitive to inexact
-        # steps: this leg solves PCG to 1e-4 (fewer Newton iterations than 1e-3)
-        g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
-                         barrier_hessian=barrier_code(args))
-        g.step()
-        torch.cuda.synchronize()
-        newton, pcg, t = 0, 0, []
-        for _ in range(sc.n_steps - 1):
-            t0 = time.perf_counter()
-            rc, st = g.step()
-            t.append(time.perf_counter() - t0)
-            newton += st.newton_iters
-            pcg += st.pcg_iters
-        g.close()
-        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "ms_per_step": round(1e3 * sum(t) / len(t), 2),
-                     "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
-                     "newton_per_step": round(newton / len(t), 2), "pcg_per_newton": round(pcg / max(newton, 1), 1),
-                     "pcg_tol": min(args.pcg_tol, 1e-4), "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
+        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "pcg_tol": min(args.pcg_tol, 1e-4),
+                     "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
+        for name, code in forms:
+            # the floating ball's near-rigid modes make Newton sensitive to inexact
+            # steps: this leg solves PCG to 1e-4 (fewer Newton iterations than 1e-3)
+            g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
+                             barrier_hessian=code)
+            g.step()
+            torch.cuda.synchronize()
+            newton, pcg, t = 0, 0, []
+            for _ in range(sc.n_steps - 1):
+                t0 = time.perf_counter()
+                rc, st = g.step()
+                t.append(time.perf_counter() - t0)
+                newton += st.newton_iters
+                pcg += st.pcg_iters
+            g.close()
+            out[size][name] = {"ms_per_step": round(1e3 * sum(t) / len(t), 2),
+                               "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
+                               "newton_per_step": round(newton / len(t), 2),
+                               "pcg_per_newton": round(pcg / max(newton, 1), 1)}
         print(f"soft ball {size}: {out[size]}", file=sys.stderr, flush=True)
     return out
 
