@@ -194,7 +194,12 @@ IPC_API int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t 
 /* Reset: positions to rest, velocities to zero, indenter to its initial pose
  * (paper section "General GIPC Simulation Pipeline"). */
 IPC_API int32_t ipc_reset(ipc_scene *s);
-/* Save / load x, v and the step index to / from a caller-owned host blob. */
+/* Save / load a scene's state to / from a caller-owned host blob of
+ * ipc_state_bytes bytes: x, v, the step index, the indenter pose of the last
+ * request and the sensor case pose (so an attached scene resumes with the
+ * case where it was). The lagged friction set and the kept candidate list are
+ * not saved: the next step rebuilds them from x. load returns
+ * IPC_E_INVALID_ARG for a blob of another scene size or format. */
 IPC_API int64_t ipc_state_bytes(const ipc_scene *s);
 IPC_API int32_t ipc_save_state(const ipc_scene *s, void *blob, int64_t cap);
 IPC_API int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes);

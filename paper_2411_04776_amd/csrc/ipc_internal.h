@@ -85,7 +85,9 @@ struct SceneOut {
     int32_t pcg_done, pcg_iters;
     int32_t n_heavy;      // incidence rows with more than kHeavyRow entries
     int32_t n_pair;       // pairs in the active arrays: n_act barrier pairs, then the friction pairs
-    int32_t pad2;
+    int32_t pcg_early;    // PCG launches past this iteration check the done flag before any load
+                          // (7/8 of the slot's last solve, written by the device; a heuristic only:
+                          // a finished solve's launches write nothing either way)
     double pinf;          // max |p| over free DOFs
     double alpha_ccd;
     double energy;

@@ -268,7 +268,10 @@ __global__ void k_cell_size(Launch one)
     double v = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) v += S.red[i];
     v = block_sum_all(v);
-    if (threadIdx.x == 0) *S.cell_h = fmax(v / (double)(S.n_edges + S.n_tris), S.dhat);
+    if (threadIdx.x == 0) {
+        *S.cell_h = fmax(v / (double)(S.n_edges + S.n_tris), S.dhat);
+        one.out[s].bad = 0;  // this broad phase's own verdict (set by its count pass)
+    }
 }
 
 __device__ __forceinline__ int cell_of(double v, double h) { return (int)floor(v / h); }

@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
     __shared__ double sdq[kRowsPerBlock];
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    if (early && S.pcg->done) return;  // launches past the expected count: a finished solve costs nothing
+    // launches past the expected count of this scene's solve: a finished solve costs nothing
+    if ((early || it > L.out[s].pcg_early) && S.pcg->done) return;
     // the previous launch's r.z partials load before the matrix rows
     const int nrz = S.pcg_nvp + L.out[s].n_heavy;
     double rzp[2];
@@ -271,6 +272,7 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
                 S.pcg->iters = it - 1;
                 L.out[s].pcg_done = conv ? 1 : 2;
                 L.out[s].pcg_iters = it - 1;
+                L.out[s].pcg_early = max(8, ((it - 1) * 7) / 8);  // for the next solve
             }
             return;
         }
@@ -756,7 +758,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it, int early)
 {
     int lb, s = scene_of_block(L, lb);
     const SceneDev &S = *L.sc[s];
-    if (early && it > 0 && S.pcg->done) return;
+    if ((early || it > L.out[s].pcg_early) && it > 0 && S.pcg->done) return;
     if (it == 0 && lb == 0 && threadIdx.x == 0) {  // a new solve
         S.pcg->done = 0;
         S.pcg->iters = 0;
@@ -1198,21 +1200,35 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     }
     iters.assign(ns, 0);
     hit_cap.assign(ns, 0);
-    // algorithmic bytes of one A launch over the list: every stored 3x3 block
+    // algorithmic bytes of one scene in one A launch: every stored 3x3 block
     // (values and column) once; per vertex the z and d gathers, the d and q
     // writes and its row pointer; per pair its off-diagonal blocks and ids
-    auto spmv_bytes = [&]() {
-        double v = 0.0;
+    std::vector<double> scene_bytes(ns, 0.0);
+    {
         const double rs = mx ? 4.0 : 8.0;
         for (size_t i = 0; i < ns; ++i) {
             if (nab[i] == 0) continue;
             const Scene &s = *b.sc[i];
-            v += (9 * rs + 4) * (double)s.nnzb + (12 * rs + 4) * (double)s.h.n +
-                 (108 * rs + 16) * (double)pair_count(s, b.h_out[i]);
+            scene_bytes[i] = (9 * rs + 4) * (double)s.nnzb + (12 * rs + 4) * (double)s.h.n +
+                             (108 * rs + 16) * (double)pair_count(s, b.h_out[i]);
         }
-        return v;
+    }
+    // Timed A launches of a chunk get their bytes once the chunk's flags are
+    // back: a scene counts in the launch of iteration it when its solve was
+    // still running there (not finished, or finished with more than it - 1
+    // iterations); finished solves exit before their first load.
+    std::vector<std::pair<size_t, int>> timed_a;  // (pending event index, it)
+    auto settle_bytes = [&]() {
+        for (auto &ta : timed_a) {
+            double v = 0.0;
+            for (size_t i = 0; i < ns; ++i) {
+                if (scene_bytes[i] == 0.0) continue;
+                if (!b.h_out[i].pcg_done || ta.second <= b.h_out[i].pcg_iters) v += scene_bytes[i];
+            }
+            b.ev_pending[ta.first].bytes = v;
+        }
+        timed_a.clear();
     };
-    double a_bytes = b.prof() ? spmv_bytes() : 0.0;
     // large lists are bandwidth-bound: a thread per row reads the slices fully coalesced
     int64_t rows_total = 0;
     for (size_t i = 0; i < ns; ++i)
@@ -1234,6 +1250,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             // vector only; later chunks may skip finished scenes early)
             bool timed = b.prof() && (it & 15) == 2 && !early;
             if (timed) b.prof_begin(kProfPcgA, ev);
+            if (timed) timed_a.push_back({b.ev_pending.size(), it});
             if (one_lane) {
                 if (mx)
                     IPC_LAUNCH(b, (k_pcg_A<float, 1>), kPhPcgA, kRowsPerBlock, it, early);
@@ -1245,7 +1262,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
                 else
                     IPC_LAUNCH(b, (k_pcg_A<double, 2>), kPhPcgA, 2 * kRowsPerBlock, it, early);
             }
-            if (timed) b.prof_end(kProfPcgA, ev, a_bytes);
+            if (timed) b.prof_end(kProfPcgA, ev, 0.0);
             if (timed) b.prof_begin(kProfPcgB, ev);
             if (mx)
                 IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it, early);
@@ -1255,6 +1272,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         }
         run_pinf(b);  // |p|_inf of the scenes done so far comes back with their flags
         b.read_out();
+        settle_bytes();
         b.prof_collect();
         bool all = true;
         for (size_t i = 0; i < ns; ++i)
@@ -1272,7 +1290,6 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         if (shrink) {
             b.set_phase(kPhPcgA, nab);
             b.set_phase(kPhPcgB, nbb);
-            if (b.prof()) a_bytes = spmv_bytes();
         }
     }
     for (size_t i = 0; i < ns; ++i) {

@@ -1289,12 +1289,13 @@ static void begin_steps(Batch &b, const std::vector<uint8_t> &on, std::vector<St
     std::vector<uint8_t> onf(ns, 0);
     bool any = false;
     for (size_t i = 0; i < ns; ++i) {
+        if (!on[i]) continue;  // scenes in mid-step keep their lagged friction set
         Scene &s = *b.sc[i];
         if (s.h.n_fric) {
             s.h.n_fric = 0;
             s.dev_dirty = true;
         }
-        if (on[i] && s.prm.mu_fric > 0.0) {
+        if (s.prm.mu_fric > 0.0) {
             onf[i] = 1;
             any = true;
         }
@@ -1922,12 +1923,14 @@ int32_t ipc_reset(ipc_scene *s)
     return rc;
 }
 
-static const uint64_t kStateMagic = 0x31657461744370ULL;
+// blob: 4 header words (magic, n, step index, 0), the indenter pose and the
+// case pose (12 doubles each), then x and v (3 n doubles each)
+static const uint64_t kStateMagic = 0x32657461744370ULL;
 
 int64_t ipc_state_bytes(const ipc_scene *s)
 {
     if (!s) return -1;
-    return 32 + 2 * 3 * (int64_t)s->h.n * 8;
+    return 32 + 24 * 8 + 2 * 3 * (int64_t)s->h.n * 8;
 }
 
 int32_t ipc_save_state(const ipc_scene *cs, void *blob, int64_t cap)
@@ -1939,7 +1942,9 @@ int32_t ipc_save_state(const ipc_scene *cs, void *blob, int64_t cap)
     int32_t rc = guarded([&]() -> int32_t {
         uint64_t hdr[4] = {kStateMagic, (uint64_t)s->h.n, (uint64_t)s->step_index, 0};
         std::memcpy(blob, hdr, sizeof hdr);
-        char *p = (char *)blob + 32;
+        std::memcpy((char *)blob + 32, s->h.pose, sizeof(double) * 12);
+        std::memcpy((char *)blob + 32 + 96, s->h.case_pose, sizeof(double) * 12);
+        char *p = (char *)blob + 32 + 192;
         size_t b = sizeof(double) * 3 * s->h.n;
         IPC_HIP(hipMemcpyAsync(p, s->h.x, b, hipMemcpyDeviceToHost, s->stream));
         IPC_HIP(hipMemcpyAsync(p + b, s->h.v, b, hipMemcpyDeviceToHost, s->stream));
@@ -1962,11 +1967,13 @@ int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes)
     bool expect = false;
     if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
     int32_t rc = guarded([&]() -> int32_t {
-        const char *p = (const char *)blob + 32;
+        const char *p = (const char *)blob + 32 + 192;
         size_t b = sizeof(double) * 3 * s->h.n;
         IPC_HIP(hipMemcpyAsync(s->h.x, p, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipMemcpyAsync(s->h.v, p + b, b, hipMemcpyHostToDevice, s->stream));
         IPC_HIP(hipStreamSynchronize(s->stream));
+        set_pose(*s, (const double *)((const char *)blob + 32));
+        set_case_pose(*s, (const double *)((const char *)blob + 32 + 96));
         s->step_index = (int)hdr[2];
         s->sw_ok = false;
         s->h.n_fric = 0;

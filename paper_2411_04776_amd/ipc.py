@@ -7,8 +7,11 @@ import fails loudly; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -215,7 +218,41 @@ class TorchRuntime:
             return 0
 
     def _free_cb(self, ptr, nbytes, stream, user):
+        # At interpreter shutdown torch (and HIP) may already be torn down;
+        # the process is ending, so its device memory goes with it.
+        if sys.is_finalizing():
+            return
         self.torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# Scenes and engines still open at exit are closed by an atexit hook, which
+# runs before module teardown (the hook is registered after torch is
+# imported, and atexit runs hooks last-in first-out), so their device frees
+# reach a live caching allocator instead of running from __del__ during
+# interpreter finalisation.
+_live = weakref.WeakSet()
+
+
+def _close_live():
+    objs = list(_live)
+    # engines first: destroying one waits for the steps of scenes it holds
+    for obj in sorted(objs, key=lambda o: not isinstance(o, Batch)):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+_atexit_registered = False
+
+
+def _track(obj):
+    global _atexit_registered
+    if not _atexit_registered:
+        import torch  # noqa: F401  (imported first, so its own exit hooks run after ours)
+        atexit.register(_close_live)
+        _atexit_registered = True
+    _live.add(obj)
 
 
 def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=None,
@@ -293,6 +330,7 @@ class GelScene:
         _check(lib().ipc_create_scene(C.byref(self.desc), C.byref(self.runtime.rt), C.byref(h)),
                "ipc_create_scene")
         self.ptr = h
+        _track(self)
         sz = np.zeros(8, dtype=np.int32)
         lib().ipc_scene_sizes(self.ptr, _i(sz))
         (self.n, self.n_gel, self.n_tet, self.n_pts, self.n_edges, self.n_tris, self.n_ind,
@@ -305,6 +343,8 @@ class GelScene:
             self.ptr = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return  # the atexit hook closed it, or the process is ending anyway
         try:
             self.close()
         except Exception:
@@ -503,6 +543,7 @@ class Batch:
         h = C.c_void_p()
         _check(lib().ipc_batch_create(C.byref(self.rt), C.byref(h)), "ipc_batch_create")
         self.ptr = h
+        _track(self)
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -510,6 +551,8 @@ class Batch:
             self.ptr = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
