@@ -167,8 +167,6 @@ IPC_API int32_t ipc_step(ipc_scene *s, const ipc_step_req *r, ipc_step_stats *st
  * IPC_DEVICE for xyz; obj_pos (host, may be NULL). cap in doubles. */
 IPC_API int32_t ipc_read_surface(const ipc_scene *s, double *xyz, int64_t cap, int32_t where, void *stream,
                          double obj_pos[3]);
-/* Surface topology: gel surface triangles (outward, vertex ids) and the
- * ascending list of gel surface vertex ids. Either pointer may be NULL. */
 /* Height map of the deformed gel surface (the input of optical tactile
  * renderers, which the paper feeds from the gel's sensing surface). Pixel
  * (i, j), 0 <= i < nx, 0 <= j < ny, has its centre at (x0 + i dx, y0 + j dy)
@@ -189,6 +187,23 @@ typedef struct ipc_height_map_spec {
 } ipc_height_map_spec;
 IPC_API int32_t ipc_height_map(const ipc_scene *s, const ipc_height_map_spec *spec, double *out, int64_t cap,
                                int32_t where, void *stream);
+/* Allocation-free height map, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops or harnesses that forbid
+ * hipMalloc). Same arguments and the same map, bit for bit, as
+ * ipc_height_map, but no allocator is called: the nx ny 8-byte pixel keys
+ * live in one library-owned device array of IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS
+ * entries (8 MiB) per GPU, held until the process ends; its address is looked
+ * up on the first call made on each device. nx ny above that maximum returns
+ * IPC_E_INVALID_ARG (use ipc_height_map). Every call on one GPU uses that
+ * same array, so calls that overlap on one GPU (from several threads, or on
+ * streams that do not serialise them) race and must not be issued; the
+ * array's contents are cleared by each call before use. Returns after the map
+ * is complete on `stream`. */
+#define IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS (1 << 20)
+IPC_API int32_t ipc_height_map_noalloc(const ipc_scene *s, const ipc_height_map_spec *spec, double *out,
+                                       int64_t cap, int32_t where, void *stream);
+/* Surface topology: gel surface triangles (outward, vertex ids) and the
+ * ascending list of gel surface vertex ids. Either pointer may be NULL. */
 IPC_API int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris,
                              int32_t *verts, int64_t vert_cap, int32_t *n_surf_verts);
 /* Reset: positions to rest, velocities to zero, indenter to its initial pose

@@ -1887,6 +1887,77 @@ int32_t ipc_height_map(const ipc_scene *cs, const ipc_height_map_spec *spec, dou
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Height map without device allocation
+// ---------------------------------------------------------------------------
+// The pixel keys live in one library-owned device array per GPU instead of
+// the scene's allocator: callers that may not allocate (HIP graph capture,
+// serving loops that forbid hipMalloc) still get the map. Host code never
+// passes the array's name to a kernel or a copy: it takes the array's device
+// address from hipGetSymbolAddress once per device (with that device
+// current) and uses that address only. With IPC_HOST output the keys are
+// turned into heights in place and copied out from the same array.
+static __device__ __align__(256) unsigned long long scratch[IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS];
+
+static std::mutex g_scratch_mu;
+static std::vector<unsigned long long *> g_scratch_dev;  // per device ordinal, null until looked up
+
+// device address of `scratch` on the current device (looked up on the first
+// call made with that device current)
+static unsigned long long *scratch_address()
+{
+    int dev = 0;
+    IPC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        IPC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = static_cast<unsigned long long *>(p);
+    }
+    return g_scratch_dev[dev];
+}
+
+int32_t ipc_height_map_noalloc(const ipc_scene *cs, const ipc_height_map_spec *spec, double *out, int64_t cap,
+                               int32_t where, void *stream)
+{
+    if (!cs || !spec || !out) return IPC_E_INVALID_ARG;
+    if (spec->nx <= 0 || spec->ny <= 0 || !(spec->dx > 0.0) || !(spec->dy > 0.0) || !std::isfinite(spec->x0) ||
+        !std::isfinite(spec->y0) || !std::isfinite(spec->z_ref)) {
+        set_error("invalid height map grid");
+        return IPC_E_INVALID_ARG;
+    }
+    int64_t np = (int64_t)spec->nx * spec->ny;
+    if (np > IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS) {
+        set_error("height map grid exceeds IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS pixels (use ipc_height_map)");
+        return IPC_E_INVALID_ARG;
+    }
+    if (cap < np) {
+        set_error("height map buffer too small");
+        return IPC_E_INVALID_ARG;
+    }
+    if (where != IPC_HOST && where != IPC_DEVICE) return IPC_E_INVALID_ARG;
+    ipc_scene *s = const_cast<ipc_scene *>(cs);
+    bool expect = false;
+    if (!s->busy.compare_exchange_strong(expect, true)) return IPC_E_BUSY;
+    int32_t rc = guarded([&]() -> int32_t {
+        hipStream_t strm = stream ? (hipStream_t)stream : s->stream;
+        unsigned long long *key = scratch_address();
+        IPC_HIP(hipStreamSynchronize(s->stream));
+        HeightSpec hs{spec->x0, spec->y0, spec->dx, spec->dy, spec->z_ref, spec->nx, spec->ny};
+        // host output: heights overwrite their own keys (one thread per pixel
+        // reads its key, then writes its height to the same 8 bytes)
+        double *dst = where == IPC_DEVICE ? out : reinterpret_cast<double *>(key);
+        launch_height_map(*s, hs, key, dst, strm);
+        if (where == IPC_HOST) IPC_HIP(hipMemcpyAsync(out, key, sizeof(double) * np, hipMemcpyDeviceToHost, strm));
+        IPC_HIP(hipStreamSynchronize(strm));
+        return IPC_OK;
+    });
+    s->busy = false;
+    return rc;
+}
+
 int32_t ipc_surface_topology(const ipc_scene *s, int32_t *tris, int64_t tri_cap, int32_t *n_tris, int32_t *verts,
                              int64_t vert_cap, int32_t *n_surf_verts)
 {

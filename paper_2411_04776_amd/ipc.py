@@ -101,6 +101,8 @@ _SIGS = {
     "ipc_surface_topology": (C.c_int32, [C.c_void_p, _I, C.c_int64, _I, _I, C.c_int64, _I]),
     "ipc_height_map": (C.c_int32, [C.c_void_p, C.POINTER(ipc_height_map_spec), C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_void_p]),
+    "ipc_height_map_noalloc": (C.c_int32, [C.c_void_p, C.POINTER(ipc_height_map_spec), C.c_void_p, C.c_int64,
+                                           C.c_int32, C.c_void_p]),
     "ipc_reset": (C.c_int32, [C.c_void_p]),
     "ipc_state_bytes": (C.c_int64, [C.c_void_p]),
     "ipc_save_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -372,6 +374,19 @@ class GelScene:
         out = np.zeros((int(ny), int(nx)))
         _check(lib().ipc_height_map(self.ptr, C.byref(sp), out.ctypes.data_as(C.c_void_p), out.size, IPC_HOST, None),
                "ipc_height_map")
+        return out
+
+    def height_map_noalloc(self, x0, y0, dx, dy, nx, ny, z_ref, device_out=None):
+        """height_map through the allocation-free entry point (pixel keys in
+        the library's own device array, at most IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS)."""
+        sp = ipc_height_map_spec(float(x0), float(y0), float(dx), float(dy), float(z_ref), int(nx), int(ny))
+        if device_out is not None:
+            _check(lib().ipc_height_map_noalloc(self.ptr, C.byref(sp), C.c_void_p(device_out.data_ptr()),
+                                                device_out.numel(), IPC_DEVICE, None), "ipc_height_map_noalloc")
+            return device_out
+        out = np.zeros((int(ny), int(nx)))
+        _check(lib().ipc_height_map_noalloc(self.ptr, C.byref(sp), out.ctypes.data_as(C.c_void_p), out.size,
+                                            IPC_HOST, None), "ipc_height_map_noalloc")
         return out
 
     def read_surface(self, device_out=None):
