@@ -86,6 +86,7 @@ def lib():
         L.ora_energy.restype = C.c_double
         L.ora_energy.argtypes = [C.c_void_p, _D]
         L.ora_gradient.argtypes = [C.c_void_p, _D, _D]
+        L.ora_gradient_terms.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, _D]
         L.ora_hess_apply.argtypes = [C.c_void_p, _D, _D, _D]
         L.ora_hess_dense.argtypes = [C.c_void_p, _D, _D]
         L.ora_pcg.restype = C.c_int32
@@ -395,6 +396,15 @@ class OracleScene:
         g = np.zeros((self.n, 3))
         lib().ora_gradient(self.ptr, _d(f64(x)), _d(g))
         return g
+
+    def gradient_terms(self, x):
+        """Per-term gradients at x (Dirichlet rows kept): dict of (n,3) arrays
+        'inertia', 'elastic', 'target', 'contact', 'friction'. The force of a
+        term on a vertex is minus its gradient."""
+        names = ("inertia", "elastic", "target", "contact", "friction")
+        out = {k: np.zeros((self.n, 3)) for k in names}
+        lib().ora_gradient_terms(self.ptr, _d(f64(x)), *[_d(out[k]) for k in names])
+        return out
 
     def hess_apply(self, x, v):
         y = np.zeros((self.n, 3))

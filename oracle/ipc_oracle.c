@@ -1612,6 +1612,76 @@ void ora_gradient(ora_scene *s, const double *x, double *g)
     assembly_free(&A);
 }
 
+/* The gradient of each term of Phi separately, at x, with no Dirichlet
+ * rows zeroed (so the forces on fixed vertices, i.e. the support reactions,
+ * can be read): inertia m_i/h^2 (x_i - xtilde_i) on free gel vertices,
+ * elasticity sum_e V_e dPsi/dx, the soft targets k_t (x - yhat) (indenter and
+ * attached vertices), the barrier over the active static candidates at x and
+ * the lagged friction. Each output is 3n doubles, or NULL to skip it. The
+ * force a term exerts on a vertex is minus its gradient. */
+void ora_gradient_terms(ora_scene *s, const double *x, double *g_inertia, double *g_elastic, double *g_target,
+                        double *g_contact, double *g_friction)
+{
+    int n = s->n;
+    double h2 = s->prm.h * s->prm.h;
+    double *outs[5] = {g_inertia, g_elastic, g_target, g_contact, g_friction};
+    for (int k = 0; k < 5; ++k)
+        if (outs[k]) memset(outs[k], 0, sizeof(double) * 3 * n);
+    if (g_inertia)
+        for (int i = 0; i < s->n_gel; ++i) {
+            if (s->fixed[i]) continue;
+            for (int c = 0; c < 3; ++c) g_inertia[3 * i + c] = s->mass[i] / h2 * (x[3 * i + c] - s->xtilde[3 * i + c]);
+        }
+    if (g_elastic)
+        for (int e = 0; e < s->n_tet; ++e) {
+            const int32_t *t = s->T + 4 * e;
+            double x12[12], g12[12], E;
+            gather12(x, t, x12);
+            ora_tet_elastic(x12, s->Bm + 9 * e, s->vol[e], s->mu, s->lam, &E, g12, NULL);
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 3; ++c) g_elastic[3 * t[a] + c] += g12[3 * a + c];
+        }
+    if (g_target) {
+        for (int j = s->n_gel; j < n; ++j)
+            for (int c = 0; c < 3; ++c) g_target[3 * j + c] = s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]);
+        for (int i = 0; i < s->n_gel; ++i)
+            if (is_attached(s, i))
+                for (int c = 0; c < 3; ++c)
+                    g_target[3 * i + c] = s->prm.k_target * (x[3 * i + c] - s->yhat[3 * i + c]);
+    }
+    if (g_contact) {
+        ivec cand = {0, 0, 0};
+        candidates_list(s, x, NULL, &cand);
+        for (int i = 0; i < cand.n / 3; ++i) {
+            const int32_t *c = cand.v + 3 * i;
+            int32_t v[4];
+            double x12[12], g12[12];
+            cand_verts(s, c, v);
+            gather12(x, v, x12);
+            double d = c[0] == 0 ? ora_pt_distance(x12, NULL) : ora_ee_distance(x12, NULL);
+            if (!(d < s->prm.dhat)) continue;
+            double eps_x = c[0] == 1 ? cand_eps_x(s, c) : 0.0;
+            ora_pair_barrier(c[0], x12, s->prm.dhat, s->prm.kappa, eps_x, 0, g12, NULL);
+            for (int a = 0; a < 4; ++a)
+                for (int k = 0; k < 3; ++k) g_contact[3 * v[a] + k] += g12[3 * a + k];
+        }
+        free(cand.v);
+    }
+    if (g_friction) {
+        double eps = s->prm.eps_v * s->prm.h;
+        for (int k = 0; k < s->n_fric; ++k) {
+            const int32_t *v = s->fric_v + 4 * k;
+            double x12[12], xt12[12], g12[12];
+            gather12(x, v, x12);
+            gather12(s->xt, v, xt12);
+            ora_pair_friction(x12, xt12, s->fric_c + 4 * k, s->fric_nrm + 3 * k, s->prm.mu_fric * s->fric_lam[k], eps,
+                              g12, NULL);
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 3; ++c) g_friction[3 * v[a] + c] += g12[3 * a + c];
+        }
+    }
+}
+
 void ora_hess_apply(ora_scene *s, const double *x, const double *v, double *y)
 {
     assembly A;

@@ -105,6 +105,10 @@ double ora_energy(ora_scene *s, const double *x);
 void ora_gradient(ora_scene *s, const double *x, double *g);
 /* y = H(x) v with the PSD-projected Hessian and Dirichlet rows/cols replaced by identity. */
 void ora_hess_apply(ora_scene *s, const double *x, const double *v, double *y);
+/* Gradient of each term of Phi at x (inertia, elasticity, soft targets,
+ * barrier, friction), Dirichlet rows NOT zeroed; 3n doubles each or NULL. */
+void ora_gradient_terms(ora_scene *s, const double *x, double *g_inertia, double *g_elastic, double *g_target,
+                        double *g_contact, double *g_friction);
 /* Dense 3n x 3n form of the matrix ora_hess_apply applies (small scenes only). */
 void ora_hess_dense(ora_scene *s, const double *x, double *H);
 /* Block-Jacobi PCG solve of H p = -g at x; returns iterations. */

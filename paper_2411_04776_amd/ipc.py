@@ -219,10 +219,12 @@ class TorchRuntime:
         except Exception:  # out of memory: report NULL to the library
             return 0
 
-    def _free_cb(self, ptr, nbytes, stream, user):
+    def _free_cb(self, ptr, nbytes, stream, user, _finalizing=sys.is_finalizing):
         # At interpreter shutdown torch (and HIP) may already be torn down;
-        # the process is ending, so its device memory goes with it.
-        if sys.is_finalizing():
+        # the process is ending, so its device memory goes with it. (The
+        # check is bound at definition: module globals such as `sys` may be
+        # gone by the time a late callback runs.)
+        if _finalizing():
             return
         self.torch.cuda.caching_allocator_delete(int(ptr))
 
@@ -344,8 +346,8 @@ class GelScene:
             lib().ipc_destroy_scene(self.ptr)
             self.ptr = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return  # the atexit hook closed it, or the process is ending anyway
         try:
             self.close()
@@ -565,8 +567,8 @@ class Batch:
             lib().ipc_batch_destroy(self.ptr)
             self.ptr = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

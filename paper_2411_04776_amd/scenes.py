@@ -315,12 +315,12 @@ class Scene:
         return float(np.linalg.norm(self.X.max(axis=0) - self.X.min(axis=0)))
 
 
-def _descent_poses(R, Y, gel_top, center_xy, depth, steps, extra=None):
-    """Lowest indenter point starts dhat above the gel top and descends `depth`
-    in `steps` equal increments; `extra` appends (direction, distance, steps)
-    of tangential motion after the descent."""
+def _descent_poses(R, Y, gel_top, center_xy, depth, steps, extra=None, gap=DHAT):
+    """Lowest indenter point starts `gap` (dhat) above the gel top and descends
+    `depth` in `steps` equal increments; `extra` appends (direction, distance,
+    steps) of tangential motion after the descent."""
     Yr = Y @ R.T
-    cz = gel_top + DHAT - Yr[:, 2].min()
+    cz = gel_top + gap - Yr[:, 2].min()
     c0 = np.array([center_xy[0], center_xy[1], cz])
     poses = [pose_matrix(R, c0)]
     for t in range(1, steps + 1):
@@ -418,7 +418,7 @@ def config5(indent_steps: int = 40, slide_steps: int = 160) -> Scene:
     poses = _descent_poses(np.eye(3), Y, GEL_SIZE[2], (GEL_SIZE[0] / 2 - 2.5e-3, GEL_SIZE[1] / 2),
                            1e-3, indent_steps, extra=((1, 0, 0), 5e-3, slide_steps))
     return Scene("c5_80x100x16_icosphere4", X, T, fixed, Y, F, poses, dt=1e-2,
-                 meta={"mu": 0.5, "eps_v": 1e-3})
+                 meta={"mu": 0.5, "eps_v": 1e-3, "radius": 8e-3})
 
 
 # Soft-ball workloads at the mesh sizes of the paper's GIPC timing table
@@ -511,3 +511,58 @@ def tiny_slide_scene(mu: float = 0.5, eps_v: float = 1e-3, grid=(6, 5, 4), press
                            extra=((1, 0, 0), slide, slide_steps))
     return Scene(f"tiny_slide_mu{mu}", X, T, fixed, Y, F, poses, dt=1e-2, meta={"mu": mu, "eps_v": eps_v})
 
+
+
+# Hertz check: a rigid sphere pressed quasi-statically into a thick block
+# (half-space Hertz contact needs the contact radius a = sqrt(R delta) well
+# below the block's thickness and width). The barrier range is cut to 10 um
+# in this scene so the contact gap stays far below the smallest depth.
+HERTZ_SIZE = (0.030, 0.030, 0.015)
+HERTZ_DHAT = 1e-5
+
+
+def hertz_scene(grid=(41, 41, 21), subdiv: int = 5, radius: float = 0.02, depth: float = 0.5e-3,
+                steps: int = 10, dt: float = 1.0, newton_tol: float = 1e-8, size=HERTZ_SIZE) -> Scene:
+    """Block `size` (bottom fixed) meshed as a Kuhn grid, icosphere of `radius`
+    starting dhat above the top centre and descending `depth` over `steps`
+    equal increments; quasi-static (dt = 1 s, no gravity), no friction, no
+    self-contact, dhat = 10 um, kappa = 1e4, Newton tolerance `newton_tol`."""
+    X, T, fixed = grid_gel(*grid, size=size)
+    Y, F = icosphere(subdiv, radius)
+    poses = _descent_poses(np.eye(3), Y, size[2], (size[0] / 2, size[1] / 2), depth, steps, gap=HERTZ_DHAT)
+    return Scene(f"hertz_{grid[0]}x{grid[1]}x{grid[2]}_R{radius * 1e3:g}mm", X, T, fixed, Y, F, poses, dt=dt,
+                 dhat=HERTZ_DHAT, newton_tol=newton_tol, self_contact=False,
+                 meta={"kind": "hertz", "radius": radius, "top": size[2], "center": (size[0] / 2, size[1] / 2),
+                       "gap0": HERTZ_DHAT})
+
+
+def pressed_state(sc: Scene, step: int, gap_frac: float = 0.5):
+    """A constructed contact state for one-iterate checks: the indenter at its
+    pose of `step` (rigid, no lag), a spherical indenter (meta 'radius',
+    centred on the pose's translation) and the gel's top surface pushed under
+    it to `gap_frac` dhat below the sphere where the undeformed top would
+    reach into it (contact radius a), falling off as (a / r)^4 outside; the
+    vertical displacement decays linearly to zero at the fixed bottom, and
+    velocities are zero. Only +, -, *, / and sqrt are used, so the state is
+    the same bits on every machine. Returns (x (n_all, 3), v (n_all, 3))."""
+    R = float(sc.meta["radius"])
+    P = sc.poses[step]
+    c = P[:, 3]
+    X = sc.X
+    top = float(X[:, 2].max())
+    bottom = float(X[:, 2].min())
+    r2 = (X[:, 0] - c[0]) ** 2 + (X[:, 1] - c[1]) ** 2
+    inside = r2 < R * R
+    zs = np.where(inside, c[2] - np.sqrt(np.where(inside, R * R - r2, 0.0)), np.inf)
+    pen = top - zs                      # > 0 where the undeformed top reaches into the sphere
+    g = gap_frac * sc.dhat
+    a2 = float(r2[pen >= 0].max()) if np.any(pen >= 0) else 0.0
+    w = np.where(pen >= 0, -(pen + g), 0.0)
+    if a2 > 0:
+        q = a2 / np.maximum(r2, a2)
+        w = np.where(pen >= 0, w, -g * q * q)
+    x = X.copy()
+    x[:, 2] += w * (X[:, 2] - bottom) / (top - bottom)
+    y = apply_pose(P, sc.Y)
+    xa = np.concatenate([x, y])
+    return xa, np.zeros_like(xa)

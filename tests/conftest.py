@@ -14,9 +14,18 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long CPU-only oracle runs")
 
 
+def pytest_addoption(parser):
+    parser.addoption("--runslow", action="store_true", default=False,
+                     help="also run the long CPU-only oracle runs marked slow")
+
+
 def pytest_collection_modifyitems(config, items):
-    # GPU tests first import torch on a fresh box; keep their order stable.
-    pass
+    if config.getoption("--runslow") or os.environ.get("IPC_RUN_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="long oracle run: use --runslow")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)
 
 
 @pytest.fixture(scope="session")

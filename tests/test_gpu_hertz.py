@@ -1,0 +1,123 @@
+"""Hertz check on the HIP path, through the C ABI.
+
+A rigid sphere (R = 20 mm) pressed quasi-statically into a 30x30x15 mm block
+with a fixed bottom: the force-depth curve against F = 4/3 E* sqrt(R)
+delta^1.5 (exponent 1.5 +- 0.15) and against that form times the
+finite-thickness factor of a bonded layer (prefactor ratio in [0.8, 1.25]),
+at the 41x41x21 resolution (also against the FP64 oracle's own curve from
+tests/golden/hertz_41x41x21_oracle.txt) and at 81x81x41, where the
+discretisation's stiffening has fallen off (half-space ratio within
+[0.8, 1.25], layer-corrected within [0.9, 1.1]). Plus one teacher-forced
+Newton iterate at 41x41x21 against the oracle's (tests/golden/hertz_tf.npz)
+within 1e-9 L, and the candidate set there bit-exact.
+
+F is the targets' pull on the indenter, k_t sum (y - yhat)_z (at
+equilibrium the contact force; the oracle's curve shows the two agree to
+1e-4); delta is the depression of the top vertex on the axis."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_04776_amd import scenes as S
+import hertz as H
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+CURVE = os.path.join(HERE, "golden", "hertz_41x41x21_oracle.txt")
+TF = os.path.join(HERE, "golden", "hertz_tf.npz")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ipc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2411_04776_amd import ipc as I
+    I.lib()
+    return I
+
+
+def press(ipc, sc):
+    g = ipc.GelScene(sc, pcg_tol=1e-6)
+    n_gel = len(sc.X)
+    ic = H.center_vertex(sc)
+    F, d = [], []
+    for k in range(1, sc.n_steps + 1):
+        rc, st = g.step()
+        assert rc == 0, (k, rc)
+        x = g.x
+        yhat = S.apply_pose(sc.poses[k], sc.Y)
+        F.append(float(sc.k_target * (x[n_gel:, 2] - yhat[:, 2]).sum()))
+        d.append(float(sc.X[ic, 2] - x[ic, 2]))
+        say(f"  step {k}: newton={st.newton_iters} pcg={st.pcg_iters} active={st.n_active} "
+            f"F={F[-1]:.6f} N delta={d[-1] * 1e3:.5f} mm F/Hertz={F[-1] / float(H.hertz_force(d[-1], 0.02, sc.E, sc.nu)):.4f}")
+    g.close()
+    return np.array(F), np.array(d)
+
+
+def fits(sc, F, d):
+    R, h = sc.meta["radius"], sc.meta["top"]
+    sel = np.arange(1, sc.n_steps, 2)      # depths 0.1 .. 0.5 mm
+    expo, ratio = H.fit(d[sel], F[sel], R, sc.E, sc.nu)
+    layer = H.fit_layer(d[sel], F[sel], R, h, sc.E, sc.nu)
+    say(f"  fit: exponent {expo:.4f}, prefactor / half-space Hertz {ratio:.4f}, / layer-corrected {layer:.4f}")
+    return expo, ratio, layer
+
+
+def test_hertz_41x41x21(ipc):
+    sc = S.hertz_scene()
+    say(sc.name, len(sc.X), "vertices", len(sc.T), "tets")
+    F, d = press(ipc, sc)
+    expo, ratio, layer = fits(sc, F, d)
+    assert 1.35 <= expo <= 1.65
+    assert 0.8 <= layer <= 1.25
+    if os.path.exists(CURVE):
+        rows = np.loadtxt(CURVE, comments="#")
+        Fo, do = rows[:, 3], rows[:, 6]
+        say(f"  vs oracle curve: max |F - F_oracle| / F_oracle = {np.abs(F / Fo - 1).max():.2e}, "
+            f"max |delta - delta_oracle| = {np.abs(d - do).max():.2e} m")
+        assert np.all(np.abs(F / Fo - 1) <= 1e-3)
+        assert np.all(np.abs(d - do) <= 1e-3 * do)
+
+
+def test_hertz_81x81x41(ipc):
+    sc = S.hertz_scene(grid=(81, 81, 41), subdiv=6)
+    say(sc.name, len(sc.X), "vertices", len(sc.T), "tets")
+    F, d = press(ipc, sc)
+    expo, ratio, layer = fits(sc, F, d)
+    assert 1.35 <= expo <= 1.65
+    assert 0.8 <= ratio <= 1.25
+    assert 0.9 <= layer <= 1.1
+
+
+@pytest.mark.skipif(not os.path.exists(TF), reason="golden not generated")
+def test_hertz_teacher_forced_iterate(ipc):
+    sc = S.hertz_scene()
+    z = np.load(TF)
+    step = int(z["step"])
+    x0, v0 = S.pressed_state(sc, step - 1, gap_frac=0.9)
+    ref = x0 + z["it1"].astype(np.float64)
+    L = sc.bbox_diag
+    o = O.OracleScene(sc)
+    ca = o.candidates(x0)
+    g = ipc.GelScene(sc)
+    cg = g.candidates(x0)
+    say(f"  candidates at the pressed state: {len(cg)} (oracle {len(ca)})")
+    assert cg.shape == ca.shape and np.array_equal(cg, ca)
+    g.x = x0
+    g.v = v0
+    g.begin_step(sc.poses[step])
+    rc, xg, st = g.newton_iterate(x0)
+    assert rc == 0
+    err = np.abs(xg - ref).max() / L
+    say(f"  iterate: alpha={st.alpha:.6f} pcg={st.pcg_iters} active={st.n_active} err/L={err:.3e} "
+        f"(step {np.abs(ref - x0).max():.3e} m)")
+    assert err <= 1e-9
+    g.close()

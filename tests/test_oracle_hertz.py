@@ -1,0 +1,133 @@
+"""Whole-step pins of the oracle's contact response.
+
+* Force balance at a stationary point: every energy term but inertia and
+  the soft targets is translation invariant (elasticity, barrier), so when
+  Newton has converged the targets' pull on the indenter, the support
+  reaction at the fixed bottom and the summed inertia of the free vertices
+  balance: sum_ind g_target = sum_fixed g_elastic - sum_free g_inertia (all
+  three components). A barrier force applied unequally to the two sides of a
+  pair, or a term missing from the gradient Newton drives to zero, breaks it.
+* The contact gap does not depend on the time step (the energy is in joules,
+  kappa multiplies the barrier without h^2): the same quasi-static press at
+  dt = 1 s and dt = 10 s ends in the same state. Under the alternative
+  reading (the IPC potential multiplied by h^2 with kappa unchanged) the
+  barrier would be 100x stiffer relative to elasticity at the larger step and
+  the gap would shrink.
+* Hertz: the force-depth curve of a rigid sphere pressed into a thick block
+  follows F = 4/3 E* sqrt(R) delta^1.5 times the finite-thickness factor of a
+  layer bonded to a rigid base. The oracle's curve at the 41x41x21 resolution
+  (tests/golden/hertz_41x41x21_oracle.txt, written by make_fullsize.py) is
+  checked on every run; re-deriving it takes about two hours on one core
+  (the `slow` test, run with --runslow).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_04776_amd import scenes as S
+import hertz as H
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hertz_41x41x21_oracle.txt")
+
+
+def small_press(dt, steps=2, depth=0.1e-3):
+    return S.hertz_scene(grid=(11, 11, 6), subdiv=3, depth=depth, steps=steps, dt=dt, newton_tol=1e-10)
+
+
+@pytest.mark.parametrize("dt", [1.0, 1e-3])
+def test_force_balance_at_equilibrium(dt):
+    sc = small_press(dt)
+    o = O.OracleScene(sc, pcg_tol=1e-12)
+    n_gel = len(sc.X)
+    fixed = sc.fixed.astype(bool)
+    for k in range(1, sc.n_steps + 1):
+        rc, st = o.step(sc.poses[k])
+        assert rc == 0, rc
+        # the oracle keeps step k's predictor and targets after the step
+        t = o.gradient_terms(o.x)
+        tgt = t["target"][n_gel:].sum(0)
+        sup = t["elastic"][:n_gel][fixed].sum(0)
+        ine = t["inertia"][:n_gel][~fixed].sum(0)
+        bar = t["contact"][:n_gel].sum(0)
+        assert tgt[2] > 1e-3, "the indenter must be pressing"
+        bal = np.abs(tgt + ine - sup).max()
+        print(f"dt {dt} step {k}: pull {tgt[2]:.6f} N, support {sup[2]:.6f} N, inertia {ine[2]:.3e} N, "
+              f"contact on gel {bar[2]:.6f} N, imbalance {bal:.2e} N")
+        assert bal <= 1e-8 * tgt[2]
+        assert abs(bar[2] - tgt[2]) <= 1e-5 * tgt[2]
+        assert np.abs(t["contact"].sum(0)).max() <= 1e-9 * tgt[2]   # action = reaction over each pair
+        if dt < 1.0:
+            assert abs(ine[2]) > 1e-4 * tgt[2], "inertia must take part in the dynamic case"
+
+
+def test_contact_gap_does_not_depend_on_dt():
+    states, gaps = [], []
+    for dt in (1.0, 10.0):
+        sc = small_press(dt, steps=2)
+        o = O.OracleScene(sc, pcg_tol=1e-12)
+        for k in range(1, sc.n_steps + 1):
+            assert o.step(sc.poses[k])[0] == 0
+        x = o.x
+        c = o.candidates(x)
+        d, _ = o.candidate_distances(x, c)
+        act = d[d < sc.dhat]
+        assert len(act) > 0
+        states.append(x)
+        gaps.append(act.mean())
+    print(f"mean active gap: {gaps[0]:.6e} m (dt 1 s), {gaps[1]:.6e} m (dt 10 s)")
+    assert abs(gaps[0] - gaps[1]) <= 1e-3 * gaps[0]
+    assert np.abs(states[0] - states[1]).max() <= 1e-3 * 1e-5
+
+
+def read_curve(path=GOLDEN):
+    rows = np.loadtxt(path, comments="#")
+    return {"step": rows[:, 0].astype(int), "status": rows[:, 1].astype(int), "F": rows[:, 3],
+            "F_support": rows[:, 4], "F_target": rows[:, 5], "delta": rows[:, 6], "descent": rows[:, 7]}
+
+
+def check_hertz(curve, sc):
+    R, h = sc.meta["radius"], sc.meta["top"]
+    sel = curve["step"] % 2 == 0          # depths 0.1 .. 0.5 mm
+    d, F = curve["delta"][sel], curve["F"][sel]
+    expo, ratio = H.fit(d, F, R, sc.E, sc.nu)
+    layer = H.fit_layer(d, F, R, h, sc.E, sc.nu)
+    print(f"Hertz fit: exponent {expo:.4f}, prefactor / half-space Hertz {ratio:.4f}, "
+          f"/ layer-corrected Hertz {layer:.4f}")
+    assert 1.35 <= expo <= 1.65
+    assert 0.8 <= layer <= 1.25
+    # equilibrium: the contact force, the support reaction and the targets' pull agree
+    assert np.all(np.abs(curve["F_support"] - curve["F"]) <= 1e-4 * curve["F"])
+    assert np.all(np.abs(curve["F_target"] - curve["F"]) <= 1e-4 * curve["F"])
+    # the surface on the axis moves by the descent past first touch plus a gap below dhat
+    gap = curve["delta"] - curve["descent"]
+    assert np.all(gap > 0) and np.all(gap < sc.dhat)
+    return expo, ratio, layer
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle Hertz curve not generated")
+def test_oracle_hertz_curve():
+    check_hertz(read_curve(), S.hertz_scene())
+
+
+@pytest.mark.slow
+def test_oracle_hertz_curve_rederived():
+    """Re-runs the oracle on the full Hertz scene (about two hours) and
+    checks the closed form and the stored curve."""
+    sc = S.hertz_scene()
+    o = O.OracleScene(sc, pcg_tol=1e-8)
+    m = O.OracleScene(sc)
+    rows = {k: [] for k in ("step", "F", "F_support", "F_target", "delta", "descent")}
+    for k in range(1, sc.n_steps + 1):
+        rc, st = o.step(sc.poses[k])
+        assert rc == 0
+        r = H.measure(sc, m, o.x, sc.poses[k])
+        rows["step"].append(k)
+        for key in ("F", "F_support", "F_target", "delta", "descent"):
+            rows[key].append(r[key])
+    curve = {k: np.asarray(v) for k, v in rows.items()}
+    check_hertz(curve, sc)
+    if os.path.exists(GOLDEN):
+        ref = read_curve()
+        assert np.allclose(curve["F"], ref["F"], rtol=1e-9, atol=0)
