@@ -221,21 +221,27 @@ IPC_API int32_t ipc_load_state(ipc_scene *s, const void *blob, int64_t bytes);
 /* Sizes: out[0..7] = n_all, n_gel, n_tets, n_points, n_edges, n_tris, n_ind, n_gel_tris. */
 IPC_API int32_t ipc_scene_sizes(const ipc_scene *s, int32_t *out);
 
-/* Batched asynchronous stepping with continuous batching. A batch owns a
- * worker thread that keeps one list of in-flight steps per precision and runs
- * Newton iterations over each list with one kernel launch per phase for all
- * of its scenes; a step submitted while others are mid-step joins the list at
- * the next iteration boundary, a finished step leaves it. Each scene's
- * results are bitwise those of ipc_step (a scene's blocks, partial sums and
- * reduction order depend on that scene alone).
- * rt->stream: stream of the batch's launches (NULL: a stream of its own);
- * rt->mem_budget > 0: the summed device bytes of the scenes in flight stay
- * within it (one scene is always admitted); alloc/free are not used.
+/* Batched asynchronous stepping with continuous batching. A batch keeps one
+ * list of in-flight steps per class -- precision x size, scenes of at least
+ * IPC_BATCH_LARGE_VERTS vertices (gel and indenter) forming the large class --
+ * each list with a worker thread and a stream of its own, and runs Newton
+ * iterations over each list with one kernel launch per phase for all of its
+ * scenes; a step submitted while others are mid-step joins its class's list
+ * at the next iteration boundary, a finished step leaves it. The classes run
+ * concurrently, so small scenes do not wait for the rounds of large ones.
+ * Each scene's results are bitwise those of ipc_step (a scene's blocks,
+ * partial sums and reduction order depend on that scene alone).
+ * rt->stream: stream of the batch's launches, shared by every class (NULL: a
+ * stream per class, created and destroyed by the batch, default priority);
+ * rt->mem_budget > 0: the summed device bytes of the scenes in flight (all
+ * classes) stay within it, except that a class with an empty list always
+ * admits one scene; alloc/free are not used.
  * submit: every scene must be idle and appear once (else IPC_E_BUSY, nothing
  * queued); returns at once with one ticket per scene. A scene with a pending
  * ticket must not be stepped, read, reset or destroyed (calls on it return
  * IPC_E_BUSY; destroying it is undefined). A HIP error inside the worker ends
  * every pending ticket with IPC_E_DEVICE. destroy waits for pending steps. */
+#define IPC_BATCH_LARGE_VERTS 65536
 IPC_API int32_t ipc_batch_create(const ipc_runtime *rt, ipc_batch **out);
 IPC_API void ipc_batch_destroy(ipc_batch *b);
 IPC_API int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, const ipc_step_req *r,
@@ -244,15 +250,27 @@ IPC_API int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, c
 IPC_API int32_t ipc_batch_poll(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
 /* Blocks until the step is done; returns its status and consumes the ticket. */
 IPC_API int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st);
+/* Wait for any step: the oldest finished step not yet consumed is returned
+ * and consumed (*t its ticket, *status its status, st its stats; status and
+ * st may be NULL). Waits up to timeout_ms (< 0: without limit) when none has
+ * finished. Returns 1 when a step was returned, 0 on timeout,
+ * IPC_E_INVALID_ARG when no step is pending or finished. Lets one host thread
+ * serve many environments without polling each ticket. */
+IPC_API int32_t ipc_batch_next(ipc_batch *b, double timeout_ms, ipc_ticket *t, int32_t *status,
+                               ipc_step_stats *st);
 /* Kernel timing inside the engine: enable (1) or disable (0) resets the
  * totals; from the next Newton round on, each phase launch and one PCG
  * launch in sixteen is bracketed by HIP events on the engine's stream (same classes as
  * ipcx_profile). profile_read returns the timed launches, their summed
- * milliseconds and, for class 0 (PCG SpMV), the summed algorithmic bytes of
- * those launches over every scene of the list: per stored 3x3 block its
- * values and column index, per vertex the z and d gathers, the d and q writes
- * and the row pointer, per contact pair its off-diagonal blocks and vertex
- * ids (4- or 8-byte reals by the list's precision). */
+ * milliseconds and, for classes 0 and 1 (the two PCG kernels), the summed
+ * algorithmic bytes of those launches over every scene of the list whose
+ * solve was still running: class 0 (SpMV) per stored 3x3 block its values and
+ * column index, per vertex the z and d gathers, the d and q writes and the
+ * row pointer, per contact pair its off-diagonal blocks and vertex ids;
+ * class 1 (update) per vertex q, d, p, r and the 3x3 inverse read and p, r, z
+ * written, per incidence entry (4 per pair) its index and 3 pair-product
+ * values, per preconditioner member 16 bytes of ids, per SpMV block its d.q
+ * partial (4- or 8-byte reals by the list's precision). */
 IPC_API int32_t ipc_batch_profile(ipc_batch *b, int32_t enable);
 IPC_API int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total,
                                        double *bytes_total);
@@ -283,6 +301,9 @@ IPC_API int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double 
  * gather, 4 broad phase, 5 narrow phase + barrier, 6 energy, 7 CCD. */
 IPC_API int32_t ipcx_profile(ipc_scene *s, int32_t enable);
 IPC_API int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches, double *ms_total);
+/* Summed algorithmic bytes of the timed launches of kernel class 0 or 1 (the
+ * PCG kernels, counted as for ipc_batch_profile_read); 0 for other classes. */
+IPC_API int32_t ipcx_profile_bytes(const ipc_scene *s, int32_t kernel, double *bytes_total);
 /* out[0..7] = stored elastic blocks, stored BELL entries incl. padding, vertices,
  * active pairs, tets, static candidates, swept candidates, gather entries. */
 IPC_API int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out);
@@ -291,6 +312,16 @@ IPC_API int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out);
  * of levels 0..2, out[5] the largest group's members, out[6] the largest
  * group's aggregates, out[7] members (free gel vertices). */
 IPC_API int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out);
+/* The launch and grouping choices the scene took at creation from the
+ * autotuner's file ($IPC_TUNING_FILE, else tuning.json beside the library;
+ * built-in defaults without one): out[0] SpMV one-thread-per-row threshold
+ * (rows of a list), out[1] preconditioner group packing target (members),
+ * out[2] first PCG chunk (fraction of the previous solve's iterations),
+ * out[3] later chunks (fraction), out[4] 1 if read from a file. */
+IPC_API int32_t ipcx_tuning(const ipc_scene *s, double *out);
+/* The same five values for a scene of n_verts vertices created now (host
+ * only: reads the tuning file, touches no device). */
+IPC_API int32_t ipcx_tuning_for(int32_t n_verts, double *out);
 IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);
 IPC_API int32_t ipcx_get_state(const ipc_scene *s, double *x, double *v);
 

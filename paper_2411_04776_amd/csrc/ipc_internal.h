@@ -205,6 +205,18 @@ __device__ __forceinline__ int scene_of_block(const Launch &L, int &local)
 }
 __device__ __forceinline__ int blocks_of(const Launch &L, int s) { return L.blk_off[s + 1] - L.blk_off[s]; }
 
+// Launch and grouping choices picked per size class by the library's
+// autotuner (paper_2411_04776_amd/autotune.py) and read from its JSON file
+// when a scene is created; the defaults below apply without a file.
+struct Tuning {
+    int64_t spmv_one_lane_rows = kSpmvOneLaneRows;  // lists with this many rows or more: one thread per SpMV row
+    int mas_target = kMasTarget;                    // preconditioner group packing target (members, <= kMasCapM)
+    double pcg_first_chunk = 0.875;                 // first PCG chunk: this fraction of the previous solve's count
+    double pcg_later_chunk = 0.25;                  // later chunks: this fraction of it (at least 8 launches)
+    int from_file = 0;                              // 1 if read from a tuning file
+};
+Tuning tuning_for(int n_verts);  // the tuning file's entry for a scene of n_verts vertices
+
 struct Params {
     double E, nu, rho, mu, lam;
     double dt, dhat, kappa, k_target;
@@ -266,6 +278,7 @@ class Scene {
     int step_index = 0;
     std::atomic<bool> busy{false};  // a step, read or hook holds the scene
     int last_pcg_iters = 0;
+    Tuning tune{};         // launch and grouping choices of the scene's size class
     bool sw_ok = false;    // the swept list holds every static pair at the current x
     int64_t sw_n = 0;      // its length
     SceneOut last{};       // last values read back

@@ -1203,41 +1203,57 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     // algorithmic bytes of one scene in one A launch: every stored 3x3 block
     // (values and column) once; per vertex the z and d gathers, the d and q
     // writes and its row pointer; per pair its off-diagonal blocks and ids
-    std::vector<double> scene_bytes(ns, 0.0);
+    // and of one B launch: per vertex q, d, p, r and the 3x3 inverse read and
+    // p, r, z written (30 reals); per incidence entry (4 per pair) its index
+    // and 3 pair-product values; per preconditioner member its vertex id and
+    // three level ids; the SpMV blocks' d.q partials
+    std::vector<double> scene_bytes(ns, 0.0), scene_bytes_b(ns, 0.0);
     {
         const double rs = mx ? 4.0 : 8.0;
         for (size_t i = 0; i < ns; ++i) {
             if (nab[i] == 0) continue;
             const Scene &s = *b.sc[i];
-            scene_bytes[i] = (9 * rs + 4) * (double)s.nnzb + (12 * rs + 4) * (double)s.h.n +
-                             (108 * rs + 16) * (double)pair_count(s, b.h_out[i]);
+            const double np_ = (double)pair_count(s, b.h_out[i]);
+            scene_bytes[i] = (9 * rs + 4) * (double)s.nnzb + (12 * rs + 4) * (double)s.h.n + (108 * rs + 16) * np_;
+            scene_bytes_b[i] = 30 * rs * (double)s.h.n + 4 * (4 + 3 * rs) * np_ +
+                               16.0 * (s.h.mas_levels > 0 ? (double)s.h.mas_nf : 0.0) + 8.0 * (double)s.h.nb_rows;
         }
     }
     // Timed A launches of a chunk get their bytes once the chunk's flags are
     // back: a scene counts in the launch of iteration it when its solve was
     // still running there (not finished, or finished with more than it - 1
     // iterations); finished solves exit before their first load.
-    std::vector<std::pair<size_t, int>> timed_a;  // (pending event index, it)
-    auto settle_bytes = [&]() {
-        for (auto &ta : timed_a) {
+    std::vector<std::pair<size_t, int>> timed_a, timed_b;  // (pending event index, it)
+    auto settle = [&](std::vector<std::pair<size_t, int>> &timed, const std::vector<double> &sb) {
+        for (auto &ta : timed) {
             double v = 0.0;
             for (size_t i = 0; i < ns; ++i) {
-                if (scene_bytes[i] == 0.0) continue;
-                if (!b.h_out[i].pcg_done || ta.second <= b.h_out[i].pcg_iters) v += scene_bytes[i];
+                if (sb[i] == 0.0) continue;
+                if (!b.h_out[i].pcg_done || ta.second <= b.h_out[i].pcg_iters) v += sb[i];
             }
             b.ev_pending[ta.first].bytes = v;
         }
-        timed_a.clear();
+        timed.clear();
+    };
+    auto settle_bytes = [&]() {
+        settle(timed_a, scene_bytes);
+        settle(timed_b, scene_bytes_b);
     };
     // large lists are bandwidth-bound: a thread per row reads the slices fully coalesced
+    // (lanes per row and chunk lengths from the tuning of the list's largest scene)
     int64_t rows_total = 0;
+    const Scene *big = nullptr;
     for (size_t i = 0; i < ns; ++i)
-        if (nab[i] > 0) rows_total += b.sc[i]->h.n;
-    const bool one_lane = rows_total >= kSpmvOneLaneRows;
+        if (nab[i] > 0) {
+            rows_total += b.sc[i]->h.n;
+            if (!big || b.sc[i]->h.n > big->h.n) big = b.sc[i];
+        }
+    const Tuning tn = big ? big->tune : Tuning{};
+    const bool one_lane = rows_total >= tn.spmv_one_lane_rows;
     int it = 1;
     // the first chunk stops short of the previous solve's count; later
     // launches check the done flag first, so overshooting them is cheap
-    int chunk = last > 16 ? (last * 7) / 8 : 8;
+    int chunk = last > 16 ? std::max(8, (int)(last * tn.pcg_first_chunk)) : 8;
     int early = 0;
     hipEvent_t ev[2];
     // launch it = maxit + 1 too: its A kernel records the cap of the scenes
@@ -1264,6 +1280,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
             }
             if (timed) b.prof_end(kProfPcgA, ev, 0.0);
             if (timed) b.prof_begin(kProfPcgB, ev);
+            if (timed) timed_b.push_back({b.ev_pending.size(), it});
             if (mx)
                 IPC_LAUNCH(b, k_pcg_B<float>, kPhPcgB, kBlock, it, early);
             else
@@ -1278,7 +1295,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         for (size_t i = 0; i < ns; ++i)
             if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && !b.h_out[i].pcg_done) all = false;
         if (all) break;
-        chunk = early ? 8 : std::max(8, last / 4);
+        chunk = early ? 8 : std::max(8, (int)(last * tn.pcg_later_chunk));
         early = 1;
         // scenes that finished leave the remaining launches of the list
         bool shrink = false;

@@ -32,9 +32,126 @@
 #include <thread>
 #include <unordered_map>
 
+#include <dlfcn.h>
+#include <sys/stat.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+
 #include "ipc_internal.h"
 
 namespace ipcg {
+
+// ---------------------------------------------------------------------------
+// Tuning file: {"classes": [{"min_verts": 0, "spmv_one_lane_rows": ..., "mas_target": ...,
+// "pcg_first_chunk": ..., "pcg_later_chunk": ...}, ...], ...}, written by the
+// autotuner; $IPC_TUNING_FILE names it (empty: none), else tuning.json beside
+// the library. A scene takes the class with the largest min_verts <= its
+// vertex count. Unknown keys are ignored; a missing or unreadable file means
+// the built-in defaults.
+// ---------------------------------------------------------------------------
+
+namespace {
+struct TuneClass {
+    int64_t min_verts = 0;
+    Tuning t;
+};
+
+std::string tuning_path()
+{
+    const char *e = std::getenv("IPC_TUNING_FILE");
+    if (e) return e;
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void *>(&tuning_for), &info) && info.dli_fname) {
+        std::string p = info.dli_fname;
+        size_t k = p.rfind('/');
+        return (k == std::string::npos ? std::string(".") : p.substr(0, k)) + "/tuning.json";
+    }
+    return "";
+}
+
+// the objects of the "classes" array, each a flat list of "key": number
+std::vector<TuneClass> parse_tuning(const std::string &text)
+{
+    std::vector<TuneClass> out;
+    size_t k = text.find("\"classes\"");
+    if (k == std::string::npos) return out;
+    k = text.find('[', k);
+    if (k == std::string::npos) return out;
+    size_t i = k + 1;
+    while (i < text.size()) {
+        while (i < text.size() && (isspace((unsigned char)text[i]) || text[i] == ',')) ++i;
+        if (i >= text.size() || text[i] == ']') break;
+        if (text[i] != '{') return {};
+        size_t e = text.find('}', i);
+        if (e == std::string::npos) return {};
+        TuneClass c;
+        std::string body = text.substr(i + 1, e - i - 1);
+        size_t q = 0;
+        while ((q = body.find('"', q)) != std::string::npos) {
+            size_t q2 = body.find('"', q + 1);
+            if (q2 == std::string::npos) break;
+            std::string key = body.substr(q + 1, q2 - q - 1);
+            size_t colon = body.find(':', q2);
+            if (colon == std::string::npos) break;
+            char *end = nullptr;
+            double v = std::strtod(body.c_str() + colon + 1, &end);
+            if (end == body.c_str() + colon + 1) {  // not a number: skip the value (a string or a literal)
+                size_t v0 = body.find_first_not_of(" \t\r\n", colon + 1);
+                if (v0 != std::string::npos && body[v0] == '"') {
+                    size_t v1 = body.find('"', v0 + 1);
+                    q = v1 == std::string::npos ? body.size() : v1 + 1;
+                } else {
+                    size_t v1 = body.find(',', colon + 1);
+                    q = v1 == std::string::npos ? body.size() : v1 + 1;
+                }
+                continue;
+            }
+            if (key == "min_verts") c.min_verts = (int64_t)v;
+            else if (key == "spmv_one_lane_rows") c.t.spmv_one_lane_rows = (int64_t)v;
+            else if (key == "mas_target") c.t.mas_target = std::max(1, std::min(kMasCapM, (int)v));
+            else if (key == "pcg_first_chunk") c.t.pcg_first_chunk = std::max(0.0, std::min(4.0, v));
+            else if (key == "pcg_later_chunk") c.t.pcg_later_chunk = std::max(0.0, std::min(4.0, v));
+            q = (size_t)(end - body.c_str());
+        }
+        c.t.from_file = 1;
+        out.push_back(c);
+        i = e + 1;
+    }
+    std::sort(out.begin(), out.end(), [](const TuneClass &a, const TuneClass &b) { return a.min_verts < b.min_verts; });
+    return out;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int64_t, std::vector<TuneClass>>> g_tune_cache;  // path -> (mtime, classes)
+}  // namespace
+
+Tuning tuning_for(int n_verts)
+{
+    std::string path = tuning_path();
+    if (path.empty()) return Tuning{};
+    struct stat st;
+    if (stat(path.c_str(), &st) != 0) return Tuning{};
+    int64_t mt = (int64_t)st.st_mtime * 1000000000LL + (int64_t)st.st_mtim.tv_nsec;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(path);
+    if (it == g_tune_cache.end() || it->second.first != mt) {
+        std::string text;
+        if (FILE *f = std::fopen(path.c_str(), "rb")) {
+            char buf[4096];
+            size_t r;
+            while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+            std::fclose(f);
+        }
+        g_tune_cache[path] = {mt, parse_tuning(text)};
+        it = g_tune_cache.find(path);
+    }
+    Tuning t{};
+    for (const TuneClass &c : it->second.second)
+        if (c.min_verts <= n_verts) t = c.t;
+    return t;
+}
 
 static const double kIdentityPose[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
 
@@ -324,7 +441,7 @@ struct MasHost {
 // aggregate, the BELL entries whose row and column first share an aggregate
 // at its level, so the block of the aggregate is its list plus its children's
 // blocks.
-static void build_multilevel(SceneDev &H, const ipc_scene_desc &d, const std::vector<int32_t> &slice_ptr,
+static void build_multilevel(SceneDev &H, int mas_target, const ipc_scene_desc &d, const std::vector<int32_t> &slice_ptr,
                              const std::vector<int32_t> &bcol, MasHost &M)
 {
     const int ng = d.n_verts, m = d.n_tets, n = H.n;
@@ -463,7 +580,7 @@ static void build_multilevel(SceneDev &H, const ipc_scene_desc &d, const std::ve
     {
         int cm = 0, ca = 0;
         for (size_t t = 0; t < top.size(); ++t) {
-            if (gstart.empty() || cm + top[t].subm > kMasTarget || ca + top[t].suba > kMasCapA) {
+            if (gstart.empty() || cm + top[t].subm > mas_target || ca + top[t].suba > kMasCapA) {
                 gstart.push_back((int32_t)t);
                 cm = ca = 0;
             }
@@ -514,6 +631,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     s.h.n = ng + ni;
     s.h.m = m;
     const int n = s.h.n;
+    s.tune = tuning_for(n);
     // ---- validation
     for (int64_t k = 0; k < 4 * (int64_t)m; ++k)
         if (d.T[k] < 0 || d.T[k] >= ng) {
@@ -663,7 +781,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     // ---- multilevel aggregates of the free gel vertices (preconditioner)
     MasHost mas;
     s.h.mas_levels = 0;
-    if (s.prm.precond == IPC_PRECOND_MULTILEVEL) build_multilevel(s.h, d, slice_ptr, bcol, mas);
+    if (s.prm.precond == IPC_PRECOND_MULTILEVEL) build_multilevel(s.h, s.tune.mas_target, d, slice_ptr, bcol, mas);
     s.mas_max_members = s.mas_max_aggs = 0;
     for (int g = 0; g < s.h.mas_ng; ++g) {
         const int G1 = s.h.mas_ng + 1;
@@ -1403,27 +1521,33 @@ struct Finished {
     int32_t status;
 };
 
-// A worker thread keeps one list of in-flight steps per precision and runs
-// Newton rounds over them; requests submitted meanwhile join the list at the
-// next round boundary, finished steps leave it. Admission: the summed device
-// bytes of the scenes in flight stay within mem_budget (if set); a list is
-// never left empty while requests wait.
+// The engine keeps one list of in-flight steps per class (precision x size:
+// scenes of at least IPC_BATCH_LARGE_VERTS vertices form the large class),
+// each with a worker thread and a stream of its own, so the Newton rounds of
+// small scenes do not wait for the much longer rounds of large ones and the
+// classes' launches overlap on the GPU. A worker runs Newton rounds over its
+// list; requests submitted meanwhile join the list at the next round
+// boundary, finished steps leave it. Admission: the summed device bytes of
+// the scenes in flight (all classes) stay within mem_budget (if set); a
+// class's list is never left empty while its requests wait.
 class Engine {
   public:
+    static constexpr int kClasses = 4;
     ipc_runtime rt{};
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream[kClasses] = {};
+    bool own_stream[kClasses] = {};
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Request> queue;
+    std::condition_variable cv_work[kClasses], cv_done;
+    std::deque<Request> queue[kClasses];
     std::unordered_map<ipc_ticket, Finished> done;
+    std::deque<ipc_ticket> done_order;            // finished tickets, oldest first (consumed ones skipped)
     std::unordered_map<ipc_ticket, int> pending;  // submitted, not yet finished
     ipc_ticket next = 1;
     bool stop = false;
     std::string fatal;  // a device error ends the engine
-    std::thread worker;
+    std::thread worker[kClasses];
 
     struct Slot {
         Scene *s;
@@ -1437,9 +1561,14 @@ class Engine {
         std::vector<Slot> slots;
         std::vector<StepCtl> ctl;
         bool changed = true;
-    } lists[2];
+    } lists[kClasses];
     ProfSink prof;
     std::atomic<bool> prof_on{false};
+
+    static int class_of(const Scene &s)
+    {
+        return (s.prm.precision == IPC_MIXED ? 2 : 0) + (s.h.n >= IPC_BATCH_LARGE_VERTS ? 1 : 0);
+    }
 
     ~Engine()
     {
@@ -1447,15 +1576,18 @@ class Engine {
             std::lock_guard<std::mutex> g(mu);
             stop = true;
         }
-        cv_work.notify_all();
-        if (worker.joinable()) worker.join();
-        for (auto &l : lists) {
-            if (stream) (void)hipStreamSynchronize(stream);
-            l.b.stream = nullptr;
+        for (auto &c : cv_work) c.notify_all();
+        for (auto &w : worker)
+            if (w.joinable()) w.join();
+        for (int c = 0; c < kClasses; ++c) {
+            if (stream[c]) (void)hipStreamSynchronize(stream[c]);
+            lists[c].b.stream = nullptr;
         }
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        for (int c = 0; c < kClasses; ++c)
+            if (own_stream[c] && stream[c]) (void)hipStreamDestroy(stream[c]);
     }
 
+    // caller holds mu
     int64_t in_flight_bytes() const
     {
         int64_t v = 0;
@@ -1464,23 +1596,30 @@ class Engine {
         return v;
     }
 
-    // move waiting requests into the lists (caller holds mu)
-    void admit()
+    // move waiting requests of class c into its list (caller holds mu)
+    void admit(int c)
     {
         int64_t bytes = in_flight_bytes();
-        while (!queue.empty()) {
-            Request &q = queue.front();
-            bool empty = lists[0].slots.empty() && lists[1].slots.empty();
-            if (rt.mem_budget > 0 && !empty && bytes + q.s->arena.used > rt.mem_budget) break;
-            List &l = lists[q.s->prm.precision == IPC_MIXED ? 1 : 0];
+        List &l = lists[c];
+        while (!queue[c].empty()) {
+            Request &q = queue[c].front();
+            if (rt.mem_budget > 0 && !l.slots.empty() && bytes + q.s->arena.used > rt.mem_budget) break;
             Slot sl{q.s, q.t, {}, true, Clock::now()};
             sl.req = q.r;
             l.slots.push_back(sl);
             l.ctl.emplace_back();
             l.changed = true;
             bytes += q.s->arena.used;
-            queue.pop_front();
+            queue[c].pop_front();
         }
+    }
+
+    // caller holds mu
+    void record(ipc_ticket t, const Finished &f)
+    {
+        done[t] = f;
+        done_order.push_back(t);
+        pending.erase(t);
     }
 
     void finish(List &l, const std::vector<uint8_t> &fin)
@@ -1496,8 +1635,7 @@ class Engine {
             }
             Finished f{l.ctl[i].st, l.ctl[i].st.status};
             f.st.ms_total = ms_since(l.slots[i].t0);
-            done[l.slots[i].t] = f;
-            pending.erase(l.slots[i].t);
+            record(l.slots[i].t, f);
             l.slots[i].s->busy = false;
             l.changed = true;
         }
@@ -1506,7 +1644,7 @@ class Engine {
         cv_done.notify_all();
     }
 
-    void round(List &l)
+    void round(List &l, hipStream_t strm)
     {
         size_t ns = l.slots.size();
         if (!ns) return;
@@ -1514,7 +1652,7 @@ class Engine {
         if (l.changed) {
             std::vector<Scene *> sc(ns);
             for (size_t i = 0; i < ns; ++i) sc[i] = l.slots[i].s;
-            l.b.bind(sc, stream);
+            l.b.bind(sc, strm);
             l.changed = false;
         } else {
             l.b.fail.assign(ns, 0);
@@ -1546,56 +1684,63 @@ class Engine {
         }
     }
 
-    void fail_all(const std::string &msg)
+    // End every step of class c with IPC_E_DEVICE (its own worker calls this,
+    // at a round boundary): after a device error the engine takes no more
+    // work; each worker fails its own list and queue, then exits.
+    void fail_class(int c, const std::string &msg)
     {
-        std::lock_guard<std::mutex> g(mu);
-        fatal = msg;
-        for (auto &l : lists) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (fatal.empty()) fatal = msg;
+            Finished f{};
+            f.status = IPC_E_DEVICE;
+            f.st.status = IPC_E_DEVICE;
+            List &l = lists[c];
             for (auto &sl : l.slots) {
-                Finished f{};
-                f.status = IPC_E_DEVICE;
-                f.st.status = IPC_E_DEVICE;
-                done[sl.t] = f;
-                pending.erase(sl.t);
+                record(sl.t, f);
                 sl.s->busy = false;
             }
             l.slots.clear();
             l.ctl.clear();
             l.changed = true;
+            for (auto &q : queue[c]) {
+                record(q.t, f);
+                q.s->busy = false;
+            }
+            queue[c].clear();
         }
-        for (auto &q : queue) {
-            Finished f{};
-            f.status = IPC_E_DEVICE;
-            f.st.status = IPC_E_DEVICE;
-            done[q.t] = f;
-            pending.erase(q.t);
-            q.s->busy = false;
-        }
-        queue.clear();
         cv_done.notify_all();
+        for (auto &cv : cv_work) cv.notify_all();
     }
 
-    void run()
+    void run(int c)
     {
         if (hipSetDevice(device) != hipSuccess) {
-            fail_all("engine could not select its device");
+            fail_class(c, "engine could not select its device");
             return;
         }
+        List &l = lists[c];
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] {
-                    return stop || !queue.empty() || !lists[0].slots.empty() || !lists[1].slots.empty();
-                });
-                if (stop && queue.empty() && lists[0].slots.empty() && lists[1].slots.empty()) return;
-                admit();
+                cv_work[c].wait(lk, [&] { return stop || !fatal.empty() || !queue[c].empty() || !l.slots.empty(); });
+                if (!fatal.empty()) {
+                    std::string msg = fatal;
+                    lk.unlock();
+                    fail_class(c, msg);
+                    return;
+                }
+                if (stop && queue[c].empty() && l.slots.empty()) return;
+                admit(c);
             }
             try {
-                for (auto &l : lists) round(l);
+                round(l, stream[c]);
             } catch (const HipError &e) {
-                fail_all(std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+                fail_class(c, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+                return;
             } catch (...) {
-                fail_all("unexpected error in the batch engine");
+                fail_class(c, "unexpected error in the batch engine");
+                return;
             }
         }
     }
@@ -2073,13 +2218,15 @@ int32_t ipc_batch_create(const ipc_runtime *rt, ipc_batch **out)
     int32_t rc = guarded([&]() -> int32_t {
         if (rt) b->rt = *rt;
         IPC_HIP(hipGetDevice(&b->device));
-        if (rt && rt->stream) {
-            b->stream = (hipStream_t)rt->stream;
-        } else {
-            IPC_HIP(hipStreamCreate(&b->stream));
-            b->own_stream = true;
+        for (int c = 0; c < Engine::kClasses; ++c) {
+            if (rt && rt->stream) {
+                b->stream[c] = (hipStream_t)rt->stream;
+            } else {
+                IPC_HIP(hipStreamCreate(&b->stream[c]));
+                b->own_stream[c] = true;
+            }
         }
-        b->worker = std::thread([b] { b->run(); });
+        for (int c = 0; c < Engine::kClasses; ++c) b->worker[c] = std::thread([b, c] { b->run(c); });
         return IPC_OK;
     });
     if (rc != IPC_OK) {
@@ -2117,11 +2264,11 @@ int32_t ipc_batch_submit(ipc_batch *b, int32_t n, ipc_scene *const *s, const ipc
         }
         for (int i = 0; i < n; ++i) {
             t[i] = b->next++;
-            b->queue.push_back(Request{s[i], r[i], t[i]});
+            b->queue[Engine::class_of(*s[i])].push_back(Request{s[i], r[i], t[i]});
             b->pending[t[i]] = 1;
         }
     }
-    b->cv_work.notify_all();
+    for (auto &c : b->cv_work) c.notify_all();
     return IPC_OK;
 }
 
@@ -2146,6 +2293,33 @@ int32_t ipc_batch_wait(ipc_batch *b, ipc_ticket t, ipc_step_stats *st)
     int32_t rc = it->second.status;
     b->done.erase(it);
     return rc;
+}
+
+int32_t ipc_batch_next(ipc_batch *b, double timeout_ms, ipc_ticket *t, int32_t *status, ipc_step_stats *st)
+{
+    if (!b || !t) return IPC_E_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(b->mu);
+    auto ready = [&] {
+        while (!b->done_order.empty() && !b->done.count(b->done_order.front())) b->done_order.pop_front();
+        return !b->done_order.empty();
+    };
+    if (!ready()) {
+        if (b->pending.empty()) return IPC_E_INVALID_ARG;
+        auto pred = [&] { return ready() || b->pending.empty(); };
+        if (timeout_ms < 0)
+            b->cv_done.wait(lk, pred);
+        else
+            b->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), pred);
+        if (!ready()) return b->pending.empty() ? IPC_E_INVALID_ARG : 0;
+    }
+    ipc_ticket k = b->done_order.front();
+    b->done_order.pop_front();
+    auto it = b->done.find(k);
+    *t = k;
+    if (status) *status = it->second.status;
+    if (st) *st = it->second.st;
+    b->done.erase(it);
+    return 1;
 }
 
 int32_t ipc_batch_profile(ipc_batch *b, int32_t enable)
@@ -2417,6 +2591,13 @@ int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches,
     return IPC_OK;
 }
 
+int32_t ipcx_profile_bytes(const ipc_scene *s, int32_t kernel, double *bytes_total)
+{
+    if (!s || !bytes_total || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    *bytes_total = s->prof_acc[kernel].bytes;
+    return IPC_OK;
+}
+
 int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
 {
     if (!s || !out) return IPC_E_INVALID_ARG;
@@ -2429,6 +2610,31 @@ int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out)
     out[6] = s->last.n_sw;
     out[7] = s->n_gather;
     return IPC_OK;
+}
+
+int32_t ipcx_tuning(const ipc_scene *s, double *out)
+{
+    if (!s || !out) return IPC_E_INVALID_ARG;
+    out[0] = (double)s->tune.spmv_one_lane_rows;
+    out[1] = s->tune.mas_target;
+    out[2] = s->tune.pcg_first_chunk;
+    out[3] = s->tune.pcg_later_chunk;
+    out[4] = s->tune.from_file;
+    return IPC_OK;
+}
+
+int32_t ipcx_tuning_for(int32_t n_verts, double *out)
+{
+    if (!out || n_verts < 0) return IPC_E_INVALID_ARG;
+    return guarded([&]() -> int32_t {
+        Tuning t = tuning_for(n_verts);
+        out[0] = (double)t.spmv_one_lane_rows;
+        out[1] = t.mas_target;
+        out[2] = t.pcg_first_chunk;
+        out[3] = t.pcg_later_chunk;
+        out[4] = t.from_file;
+        return IPC_OK;
+    });
 }
 
 int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out)

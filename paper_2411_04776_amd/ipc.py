@@ -38,6 +38,8 @@ IPC_PRECOND_MULTILEVEL = 0
 IPC_PRECOND_JACOBI = 1
 IPC_BARRIER_PROJECTED = 0
 IPC_BARRIER_GAUSS_NEWTON = 1
+IPC_BATCH_LARGE_VERTS = 65536       # engine size classes: scenes with at least this many vertices are large
+IPC_HEIGHT_MAP_NOALLOC_MAX_PIXELS = 1 << 20
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
@@ -113,6 +115,7 @@ _SIGS = {
     "ipc_batch_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(ipc_step_req), _I64]),
     "ipc_batch_poll": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(ipc_step_stats)]),
     "ipc_batch_wait": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(ipc_step_stats)]),
+    "ipc_batch_next": (C.c_int32, [C.c_void_p, C.c_double, _I64, _I, C.POINTER(ipc_step_stats)]),
     "ipc_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "ipc_batch_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D, _D]),
     "ipc_status_str": (C.c_char_p, [C.c_int32]),
@@ -128,6 +131,9 @@ _SIGS = {
     "ipcx_ccd": (C.c_int32, [C.c_void_p, _D, _D, _D]),
     "ipcx_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "ipcx_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
+    "ipcx_profile_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _D]),
+    "ipcx_tuning": (C.c_int32, [C.c_void_p, _D]),
+    "ipcx_tuning_for": (C.c_int32, [C.c_int32, _D]),
     "ipcx_matrix_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_precond_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_set_state": (C.c_int32, [C.c_void_p, _D, _D]),
@@ -320,6 +326,14 @@ def scene_case_pose(scene, step):
     return None if cp is None else cp[step]
 
 
+def tuning_for(n_verts):
+    """The autotuner's choices a scene of n_verts vertices would take now."""
+    o = np.zeros(5)
+    _check(lib().ipcx_tuning_for(int(n_verts), _d(o)), "ipcx_tuning_for")
+    return {"spmv_one_lane_rows": int(o[0]), "mas_target": int(o[1]), "pcg_first_chunk": float(o[2]),
+            "pcg_later_chunk": float(o[3]), "from_file": bool(o[4])}
+
+
 class GelScene:
     """One library scene built from a scenes.Scene."""
 
@@ -506,11 +520,25 @@ class GelScene:
             out[name] = (n.value, ms.value)
         return out
 
+    def profile_bytes(self, kernel):
+        """Summed algorithmic bytes of the timed launches of PCG kernel class
+        0 (SpMV) or 1 (update)."""
+        by = C.c_double()
+        _check(lib().ipcx_profile_bytes(self.ptr, int(kernel), C.byref(by)), "ipcx_profile_bytes")
+        return by.value
+
     def matrix_info(self):
         o = np.zeros(8, dtype=np.int64)
         lib().ipcx_matrix_info(self.ptr, o.ctypes.data_as(_I64))
         keys = ("nnzb", "bell_entries", "n", "n_active", "n_tets", "n_cand", "n_cand_swept", "n_gather")
         return dict(zip(keys, map(int, o)))
+
+    def tuning(self):
+        """The autotuner's choices this scene took at creation."""
+        o = np.zeros(5)
+        _check(lib().ipcx_tuning(self.ptr, _d(o)), "ipcx_tuning")
+        return {"spmv_one_lane_rows": int(o[0]), "mas_target": int(o[1]), "pcg_first_chunk": float(o[2]),
+                "pcg_later_chunk": float(o[3]), "from_file": bool(o[4])}
 
     def precond_info(self):
         o = np.zeros(8, dtype=np.int64)
@@ -604,6 +632,16 @@ class Batch:
         if rc < 0:
             raise IPCError(rc, "ipc_batch_wait")
         return rc, st
+
+    def next(self, timeout_ms=-1.0):
+        """The oldest finished step not yet consumed: (ticket, status, stats),
+        waiting up to timeout_ms (< 0: without limit); None on timeout."""
+        t = np.zeros(1, dtype=np.int64)
+        stt = C.c_int32()
+        st = ipc_step_stats()
+        rc = _check(lib().ipc_batch_next(self.ptr, float(timeout_ms), t.ctypes.data_as(_I64), C.byref(stt),
+                                         C.byref(st)), "ipc_batch_next")
+        return (int(t[0]), int(stt.value), st) if rc == 1 else None
 
     def profile(self, enable=True):
         _check(lib().ipc_batch_profile(self.ptr, int(bool(enable))), "ipc_batch_profile")

@@ -10,8 +10,10 @@ continuous-batching engine, which runs every in-flight step in shared
 launches and takes new steps in at each Newton-iteration boundary. Latency of
 a request = completion time - arrival time.
 
-The loop itself only generates arrivals and collects completions; all
-stepping runs in the native engine (ipc_batch_submit / ipc_batch_poll).
+The loop itself only generates arrivals and collects completions (the
+engine's wait-any, ipc_batch_next, so one thread serves every environment);
+all stepping runs in the native engine, whose size classes step the large
+scenes in a list and on a stream of their own.
 """
 from __future__ import annotations
 
@@ -21,6 +23,9 @@ import time
 import numpy as np
 
 from . import ipc, scenes
+
+
+LARGE_VERTS = ipc.IPC_BATCH_LARGE_VERTS   # the engine's size classes
 
 
 @dataclasses.dataclass
@@ -35,11 +40,17 @@ class ServeResult:
     refused: int
     footprint_gb: float
     statuses: dict
+    by_class: dict          # "small" / "large": completed, p50, p99 (ms)
+    offered_hz: float
 
 
 def footprint(scene, precision) -> int:
     d = ipc.make_desc(scene, precision=precision, keep=[])
     return int(ipc.lib().ipc_scene_footprint_bytes(d))
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v) * 1e3, q)) if len(v) else float("nan")
 
 
 class Server:
@@ -60,6 +71,7 @@ class Server:
             self.envs.append(ipc.GelScene(sc, runtime=rt, precision=precision, pcg_tol=pcg_tol, precond=precond))
             used += need
         self.footprint = used
+        self.large = [g.n >= LARGE_VERTS for g in self.envs]
         self.engine = ipc.Batch()
 
     def next_pose(self, g):
@@ -69,52 +81,73 @@ class Server:
         return g.scene.poses[g.step_index + 1]
 
     def run(self, rate_hz: float, n_requests: int, seed: int = 7, time_limit_s: float = 60.0) -> ServeResult:
+        """Poisson arrivals at rate_hz over the environments (uniformly), at
+        most one request in flight per environment (a request for a busy
+        environment waits for it); every due arrival is submitted in one call
+        and completions are taken with the engine's wait-any."""
         rng = np.random.default_rng(seed)
         n = len(self.envs)
-        busy = [None] * n          # (ticket, arrival time) of the env's request in flight
-        waiting = []               # arrivals whose env was busy: (arrival, env)
-        lat, newton, statuses = [], 0, {}
+        busy = [False] * n
+        waiting = [[] for _ in range(n)]   # arrival times of requests for a busy environment
+        owner = {}                         # ticket -> (env, arrival)
+        lat = {False: [], True: []}
+        newton, statuses = 0, {}
         t0 = time.perf_counter()
         next_arrival = t0 + rng.exponential(1.0 / rate_hz)
         issued = done = 0
+
+        def submit(items):
+            gs = [self.envs[e] for e, _ in items]
+            tks = self.engine.submit(gs, [self.next_pose(g) for g in gs])
+            for (e, arr), t in zip(items, tks):
+                owner[t] = (e, arr)
+
         while done < n_requests:
             now = time.perf_counter()
             if now - t0 > time_limit_s:
                 break
+            due = []
             while issued < n_requests and next_arrival <= now:
-                waiting.append((next_arrival, int(rng.integers(0, n))))
+                e = int(rng.integers(0, n))
+                if busy[e]:
+                    waiting[e].append(next_arrival)
+                else:
+                    busy[e] = True
+                    due.append((e, next_arrival))
                 issued += 1
                 next_arrival += rng.exponential(1.0 / rate_hz)
-            # hand arrivals to idle environments, oldest first
-            still = []
-            for arr, e in waiting:
-                if busy[e] is None:
-                    g = self.envs[e]
-                    pose = self.next_pose(g)
-                    busy[e] = (self.engine.submit([g], [pose])[0], arr)
+            if due:
+                submit(due)
+            timeout = max(0.0, next_arrival - time.perf_counter()) * 1e3 if issued < n_requests else 20.0
+            if not owner:
+                time.sleep(timeout / 1e3)
+                continue
+            r = self.engine.next(timeout)
+            follow = []
+            while r is not None:
+                t, rc, st = r
+                e, arr = owner.pop(t)
+                lat[self.large[e]].append(time.perf_counter() - arr)
+                newton += st.newton_iters
+                statuses[rc] = statuses.get(rc, 0) + 1
+                done += 1
+                if waiting[e]:
+                    follow.append((e, waiting[e].pop(0)))
                 else:
-                    still.append((arr, e))
-            waiting = still
-            for e in range(n):
-                if busy[e] is None:
-                    continue
-                fin, _ = self.engine.poll(busy[e][0])
-                if fin:
-                    rc, st = self.engine.wait(busy[e][0])
-                    lat.append(time.perf_counter() - busy[e][1])
-                    newton += st.newton_iters
-                    statuses[rc] = statuses.get(rc, 0) + 1
-                    busy[e] = None
-                    done += 1
-            time.sleep(0.0002)
-        for e in range(n):  # drain
-            if busy[e] is not None:
-                rc, st = self.engine.wait(busy[e][0])
+                    busy[e] = False
+                r = self.engine.next(0.0) if owner else None
+            if follow:
+                submit(follow)
+        while owner:  # drain
+            r = self.engine.next(-1.0)
+            owner.pop(r[0], None)
         wall = time.perf_counter() - t0
-        lat_ms = np.array(lat) * 1e3 if lat else np.array([np.nan])
-        return ServeResult(done, wall, done / wall, newton / wall, float(np.percentile(lat_ms, 50)),
-                           float(np.percentile(lat_ms, 99)), len(self.envs), self.refused,
-                           self.footprint / 2 ** 30, statuses)
+        allv = lat[False] + lat[True]
+        by = {name: {"completed": len(lat[k]), "p50_ms": round(_pct(lat[k], 50), 3),
+                     "p99_ms": round(_pct(lat[k], 99), 3)}
+              for name, k in (("small", False), ("large", True)) if lat[k]}
+        return ServeResult(done, wall, done / wall, newton / wall, _pct(allv, 50), _pct(allv, 99), len(self.envs),
+                           self.refused, self.footprint / 2 ** 30, statuses, by, rate_hz)
 
     def close(self):
         self.engine.close()

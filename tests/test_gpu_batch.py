@@ -177,3 +177,37 @@ def test_large_list_bitwise_equals_alone(ipc):
         assert (rc, st.newton_iters, st.pcg_iters) == ref[i][:3]
         assert np.array_equal(gs[i].x, ref[i][3])
     b.close()
+
+
+def test_size_classes_and_wait_any(ipc):
+    """A scene above IPC_BATCH_LARGE_VERTS steps in the large class (its own
+    list, worker and stream) while small scenes of both precisions keep
+    stepping; every result is bitwise the one alone, and the wait-any call
+    hands back every ticket exactly once."""
+    big = S.uneven_scene(7200, steps=3, grid=(64, 64, 17))
+    assert len(big.X) + len(big.Y) >= 65536
+    scs = [big] + mix()
+    precs = [1, 0, 1, 0, 1]
+    steps = 2
+    ref = [run_alone(ipc, sc, steps, p) for sc, p in zip(scs, precs)]
+    gs = [ipc.GelScene(sc, precision=p, pcg_tol=PCG_TOL[p]) for sc, p in zip(scs, precs)]
+    b = ipc.Batch()
+    with pytest.raises(ipc.IPCError):
+        b.next(0.0)  # nothing pending or finished
+    for k in range(steps):
+        tks = b.submit(gs[:1])
+        tks += b.submit(gs[1:])
+        seen, order = {}, []
+        while len(seen) < len(tks):
+            r = b.next(10000.0)
+            assert r is not None, "wait-any timed out"
+            t, rc, st = r
+            assert t in tks and t not in seen
+            i = tks.index(t)
+            seen[t] = (rc, st.newton_iters, st.pcg_iters, st.ls_halvings)
+            order.append(i)
+        say(f"  step {k + 1}: completion order {order}")
+        for i, t in enumerate(tks):
+            assert seen[t] == ref[i][1][k], (i, seen[t], ref[i][1][k])
+            assert np.array_equal(gs[i].x, ref[i][0][k])
+    b.close()
