@@ -1,16 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the IPC gel-pad step on one MI355X.
 
-Workload: the larger single-scene configuration -- a 40x50x8 vertex gel
-(16,000 vertices, 80,262 tets) over a 20x25x4 mm box, bottom face fixed,
-pressed 1.5 mm over 50 steps (dt = 5e-3 s) by the seed's indenter (seed 0:
-a capped cylinder), plain FP64. A "step" is one ipc_step: the whole Newton
-solve of one time step (candidates, distances, barrier, elasticity, PCG,
-CCD, line search). Inputs are resident in HBM before the timed region.
+Headline workload (`value`): the batched mixed-precision form -- 256 uneven
+gel scenes (grids U{12..40} x U{15..50} x U{3..8}, random icosphere /
+cylinder / box indenters tilted up to 20 degrees, 0.5-2 mm deep over 20
+steps, dt = 1e-2 s; scene i from seed 1000 + i) stepped through the whole
+20-step episode from rest by the library's continuous-batching engine, one
+launch per Newton phase for the list. A "step" of the JSON line is one list
+step (every scene advances one time step); `value` is env-steps/s (completed
+ipc_step results per second). Inputs are resident in HBM before the timed
+region (the scenes are created, warmed up for W list steps, then reset to
+rest). The final positions of 16 sampled scenes are compared with the FP64
+oracle's (tests/golden/c3_*_final.npz): the fixed-error condition of the
+metric (max |x - x_oracle| / L <= 1e-4). The same 16 scenes are also stepped
+one at a time in plain FP64 (the per-scene GPU step the batched form is
+compared with) and in mixed precision.
 
-Prints one JSON line: env-steps/s (value), Newton iters/s, p50/p99 step
-latency, the roofline of the dominant kernel (PCG SpMV) from HIP events on
-the library's stream, and the FP64 CPU oracle timed on a bounded sample.
+Legs of the same line: config 2 (one 40x50x8 scene, FP64, all 50 steps),
+config 5 (80x100x16 gel, friction, mixed, 200 steps), serving at the config-4
+shape (1024 environments, 10% at 80x100x16, Poisson arrivals at 2k-20k
+req/s), the soft-ball scenes at the paper's Table 3 sizes, and the FP64
+oracle timed on the host cores.
+
+The roofline is that of the dominant PCG kernel of the headline list, from
+the engine's HIP events around one launch in sixteen inside the timed
+region (algorithmic bytes of the scenes whose solve was running, over the
+event-timed duration).
 """
 import argparse
 import json
@@ -23,11 +38,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+C3_SAMPLE = tuple(range(0, 256, 16))   # the 16 scenes compared with the oracle
 
 PCG_SOURCES = ("paper_2411_04776_amd/csrc/k_solver.hip", "paper_2411_04776_amd/csrc/incidence.h",
                "paper_2411_04776_amd/csrc/device_util.h", "paper_2411_04776_amd/csrc/ipc_internal.h")
-TRAFFIC_PROFILES = {"k_pcg_A": "profiles/k_pcg_A_c2_fp64_pmc.md", "k_pcg_B": "profiles/k_pcg_B_c2_fp64_pmc.md"}
+ELASTIC_SOURCES = ("paper_2411_04776_amd/csrc/k_elastic.hip", "paper_2411_04776_amd/csrc/device_util.h",
+                   "paper_2411_04776_amd/csrc/ipc_internal.h")
+TRAFFIC_PROFILES = {
+    "c3": {"k_pcg_A": "profiles/k_pcg_A_batch256_mixed_pmc.md", "k_pcg_B": "profiles/k_pcg_B_batch256_mixed_pmc.md"},
+    "c2": {"k_pcg_A": "profiles/k_pcg_A_c2_fp64_pmc.md", "k_pcg_B": "profiles/k_pcg_B_c2_fp64_pmc.md"},
+    "c5": {"k_pcg_A": "profiles/k_pcg_A_c5_mixed_pmc.md", "k_pcg_B": "profiles/k_pcg_B_c5_mixed_pmc.md"},
+}
+VALU_PROFILE = "profiles/assembly_c5_mixed_valu.md"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def precond_code(args):
@@ -40,29 +67,36 @@ def barrier_code(args):
     return ipc.IPC_BARRIER_GAUSS_NEWTON if args.barrier_hessian == "gauss-newton" else ipc.IPC_BARRIER_PROJECTED
 
 
-def pcg_source_hash():
+def source_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for f in PCG_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of a PCG kernel from the committed rocprofv3 --pmc
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size),
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILES[kernel])
+def summary_values(path, keys):
+    """`key: value` lines of a committed profile summary (None if missing)."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
-                k, v = line.strip().split(":", 1)
+            s = line.strip().lstrip("-* ")
+            if ":" in s and s.split(":", 1)[0].strip() in keys:
+                k, v = s.split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != pcg_source_hash():
+    return vals
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of a PCG kernel from a committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size),
+    or None when the kernel sources changed since the counters were taken."""
+    vals = summary_values(path, ("traffic_bytes_per_launch", "kernel_source_sha256"))
+    if not vals or vals.get("kernel_source_sha256") != source_hash(PCG_SOURCES):
         return None
     try:
         return int(float(vals["traffic_bytes_per_launch"]))
@@ -70,45 +104,442 @@ def measured_traffic(kernel):
         return None
 
 
-def update_bytes_per_launch(info, n_active, members):
-    """Algorithmic bytes of one PCG update launch (k_pcg_B, FP64): per vertex
-    q, d, p, r and the 3x3 inverse read (21 values) and p, r, z written (9),
-    per incidence entry (4 per active pair) its index and 3 pair-product
-    values, per preconditioner member its vertex id and three level ids, and
-    the SpMV blocks' d.q partials once."""
-    n = info["n"]
-    return 240 * n + 28 * 4 * n_active + 16 * members + 8 * ((n + 63) // 64)
+def pct(v, q):
+    import numpy as np
+    return round(float(np.percentile(v, q)), 3) if len(v) else None
 
 
-def spmv_bytes_per_launch(info, n_active):
-    """Algorithmic bytes of one PCG SpMV launch (FP64): each stored 3x3 block
-    (72 B values + 4 B column) once, per vertex the z and d gathers and the d,
-    q writes (4 x 24 B) plus its row pointers, and per active contact pair the
-    off-diagonal 3x3 blocks of its 4 rows (108 doubles) and vertex ids."""
-    n = info["n"]
-    return 76 * info["nnzb"] + 100 * n + 880 * n_active
+def pcg_roofline(prof, workload, note):
+    """Roofline objects of the two PCG kernels from event timings: prof maps
+    kernel name -> (timed launches, summed ms, summed algorithmic bytes)."""
+    out = {}
+    for kname, what in (("k_pcg_A", "PCG SpMV + direction update"),
+                        ("k_pcg_B", "PCG update + multilevel preconditioner")):
+        n, ms, by = prof[kname]
+        avg_s = ms / 1e3 / max(n, 1)
+        bpl = by / max(n, 1)
+        ach = bpl / avg_s / 1e9 if avg_s > 0 else 0.0
+        out[kname] = {"kernel": f"{kname} ({what})", "bound": "hbm", "achieved": round(ach, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                      "traffic": measured_traffic(TRAFFIC_PROFILES[workload][kname]),
+                      "traffic_source": TRAFFIC_PROFILES[workload][kname], "bytes_per_launch": int(bpl),
+                      "timed_launches": int(n), "avg_launch_us": round(avg_s * 1e6, 3), "event_ms": round(ms, 3),
+                      "timing": "HIP events around one launch in sixteen, on the launch stream, timed region"}
+    dom = max(out, key=lambda k: out[k]["event_ms"])
+    other = [k for k in out if k != dom][0]
+    roof = dict(out[dom])
+    roof["other_pcg_kernel"] = out[other]
+    roof["note"] = note
+    return roof
 
+
+# ---------------------------------------------------------------------------
+# headline: config 3
+# ---------------------------------------------------------------------------
+
+def fixed_error(gs, idx):
+    """max over the sampled scenes of max_i |x_i - x_i^oracle| / L (gel
+    vertices), from tests/golden/c3_{i}_final.npz; None if a golden is missing."""
+    import numpy as np
+    errs = {}
+    for i in idx:
+        path = os.path.join(GOLDEN, f"c3_{i}_final.npz")
+        if not os.path.exists(path):
+            return None
+        z = np.load(path)
+        g = gs[i] if isinstance(gs, dict) else gs[i]
+        ref = g.scene.X + z["dx"].astype(np.float64)
+        errs[i] = float(np.linalg.norm(g.x[:len(ref)] - ref, axis=1).max() / float(z["L"]))
+    return errs
+
+
+def c3_leg(args, ipc, scenes, torch, np):
+    rt = ipc.TorchRuntime()
+    t0 = time.perf_counter()
+    scs = [scenes.config3_scene(i) for i in range(args.batch)]
+    gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol,
+                       precond=precond_code(args), barrier_hessian=barrier_code(args)) for sc in scs]
+    build_s = time.perf_counter() - t0
+    nv = sum(g.n for g in gs)
+    nt = sum(g.n_tet for g in gs)
+    eng = ipc.Batch()
+
+    def list_step():
+        t_sub = time.perf_counter()
+        tks = eng.submit(gs)
+        left = set(tks)
+        lat, newton, pcg, bad = [], 0, 0, 0
+        while left:
+            t, rc, st = eng.next(-1.0)
+            left.discard(t)
+            lat.append(1e3 * (time.perf_counter() - t_sub))
+            newton += st.newton_iters
+            pcg += st.pcg_iters
+            bad += rc < 0
+        if bad:
+            raise RuntimeError(f"{bad} batched steps failed")
+        return lat, newton, pcg
+
+    for k in range(args.warmup):
+        list_step()
+    for g in gs:
+        g.reset()
+    torch.cuda.synchronize()
+    eng.profile(True)
+    lat, newton, pcg = [], 0, 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ls, nw, pc = list_step()
+        lat += ls
+        newton += nw
+        pcg += pc
+        log(f"c3 list step {k + 1}: {len(gs)} scenes, newton {nw}, pcg {pc}, "
+            f"{time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {"k_pcg_A": eng.profile_read(0), "k_pcg_B": eng.profile_read(1)}
+    eng.profile(False)
+    eng.close()
+    err = fixed_error(gs, C3_SAMPLE) if args.steps == 20 else None
+    env_steps = args.steps * len(gs)
+    res = {"value": env_steps / el, "elapsed": el, "env_steps": env_steps, "newton": newton, "pcg": pcg,
+           "lat": lat, "nv": nv, "nt": nt, "build_s": build_s, "prof": prof, "err": err}
+    # the 16 sampled scenes one at a time: plain FP64 and mixed, from rest
+    if not args.no_per_scene and args.steps == 20:
+        for name, prec in (("fp64", ipc.IPC_FP64), ("mixed", ipc.IPC_MIXED)):
+            sel = {i: ipc.GelScene(scs[i], precision=prec, pcg_tol=args.pcg_tol, precond=precond_code(args),
+                                   barrier_hessian=barrier_code(args)) for i in C3_SAMPLE if i < len(scs)}
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            steps, slat = 0, []
+            for i, g in sel.items():
+                for _ in range(20):
+                    ts = time.perf_counter()
+                    rc, st = g.step()
+                    slat.append(1e3 * (time.perf_counter() - ts))
+                    if rc < 0:
+                        raise RuntimeError(f"per-scene {name} step failed: {rc}")
+                    steps += 1
+            torch.cuda.synchronize()
+            el1 = time.perf_counter() - t1
+            e1 = fixed_error(sel, sel.keys())
+            res[f"per_scene_{name}"] = {
+                "env_steps_per_s": round(steps / el1, 2), "scenes": len(sel), "steps": steps,
+                "latency_ms": {"p50": pct(slat, 50), "p99": pct(slat, 99)},
+                "fixed_error_max": None if e1 is None else max(e1.values())}
+            for g in sel.values():
+                g.close()
+            log(f"per-scene {name}: {res[f'per_scene_{name}']}")
+    for g in gs:
+        g.close()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# config 2: one scene, FP64, all 50 steps
+# ---------------------------------------------------------------------------
+
+def c2_leg(args, ipc, scenes, torch, np):
+    sc = scenes.config2(args.seed)
+    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args),
+                     barrier_hessian=barrier_code(args))
+    for _ in range(args.c2_warmup):
+        g.step()
+    g.reset()
+    g.profile(True)
+    torch.cuda.synchronize()
+    lat, newton, pcg = [], 0, 0
+    t0 = time.perf_counter()
+    for _ in range(sc.n_steps):
+        rc, st = g.step()
+        if rc < 0:
+            raise RuntimeError(f"config 2 step failed: {rc}")
+        lat.append(st.ms_total)
+        newton += st.newton_iters
+        pcg += st.pcg_iters
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pr = g.profile_read()
+    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0)), "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1))}
+    g.profile(False)
+    err = None
+    path = os.path.join(GOLDEN, f"c2_seed{args.seed}_final.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        ref = sc.X + z["dx"].astype(np.float64)
+        err = float(np.linalg.norm(g.x[:len(ref)] - ref, axis=1).max() / float(z["L"]))
+    g.close()
+    out = {"workload": f"40x50x8 gel (16000 v, 80262 tets), {sc.meta['kind']} indenter seed {args.seed}, "
+                       f"1.5 mm over 50 steps, dt 5e-3 s, FP64, all 50 steps (warm-up on the same scene, then reset)",
+           "env_steps_per_s": round(sc.n_steps / el, 3), "ms_per_step": round(1e3 * el / sc.n_steps, 3),
+           "newton_iters_per_s": round(newton / el, 2), "pcg_iters_per_newton": round(pcg / max(newton, 1), 1),
+           "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}, "fixed_error": err,
+           "roofline": pcg_roofline(prof, "c2", "one 16k-vertex scene: ~250 SpMV blocks for 256 CUs, a chain of "
+                                                "dependent loads per launch (latency-bound)")}
+    log(f"config 2: {out['env_steps_per_s']} env-steps/s, error {err}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# config 5: large scene with friction, mixed
+# ---------------------------------------------------------------------------
+
+def c5_leg(args, ipc, scenes, torch, np):
+    sc = scenes.config5()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    g = ipc.GelScene(sc, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol, precond=precond_code(args),
+                     barrier_hessian=barrier_code(args))
+    g.profile(True)
+    torch.cuda.synchronize()
+    lat, newton, pcg, st_codes = [], 0, 0, {}
+    steps = min(args.c5_steps, sc.n_steps)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        rc, st = g.step()
+        if rc < 0:
+            raise RuntimeError(f"config 5 step failed: {rc}")
+        st_codes[rc] = st_codes.get(rc, 0) + 1
+        lat.append(st.ms_total)
+        newton += st.newton_iters
+        pcg += st.pcg_iters
+        if (k + 1) % 40 == 0:
+            log(f"config 5 step {k + 1}: {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pr = g.profile_read()
+    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0)), "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1))}
+    peak = torch.cuda.max_memory_allocated() - base
+    g.close()
+    roof = pcg_roofline(prof, "c5", "128k-vertex scene with 1.83M stored blocks")
+    valu = summary_values(VALU_PROFILE, ("k_elastic_elements_valu_utilisation", "k_elastic_elements_fp32_tflops",
+                                         "k_elastic_elements_fp64_tflops", "kernel_source_sha256"))
+    if valu and valu.pop("kernel_source_sha256", None) != source_hash(ELASTIC_SOURCES):
+        valu = None
+    out = {"workload": "80x100x16 gel (128000 v, 703890 tets), icosphere-4 r = 8 mm, 1 mm indent (40 steps) then "
+                       f"5 mm slide (160 steps), friction mu 0.5, eps_v 1e-3 m/s, dt 1e-2 s, mixed, steps 1-{steps}",
+           "env_steps_per_s": round(steps / el, 3), "ms_per_step": round(1e3 * el / steps, 2),
+           "newton_iters_per_s": round(newton / el, 2), "pcg_iters_per_newton": round(pcg / max(newton, 1), 1),
+           "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}, "statuses": {str(k): v for k, v in st_codes.items()},
+           "peak_device_bytes": int(peak),
+           "pcg_hbm_gbs": {"k_pcg_A": roof["achieved"] if roof["kernel"].startswith("k_pcg_A") else
+                           roof["other_pcg_kernel"]["achieved"],
+                           "k_pcg_B": roof["achieved"] if roof["kernel"].startswith("k_pcg_B") else
+                           roof["other_pcg_kernel"]["achieved"]},
+           "roofline": roof,
+           "assembly_valu": valu, "assembly_valu_source": VALU_PROFILE}
+    log(f"config 5: {out['env_steps_per_s']} env-steps/s, p50 {out['latency_ms']['p50']} ms")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# serving: the config-4 shape
+# ---------------------------------------------------------------------------
+
+def serving_leg(args, ipc, torch, np):
+    from paper_2411_04776_amd import serve
+    t0 = time.perf_counter()
+    envs = serve.serving_envs(args.serve_envs, large_frac=args.serve_large_frac)
+    srv = serve.Server(envs, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol, precond=precond_code(args))
+    build_s = time.perf_counter() - t0
+    n_large = sum(srv.large)
+    log(f"serving: {len(srv.envs)} environments ({n_large} large) built in {build_s:.1f} s")
+
+    def closed_round():
+        tks = srv.engine.submit(srv.envs, [srv.next_pose(g) for g in srv.envs])
+        left = set(tks)
+        newton = 0
+        while left:
+            t, rc, st = srv.engine.next(-1.0)
+            left.discard(t)
+            newton += st.newton_iters
+        return newton
+
+    closed_round()   # contact set-up and buffer growth of every scene
+    t1 = time.perf_counter()
+    nw = closed_round()
+    el = time.perf_counter() - t1
+    capacity = len(srv.envs) / el
+    log(f"serving closed loop: {capacity:.0f} env-steps/s")
+    rates = []
+    for r in (float(v) for v in args.serve_rates.split(",")):
+        res = srv.run(rate_hz=r, n_requests=args.serve_requests, seed=7, time_limit_s=args.serve_time_limit)
+        rates.append({"offered_req_per_s": r, "completed": res.completed,
+                      "env_steps_per_s": round(res.env_steps_per_s, 1),
+                      "newton_iters_per_s": round(res.newton_iters_per_s, 1),
+                      "latency_ms": {"p50": round(res.latency_ms_p50, 2), "p99": round(res.latency_ms_p99, 2)},
+                      "by_size_class": res.by_class, "statuses": {str(k): v for k, v in res.statuses.items()}})
+        log(f"serving at {r:.0f} req/s: {rates[-1]}")
+    # the plain per-scene loop: ipc_step one environment at a time
+    small = [g for g, big in zip(srv.envs, srv.large) if not big][:32]
+    large = [g for g, big in zip(srv.envs, srv.large) if big][:4]
+    per = {}
+    for name, sel in (("small", small), ("large", large)):
+        if not sel:
+            continue
+        t = []
+        for g in sel:
+            pose = srv.next_pose(g)
+            ts = time.perf_counter()
+            g.step(pose)
+            t.append(time.perf_counter() - ts)
+        per[name] = float(np.mean(t))
+    frac = n_large / max(len(srv.envs), 1)
+    plain = None
+    if per:
+        mean_t = (1 - frac) * per.get("small", 0.0) + frac * per.get("large", 0.0)
+        plain = {"env_steps_per_s": round(1.0 / mean_t, 1),
+                 "ms_per_step": {k: round(1e3 * v, 2) for k, v in per.items()},
+                 "note": "ipc_step of one environment at a time (mean over 32 small and 4 large environments, "
+                         "weighted by the mix)"}
+    srv.close()
+    return {"workload": f"{len(srv.envs)} environments (uneven scenes, seeds 5000-{4999 + len(srv.envs)}, "
+                        f"{n_large} at 80x100x16), Poisson arrivals, at most one request in flight per "
+                        f"environment, mixed precision, engine with size classes",
+            "build_s": round(build_s, 1), "footprint_gib": round(srv.footprint / 2 ** 30, 2),
+            "closed_loop_env_steps_per_s": round(capacity, 1), "rates": rates, "plain_per_scene_loop": plain}
+
+
+# ---------------------------------------------------------------------------
+# soft ball (the paper's Table 3 sizes; context)
+# ---------------------------------------------------------------------------
+
+PAPER_SOFT_BALL_MS = {"small": 24.95, "medium": 110.47, "large": 221.61}
+
+
+def soft_ball_leg(args, ipc, scenes, torch):
+    """Gel pad + soft ball squeezed by a rigid plate at the three mesh sizes
+    of the paper's GIPC timing table (gel + ball vertex/tet counts), FP64,
+    20 steps each after one untimed step, with both pair-Hessian forms;
+    ms per step beside the paper's per-frame times on its own hardware (a
+    different scene: context)."""
+    out = {}
+    forms = (("projected", ipc.IPC_BARRIER_PROJECTED), ("gauss_newton", ipc.IPC_BARRIER_GAUSS_NEWTON))
+    for size in ("small", "medium", "large"):
+        sc = scenes.soft_ball_scene(size, steps=21)
+        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "pcg_tol": min(args.pcg_tol, 1e-4),
+                     "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
+        for name, code in forms:
+            g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
+                             barrier_hessian=code)
+            g.step()
+            torch.cuda.synchronize()
+            newton, pcg, t = 0, 0, []
+            for _ in range(sc.n_steps - 1):
+                t0 = time.perf_counter()
+                rc, st = g.step()
+                t.append(time.perf_counter() - t0)
+                newton += st.newton_iters
+                pcg += st.pcg_iters
+            g.close()
+            out[size][name] = {"ms_per_step": round(1e3 * sum(t) / len(t), 2),
+                               "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
+                               "newton_per_step": round(newton / len(t), 2),
+                               "pcg_per_newton": round(pcg / max(newton, 1), 1)}
+        log(f"soft ball {size}: {out[size]}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the FP64 oracle on the host cores
+# ---------------------------------------------------------------------------
+
+def _oracle_worker(job):
+    """One oracle process: steps its scene from rest until the budget is
+    spent; returns (completed steps, seconds, per-step seconds)."""
+    kind, arg, budget, pcg_tol = job
+    sys.path.insert(0, ROOT)
+    import oracle
+    from paper_2411_04776_amd import scenes
+    sc = scenes.config3_scene(arg) if kind == "c3" else (scenes.config1() if kind == "c1" else scenes.config2(arg))
+    o = oracle.OracleScene(sc, pcg_tol=pcg_tol)
+    t0 = time.perf_counter()
+    per = []
+    for k in range(1, sc.n_steps + 1):
+        ts = time.perf_counter()
+        o.step(sc.poses[k])
+        per.append(time.perf_counter() - ts)
+        if time.perf_counter() - t0 > budget:
+            break
+    return len(per), time.perf_counter() - t0, per
+
+
+def cpu_baseline(args):
+    """The FP64 oracle (single-threaded C, -O2) on the host: P independent
+    processes over distinct config-3 scenes (P = the CPU share, at most 16)
+    stepping from rest for a bounded time each: summed env-steps/s, the
+    headline workload's unit; plus one core's per-step latency on configs 1
+    and 2 (first steps from rest)."""
+    import multiprocessing as mp
+    import platform
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    P = max(1, min(16, ncpu))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor()
+    ctx = mp.get_context("spawn")
+    jobs = [("c3", i, args.cpu_budget, args.pcg_tol) for i in range(P)]
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    steps = sum(r[0] for r in res)
+    thr = sum(r[0] / r[1] for r in res)
+    single = {}
+    with ctx.Pool(2) as pool:
+        r1, r2 = pool.map(_oracle_worker, [("c1", 0, args.cpu_budget / 2, args.pcg_tol),
+                                           ("c2", args.seed, args.cpu_budget, args.pcg_tol)])
+    for name, r in (("config1", r1), ("config2", r2)):
+        single[name] = {"steps": r[0], "ms_per_step": round(1e3 * r[1] / max(r[0], 1), 1),
+                        "p50_ms": round(1e3 * statistics.median(r[2]), 1)}
+    return {"value": round(thr, 4), "unit": "env-steps/s", "cores": P, "kind": "oracle",
+            "sample": f"{P} oracle processes, one per config-3 scene (seeds 1000-{999 + P}), each stepping from "
+                      f"rest for about {args.cpu_budget:.0f} s: {steps} steps in {wall:.1f} s wall, summed "
+                      f"per-process rates; PCG tolerance {args.pcg_tol}",
+            "nproc_visible": os.cpu_count(), "cpu_share": ncpu, "cpu_model": model,
+            "single_core": single,
+            "config5": "not timed here: one oracle Newton iteration of config 5 takes minutes on one core "
+                       "(all-pairs candidate tests over 21k surface points and 63k edges)"}
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--seed", type=int, default=0)
-    # PCG tolerance of the timed runs: the loosest that keeps the final error of
-    # config 2 far inside 1e-4 L (tests/test_gpu_fixed_error.py: 8e-6 L)
+    ap.add_argument("--steps", type=int, default=20, help="timed list steps of the config-3 episode (20 = all)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed list steps before the reset to rest")
+    ap.add_argument("--batch", type=int, default=256, help="scenes of the headline list")
+    ap.add_argument("--seed", type=int, default=0, help="config-2 seed")
+    # PCG tolerance of the timed runs: the loosest that keeps the final error far
+    # inside 1e-4 L (checked in the line itself: fixed_error)
     ap.add_argument("--pcg-tol", type=float, default=1e-3)
-    ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel",
-                    help="PCG preconditioner: additive multilevel aggregates or block-Jacobi")
-    ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected",
-                    help="pair barrier Hessian: PSD-projected exact Hessian or the Gauss-Newton form")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel")
+    ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected")
+    ap.add_argument("--no-per-scene", action="store_true", help="skip the one-at-a-time runs of the 16 sampled scenes")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--c2-warmup", type=int, default=3)
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--c5-steps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-envs", type=int, default=1024)
+    ap.add_argument("--serve-large-frac", type=float, default=0.1)
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000")
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-time-limit", type=float, default=20.0)
+    ap.add_argument("--no-soft-ball", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=256, help="scenes of the batched uneven-scene leg (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=4)
-    ap.add_argument("--serve", type=int, default=64, help="environments of the serving leg (0: skip)")
-    ap.add_argument("--no-soft-ball", action="store_true", help="skip the soft-ball leg")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work per process")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only copy a buffer of this many MiB with torch (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -116,10 +547,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU: the library has no multi-GPU path (scenes are independent and "
-              "would shard across GPUs without communication). Use --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-    if args.warmup + args.steps > 50:
-        print("warmup + steps must fit the 50-step trajectory", file=sys.stderr)
+              "would shard across GPUs by scene without communication). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -137,267 +565,50 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
         return
-    sc = scenes.config2(args.seed)
-    g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=args.pcg_tol, precond=precond_code(args),
-                     barrier_hessian=barrier_code(args))
-    for _ in range(args.warmup):
-        rc, st = g.step()
-        print(f"warmup step {g.step_index}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
-              f"ms={st.ms_total:.1f}", file=sys.stderr, flush=True)
-    x_start, v_start = g.x, g.v
-    g.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat, newton, pcg, active = [], 0, 0, []
-    for _ in range(args.steps):
-        rc, st = g.step()
-        lat.append(st.ms_total)
-        newton += st.newton_iters
-        pcg += st.pcg_iters
-        active.append(st.n_active)
-        print(f"step {g.step_index}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
-              f"active={st.n_active} alpha_ccd={st.alpha_ccd:.3g} halvings={st.ls_halvings} "
-              f"ms={st.ms_total:.1f}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    prof = g.profile_read()
-    info = g.matrix_info()
-    g.profile(False)
 
-    # the two PCG kernels (the dominant launches): achieved = algorithmic
-    # bytes per launch / mean event-timed launch duration
-    n_act_mean = float(np.mean(active)) if active else 0.0
-    members = g.precond_info()["members"]
-    pcg_k = {}
-    for cls, kname, what, nbytes in (
-            ("pcg_spmv", "k_pcg_A", "PCG SpMV + direction update", spmv_bytes_per_launch(info, n_act_mean)),
-            ("pcg_update", "k_pcg_B", "PCG update + multilevel preconditioner", update_bytes_per_launch(info, n_act_mean, members))):
-        n_launch, ms = prof[cls]
-        avg_s = ms / 1e3 / max(n_launch, 1)
-        achieved = nbytes / avg_s / 1e9 if avg_s > 0 else 0.0
-        pcg_k[kname] = {
-            "kernel": f"{kname} ({what})", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-            "traffic_source": TRAFFIC_PROFILES[kname], "bytes_per_launch": int(nbytes), "timed_launches": int(n_launch),
-            "timing": "HIP events around 1 in 16 launches in the timed region", "avg_launch_us": round(avg_s * 1e6, 3),
-            "event_ms": round(ms, 3)}
-    dom_k = max(pcg_k, key=lambda k: pcg_k[k]["event_ms"])
-    other = [k for k in pcg_k if k != dom_k][0]
-    roofline = dict(pcg_k[dom_k])
-    # PCG classes time one launch in sixteen: scale them to all pcg iterations
-    est = {k: v[1] for k, v in prof.items()}
-    for cls in ("pcg_spmv", "pcg_update"):
-        if prof[cls][0] > 0:
-            est[cls] = prof[cls][1] / prof[cls][0] * pcg
-    roofline["share_of_event_time"] = {k: round(v / max(sum(est.values()), 1e-12), 4) for k, v in est.items()}
-    roofline["dominant_by_event_time"] = max(est, key=est.get)
-    roofline["other_pcg_kernel"] = pcg_k[other]
-    roofline["note"] = ("one 16k-vertex scene is latency-bound (a chain of dependent loads and block barriers per "
-                        "launch, ~250 blocks for 256 CUs); the batch leg's pcg_spmv_roofline is the bandwidth case")
-
+    h = c3_leg(args, ipc, scenes, torch, np)
+    roof = pcg_roofline(h["prof"], "c3", "the headline list: 256 scenes share every PCG launch")
+    err = h["err"]
     line = {
-        "metric": "env-steps/sec", "value": round(args.steps / elapsed, 4), "unit": "env-steps/s",
+        "metric": "env-steps/sec", "value": round(h["value"], 2), "unit": "env-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": round(1e3 * h["elapsed"] / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "newton_iters_per_sec": round(newton / elapsed, 3),
-        "pcg_iters_per_newton": round(pcg / max(newton, 1), 1),
-        "latency_ms": {"p50": round(statistics.median(lat), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3)},
-        "config": {"workload": f"40x50x8 gel (16000 v, 80262 tets), {sc.meta['kind']} indenter seed "
-                               f"{args.seed}, 1.5 mm over 50 steps, dt 5e-3 s, FP64, steps "
-                               f"{args.warmup + 1}-{args.warmup + args.steps}",
-                   "precision": "fp64", "pcg_tol": args.pcg_tol, "precond": args.precond,
-                   "barrier_hessian": args.barrier_hessian, "newton_tol_m": sc.newton_tol,
-                   "dhat_m": sc.dhat, "kappa": sc.kappa},
-        "roofline": roofline,
+        "dtype": "mixed f32/f64", "data": "synthetic",
+        "newton_iters_per_sec": round(h["newton"] / h["elapsed"], 1),
+        "pcg_iters_per_newton": round(h["pcg"] / max(h["newton"], 1), 1),
+        "latency_ms": {"p50": pct(h["lat"], 50), "p99": pct(h["lat"], 99),
+                       "note": "per env-step: completion - submission of its list step"},
+        "fixed_error": None if err is None else {
+            "max_over_sampled": max(err.values()), "bound": 1e-4, "met": max(err.values()) <= 1e-4,
+            "sampled_scenes": list(err.keys()),
+            "definition": "max_i |x_i - x_i^oracle| / L after step 20, FP64 oracle at PCG tolerance 1e-12"},
+        "config": {"workload": f"{args.batch} uneven gel scenes (config 3: grids U{{12..40}}xU{{15..50}}xU{{3..8}}, "
+                               f"{h['nv']} vertices and {h['nt']} tets in total, seeds 1000-{999 + args.batch}), "
+                               f"random indenters, 0.5-2 mm over 20 steps, dt 1e-2 s, list steps 1-{args.steps} from "
+                               f"rest, mixed precision, continuous-batching engine",
+                   "precision": "mixed: FP32 assembly/SpMV/PCG vectors, FP64 dots, positions, distances, CCD, "
+                                "energies", "pcg_tol": args.pcg_tol, "precond": args.precond,
+                   "barrier_hessian": args.barrier_hessian, "newton_tol_m": 1e-6, "dhat_m": 1e-4, "kappa": 1e4,
+                   "scene_build_s": round(h["build_s"], 2)},
+        "roofline": roof,
     }
-
-    g.close()
-    if args.batch > 0:
-        line["batch"] = batch_leg(args, ipc, scenes, torch)
-    if args.serve > 0:
-        line["serving"] = serving_leg(args, ipc, torch)
+    for k in ("per_scene_fp64", "per_scene_mixed"):
+        if k in h:
+            line[k] = h[k]
+    if "per_scene_fp64" in h:
+        line["batched_vs_per_scene_fp64"] = round(h["value"] / h["per_scene_fp64"]["env_steps_per_s"], 2)
+    if not args.no_c2:
+        line["config2"] = c2_leg(args, ipc, scenes, torch, np)
+    if not args.no_c5:
+        line["config5"] = c5_leg(args, ipc, scenes, torch, np)
+    if not args.no_serve:
+        line["serving"] = serving_leg(args, ipc, torch, np)
     if not args.no_soft_ball:
         line["soft_ball"] = soft_ball_leg(args, ipc, scenes, torch)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sc, x_start, v_start, args, newton / args.steps)
-
+        line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)
-
-
-def batch_leg(args, ipc, scenes, torch):
-    """Uneven scenes (grid U{12..40}xU{15..50}xU{3..8}, random indenters)
-    stepped together through the continuous-batching engine, mixed precision:
-    every Newton phase is one launch for the whole list. Also the same first
-    16 scenes stepped one at a time (ipc_step) for the batching gain."""
-    rt = ipc.TorchRuntime()
-    t0 = time.perf_counter()
-    scs = [scenes.config3_scene(i) for i in range(args.batch)]
-    gs = [ipc.GelScene(sc, runtime=rt, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol,
-                         precond=precond_code(args), barrier_hessian=barrier_code(args)) for sc in scs]
-    build_s = time.perf_counter() - t0
-    nv = sum(len(sc.X) for sc in scs)
-    nt = sum(len(sc.T) for sc in scs)
-    eng = ipc.Batch()
-
-    def list_step():
-        tks = eng.submit(gs)
-        newton = 0
-        for t in tks:
-            rc, st = eng.wait(t)
-            if rc < 0:
-                raise RuntimeError(f"batched step failed: {rc}")
-            newton += st.newton_iters
-        return newton
-
-    list_step()  # warm-up: first contact, buffer growth
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    newton = 0
-    for _ in range(args.batch_steps):
-        newton += list_step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # one more list step with the engine's HIP-event timing of the SpMV (kernel
-    # class 0): achieved = algorithmic bytes of the timed launches / their time
-    eng.profile(True)
-    list_step()
-    n_a, ms_a, by_a = eng.profile_read(0)
-    eng.profile(False)
-    eng.close()
-    spmv = None
-    if n_a and ms_a > 0:
-        gbs = by_a / (ms_a * 1e-3) / 1e9
-        spmv = {"kernel": "k_pcg_A over the list (PCG SpMV + direction update)", "bound": "hbm",
-                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "timed_launches": n_a, "avg_launch_us": round(1e3 * ms_a / n_a, 2),
-                "bytes_per_launch": int(by_a / n_a),
-                "timing": "engine HIP events around 1 in 16 launches of one list step"}
-    # the same scenes one at a time, from the same states
-    k = min(16, len(gs))
-    states = [g.save_state() for g in gs[:k]]
-    t0 = time.perf_counter()
-    alone_steps = 0
-    for g in gs[:k]:
-        for _ in range(args.batch_steps):
-            g.step()
-            alone_steps += 1
-    torch.cuda.synchronize()
-    el_alone = time.perf_counter() - t0
-    for g, b in zip(gs[:k], states):
-        g.load_state(b)
-    for g in gs:
-        g.close()
-    steps = args.batch_steps * len(gs)
-    print(f"batch leg: {len(gs)} scenes, {steps} env-steps in {el:.2f} s", file=sys.stderr, flush=True)
-    return {"workload": f"{len(gs)} uneven scenes ({nv} v, {nt} tets in total), seeds 1000-{999 + len(gs)}, "
-                        f"steps 2-{1 + args.batch_steps}, mixed precision, continuous-batching engine",
-            "env_steps_per_s": round(steps / el, 2), "newton_iters_per_s": round(newton / el, 1),
-            "ms_per_list_step": round(1e3 * el / args.batch_steps, 2), "scene_build_s": round(build_s, 2),
-            "alone_env_steps_per_s": round(alone_steps / el_alone, 2), "alone_scenes": k,
-            "pcg_spmv_roofline": spmv}
-
-
-# GIPC ms per frame of the paper's timing table (soft ball, RTX 3080 Ti; context only)
-PAPER_SOFT_BALL_MS = {"small": 24.95, "medium": 110.47, "large": 221.61}
-
-
-def soft_ball_leg(args, ipc, scenes, torch):
-    """Gel pad + soft ball squeezed by a rigid plate at the three mesh sizes
-    of the paper's GIPC timing table (gel + ball vertex/tet counts), FP64,
-    20 steps each after one untimed step, with both pair-Hessian forms (the
-    projected one and the Gauss-Newton one GIPC uses); ms per step beside the
-    paper's per-frame times on its own hardware (a different scene: context)."""
-    out = {}
-    forms = (("projected", ipc.IPC_BARRIER_PROJECTED), ("gauss_newton", ipc.IPC_BARRIER_GAUSS_NEWTON))
-    for size in ("small", "medium", "large"):
-        sc = scenes.soft_ball_scene(size, steps=21)
-        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "pcg_tol": min(args.pcg_tol, 1e-4),
-                     "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
-        for name, code in forms:
-            # the floating ball's near-rigid modes make Newton sensitive to inexact
-            # steps: this leg solves PCG to 1e-4 (fewer Newton iterations than 1e-3)
-            g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
-                             barrier_hessian=code)
-            g.step()
-            torch.cuda.synchronize()
-            newton, pcg, t = 0, 0, []
-            for _ in range(sc.n_steps - 1):
-                t0 = time.perf_counter()
-                rc, st = g.step()
-                t.append(time.perf_counter() - t0)
-                newton += st.newton_iters
-                pcg += st.pcg_iters
-            g.close()
-            out[size][name] = {"ms_per_step": round(1e3 * sum(t) / len(t), 2),
-                               "p99_ms": round(1e3 * sorted(t)[int(0.99 * (len(t) - 1))], 2),
-                               "newton_per_step": round(newton / len(t), 2),
-                               "pcg_per_newton": round(pcg / max(newton, 1), 1)}
-        print(f"soft ball {size}: {out[size]}", file=sys.stderr, flush=True)
-    return out
-
-
-def serving_leg(args, ipc, torch):
-    """Request loop: Poisson arrivals over environments whose scenes stay
-    resident in HBM, at most one request in flight per environment, each
-    handed to the continuous-batching engine; latency = completion - arrival."""
-    from paper_2411_04776_amd import serve
-    envs = serve.serving_envs(args.serve, large_frac=0.0)
-    srv = serve.Server(envs, precision=ipc.IPC_MIXED, pcg_tol=args.pcg_tol, precond=precond_code(args))
-    # warm every scene once (contact set-up, buffer growth), then the closed-loop
-    # capacity with every environment in flight; the open loop offers 70% of it
-    def closed_round():
-        tks = srv.engine.submit(srv.envs, [srv.next_pose(g) for g in srv.envs])
-        for t in tks:
-            srv.engine.wait(t)
-
-    closed_round()
-    t0 = time.perf_counter()
-    for _ in range(2):
-        closed_round()
-    capacity = 2 * len(srv.envs) / (time.perf_counter() - t0)
-    rate = 0.7 * capacity
-    res = srv.run(rate_hz=rate, n_requests=args.serve_requests, seed=7, time_limit_s=60.0)
-    srv.close()
-    return {"workload": f"{args.serve} environments (uneven scenes, seeds 5000-{4999 + args.serve}), "
-                        f"Poisson arrivals at {rate:.0f} req/s, mixed precision",
-            "closed_loop_env_steps_per_s": round(capacity, 2),
-            "completed": res.completed, "env_steps_per_s": round(res.env_steps_per_s, 2),
-            "newton_iters_per_s": round(res.newton_iters_per_s, 1),
-            "latency_ms": {"p50": round(res.latency_ms_p50, 2), "p99": round(res.latency_ms_p99, 2)},
-            "admitted": res.admitted, "refused": res.refused, "footprint_gib": round(res.footprint_gb, 3),
-            "statuses": {str(k): v for k, v in res.statuses.items()}}
-
-
-def cpu_baseline(sc, x0, v0, args, newton_per_step):
-    """FP64 oracle, single thread, teacher-forced from the GPU state at the
-    start of the timed region: Newton iterations of the first timed step until
-    the budget is spent; env-steps/s = (Newton iters/s) / (Newton iters per
-    step measured on the GPU for the same steps)."""
-    import oracle
-    o = oracle.OracleScene(sc, pcg_tol=args.pcg_tol)
-    o.x = x0
-    o.v = v0
-    o.begin_step(sc.poses[args.warmup + 1])
-    x = x0
-    t0 = time.perf_counter()
-    iters = 0
-    while True:
-        r, xn, st = o.newton_iterate(x)
-        iters += 1
-        x = xn
-        if r != 0 or time.perf_counter() - t0 > args.cpu_budget:
-            break
-    dt = time.perf_counter() - t0
-    it_per_s = iters / dt
-    return {"value": round(it_per_s / max(newton_per_step, 1e-9), 6), "unit": "env-steps/s", "cores": 1,
-            "kind": "oracle",
-            "newton_iters_per_sec": round(it_per_s, 4),
-            "sample": f"{iters} oracle Newton iterations ({dt:.1f} s) of step {args.warmup + 1} from the GPU "
-                      f"state, scaled by {newton_per_step:.2f} Newton iterations per step"}
 
 
 if __name__ == "__main__":

@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2411_04776_amd import scenes as S
+from parity_util import assert_rows_close
 
 pytestmark = pytest.mark.gpu
 
@@ -85,11 +86,11 @@ def test_soft_ball_candidates_and_derivatives(ipc, ball_run):
     say(f"  active pairs {len(act)}, gel-ball {nb}")
     assert nb > 0
     gg, go = g.gradient(x), oo.gradient(x)
-    assert np.abs(gg - go).max() <= 1e-11 * np.abs(go).max()
+    assert_rows_close(gg, go, oo.n_gel, 1e-11)
     rng = np.random.default_rng(1)
     v = rng.normal(size=x.shape)
     yg, yo = g.hess_apply(x, v), oo.hess_apply(x, v)
-    assert np.abs(yg - yo).max() <= 1e-11 * np.abs(yo).max()
+    assert_rows_close(yg, yo, oo.n_gel, 1e-11)
 
 
 def test_soft_ball_teacher_forced_iterates(ipc, ball_run):
