@@ -363,9 +363,11 @@ def serving_leg(args, ipc, torch, np):
     capacity = len(srv.envs) / el
     log(f"serving closed loop: {capacity:.0f} env-steps/s")
     rates = []
-    for r in (float(v) for v in args.serve_rates.split(",")):
-        res = srv.run(rate_hz=r, n_requests=args.serve_requests, seed=7, time_limit_s=args.serve_time_limit)
-        rates.append({"offered_req_per_s": r, "completed": res.completed,
+    offered = [round(f * capacity) for f in (0.5, 0.8)] + [float(v) for v in args.serve_rates.split(",")]
+    for r in offered:
+        res = srv.run(rate_hz=r, duration_s=args.serve_seconds, seed=7)
+        rates.append({"offered_req_per_s": r, "arrived": res.arrived, "completed": res.completed,
+                      "backlog_at_end": res.backlog, "window_s": round(res.wall_s, 2),
                       "env_steps_per_s": round(res.env_steps_per_s, 1),
                       "newton_iters_per_s": round(res.newton_iters_per_s, 1),
                       "latency_ms": {"p50": round(res.latency_ms_p50, 2), "p99": round(res.latency_ms_p99, 2)},
@@ -398,7 +400,10 @@ def serving_leg(args, ipc, torch, np):
                         f"{n_large} at 80x100x16), Poisson arrivals, at most one request in flight per "
                         f"environment, mixed precision, engine with size classes",
             "build_s": round(build_s, 1), "footprint_gib": round(srv.footprint / 2 ** 30, 2),
-            "closed_loop_env_steps_per_s": round(capacity, 1), "rates": rates, "plain_per_scene_loop": plain}
+            "closed_loop_env_steps_per_s": round(capacity, 1), "rates": rates, "plain_per_scene_loop": plain,
+            "note": "each rate: Poisson arrivals for a fixed window, throughput and latency of the requests completed "
+                    "within it (the first two rates are 50% and 80% of the closed-loop capacity; above capacity "
+                    "the backlog and the latency grow with the window)"}
 
 
 # ---------------------------------------------------------------------------
@@ -535,8 +540,7 @@ def main():
     ap.add_argument("--serve-envs", type=int, default=1024)
     ap.add_argument("--serve-large-frac", type=float, default=0.1)
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000")
-    ap.add_argument("--serve-requests", type=int, default=3000)
-    ap.add_argument("--serve-time-limit", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per offered rate")
     ap.add_argument("--no-soft-ball", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work per process")

@@ -317,9 +317,11 @@ IPC_API int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out);
  * built-in defaults without one): out[0] SpMV one-thread-per-row threshold
  * (rows of a list), out[1] preconditioner group packing target (members),
  * out[2] first PCG chunk (fraction of the previous solve's iterations),
- * out[3] later chunks (fraction), out[4] 1 if read from a file. */
+ * out[3] later chunks (fraction of the remaining count), out[4] 1 if read
+ * from a file, out[5] the quantile of a list's scenes' remaining PCG counts
+ * the chunk lengths follow. */
 IPC_API int32_t ipcx_tuning(const ipc_scene *s, double *out);
-/* The same five values for a scene of n_verts vertices created now (host
+/* The same six values for a scene of n_verts vertices created now (host
  * only: reads the tuning file, touches no device). */
 IPC_API int32_t ipcx_tuning_for(int32_t n_verts, double *out);
 IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);

@@ -7,12 +7,14 @@ of at least spmv_one_lane_rows rows, else two lanes per row), the packing
 target of the multilevel preconditioner's groups (members per block of the
 update kernel), and the PCG chunk lengths (launches between two reads of the
 per-scene convergence flags: the first chunk a fraction of the previous
-solve's iteration count, later ones another fraction).
+solve's iteration count, later ones another fraction of the remaining
+count; in a list, of a quantile of its scenes' counts).
 
 This script measures them on the GPU: for each class a representative
 workload (small: a list of uneven config-3 scenes through the batching
 engine; large: an 80x100x16 scene of the serving mix), mixed precision, a
-few warm-up steps, a reset to rest and a few timed steps; coordinate descent
+warm-up step, a reset to rest, a few untimed steps and the timed middle
+of the episode; coordinate descent
 over the candidate values (two sweeps, each measurement the best of two
 runs), env-steps/s as the objective. It writes the chosen values and every
 measurement to tuning.json.
@@ -39,14 +41,18 @@ SPACE = {
     "mas_target": [128, 256, 384, 512],
     "pcg_first_chunk": [0.5, 0.75, 0.875, 1.0],
     "pcg_later_chunk": [0.125, 0.25, 0.5],
+    "pcg_list_quantile": [0.0, 0.1, 0.25, 0.5, 1.0],
 }
-DEFAULTS = {"spmv_one_lane_rows": 65536, "mas_target": 256, "pcg_first_chunk": 0.875, "pcg_later_chunk": 0.25}
+DEFAULTS = {"spmv_one_lane_rows": 65536, "mas_target": 256, "pcg_first_chunk": 0.875, "pcg_later_chunk": 0.25,
+            "pcg_list_quantile": 0.25}
 
 
 def _workload(name, small_scenes):
+    """Scenes, untimed steps after the reset, timed steps (the middle of the
+    20-step episode, where contact builds up)."""
     if name == "small":
-        return [scenes.config3_scene(i, steps=20) for i in range(small_scenes)], 2, 4
-    return [scenes.serving_scene(9, large=True)], 2, 4
+        return [scenes.config3_scene(i, steps=20) for i in range(small_scenes)], 6, 8
+    return [scenes.serving_scene(9, large=True)], 6, 6
 
 
 def _write(path, classes):
@@ -70,8 +76,7 @@ def measure(name, small_scenes, classes, tmp, pcg_tol=1e-3):
             if rc < 0:
                 raise RuntimeError(f"step failed: {rc}")
 
-    for _ in range(warm):
-        list_step()
+    list_step()   # contact set-up and buffer growth
     for g in gs:
         g.reset()
     for _ in range(warm):
@@ -105,7 +110,7 @@ def tune(out=DEFAULT_OUT, small_scenes=128, sweeps=2, reps=2, log=print):
             for sweep in range(sweeps):
                 for key, values in SPACE.items():
                     for v in values:
-                        if v == cls[key]:
+                        if v == classes[ci][key]:
                             continue
                         trial = [dict(c) for c in classes]
                         trial[ci][key] = v
@@ -123,8 +128,8 @@ def tune(out=DEFAULT_OUT, small_scenes=128, sweeps=2, reps=2, log=print):
     doc = {"classes": classes,
            "device": __import__("torch").cuda.get_device_name(0),
            "objective": "env-steps/s, mixed precision, PCG tolerance 1e-3; small: a list of "
-                        f"{small_scenes} config-3 scenes through the batching engine; large: one 80x100x16 "
-                        "serving scene; each after warm-up and a reset, best of two runs",
+                        f"{small_scenes} config-3 scenes through the batching engine (steps 7-14 of the episode); "
+                        "large: one 80x100x16 serving scene (steps 7-12); best of two runs",
            "measurements": records}
     with open(out, "w") as f:
         json.dump(doc, f, indent=1)

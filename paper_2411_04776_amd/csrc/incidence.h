@@ -15,12 +15,13 @@ namespace ipcg {
 
 // NC components per entry; val(p, a, c) reads component c of pair p, slot a.
 // out[c] += the sum over the entries of a light row, in list order, by one
-// thread (at most kHeavyRow independent entry loads).
-template <int NC, class F>
+// thread (at most kHeavyRow independent entry loads). U entries are unrolled
+// (loads in flight against registers held).
+template <int NC, class F, int U = 4>
 __device__ __forceinline__ void thread_row_sums(const SceneDev &S, int row, F val, double out[NC])
 {
     int e0 = S.c_ptr[row], e1 = S.c_ptr[row + 1];
-#pragma unroll 4
+#pragma unroll U
     for (int t = e0; t < e1; ++t) {
         int src = S.c_list[t];
         int p = src >> 2, a = src & 3;

@@ -212,7 +212,8 @@ struct Tuning {
     int64_t spmv_one_lane_rows = kSpmvOneLaneRows;  // lists with this many rows or more: one thread per SpMV row
     int mas_target = kMasTarget;                    // preconditioner group packing target (members, <= kMasCapM)
     double pcg_first_chunk = 0.875;                 // first PCG chunk: this fraction of the previous solve's count
-    double pcg_later_chunk = 0.25;                  // later chunks: this fraction of it (at least 8 launches)
+    double pcg_later_chunk = 0.25;                  // later chunks: this fraction of the remaining count (at least 8)
+    double pcg_list_quantile = 0.25;                // in a list: the quantile of the scenes' remaining counts used
     int from_file = 0;                              // 1 if read from a tuning file
 };
 Tuning tuning_for(int n_verts);  // the tuning file's entry for a scene of n_verts vertices

@@ -323,13 +323,16 @@ __global__ void __launch_bounds__(kRowsPerBlock * LPR) k_pcg_A(Launch L, int it,
     }
 }
 
-// the incident pairs' (H_p d_p)_i of a light row, by one thread
+// the incident pairs' (H_p d_p)_i of a light row, by one thread (two entries
+// in flight: the update kernel holds a vertex's PCG state meanwhile, and its
+// register count sets how many blocks a CU keeps resident)
 template <class R>
 __device__ __forceinline__ void contact_row_light(const SceneDev &S, int row, double qc[3])
 {
     const R *Y = as<R>(S.act_y);
     const int64_t cap = S.act_cap;
-    thread_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
+    auto val = [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; };
+    thread_row_sums<3, decltype(val), 2>(S, row, val, qc);
 }
 
 // the same sum for one heavy row, by the whole block
@@ -561,6 +564,14 @@ __device__ void pcg_B_heavy(const Launch &L, const SceneDev &S, int s, int j, in
     }
 }
 
+// a[l] of a per-level register array at a run-time level: selects, so the
+// array stays in registers (dynamic indexing would move it to scratch)
+__device__ __forceinline__ int lvl(const int (&a)[kMasLevels], int l)
+{
+    static_assert(kMasLevels == 3, "lvl selects among three levels");
+    return l == 0 ? a[0] : (l == 1 ? a[1] : a[2]);
+}
+
 static_assert(kMasCapA <= kMasCapM, "corrections reuse the members' LDS rows");
 static_assert(kMasCapM % kBlock == 0, "members per thread");
 constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group block
@@ -569,8 +580,8 @@ constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group b
 // aggregate (members, then children, in order), e = E^-1 r_agg per aggregate,
 // and z = D^-1 r + the corrections of the member's aggregates. The r.z
 // partial is r.D^-1 r + sum over the group's aggregates of r_agg.e. The
-// group's index data and the inverses of the first kBlock aggregates of each
-// level are loaded at the start, beside the members' vertex data.
+// group's index data is loaded at the start, beside the members' vertex data;
+// the aggregates' inverses where they are applied.
 template <class R>
 __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it)
 {
@@ -585,7 +596,6 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
     // level ranges, LDS bases, this thread's first aggregate per level
     int ga0[kMasLevels], ga1[kMasLevels], gbase[kMasLevels];
     int amb[kMasLevels], ame[kMasLevels];
-    R dinv[kMasLevels][9];
     const R *Di = as<R>(S.mas_dinv);
     {
         int bsum = 0;
@@ -603,8 +613,6 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                 int64_t g = S.mas_off[l] + a;
                 amb[l] = S.mas_mb[g];
                 ame[l] = S.mas_me[g];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) dinv[l][c] = Di[9 * g + c];
             }
         }
     }
@@ -686,22 +694,19 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
     }
     __syncthreads();
     // restriction and coarse solves, a barrier per level: the sums of level l
-    // are formed while the corrections of level l - 1 are
-#pragma unroll
+    // are formed while the corrections of level l - 1 are (not unrolled: the
+    // unrolled form held every level's state in registers at once)
+#pragma unroll 1
     for (int l = 0; l <= kMasLevels; ++l) {
         if (l > nl) break;
         if (l > 0) {
             const int pl = l - 1;
-            for (int a = ga0[pl] + tid; a < ga1[pl]; a += kBlock) {
-                int lc = gbase[pl] + a - ga0[pl];
+            const int g0 = lvl(ga0, pl), g1 = lvl(ga1, pl), gb = lvl(gbase, pl);
+            for (int a = g0 + tid; a < g1; a += kBlock) {
+                int lc = gb + a - g0;
                 R D[9];
-                if (a == ga0[pl] + tid) {
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) D[c] = dinv[pl][c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) D[c] = Di[9 * ((int64_t)S.mas_off[pl] + a) + c];
-                }
+                for (int c = 0; c < 9; ++c) D[c] = Di[9 * ((int64_t)S.mas_off[pl] + a) + c];
                 R sa[3] = {(R)ra[lc][0], (R)ra[lc][1], (R)ra[lc][2]};
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -712,11 +717,13 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             }
         }
         if (l < nl) {
-            for (int a = ga0[l] + tid; a < ga1[l]; a += kBlock) {
+            const int g0 = lvl(ga0, l), g1 = lvl(ga1, l), gb = lvl(gbase, l);
+            const int c0 = l > 0 ? lvl(ga0, l - 1) : 0, cb = l > 0 ? lvl(gbase, l - 1) : 0;
+            for (int a = g0 + tid; a < g1; a += kBlock) {
                 int j0, j1;
-                if (a == ga0[l] + tid) {
-                    j0 = amb[l];
-                    j1 = ame[l];
+                if (a == g0 + tid) {
+                    j0 = lvl(amb, l);
+                    j1 = lvl(ame, l);
                 } else {
                     int64_t g = S.mas_off[l] + a;
                     j0 = S.mas_mb[g];
@@ -724,12 +731,12 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                 }
                 double acc[3] = {0.0, 0.0, 0.0};
                 for (int j = j0; j < j1; ++j) {
-                    const double *src = l == 0 ? rm[j - k0] : ra[gbase[l - 1] + j - ga0[l - 1]];
+                    const double *src = l == 0 ? rm[j - k0] : ra[cb + j - c0];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) acc[c] += src[c];
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ra[gbase[l] + a - ga0[l]][c] = acc[c];
+                for (int c = 0; c < 3; ++c) ra[gb + a - g0][c] = acc[c];
             }
         }
         __syncthreads();
@@ -1251,9 +1258,22 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     const Tuning tn = big ? big->tune : Tuning{};
     const bool one_lane = rows_total >= tn.spmv_one_lane_rows;
     int it = 1;
-    // the first chunk stops short of the previous solve's count; later
-    // launches check the done flag first, so overshooting them is cheap
-    int chunk = last > 16 ? std::max(8, (int)(last * tn.pcg_first_chunk)) : 8;
+    // Chunk lengths: a quantile (tuned) of the running scenes' expected
+    // remaining iterations (their previous solve's count minus the launches
+    // done) times a fraction, at least 8. A short chunk costs a read-back; a
+    // long one keeps finished scenes' blocks in the launches (they exit at
+    // once, but still take dispatch slots). One scene: the fraction of its own
+    // previous count.
+    auto next_chunk = [&](double frac) {
+        std::vector<int> rem;
+        for (size_t i = 0; i < ns; ++i)
+            if (nab[i] > 0 && !(it > 1 && b.h_out[i].pcg_done)) rem.push_back(std::max(0, b.sc[i]->last_pcg_iters - (it - 1)));
+        if (rem.empty()) return 8;
+        std::sort(rem.begin(), rem.end());
+        size_t k = (size_t)(tn.pcg_list_quantile * (double)(rem.size() - 1) + 0.5);
+        return std::max(8, (int)(frac * rem[std::min(k, rem.size() - 1)]));
+    };
+    int chunk = last > 16 ? next_chunk(tn.pcg_first_chunk) : 8;
     int early = 0;
     hipEvent_t ev[2];
     // launch it = maxit + 1 too: its A kernel records the cap of the scenes
@@ -1295,7 +1315,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         for (size_t i = 0; i < ns; ++i)
             if (b.h_off[kPhVert][i + 1] > b.h_off[kPhVert][i] && !b.h_out[i].pcg_done) all = false;
         if (all) break;
-        chunk = early ? 8 : std::max(8, (int)(last * tn.pcg_later_chunk));
+        chunk = next_chunk(tn.pcg_later_chunk);
         early = 1;
         // scenes that finished leave the remaining launches of the list
         bool shrink = false;

@@ -113,6 +113,7 @@ std::vector<TuneClass> parse_tuning(const std::string &text)
             else if (key == "mas_target") c.t.mas_target = std::max(1, std::min(kMasCapM, (int)v));
             else if (key == "pcg_first_chunk") c.t.pcg_first_chunk = std::max(0.0, std::min(4.0, v));
             else if (key == "pcg_later_chunk") c.t.pcg_later_chunk = std::max(0.0, std::min(4.0, v));
+            else if (key == "pcg_list_quantile") c.t.pcg_list_quantile = std::max(0.0, std::min(1.0, v));
             q = (size_t)(end - body.c_str());
         }
         c.t.from_file = 1;
@@ -2620,6 +2621,7 @@ int32_t ipcx_tuning(const ipc_scene *s, double *out)
     out[2] = s->tune.pcg_first_chunk;
     out[3] = s->tune.pcg_later_chunk;
     out[4] = s->tune.from_file;
+    out[5] = s->tune.pcg_list_quantile;
     return IPC_OK;
 }
 
@@ -2633,6 +2635,7 @@ int32_t ipcx_tuning_for(int32_t n_verts, double *out)
         out[2] = t.pcg_first_chunk;
         out[3] = t.pcg_later_chunk;
         out[4] = t.from_file;
+        out[5] = t.pcg_list_quantile;
         return IPC_OK;
     });
 }

@@ -328,10 +328,11 @@ def scene_case_pose(scene, step):
 
 def tuning_for(n_verts):
     """The autotuner's choices a scene of n_verts vertices would take now."""
-    o = np.zeros(5)
+    o = np.zeros(6)
     _check(lib().ipcx_tuning_for(int(n_verts), _d(o)), "ipcx_tuning_for")
     return {"spmv_one_lane_rows": int(o[0]), "mas_target": int(o[1]), "pcg_first_chunk": float(o[2]),
-            "pcg_later_chunk": float(o[3]), "from_file": bool(o[4])}
+            "pcg_later_chunk": float(o[3]), "from_file": bool(o[4]),
+            "pcg_list_quantile": float(o[5])}
 
 
 class GelScene:
@@ -535,10 +536,11 @@ class GelScene:
 
     def tuning(self):
         """The autotuner's choices this scene took at creation."""
-        o = np.zeros(5)
+        o = np.zeros(6)
         _check(lib().ipcx_tuning(self.ptr, _d(o)), "ipcx_tuning")
         return {"spmv_one_lane_rows": int(o[0]), "mas_target": int(o[1]), "pcg_first_chunk": float(o[2]),
-                "pcg_later_chunk": float(o[3]), "from_file": bool(o[4])}
+                "pcg_later_chunk": float(o[3]), "from_file": bool(o[4]),
+            "pcg_list_quantile": float(o[5])}
 
     def precond_info(self):
         o = np.zeros(8, dtype=np.int64)

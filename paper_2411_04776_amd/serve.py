@@ -30,11 +30,11 @@ LARGE_VERTS = ipc.IPC_BATCH_LARGE_VERTS   # the engine's size classes
 
 @dataclasses.dataclass
 class ServeResult:
-    completed: int
-    wall_s: float
-    env_steps_per_s: float
+    completed: int          # requests completed within the arrival window
+    wall_s: float           # the arrival window
+    env_steps_per_s: float  # completions per second within the window
     newton_iters_per_s: float
-    latency_ms_p50: float
+    latency_ms_p50: float   # of the requests completed within the window
     latency_ms_p99: float
     admitted: int
     refused: int
@@ -42,6 +42,8 @@ class ServeResult:
     statuses: dict
     by_class: dict          # "small" / "large": completed, p50, p99 (ms)
     offered_hz: float
+    arrived: int            # requests that arrived within the window
+    backlog: int            # of them, not completed by its end (in flight or waiting)
 
 
 def footprint(scene, precision) -> int:
@@ -80,11 +82,15 @@ class Server:
             g.reset()
         return g.scene.poses[g.step_index + 1]
 
-    def run(self, rate_hz: float, n_requests: int, seed: int = 7, time_limit_s: float = 60.0) -> ServeResult:
-        """Poisson arrivals at rate_hz over the environments (uniformly), at
-        most one request in flight per environment (a request for a busy
-        environment waits for it); every due arrival is submitted in one call
-        and completions are taken with the engine's wait-any."""
+    def run(self, rate_hz: float, duration_s: float = 8.0, seed: int = 7) -> ServeResult:
+        """Poisson arrivals at rate_hz over the environments (uniformly) for
+        duration_s, at most one request in flight per environment (a request
+        for a busy environment waits for it); every due arrival is submitted
+        in one call and completions are taken with the engine's wait-any.
+        Throughput and latency are those of the requests completed within
+        the window (steady state: above capacity the backlog grows and
+        latency with it); afterwards the requests in flight are drained and
+        the waiting ones dropped."""
         rng = np.random.default_rng(seed)
         n = len(self.envs)
         busy = [False] * n
@@ -93,8 +99,9 @@ class Server:
         lat = {False: [], True: []}
         newton, statuses = 0, {}
         t0 = time.perf_counter()
+        t_end = t0 + duration_s
         next_arrival = t0 + rng.exponential(1.0 / rate_hz)
-        issued = done = 0
+        arrived = done = 0
 
         def submit(items):
             gs = [self.envs[e] for e, _ in items]
@@ -102,23 +109,23 @@ class Server:
             for (e, arr), t in zip(items, tks):
                 owner[t] = (e, arr)
 
-        while done < n_requests:
+        while True:
             now = time.perf_counter()
-            if now - t0 > time_limit_s:
+            if now >= t_end:
                 break
             due = []
-            while issued < n_requests and next_arrival <= now:
+            while next_arrival <= now and next_arrival < t_end:
                 e = int(rng.integers(0, n))
                 if busy[e]:
                     waiting[e].append(next_arrival)
                 else:
                     busy[e] = True
                     due.append((e, next_arrival))
-                issued += 1
+                arrived += 1
                 next_arrival += rng.exponential(1.0 / rate_hz)
             if due:
                 submit(due)
-            timeout = max(0.0, next_arrival - time.perf_counter()) * 1e3 if issued < n_requests else 20.0
+            timeout = max(0.0, min(next_arrival, t_end) - time.perf_counter()) * 1e3
             if not owner:
                 time.sleep(timeout / 1e3)
                 continue
@@ -127,27 +134,30 @@ class Server:
             while r is not None:
                 t, rc, st = r
                 e, arr = owner.pop(t)
-                lat[self.large[e]].append(time.perf_counter() - arr)
-                newton += st.newton_iters
-                statuses[rc] = statuses.get(rc, 0) + 1
-                done += 1
-                if waiting[e]:
+                fin = time.perf_counter()
+                if fin <= t_end:
+                    lat[self.large[e]].append(fin - arr)
+                    newton += st.newton_iters
+                    statuses[rc] = statuses.get(rc, 0) + 1
+                    done += 1
+                if waiting[e] and fin < t_end:
                     follow.append((e, waiting[e].pop(0)))
                 else:
                     busy[e] = False
                 r = self.engine.next(0.0) if owner else None
             if follow:
                 submit(follow)
-        while owner:  # drain
+        wall = time.perf_counter() - t0
+        backlog = len(owner) + sum(len(w) for w in waiting)
+        while owner:  # drain the requests in flight (not counted)
             r = self.engine.next(-1.0)
             owner.pop(r[0], None)
-        wall = time.perf_counter() - t0
         allv = lat[False] + lat[True]
         by = {name: {"completed": len(lat[k]), "p50_ms": round(_pct(lat[k], 50), 3),
                      "p99_ms": round(_pct(lat[k], 99), 3)}
               for name, k in (("small", False), ("large", True)) if lat[k]}
         return ServeResult(done, wall, done / wall, newton / wall, _pct(allv, 50), _pct(allv, 99), len(self.envs),
-                           self.refused, self.footprint / 2 ** 30, statuses, by, rate_hz)
+                           self.refused, self.footprint / 2 ** 30, statuses, by, rate_hz, arrived, backlog)
 
     def close(self):
         self.engine.close()
