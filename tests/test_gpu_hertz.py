@@ -80,7 +80,7 @@ def test_hertz_41x41x21(ipc):
     assert 0.8 <= layer <= 1.25
     if os.path.exists(CURVE):
         rows = np.loadtxt(CURVE, comments="#")
-        Fo, do = rows[:, 3], rows[:, 6]
+        Fo, do = rows[:, 5], rows[:, 6]   # the oracle's target pull (the same measure as F here), axis depth
         say(f"  vs oracle curve: max |F - F_oracle| / F_oracle = {np.abs(F / Fo - 1).max():.2e}, "
             f"max |delta - delta_oracle| = {np.abs(d - do).max():.2e} m")
         assert np.all(np.abs(F / Fo - 1) <= 1e-3)
