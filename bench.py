@@ -92,16 +92,18 @@ def summary_values(path, keys):
 
 
 def measured_traffic(path):
-    """HBM bytes per launch of a PCG kernel from a committed rocprofv3 --pmc
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size),
-    or None when the kernel sources changed since the counters were taken."""
-    vals = summary_values(path, ("traffic_bytes_per_launch", "kernel_source_sha256"))
+    """(HBM bytes per launch, ratio to the algorithmic bytes of the same
+    launches) of a PCG kernel from a committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size, over
+    every launch of the profiled command), or (None, None) when the kernel
+    sources changed since the counters were taken."""
+    vals = summary_values(path, ("traffic_bytes_per_launch", "traffic_over_algorithmic", "kernel_source_sha256"))
     if not vals or vals.get("kernel_source_sha256") != source_hash(PCG_SOURCES):
-        return None
+        return None, None
     try:
-        return int(float(vals["traffic_bytes_per_launch"]))
+        return int(float(vals["traffic_bytes_per_launch"])), float(vals.get("traffic_over_algorithmic", "nan"))
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 def pct(v, q):
@@ -115,16 +117,19 @@ def pcg_roofline(prof, workload, note):
     out = {}
     for kname, what in (("k_pcg_A", "PCG SpMV + direction update"),
                         ("k_pcg_B", "PCG update + multilevel preconditioner")):
-        n, ms, by = prof[kname]
+        n, ms, by, n_all, by_all = prof[kname]
         avg_s = ms / 1e3 / max(n, 1)
         bpl = by / max(n, 1)
         ach = bpl / avg_s / 1e9 if avg_s > 0 else 0.0
+        tr, ratio = measured_traffic(TRAFFIC_PROFILES[workload][kname])
         out[kname] = {"kernel": f"{kname} ({what})", "bound": "hbm", "achieved": round(ach, 1),
                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                      "traffic": measured_traffic(TRAFFIC_PROFILES[workload][kname]),
+                      "traffic": tr, "traffic_over_algorithmic": ratio,
                       "traffic_source": TRAFFIC_PROFILES[workload][kname], "bytes_per_launch": int(bpl),
                       "timed_launches": int(n), "avg_launch_us": round(avg_s * 1e6, 3), "event_ms": round(ms, 3),
-                      "timing": "HIP events around one launch in sixteen, on the launch stream, timed region"}
+                      "timing": "HIP events around one launch in sixteen, on the launch stream, timed region",
+                      "all_launches": {"launches": int(n_all),
+                                       "algorithmic_bytes_per_launch": int(by_all / max(n_all, 1))}}
     dom = max(out, key=lambda k: out[k]["event_ms"])
     other = [k for k in out if k != dom][0]
     roof = dict(out[dom])
@@ -197,13 +202,38 @@ def c3_leg(args, ipc, scenes, torch, np):
             f"{time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = {"k_pcg_A": eng.profile_read(0), "k_pcg_B": eng.profile_read(1)}
+    prof = {"k_pcg_A": (*eng.profile_read(0), *eng.profile_totals(0)),
+            "k_pcg_B": (*eng.profile_read(1), *eng.profile_totals(1))}
     eng.profile(False)
-    eng.close()
     err = fixed_error(gs, C3_SAMPLE) if args.steps == 20 else None
+    # the same episode with each environment submitting its next step as soon
+    # as its previous one is done (continuous batching; no list-wide barrier)
+    closed = None
+    if args.steps == 20 and not args.no_closed_loop:
+        for g in gs:
+            g.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        owner = {t: i for i, t in enumerate(eng.submit(gs))}
+        left = len(gs) * args.steps
+        while left:
+            t, rc, st = eng.next(-1.0)
+            if rc < 0:
+                raise RuntimeError(f"closed-loop step failed: {rc}")
+            i = owner.pop(t)
+            left -= 1
+            if gs[i].step_index < args.steps:
+                owner[eng.submit([gs[i]])[0]] = i
+        torch.cuda.synchronize()
+        el_c = time.perf_counter() - t1
+        closed = {"env_steps_per_s": round(args.steps * len(gs) / el_c, 2), "elapsed_s": round(el_c, 3),
+                  "note": "the same 20-step episode of every scene, each scene's next step submitted as soon as its "
+                          "previous one finished (no barrier across the list)"}
+        log(f"c3 closed loop: {closed}")
+    eng.close()
     env_steps = args.steps * len(gs)
     res = {"value": env_steps / el, "elapsed": el, "env_steps": env_steps, "newton": newton, "pcg": pcg,
-           "lat": lat, "nv": nv, "nt": nt, "build_s": build_s, "prof": prof, "err": err}
+           "lat": lat, "nv": nv, "nt": nt, "build_s": build_s, "prof": prof, "err": err, "closed": closed}
     # the 16 sampled scenes one at a time: plain FP64 and mixed, from rest
     if not args.no_per_scene and args.steps == 20:
         for name, prec in (("fp64", ipc.IPC_FP64), ("mixed", ipc.IPC_MIXED)):
@@ -260,7 +290,8 @@ def c2_leg(args, ipc, scenes, torch, np):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pr = g.profile_read()
-    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0)), "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1))}
+    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0), *g.profile_totals(0)),
+            "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1), *g.profile_totals(1))}
     g.profile(False)
     err = None
     path = os.path.join(GOLDEN, f"c2_seed{args.seed}_final.npz")
@@ -309,7 +340,8 @@ def c5_leg(args, ipc, scenes, torch, np):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pr = g.profile_read()
-    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0)), "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1))}
+    prof = {"k_pcg_A": (*pr["pcg_spmv"], g.profile_bytes(0), *g.profile_totals(0)),
+            "k_pcg_B": (*pr["pcg_update"], g.profile_bytes(1), *g.profile_totals(1))}
     peak = torch.cuda.max_memory_allocated() - base
     g.close()
     roof = pcg_roofline(prof, "c5", "128k-vertex scene with 1.83M stored blocks")
@@ -532,6 +564,7 @@ def main():
     ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel")
     ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected")
     ap.add_argument("--no-per-scene", action="store_true", help="skip the one-at-a-time runs of the 16 sampled scenes")
+    ap.add_argument("--no-closed-loop", action="store_true", help="skip the closed-loop run of the episode")
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--c2-warmup", type=int, default=3)
     ap.add_argument("--no-c5", action="store_true")
@@ -544,6 +577,8 @@ def main():
     ap.add_argument("--no-soft-ball", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work per process")
+    ap.add_argument("--only", choices=["config2", "config5", "serving"], default=None,
+                    help="run one leg alone and print its JSON (for profiler runs; not the benchmark line)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only copy a buffer of this many MiB with torch (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -570,6 +605,11 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
         return
 
+    if args.only:
+        leg = {"config2": c2_leg, "config5": c5_leg}.get(args.only)
+        out = leg(args, ipc, scenes, torch, np) if leg else serving_leg(args, ipc, torch, np)
+        print(json.dumps({args.only: out}), flush=True)
+        return
     h = c3_leg(args, ipc, scenes, torch, np)
     roof = pcg_roofline(h["prof"], "c3", "the headline list: 256 scenes share every PCG launch")
     err = h["err"]
@@ -597,6 +637,8 @@ def main():
                    "scene_build_s": round(h["build_s"], 2)},
         "roofline": roof,
     }
+    if h["closed"]:
+        line["closed_loop"] = h["closed"]
     for k in ("per_scene_fp64", "per_scene_mixed"):
         if k in h:
             line[k] = h[k]

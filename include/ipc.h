@@ -272,6 +272,10 @@ IPC_API int32_t ipc_batch_next(ipc_batch *b, double timeout_ms, ipc_ticket *t, i
  * values, per preconditioner member 16 bytes of ids, per SpMV block its d.q
  * partial (4- or 8-byte reals by the list's precision). */
 IPC_API int32_t ipc_batch_profile(ipc_batch *b, int32_t enable);
+/* Every launch of PCG class 0 or 1 while profiling was on (not only the
+ * timed ones) and their summed algorithmic bytes, counted as above: the
+ * population a hardware-counter run of the same command measures. */
+IPC_API int32_t ipc_batch_profile_totals(ipc_batch *b, int32_t kernel, int64_t *launches, double *bytes_total);
 IPC_API int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total,
                                        double *bytes_total);
 
@@ -304,6 +308,9 @@ IPC_API int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *l
 /* Summed algorithmic bytes of the timed launches of kernel class 0 or 1 (the
  * PCG kernels, counted as for ipc_batch_profile_read); 0 for other classes. */
 IPC_API int32_t ipcx_profile_bytes(const ipc_scene *s, int32_t kernel, double *bytes_total);
+/* Every launch of PCG class 0 or 1 while profiling (not only the timed ones)
+ * and their summed algorithmic bytes. */
+IPC_API int32_t ipcx_profile_totals(const ipc_scene *s, int32_t kernel, int64_t *launches, double *bytes_total);
 /* out[0..7] = stored elastic blocks, stored BELL entries incl. padding, vertices,
  * active pairs, tets, static candidates, swept candidates, gather entries. */
 IPC_API int32_t ipcx_matrix_info(const ipc_scene *s, int64_t *out);

@@ -245,6 +245,8 @@ struct ProfAcc {
     int64_t launches = 0;
     double ms = 0.0;
     double bytes = 0.0;
+    int64_t launches_all = 0;  // every launch of the class while profiling (PCG classes)
+    double bytes_all = 0.0;    // and their algorithmic bytes
 };
 
 // accumulators shared by the lists of a batch engine
@@ -388,6 +390,7 @@ class Batch {
     void prof_begin(int kernel, hipEvent_t *pair);
     void prof_end(int kernel, hipEvent_t *pair, double bytes = 0.0);
     void prof_collect();
+    void prof_totals(int kernel, int64_t launches, double bytes);  // every launch, not only the timed ones
 };
 
 // launch `kernel` over phase `kind` of batch b with `bs` threads per block;

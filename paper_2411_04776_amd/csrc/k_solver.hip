@@ -1275,11 +1275,28 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     };
     int chunk = last > 16 ? next_chunk(tn.pcg_first_chunk) : 8;
     int early = 0;
+    // every launch of a chunk, with the algorithmic bytes of the scenes whose
+    // solve was running there (when profiling)
+    auto account_chunk = [&](int it0, int it1) {
+        if (!b.prof()) return;
+        double ba = 0.0, bb = 0.0;
+        for (int j = it0; j < it1; ++j)
+            for (size_t i = 0; i < ns; ++i) {
+                if (nab[i] == 0) continue;
+                if (!b.h_out[i].pcg_done || j <= b.h_out[i].pcg_iters) {
+                    ba += scene_bytes[i];
+                    bb += scene_bytes_b[i];
+                }
+            }
+        b.prof_totals(kProfPcgA, it1 - it0, ba);
+        b.prof_totals(kProfPcgB, it1 - it0, bb);
+    };
     hipEvent_t ev[2];
     // launch it = maxit + 1 too: its A kernel records the cap of the scenes
     // that did not converge
     while (it <= maxit + 1) {
         int c = std::min(chunk, maxit + 2 - it);
+        const int it_chunk = it;
         for (int j = 0; j < c; ++j, ++it) {
             // time one launch in sixteen when profiling: iterations 2, 18, 34, ...
             // of the first chunk (the first iteration applies the matrix to one
@@ -1310,6 +1327,7 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
         run_pinf(b);  // |p|_inf of the scenes done so far comes back with their flags
         b.read_out();
         settle_bytes();
+        account_chunk(it_chunk, it);
         b.prof_collect();
         bool all = true;
         for (size_t i = 0; i < ns; ++i)

@@ -1091,6 +1091,23 @@ void Batch::prof_end(int kernel, hipEvent_t *pair, double bytes)
     ev_pending.push_back({kernel, pair[0], pair[1], bytes});
 }
 
+void Batch::prof_totals(int kernel, int64_t launches, double bytes)
+{
+    if (!prof()) return;
+    ProfAcc *acc = nullptr;
+    std::unique_lock<std::mutex> lk;
+    if (sink) {
+        lk = std::unique_lock<std::mutex>(sink->mu);
+        acc = &sink->acc[kernel];
+    } else if (!sc.empty()) {
+        acc = &sc[0]->prof_acc[kernel];
+    }
+    if (acc) {
+        acc->launches_all += launches;
+        acc->bytes_all += bytes;
+    }
+}
+
 void Batch::prof_collect()
 {
     if (ev_pending.empty()) return;
@@ -2332,6 +2349,15 @@ int32_t ipc_batch_profile(ipc_batch *b, int32_t enable)
     return IPC_OK;
 }
 
+int32_t ipc_batch_profile_totals(ipc_batch *b, int32_t kernel, int64_t *launches, double *bytes_total)
+{
+    if (!b || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(b->prof.mu);
+    if (launches) *launches = b->prof.acc[kernel].launches_all;
+    if (bytes_total) *bytes_total = b->prof.acc[kernel].bytes_all;
+    return IPC_OK;
+}
+
 int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total, double *bytes_total)
 {
     if (!b || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
@@ -2589,6 +2615,14 @@ int32_t ipcx_profile_read(const ipc_scene *s, int32_t kernel, int64_t *launches,
     if (!s || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
     if (launches) *launches = s->prof_acc[kernel].launches;
     if (ms_total) *ms_total = s->prof_acc[kernel].ms;
+    return IPC_OK;
+}
+
+int32_t ipcx_profile_totals(const ipc_scene *s, int32_t kernel, int64_t *launches, double *bytes_total)
+{
+    if (!s || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    if (launches) *launches = s->prof_acc[kernel].launches_all;
+    if (bytes_total) *bytes_total = s->prof_acc[kernel].bytes_all;
     return IPC_OK;
 }
 

@@ -117,6 +117,7 @@ _SIGS = {
     "ipc_batch_wait": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(ipc_step_stats)]),
     "ipc_batch_next": (C.c_int32, [C.c_void_p, C.c_double, _I64, _I, C.POINTER(ipc_step_stats)]),
     "ipc_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "ipc_batch_profile_totals": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipc_batch_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D, _D]),
     "ipc_status_str": (C.c_char_p, [C.c_int32]),
     "ipc_last_error": (C.c_int32, [C.c_char_p, C.c_size_t]),
@@ -132,6 +133,7 @@ _SIGS = {
     "ipcx_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "ipcx_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipcx_profile_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _D]),
+    "ipcx_profile_totals": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipcx_tuning": (C.c_int32, [C.c_void_p, _D]),
     "ipcx_tuning_for": (C.c_int32, [C.c_int32, _D]),
     "ipcx_matrix_info": (C.c_int32, [C.c_void_p, _I64]),
@@ -521,6 +523,14 @@ class GelScene:
             out[name] = (n.value, ms.value)
         return out
 
+    def profile_totals(self, kernel):
+        """(launches, summed algorithmic bytes) of every launch of PCG class
+        0 or 1 while profiling was on."""
+        n = C.c_int64()
+        by = C.c_double()
+        _check(lib().ipcx_profile_totals(self.ptr, int(kernel), C.byref(n), C.byref(by)), "ipcx_profile_totals")
+        return n.value, by.value
+
     def profile_bytes(self, kernel):
         """Summed algorithmic bytes of the timed launches of PCG kernel class
         0 (SpMV) or 1 (update)."""
@@ -647,6 +657,15 @@ class Batch:
 
     def profile(self, enable=True):
         _check(lib().ipc_batch_profile(self.ptr, int(bool(enable))), "ipc_batch_profile")
+
+    def profile_totals(self, kernel):
+        """(launches, summed algorithmic bytes) of every launch of PCG class
+        0 or 1 while profiling was on."""
+        n = np.zeros(1, dtype=np.int64)
+        by = np.zeros(1)
+        _check(lib().ipc_batch_profile_totals(self.ptr, int(kernel), n.ctypes.data_as(_I64), _d(by)),
+               "ipc_batch_profile_totals")
+        return int(n[0]), float(by[0])
 
     def profile_read(self, kernel):
         """(timed launches, summed ms, summed algorithmic bytes) of a kernel class."""

@@ -1,0 +1,124 @@
+"""Summaries of rocprofv3 output (csv) in the form kept under profiles/.
+
+  python -m paper_2411_04776_amd.profsum trace --dir D --command CMD --out F
+      kernel-trace statistics: per kernel launches, total, mean and median
+      duration, share of kernel time.
+  python -m paper_2411_04776_amd.profsum pmc --fetch D1 --write D2 --copy-fetch D3 --copy-write D4
+         --json J --leg LEG --kernel NAME --commands C1 C2 C3 C4 --out F
+      HBM traffic of one kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch) summed over every dispatch of the kernel, each scaled by what
+      the same counter reads for a device copy of known size, against the
+      algorithmic bytes the library counted for the same launches
+      (bench.py's JSON line of the same command: roofline.all_launches).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PCG_SOURCES = ("paper_2411_04776_amd/csrc/k_solver.hip", "paper_2411_04776_amd/csrc/incidence.h",
+               "paper_2411_04776_amd/csrc/device_util.h", "paper_2411_04776_amd/csrc/ipc_internal.h")
+
+
+def source_hash(files=PCG_SOURCES):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _rows(d, suffix):
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f) as fh:
+            yield from csv.DictReader(fh)
+
+
+def counter(d, name, kernel_substr):
+    vals = [float(r["Counter_Value"]) for r in _rows(d, "counter_collection.csv")
+            if r.get("Counter_Name") == name and kernel_substr in r["Kernel_Name"]]
+    return vals
+
+
+def trace(args):
+    per = {}
+    for r in _rows(args.dir, "kernel_trace.csv"):
+        per.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tot = sum(sum(v) for v in per.values())
+    lines = [f"# Kernel time: {args.title}", "", "Command (repository root, MI355X):", "```", args.command, "```", "",
+             f"Total kernel time {tot / 1e3:.1f} ms over {sum(len(v) for v in per.values())} dispatches.", "",
+             "| kernel | launches | total ms | share | mean us | median us |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:args.top]:
+        name = k.split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {len(v)} | {sum(v) / 1e3:.2f} | {100 * sum(v) / tot:.1f} % | "
+                     f"{statistics.mean(v):.2f} | {statistics.median(v):.2f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def pmc(args):
+    cf = counter(args.copy_fetch, "FETCH_SIZE", "copyBuffer")
+    cw = counter(args.copy_write, "WRITE_SIZE", "copyBuffer")
+    copy_kib = args.copy_mib * 1024.0
+    sf = copy_kib / cf[0]
+    sw = copy_kib / cw[0]
+    f = counter(args.fetch, "FETCH_SIZE", args.kernel + "<")
+    w = counter(args.write, "WRITE_SIZE", args.kernel + "<")
+    line = json.load(open(args.json))
+    leg = line if args.leg == "headline" else line[args.leg]
+    roof = leg["roofline"]
+    k = roof if roof["kernel"].startswith(args.kernel) else roof["other_pcg_kernel"]
+    n_alg = k["all_launches"]["launches"]
+    alg = k["all_launches"]["algorithmic_bytes_per_launch"]
+    tf = sum(f) * 1024.0 * sf
+    tw = sum(w) * 1024.0 * sw
+    per = (tf + tw) / max(len(f), 1)
+    ratio = per / alg if alg else float("nan")
+    lines = [f"# HBM traffic of {args.kernel}: {args.title}", "",
+             "Commands (repository root, MI355X box), one counter per run:", "```", *args.commands, "```", "",
+             f"Calibration: a {args.copy_mib} MiB device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
+             f"{cf[0]:.1f} KiB and WRITE_SIZE = {cw[0]:.1f} KiB, so FETCH_SIZE is scaled by {sf:.4f} and WRITE_SIZE "
+             f"by {sw:.4f}.", "",
+             f"{args.kernel} over {len(f)} dispatches (FETCH run) / {len(w)} (WRITE run): summed FETCH_SIZE "
+             f"{sum(f):.0f} KiB, WRITE_SIZE {sum(w):.0f} KiB; scaled: {tf / 2**20:.1f} MiB read + "
+             f"{tw / 2**20:.1f} MiB written, {per / 2**20:.3f} MiB per dispatch (median FETCH "
+             f"{statistics.median(f):.1f} KiB, WRITE {statistics.median(w):.1f} KiB).", "",
+             f"Algorithmic bytes the library counted for the same launches ({n_alg} launches in the JSON line of the "
+             f"FETCH run): {alg / 2**20:.3f} MiB per launch.", "",
+             f"traffic_bytes_per_launch: {int(per)}",
+             f"traffic_over_algorithmic: {ratio:.3f}",
+             f"kernel_source_sha256: `{source_hash()}`", "",
+             "(the hash covers the PCG kernel sources; bench.py reports `traffic` only while it matches)"]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"{args.kernel}: {per / 2**20:.3f} MiB per dispatch, algorithmic {alg / 2**20:.3f}, ratio {ratio:.3f}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--dir", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--title", default="")
+    t.add_argument("--top", type=int, default=25)
+    t.add_argument("--out", required=True)
+    p = sub.add_parser("pmc")
+    for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--json", "--kernel", "--out"):
+        p.add_argument(a, required=True)
+    p.add_argument("--leg", default="headline")
+    p.add_argument("--copy-mib", type=int, default=256)
+    p.add_argument("--commands", nargs="+", required=True)
+    p.add_argument("--title", default="")
+    args = ap.parse_args()
+    trace(args) if args.what == "trace" else pmc(args)
+
+
+if __name__ == "__main__":
+    main()
