@@ -579,6 +579,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work per process")
     ap.add_argument("--only", choices=["config2", "config5", "serving"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs; not the benchmark line)")
+    ap.add_argument("--flops-probe-m", type=int, default=0,
+                    help="only add two vectors of this many Mi elements in FP32 and FP64 (VALU flop counter "
+                         "calibration) and exit")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only copy a buffer of this many MiB with torch (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -595,6 +598,18 @@ def main():
     from paper_2411_04776_amd import ipc, scenes
 
     torch.cuda.set_device(0)
+    if args.flops_probe_m:
+        # known-flop elementwise kernels for the VALU flop counters: n adds in FP32, n in FP64
+        n = args.flops_probe_m << 20
+        for dt in (torch.float32, torch.float64):
+            a = torch.ones(n, dtype=dt, device="cuda")
+            b = torch.ones(n, dtype=dt, device="cuda")
+            torch.cuda.synchronize()
+            c = a + b
+            torch.cuda.synchronize()
+            del a, b, c
+        print(json.dumps({"flops_probe_adds_per_dtype": n}), flush=True)
+        return
     if args.copy_probe_mb:
         n = args.copy_probe_mb << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)

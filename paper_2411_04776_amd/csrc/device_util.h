@@ -85,6 +85,29 @@ __device__ inline double wave_reduce_partials(const double *partials, int n)
     return __shfl(acc, 0, kWave);
 }
 
+// wave_reduce_partials with eight loads in flight per lane: the same
+// additions in the same order (bit-identical), one memory round trip per
+// 512 partials instead of one per 64 (a scene of 128k vertices has ~2000).
+__device__ inline double wave_reduce_partials_u8(const double *partials, int n)
+{
+    constexpr int kU = 8;
+    int lane = threadIdx.x & (kWave - 1);
+    double acc = 0.0;
+    for (int base = lane; base < n; base += kU * kWave) {
+        double b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            int i = base + u * kWave;
+            b[u] = i < n ? partials[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (base + u * kWave < n) acc += b[u];
+    }
+    acc = wave_sum(acc);
+    return __shfl(acc, 0, kWave);
+}
+
 // The same sum in two parts, for a kernel that can issue the loads before
 // other dependent loads: wave_partials_load fetches a lane's first U entries,
 // wave_partials_sum adds them and the rest (four loads ahead of the adds) in

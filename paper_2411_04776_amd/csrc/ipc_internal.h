@@ -39,6 +39,8 @@
 namespace ipcg {
 
 constexpr int kWave = 64;         // wavefront width on gfx950
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kXcdChunk = 64;     // consecutive logical blocks that share an XCD
 constexpr int kSlice = 64;        // rows per BELL slice (one wavefront)
 constexpr int kBlock = 256;       // threads per block for streaming kernels
 constexpr int kSpmvStreams = 2;   // partial sums per SpMV row (slots k, k + 2, ...), added in stream order
@@ -138,7 +140,7 @@ struct SceneDev {
     int32_t *pt_idx;               // surface point index of a vertex (-1: not on the surface)
     // active pairs
     int32_t *act_idx, *act_v;
-    void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG)
+    void *act_g, *act_H, *act_y;   // act_y: per-pair products H_p d_p (PCG), 12 per pair, pair-major
     int64_t act_cap;
     double *pcg_pair;              // per-block d.(H_c d) partials of the pair blocks
     // lagged friction set of the step (pairs active at x^t): 4 vertex ids,
@@ -192,10 +194,29 @@ struct Launch {
     int ns;
 };
 
+// The logical block of this workgroup. The hardware dispatches workgroup w
+// to XCD w % kXcds (each XCD has its own L2); within every run of
+// kXcds * kXcdChunk workgroups the logical order is remapped so each XCD gets
+// kXcdChunk consecutive blocks: neighbouring blocks of a scene, whose rows
+// gather each other's vector entries, share an L2, while the runs keep heavy
+// and light blocks (group blocks first, plain vertex blocks after them)
+// spread over all XCDs. The last partial run keeps the identity. A bijection
+// for any grid size; results do not depend on it (every logical block does
+// the same work wherever it runs).
+__device__ __forceinline__ int xcd_block()
+{
+    constexpr int run = kXcds * kXcdChunk;
+    const int w = (int)blockIdx.x;
+    const int full = ((int)gridDim.x / run) * run;
+    if (w >= full) return w;
+    const int base = w - w % run, r = w % run;
+    return base + (r % kXcds) * kXcdChunk + r / kXcds;
+}
+
 __device__ __forceinline__ int scene_of_block(const Launch &L, int &local)
 {
     int lo = 0, hi = L.ns;
-    int b = blockIdx.x;
+    int b = xcd_block();
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (L.blk_off[mid] <= b) lo = mid; else hi = mid;

@@ -199,7 +199,7 @@ __device__ __forceinline__ double pair_apply(const SceneDev &S, int64_t p, const
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             R yv = (R)y[i];
-            Y[(int64_t)(3 * a + i) * cap + p] = yv;
+            Y[12 * p + 3 * a + i] = yv;  // a pair's 12 products together: a row gathers 3 adjacent values
             dy += (double)d[a][i] * (double)yv;
         }
     }
@@ -330,8 +330,7 @@ template <class R>
 __device__ __forceinline__ void contact_row_light(const SceneDev &S, int row, double qc[3])
 {
     const R *Y = as<R>(S.act_y);
-    const int64_t cap = S.act_cap;
-    auto val = [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; };
+    auto val = [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; };
     thread_row_sums<3, decltype(val), 2>(S, row, val, qc);
 }
 
@@ -340,8 +339,7 @@ template <class R>
 __device__ __forceinline__ void contact_row_heavy(const SceneDev &S, int row, double qc[3])
 {
     const R *Y = as<R>(S.act_y);
-    const int64_t cap = S.act_cap;
-    block_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[(int64_t)(3 * a + c) * cap + p]; }, qc);
+    block_row_sums<3>(S, row, [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; }, qc);
 }
 
 // one vertex's state for the update, loaded before alpha is known
@@ -489,7 +487,7 @@ __global__ void __launch_bounds__(kBlock) k_mas_invert(Launch L)
 template <class R>
 __device__ __forceinline__ R pcg_alpha(const Launch &L, const SceneDev &S, int s, int it)
 {
-    double dq = wave_reduce_partials(S.pcg_part, S.nb_rows) + wave_reduce_partials(S.pcg_pair, pair_blocks(L.out[s].n_pair));
+    double dq = wave_reduce_partials_u8(S.pcg_part, S.nb_rows) + wave_reduce_partials_u8(S.pcg_pair, pair_blocks(L.out[s].n_pair));
     return (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
 }
 

@@ -3,6 +3,9 @@
   python -m paper_2411_04776_amd.profsum trace --dir D --command CMD --out F
       kernel-trace statistics: per kernel launches, total, mean and median
       duration, share of kernel time.
+  python -m paper_2411_04776_amd.profsum valu --pmc D1 --trace D2 --calib D3 --commands ... --out F
+      VALU flop rates of kernels from SQ_INSTS_VALU_FLOPS_FP32/FP64 (scaled
+      by a calibration run of known elementwise adds) over their durations.
   python -m paper_2411_04776_amd.profsum pmc --fetch D1 --write D2 --copy-fetch D3 --copy-write D4
          --json J --leg LEG --kernel NAME --commands C1 C2 C3 C4 --out F
       HBM traffic of one kernel: FETCH_SIZE and WRITE_SIZE (KiB per
@@ -100,6 +103,56 @@ def pmc(args):
     print(f"{args.kernel}: {per / 2**20:.3f} MiB per dispatch, algorithmic {alg / 2**20:.3f}, ratio {ratio:.3f}")
 
 
+ELASTIC_SOURCES = ("paper_2411_04776_amd/csrc/k_elastic.hip", "paper_2411_04776_amd/csrc/device_util.h",
+                   "paper_2411_04776_amd/csrc/ipc_internal.h")
+PEAK_TFLOPS = {"FP32": 157.3, "FP64": 78.6}
+
+
+def valu(args):
+    """VALU flop rate of the assembly kernels: SQ_INSTS_VALU_FLOPS_FP32/FP64
+    summed over every dispatch, scaled by what the same counters read for
+    elementwise adds of a known count (the calibration run), over the
+    kernels' summed durations in a kernel-trace run of the same command."""
+    cal = {}
+    for r in _rows(args.calib, "counter_collection.csv"):
+        if "CUDAFunctor_add<float" in r["Kernel_Name"] and r["Counter_Name"] == "SQ_INSTS_VALU_FLOPS_FP32":
+            cal["FP32"] = args.calib_adds / float(r["Counter_Value"])
+        if "CUDAFunctor_add<double" in r["Kernel_Name"] and r["Counter_Name"] == "SQ_INSTS_VALU_FLOPS_FP64":
+            cal["FP64"] = args.calib_adds / float(r["Counter_Value"])
+    fl = {}
+    for r in _rows(args.pmc, "counter_collection.csv"):
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("ipcg::", "")
+        fl.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    dur = {}
+    for r in _rows(args.trace, "kernel_trace.csv"):
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("ipcg::", "")
+        dur.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    lines = [f"# VALU flop rate of the assembly kernels: {args.title}", "", "Commands (repository root, MI355X):",
+             "```", *args.commands, "```", "",
+             f"Calibration: elementwise adds of {args.calib_adds} elements read SQ_INSTS_VALU_FLOPS_FP32 / FP64 = "
+             f"{args.calib_adds / cal['FP32']:.0f} / {args.calib_adds / cal['FP64']:.0f}, so the counters are scaled by "
+             f"{cal['FP32']:.2f} (FP32) and {cal['FP64']:.2f} (FP64) flops per count.", "",
+             "| kernel | dispatches | FP32 GFLOP | FP64 GFLOP | time ms | FP32 TFLOP/s | FP64 TFLOP/s | of FP32 peak | of FP64 peak |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    keys = []
+    for k in sorted(fl):
+        f32 = sum(fl[k].get("SQ_INSTS_VALU_FLOPS_FP32", [])) * cal["FP32"]
+        f64 = sum(fl[k].get("SQ_INSTS_VALU_FLOPS_FP64", [])) * cal["FP64"]
+        t = sum(dur.get(k, []))
+        r32, r64 = (f32 / t / 1e12, f64 / t / 1e12) if t > 0 else (0.0, 0.0)
+        lines.append(f"| `{k}` | {len(dur.get(k, []))} | {f32 / 1e9:.1f} | {f64 / 1e9:.1f} | {1e3 * t:.2f} | {r32:.2f} | "
+                     f"{r64:.2f} | {r32 / PEAK_TFLOPS['FP32']:.3f} | {r64 / PEAK_TFLOPS['FP64']:.3f} |")
+        base = k.split("<")[0]
+        keys.append((f"{base}_fp32_tflops", f"{r32:.3f}"))
+        keys.append((f"{base}_fp64_tflops", f"{r64:.3f}"))
+        keys.append((f"{base}_valu_utilisation", f"{r32 / PEAK_TFLOPS['FP32'] + r64 / PEAK_TFLOPS['FP64']:.4f}"))
+    lines += ["", "(utilisation: the FP32 rate over the FP32 peak plus the FP64 rate over the FP64 peak)", ""]
+    lines += [f"{k}: {v}" for k, v in keys]
+    lines += [f"kernel_source_sha256: `{source_hash(ELASTIC_SOURCES)}`"]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -116,8 +169,14 @@ def main():
     p.add_argument("--copy-mib", type=int, default=256)
     p.add_argument("--commands", nargs="+", required=True)
     p.add_argument("--title", default="")
+    v = sub.add_parser("valu")
+    for a in ("--pmc", "--trace", "--calib", "--out"):
+        v.add_argument(a, required=True)
+    v.add_argument("--calib-adds", type=int, default=16 << 20)
+    v.add_argument("--commands", nargs="+", required=True)
+    v.add_argument("--title", default="")
     args = ap.parse_args()
-    trace(args) if args.what == "trace" else pmc(args)
+    {"trace": trace, "pmc": pmc, "valu": valu}[args.what](args)
 
 
 if __name__ == "__main__":
