@@ -558,9 +558,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed list steps before the reset to rest")
     ap.add_argument("--batch", type=int, default=256, help="scenes of the headline list")
     ap.add_argument("--seed", type=int, default=0, help="config-2 seed")
-    # PCG tolerance of the timed runs: the loosest that keeps the final error far
-    # inside 1e-4 L (checked in the line itself: fixed_error)
-    ap.add_argument("--pcg-tol", type=float, default=1e-3)
+    # PCG tolerance of the timed runs: the loosest that keeps the final error
+    # inside 1e-4 L on every scene checked against the oracle (the 16 sampled
+    # config-3 scenes: 3.4e-5 L; config-2 seeds 0, 1, 3, 4: at most 5.6e-5 L;
+    # 1e-3 let config-2 seed 3 end 6.1e-4 L away); checked in the line itself
+    ap.add_argument("--pcg-tol", type=float, default=1e-4)
     ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel")
     ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected")
     ap.add_argument("--no-per-scene", action="store_true", help="skip the one-at-a-time runs of the 16 sampled scenes")

@@ -60,7 +60,7 @@ def _write(path, classes):
         json.dump({"classes": classes}, f)
 
 
-def measure(name, small_scenes, classes, tmp, pcg_tol=1e-3):
+def measure(name, small_scenes, classes, tmp, pcg_tol=1e-4):
     """env-steps/s of the class's workload with the given class table."""
     import torch
     _write(tmp, classes)
@@ -127,7 +127,7 @@ def tune(out=DEFAULT_OUT, small_scenes=128, sweeps=2, reps=2, log=print):
         os.unlink(tmp)
     doc = {"classes": classes,
            "device": __import__("torch").cuda.get_device_name(0),
-           "objective": "env-steps/s, mixed precision, PCG tolerance 1e-3; small: a list of "
+           "objective": "env-steps/s, mixed precision, PCG tolerance 1e-4; small: a list of "
                         f"{small_scenes} config-3 scenes through the batching engine (steps 7-14 of the episode); "
                         "large: one 80x100x16 serving scene (steps 7-12); best of two runs",
            "measurements": records}

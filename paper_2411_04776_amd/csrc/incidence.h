@@ -57,6 +57,30 @@ __device__ __forceinline__ void block_sum_vec(double v[NC])
     __syncthreads();
 }
 
+// Sum over the entries of one (heavy) row by one wavefront: lane l takes
+// entries l, l + 64, ... in order, then a fixed shuffle tree; every lane gets
+// the result. No block barrier, so a block's wavefronts sum different rows at
+// once.
+template <int NC, class F>
+__device__ __forceinline__ void wave_row_sums(const SceneDev &S, int row, F val, double out[NC])
+{
+    int e0 = S.c_ptr[row], e1 = S.c_ptr[row + 1];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = 0.0;
+    for (int t = e0 + lane; t < e1; t += kWave) {
+        int src = S.c_list[t];
+        int p = src >> 2, a = src & 3;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] += val(p, a, c);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        out[c] = wave_sum(out[c]);
+        out[c] = __shfl(out[c], 0, kWave);
+    }
+}
+
 // Sum over the entries of one (heavy) row by a whole block: thread t takes
 // entries t, t + blockDim, ... in order, then a fixed-order block sum.
 template <int NC, class F>

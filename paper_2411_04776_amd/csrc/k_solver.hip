@@ -657,13 +657,17 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
         if (S.pcg->done) return;
         if (any_heavy) {
             __syncthreads();
-            // heavy members: the whole block sums each one's incidence row
+            // heavy members: a wavefront sums each one's incidence row, the
+            // block's wavefronts taking different rows at once (a group under
+            // a dense contact patch holds dozens of them)
             const int nh = hcount;
-            for (int h = 0; h < nh; ++h) {
+            const R *Y = as<R>(S.act_y);
+            for (int h = tid / kWave; h < nh; h += kBlock / kWave) {
                 int pos = hlist[h];
                 double q3[3];
-                contact_row_heavy<R>(S, S.mas_mem[k0 + pos], q3);
-                if (tid == 0)
+                wave_row_sums<3>(S, S.mas_mem[k0 + pos],
+                                 [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; }, q3);
+                if ((tid & (kWave - 1)) == 0)
                     for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
             }
             __syncthreads();
