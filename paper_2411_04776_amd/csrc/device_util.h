@@ -10,6 +10,20 @@
 
 namespace ipcg {
 
+// Global-memory views of device pointers. The arrays of a scene's view are
+// reached through generic pointers, so plain accesses compile to flat
+// instructions, which also count against the LDS counter: every LDS wait and
+// block barrier after them waits for them too. Through these views they are
+// global loads and stores, which the latency-bound PCG update kernel keeps in
+// flight across its LDS work and barriers.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> glob(T *p)
+{
+    return (gptr<T>)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);

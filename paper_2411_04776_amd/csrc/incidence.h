@@ -81,6 +81,79 @@ __device__ __forceinline__ void wave_row_sums(const SceneDev &S, int row, F val,
     }
 }
 
+// Rows of more than kRowInline entries are listed by their owner thread and
+// summed by teams of kTeam lanes: team t of the block takes the listed rows
+// t, t + teams, ...; lane u of a team adds the row's entries e0 + u,
+// e0 + u + kTeam, ... in order (four entries' loads in flight per pass), then
+// a fixed xor tree over the team's lanes (every lane of the team ends with the
+// same value: the adds commute). A dense contact patch gives rows of 10-50
+// entries; one thread would walk them one dependent load pair at a time.
+constexpr int kRowInline = 2;
+constexpr int kTeam = 8;
+static_assert(kTeam == 8 && kBlock % kTeam == 0, "the team sum is an xor tree over eight lanes");
+
+struct RowList {
+    int32_t e0[kMasCapM], e1[kMasCapM], dst[kMasCapM];
+    int32_t count;
+};
+
+// Light row: at most kRowInline entries summed by the calling thread (loads
+// issued together), or else listed for the teams. Returns true if listed.
+template <class F>
+__device__ __forceinline__ bool row_sum_or_list(const SceneDev &S, int row, int dst, F val, double out[3], RowList &rl)
+{
+    const auto cp = glob(S.c_ptr);
+    const auto cl = glob(S.c_list);
+    const int e0 = cp[row], e1 = cp[row + 1];
+    if (e1 - e0 > kRowInline) {
+        int slot = atomicAdd(&rl.count, 1);
+        rl.e0[slot] = e0;
+        rl.e1[slot] = e1;
+        rl.dst[slot] = dst;
+        return true;
+    }
+    int src[kRowInline];
+#pragma unroll
+    for (int k = 0; k < kRowInline; ++k) src[k] = e0 + k < e1 ? cl[e0 + k] : -1;
+#pragma unroll
+    for (int k = 0; k < kRowInline; ++k)
+        if (src[k] >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[c] += val(src[k] >> 2, src[k] & 3, c);
+    return false;
+}
+
+// The teams' pass over a block's list (between two block barriers); put(dst,
+// sums) runs on each team's first lane.
+template <class F, class P>
+__device__ __forceinline__ void team_row_sums(const SceneDev &S, const RowList &rl, F val, P put)
+{
+    const int tid = (int)threadIdx.x, u = tid % kTeam, teams = (int)blockDim.x / kTeam;
+    const int n = rl.count;
+    const auto cl = glob(S.c_list);
+    for (int h = tid / kTeam; h < n; h += teams) {
+        const int e0 = rl.e0[h], e1 = rl.e1[h];
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int base = e0 + u; base < e1; base += 4 * kTeam) {
+            int src[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) src[k] = base + k * kTeam < e1 ? cl[base + k * kTeam] : -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (src[k] >= 0)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += val(src[k] >> 2, src[k] & 3, c);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] += __shfl_xor(acc[c], 4, kTeam);
+            acc[c] += __shfl_xor(acc[c], 2, kTeam);
+            acc[c] += __shfl_xor(acc[c], 1, kTeam);
+        }
+        if (u == 0) put(rl.dst[h], acc);
+    }
+}
+
 // Sum over the entries of one (heavy) row by a whole block: thread t takes
 // entries t, t + blockDim, ... in order, then a fixed-order block sum.
 template <int NC, class F>

@@ -351,10 +351,11 @@ struct VertexPcg {
 template <class R>
 __device__ __forceinline__ void pcg_vertex_load(const SceneDev &S, int i, const R *dcur, VertexPcg<R> &v)
 {
-    const R *q = as<R>(S.q), *Mi = as<R>(S.Minv), *sol = as<R>(S.sol), *r = as<R>(S.r);
+    const auto q = glob(as<R>(S.q)), Mi = glob(as<R>(S.Minv)), sol = glob(as<R>(S.sol)), r = glob(as<R>(S.r));
+    const auto dc = glob(dcur);
     for (int c = 0; c < 3; ++c) {
         v.q[c] = q[3 * i + c];
-        v.d[c] = dcur[3 * i + c];
+        v.d[c] = dc[3 * i + c];
         v.p[c] = sol[3 * i + c];
         v.r[c] = r[3 * i + c];
     }
@@ -366,7 +367,7 @@ template <class R>
 __device__ __forceinline__ double pcg_vertex_update(const SceneDev &S, int i, R alpha, const VertexPcg<R> &v,
                                                     const double qc[3])
 {
-    R *sol = as<R>(S.sol), *r = as<R>(S.r), *z = as<R>(S.z);
+    const auto sol = glob(as<R>(S.sol)), r = glob(as<R>(S.r)), z = glob(as<R>(S.z));
     R ri[3];
     for (int c = 0; c < 3; ++c) {
         R qv = (R)((double)v.q[c] + qc[c]);
@@ -435,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_mas_diag(Launch L)
 // group's level-l aggregate range [a0, a1) (level-local ids); l = -1: members
 __device__ __forceinline__ void mas_group_range(const SceneDev &S, int grp, int l, int &a0, int &a1)
 {
-    const int32_t *row = S.mas_gofs + (size_t)(l + 1) * (S.mas_ng + 1);
+    const auto row = glob(S.mas_gofs) + (size_t)(l + 1) * (S.mas_ng + 1);
     a0 = row[grp];
     a1 = row[grp + 1];
 }
@@ -483,12 +484,64 @@ __global__ void __launch_bounds__(kBlock) k_mas_invert(Launch L)
 // the aggregate corrections) and its r.z partial. B(0) starts the solve
 // from p = 0, r = -g instead.
 
-// alpha = r.z / d.q for iteration it (every lane of the wavefront takes part)
-template <class R>
-__device__ __forceinline__ R pcg_alpha(const Launch &L, const SceneDev &S, int s, int it)
+// alpha = r.z / d.q for iteration it, d.q from the A launch's partials (its
+// SpMV blocks, then its pair blocks) summed by the whole block: thread t adds
+// partials t, t + 256, ... in order, a wavefront tree, then the wavefronts in
+// order, so every block of the scene forms the same value. dq_issue loads a
+// thread's first partials, the scene's done flag and r.z of iteration it - 1
+// before the block's vertex loads; dq_stage adds them (and any rest) after
+// those and leaves the wavefront sums in LDS; dq_alpha, after a block
+// barrier, forms alpha.
+constexpr int kDqU = 8;   // SpMV-block partials per thread in flight (2048: a scene of 131k vertices)
+constexpr int kDqUP = 2;  // pair-block partials per thread in flight
+struct DqIssue {
+    double part[kDqU], pair[kDqUP];
+    double rz;
+    int done;
+};
+
+__device__ __forceinline__ void dq_issue(const Launch &L, const SceneDev &S, int s, int it, DqIssue &q)
 {
-    double dq = wave_reduce_partials_u8(S.pcg_part, S.nb_rows) + wave_reduce_partials_u8(S.pcg_pair, pair_blocks(L.out[s].n_pair));
-    return (R)(S.pcg->rzv[it & 1] / dq);  // r.z of iteration it - 1, stored by A(it)
+    const int t = (int)threadIdx.x, npart = S.nb_rows, npair = pair_blocks(L.out[s].n_pair);
+#pragma unroll
+    for (int u = 0; u < kDqU; ++u) q.part[u] = t + u * kBlock < npart ? glob(S.pcg_part)[t + u * kBlock] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kDqUP; ++u) q.pair[u] = t + u * kBlock < npair ? glob(S.pcg_pair)[t + u * kBlock] : 0.0;
+    q.rz = glob(S.pcg)->rzv[it & 1];  // stored by A(it)
+    q.done = glob(S.pcg)->done;
+}
+
+__device__ __forceinline__ void dq_stage(const Launch &L, const SceneDev &S, int s, const DqIssue &q,
+                                         double (&sh)[kBlock / kWave][2])
+{
+    const int t = (int)threadIdx.x, npart = S.nb_rows, npair = pair_blocks(L.out[s].n_pair);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDqU; ++u)
+        if (t + u * kBlock < npart) a += q.part[u];
+    for (int i = t + kDqU * kBlock; i < npart; i += kBlock) a += glob(S.pcg_part)[i];
+#pragma unroll
+    for (int u = 0; u < kDqUP; ++u)
+        if (t + u * kBlock < npair) b += q.pair[u];
+    for (int i = t + kDqUP * kBlock; i < npair; i += kBlock) b += glob(S.pcg_pair)[i];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((t & (kWave - 1)) == 0) {
+        sh[t / kWave][0] = a;
+        sh[t / kWave][1] = b;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ R dq_alpha(const DqIssue &q, const double (&sh)[kBlock / kWave][2])
+{
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        a += sh[w][0];
+        b += sh[w][1];
+    }
+    return (R)(q.rz / (a + b));
 }
 
 // start of the solve for vertex i: r = -g, p = 0, z = D^-1 r; returns r.z
@@ -510,8 +563,19 @@ __device__ __forceinline__ double pcg_vertex_start(const SceneDev &S, int i, R z
     return rz;
 }
 
+// LDS of an update block: the group's members' r, contact sums and
+// corrections, the aggregate sums, the list of rows for the teams, and the
+// group's level ranges (block-uniform; read in the level loop)
+struct BShared {
+    double rm[kMasCapM][3];
+    double ra[kMasCapA][3];
+    RowList rl;
+    int32_t lv[kMasLevels][4];  // first aggregate, end, LDS base, offset of the level's aggregates
+    double dq[kBlock / kWave][2];
+};
+
 template <class R>
-__device__ void pcg_B_vertices(const Launch &L, const SceneDev &S, int s, int vb, int it, int lb)
+__device__ void pcg_B_vertices(const Launch &L, const SceneDev &S, int s, int vb, int it, int lb, BShared &sh)
 {
     int k = vb * blockDim.x + threadIdx.x;
     int i = S.mas_levels > 0 ? (k < S.mas_nother ? S.mas_other[k] : -1) : (k < S.n ? k : -1);
@@ -525,23 +589,43 @@ __device__ void pcg_B_vertices(const Launch &L, const SceneDev &S, int s, int vb
         }
     } else {
         const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
-        bool own = i >= 0 && !S.hflag[i];
+        const auto Y = glob(as<R>(S.act_y));
+        auto yv = [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; };
+        const bool contact = L.out[s].n_pair > 0;  // the same for the whole scene
+        if (contact) {
+            if (threadIdx.x == 0) sh.rl.count = 0;
+            __syncthreads();
+        }
+        DqIssue dqi;
+        dq_issue(L, S, s, it, dqi);
+        bool own = i >= 0 && !glob(S.hflag)[i];  // a heavy row has a block of its own
         VertexPcg<R> v;
         double qc[3] = {0.0, 0.0, 0.0};
+        bool listed = false;
         if (own) {
             pcg_vertex_load<R>(S, i, dcur, v);
-            contact_row_light<R>(S, i, qc);
+            if (contact) listed = row_sum_or_list(S, i, (int)threadIdx.x, yv, qc, sh.rl);
         }
-        if (S.pcg->done) return;
-        R alpha = pcg_alpha<R>(L, S, s, it);
+        if (dqi.done) return;
+        dq_stage(L, S, s, dqi, sh.dq);
+        __syncthreads();
+        if (contact) {
+            team_row_sums(S, sh.rl, yv, [&](int d, const double (&q)[3]) {
+                for (int c = 0; c < 3; ++c) sh.rm[d][c] = q[c];
+            });
+            __syncthreads();
+            if (listed)
+                for (int c = 0; c < 3; ++c) qc[c] = sh.rm[threadIdx.x][c];
+        }
+        R alpha = dq_alpha<R>(dqi, sh.dq);
         if (own) rz = pcg_vertex_update<R>(S, i, alpha, v, qc);
     }
     rz = block_sum_all(rz);
-    if (threadIdx.x == 0) rz_slot(S, it)[lb] = rz;
+    if (threadIdx.x == 0) glob(rz_slot(S, it))[lb] = rz;
 }
 
 template <class R>
-__device__ void pcg_B_heavy(const Launch &L, const SceneDev &S, int s, int j, int it)
+__device__ void pcg_B_heavy(const Launch &L, const SceneDev &S, int s, int j, int it, BShared &sh)
 {
     if (j >= L.out[s].n_heavy) return;
     int row = S.heavy_rows[j];
@@ -551,10 +635,14 @@ __device__ void pcg_B_heavy(const Launch &L, const SceneDev &S, int s, int j, in
         return;
     }
     const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
+    DqIssue dqi;
+    dq_issue(L, S, s, it, dqi);
     double qc[3];
     contact_row_heavy<R>(S, row, qc);
-    if (S.pcg->done) return;
-    R alpha = pcg_alpha<R>(L, S, s, it);
+    if (dqi.done) return;
+    dq_stage(L, S, s, dqi, sh.dq);
+    __syncthreads();
+    R alpha = dq_alpha<R>(dqi, sh.dq);
     if (threadIdx.x == 0) {
         VertexPcg<R> v;
         pcg_vertex_load<R>(S, row, dcur, v);
@@ -581,12 +669,8 @@ constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group b
 // group's index data is loaded at the start, beside the members' vertex data;
 // the aggregates' inverses where they are applied.
 template <class R>
-__device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it)
+__device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it, BShared &sh)
 {
-    __shared__ double rm[kMasCapM][3];  // heavy members' contact sums, the members' r, then the corrections
-    __shared__ double ra[kMasCapA][3];  // aggregate sums of r
-    __shared__ int32_t hlist[kMasCapM];
-    __shared__ int32_t hcount;
     const int nl = S.mas_levels;
     const int tid = (int)threadIdx.x;
     int k0, k1;
@@ -609,10 +693,16 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             int a = a0 + tid;
             if (a < a1) {
                 int64_t g = S.mas_off[l] + a;
-                amb[l] = S.mas_mb[g];
-                ame[l] = S.mas_me[g];
+                amb[l] = glob(S.mas_mb)[g];
+                ame[l] = glob(S.mas_me)[g];
             }
         }
+    }
+    if (tid < kMasLevels) {  // the level loop reads these from LDS (block-uniform)
+        sh.lv[tid][0] = lvl(ga0, tid);
+        sh.lv[tid][1] = lvl(ga1, tid);
+        sh.lv[tid][2] = lvl(gbase, tid);
+        sh.lv[tid][3] = S.mas_off[tid];
     }
     int vid[kMasSlots], loc[kMasSlots][kMasLevels];
     R zo[kMasSlots][3];
@@ -620,10 +710,10 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
 #pragma unroll
     for (int j = 0; j < kMasSlots; ++j) {
         int k = k0 + tid + j * kBlock;
-        vid[j] = k < k1 ? S.mas_mem[k] : -1;
+        vid[j] = k < k1 ? glob(S.mas_mem)[k] : -1;
 #pragma unroll
         for (int l = 0; l < kMasLevels; ++l)
-            loc[j][l] = (vid[j] >= 0 && l < nl) ? gbase[l] + S.mas_manc[(int64_t)l * S.mas_nf + k] - ga0[l] : 0;
+            loc[j][l] = (vid[j] >= 0 && l < nl) ? gbase[l] + glob(S.mas_manc)[(int64_t)l * S.mas_nf + k] - ga0[l] : 0;
     }
     if (it == 0) {
 #pragma unroll
@@ -631,55 +721,48 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             if (vid[j] >= 0) {
                 R ri[3];
                 rz += pcg_vertex_start<R>(S, vid[j], zo[j], ri);
-                for (int c = 0; c < 3; ++c) rm[tid + j * kBlock][c] = (double)ri[c];
+                for (int c = 0; c < 3; ++c) sh.rm[tid + j * kBlock][c] = (double)ri[c];
             }
     } else {
-        const bool any_heavy = L.out[s].n_heavy > 0;  // the same for the whole scene
-        if (tid == 0) hcount = 0;
+        const bool contact = L.out[s].n_pair > 0;  // the same for the whole scene
+        const auto Y = glob(as<R>(S.act_y));
+        auto yv = [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; };
+        if (contact) {
+            if (tid == 0) sh.rl.count = 0;
+            __syncthreads();
+        }
+        DqIssue dqi;
+        dq_issue(L, S, s, it, dqi);
         const R *dcur = as<R>((it & 1) ? S.dA : S.dB);
         VertexPcg<R> v[kMasSlots];
         double qc[kMasSlots][3];
-        bool heavy[kMasSlots];
-        if (any_heavy) __syncthreads();
+        bool listed[kMasSlots];
 #pragma unroll
         for (int j = 0; j < kMasSlots; ++j) {
-            heavy[j] = false;
+            listed[j] = false;
             qc[j][0] = qc[j][1] = qc[j][2] = 0.0;
             if (vid[j] >= 0) {
                 pcg_vertex_load<R>(S, vid[j], dcur, v[j]);
-                heavy[j] = S.hflag[vid[j]] != 0;
-                if (!heavy[j])
-                    contact_row_light<R>(S, vid[j], qc[j]);
-                else
-                    hlist[atomicAdd(&hcount, 1)] = tid + j * kBlock;
+                if (contact) listed[j] = row_sum_or_list(S, vid[j], tid + j * kBlock, yv, qc[j], sh.rl);
             }
         }
-        if (S.pcg->done) return;
-        if (any_heavy) {
-            __syncthreads();
-            // heavy members: a wavefront sums each one's incidence row, the
-            // block's wavefronts taking different rows at once (a group under
-            // a dense contact patch holds dozens of them)
-            const int nh = hcount;
-            const R *Y = as<R>(S.act_y);
-            for (int h = tid / kWave; h < nh; h += kBlock / kWave) {
-                int pos = hlist[h];
-                double q3[3];
-                wave_row_sums<3>(S, S.mas_mem[k0 + pos],
-                                 [&](int p, int a, int c) { return (double)Y[12 * (int64_t)p + 3 * a + c]; }, q3);
-                if ((tid & (kWave - 1)) == 0)
-                    for (int c = 0; c < 3; ++c) rm[pos][c] = q3[c];
-            }
+        if (dqi.done) return;
+        dq_stage(L, S, s, dqi, sh.dq);
+        __syncthreads();
+        if (contact) {
+            team_row_sums(S, sh.rl, yv, [&](int d, const double (&q)[3]) {
+                for (int c = 0; c < 3; ++c) sh.rm[d][c] = q[c];
+            });
             __syncthreads();
         }
-        R alpha = pcg_alpha<R>(L, S, s, it);
-        R *sol = as<R>(S.sol), *r = as<R>(S.r);
+        R alpha = dq_alpha<R>(dqi, sh.dq);
+        const auto sol = glob(as<R>(S.sol)), r = glob(as<R>(S.r));
 #pragma unroll
         for (int j = 0; j < kMasSlots; ++j) {
             if (vid[j] < 0) continue;
             int i = vid[j], pos = tid + j * kBlock;
-            if (heavy[j])
-                for (int c = 0; c < 3; ++c) qc[j][c] = rm[pos][c];
+            if (listed[j])
+                for (int c = 0; c < 3; ++c) qc[j][c] = sh.rm[pos][c];
             R ri[3];
             for (int c = 0; c < 3; ++c) {
                 R qv = (R)((double)v[j].q[c] + qc[j][c]);
@@ -691,7 +774,7 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                 zo[j][a] = v[j].M[3 * a] * ri[0] + v[j].M[3 * a + 1] * ri[1] + v[j].M[3 * a + 2] * ri[2];
                 rz += (double)ri[a] * (double)zo[j][a];
             }
-            for (int c = 0; c < 3; ++c) rm[pos][c] = (double)ri[c];
+            for (int c = 0; c < 3; ++c) sh.rm[pos][c] = (double)ri[c];
         }
     }
     __syncthreads();
@@ -703,24 +786,25 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
         if (l > nl) break;
         if (l > 0) {
             const int pl = l - 1;
-            const int g0 = lvl(ga0, pl), g1 = lvl(ga1, pl), gb = lvl(gbase, pl);
+            const int g0 = sh.lv[pl][0], g1 = sh.lv[pl][1], gb = sh.lv[pl][2];
             for (int a = g0 + tid; a < g1; a += kBlock) {
                 int lc = gb + a - g0;
                 R D[9];
+                const int64_t g = (int64_t)sh.lv[pl][3] + a;
 #pragma unroll
-                for (int c = 0; c < 9; ++c) D[c] = Di[9 * ((int64_t)S.mas_off[pl] + a) + c];
-                R sa[3] = {(R)ra[lc][0], (R)ra[lc][1], (R)ra[lc][2]};
+                for (int c = 0; c < 9; ++c) D[c] = glob(Di)[9 * g + c];
+                R sa[3] = {(R)sh.ra[lc][0], (R)sh.ra[lc][1], (R)sh.ra[lc][2]};
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     R e = D[3 * q] * sa[0] + D[3 * q + 1] * sa[1] + D[3 * q + 2] * sa[2];
-                    rm[lc][q] = (double)e;
-                    rz += ra[lc][q] * (double)e;
+                    sh.rm[lc][q] = (double)e;
+                    rz += sh.ra[lc][q] * (double)e;
                 }
             }
         }
         if (l < nl) {
-            const int g0 = lvl(ga0, l), g1 = lvl(ga1, l), gb = lvl(gbase, l);
-            const int c0 = l > 0 ? lvl(ga0, l - 1) : 0, cb = l > 0 ? lvl(gbase, l - 1) : 0;
+            const int g0 = sh.lv[l][0], g1 = sh.lv[l][1], gb = sh.lv[l][2];
+            const int c0 = l > 0 ? sh.lv[l - 1][0] : 0, cb = l > 0 ? sh.lv[l - 1][2] : 0;
             for (int a = g0 + tid; a < g1; a += kBlock) {
                 int j0, j1;
                 if (a == g0 + tid) {
@@ -728,23 +812,23 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
                     j1 = lvl(ame, l);
                 } else {
                     int64_t g = S.mas_off[l] + a;
-                    j0 = S.mas_mb[g];
-                    j1 = S.mas_me[g];
+                    j0 = glob(S.mas_mb)[g];
+                    j1 = glob(S.mas_me)[g];
                 }
                 double acc[3] = {0.0, 0.0, 0.0};
                 for (int j = j0; j < j1; ++j) {
-                    const double *src = l == 0 ? rm[j - k0] : ra[cb + j - c0];
+                    const double *src = l == 0 ? sh.rm[j - k0] : sh.ra[cb + j - c0];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) acc[c] += src[c];
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ra[gb + a - g0][c] = acc[c];
+                for (int c = 0; c < 3; ++c) sh.ra[gb + a - g0][c] = acc[c];
             }
         }
         __syncthreads();
     }
     // prolongation: z = D^-1 r + the corrections of the member's aggregates
-    R *z = as<R>(S.z);
+    const auto z = glob(as<R>(S.z));
 #pragma unroll
     for (int j = 0; j < kMasSlots; ++j) {
         if (vid[j] < 0) continue;
@@ -753,13 +837,13 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
         for (int l = 0; l < kMasLevels; ++l) {
             if (l >= nl) break;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) zi[c] += rm[loc[j][l]][c];
+            for (int c = 0; c < 3; ++c) zi[c] += sh.rm[loc[j][l]][c];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) z[3 * vid[j] + c] = (R)zi[c];
     }
     rz = block_sum_all(rz);
-    if (tid == 0) rz_slot(S, it)[grp] = rz;
+    if (tid == 0) glob(rz_slot(S, it))[grp] = rz;
 }
 
 template <class R>
@@ -775,13 +859,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_B(Launch L, int it, int early)
         L.out[s].pcg_done = 0;
         L.out[s].pcg_iters = 0;
     }
+    __shared__ BShared sh;
     const int ngrp = S.mas_levels > 0 ? S.mas_ng : 0;
     if (lb < ngrp)
-        pcg_B_group<R>(L, S, s, lb, it);
+        pcg_B_group<R>(L, S, s, lb, it, sh);
     else if (lb < S.pcg_nvp)
-        pcg_B_vertices<R>(L, S, s, lb - ngrp, it, lb);
+        pcg_B_vertices<R>(L, S, s, lb - ngrp, it, lb, sh);
     else
-        pcg_B_heavy<R>(L, S, s, lb - S.pcg_nvp, it);
+        pcg_B_heavy<R>(L, S, s, lb - S.pcg_nvp, it, sh);
 }
 
 // y = H v for the test hook (v in S.dB, y in S.q), in the PCG's three parts:
