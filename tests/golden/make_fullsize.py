@@ -9,6 +9,11 @@ oracle's, at PCG tolerance 1e-12 (the parity setting).
             rounded to float32 offsets: that rounded state is the input) and
             the oracle's first two Newton iterates of step 26 from it.
             About 2-3 h per seed on one core.
+  c2gn SEED the same trajectory with the Gauss-Newton pair barrier Hessian
+            (the oracle's barrier_hessian = 1): c2_seed{SEED}_gn_final.npz.
+            Newton stops where the direction of that form is small, so its
+            path through the non-convex steps is its own: the GPU's
+            Gauss-Newton form is held to this trajectory.
   c3 I      scene I of the 256-scene uneven batch (seed 1000 + I), all 20
             steps: c3_{I}_final.npz = gel positions after step 20.
   c5        config 5 (80x100x16 gel, sphere r = 8 mm, friction mu = 0.5):
@@ -77,16 +82,16 @@ def iterates(sc, x0, v0, step, count, **kw):
     return xs
 
 
-def c2(seed):
+def c2(seed, gn=False):
     sc = S.config2(seed)
-    o = O.OracleScene(sc, pcg_tol=1e-12)
+    o = O.OracleScene(sc, pcg_tol=1e-12, barrier_hessian=1 if gn else 0)
     t0 = time.time()
     n = len(sc.X)
     for k in range(1, sc.n_steps + 1):
         rc, st = o.step(sc.poses[k])
         log(f"c2 seed {seed} step {k}: rc={rc} newton={st.newton_iters} pcg={st.pcg_iters} "
             f"active={st.n_active} ({time.time() - t0:.0f} s)")
-        if k == 25 and seed in (0, 1, 2):
+        if k == 25 and seed in (0, 1, 2) and not gn:
             ref = rest_all(sc, 25)
             dx = f32_offset(o.x, ref)
             dv = o.v.astype(np.float32)
@@ -96,7 +101,8 @@ def c2(seed):
             np.savez_compressed(os.path.join(HERE, f"c2_seed{seed}_tf.npz"), step=26, dx=dx, dv=dv,
                                 it1=f32_offset(xs[1], xs[0]), it2=f32_offset(xs[2], xs[1]),
                                 L=sc.bbox_diag, name=sc.name)
-    np.savez_compressed(os.path.join(HERE, f"c2_seed{seed}_final.npz"), steps=sc.n_steps,
+    name = f"c2_seed{seed}_gn_final.npz" if gn else f"c2_seed{seed}_final.npz"
+    np.savez_compressed(os.path.join(HERE, name), steps=sc.n_steps,
                         dx=f32_offset(o.x[:n], sc.X), L=sc.bbox_diag, name=sc.name)
 
 
@@ -155,6 +161,8 @@ if __name__ == "__main__":
     what = sys.argv[1]
     if what == "c2":
         c2(int(sys.argv[2]))
+    elif what == "c2gn":
+        c2(int(sys.argv[2]), gn=True)
     elif what == "c3":
         c3(int(sys.argv[2]))
     elif what == "c5":

@@ -7,7 +7,14 @@ form, with either preconditioner and with the Gauss-Newton barrier Hessian;
 seeds 1-5 (cube edge, bumpy plate, ...) in FP64 and mixed. (At tolerance
 1e-3 seed 3 ends 6.1e-4 L away at a vertex beside the contact edge, where
 the barrier is soft: the looser solves take the trajectory elsewhere; seed 0
-stays at 8e-6 L, recorded here as a form of its own.)"""
+stays at 3.0e-5 L, recorded here as a form of its own.)
+
+The Gauss-Newton form is held to the oracle's trajectory in the same form
+(c2_seed0_gn_final.npz): its Newton stop test reads that form's direction,
+so it leaves each non-convex step at its own point. Against the projected
+oracle it ends 1.1e-4 L away at a vertex on the cylinder's edge, and a
+tighter Newton tolerance moves it further (4e-4 L at a quarter): it does
+not converge toward the projected form's path."""
 import os
 import sys
 
@@ -34,16 +41,17 @@ def ipc():
     return I
 
 
-def golden(seed):
-    path = os.path.join(GOLDEN, f"c2_seed{seed}_final.npz")
+def golden(seed, gn=False):
+    name = f"c2_seed{seed}_gn_final.npz" if gn else f"c2_seed{seed}_final.npz"
+    path = os.path.join(GOLDEN, name)
     if not os.path.exists(path):
-        pytest.skip(f"c2_seed{seed}_final.npz not generated")
+        pytest.skip(f"{name} not generated")
     z = np.load(path)
     return z["dx"].astype(np.float64), float(z["L"])
 
 
 def run(ipc, seed, form):
-    dx, L = golden(seed)
+    dx, L = golden(seed, gn=form == "fp64-gauss-newton")
     sc = S.config2(seed)
     ref = sc.X + dx
     kw = dict(pcg_tol=1e-3 if form == "fp64-tol1e-3" else 1e-4)
