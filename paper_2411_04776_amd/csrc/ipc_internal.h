@@ -102,6 +102,7 @@ struct SceneOut {
 // cast them.
 struct SceneDev {
     int n, n_gel, n_ind, m, n_pts, n_edges, n_tris, n_slices, n_slots, n_surf;
+    int n_gel_tris, n_gel_edges;  // surface primitives of the gel come first (then the indenter's)
     int self_contact, ccd_max_iter, precision, nb_vert, nb_rows, pcg_maxit;
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
     double mu_fric, eps_fric;  // friction coefficient, smoothing length eps_v h

@@ -275,9 +275,15 @@ __global__ void k_cell_size(Launch one)
 }
 
 __device__ __forceinline__ int cell_of(double v, double h) { return (int)floor(v / h); }
-__device__ __forceinline__ uint32_t cell_hash(int ix, int iy, int iz, uint32_t mask)
+// Bucket of a cell's entries of one body (0: the gel, 1: the indenter): a
+// primitive looks only in the buckets of the bodies it can pair with (the
+// indenter never with itself, the gel with itself only under self-contact),
+// so a gel primitive away from the indenter scans empty buckets instead of
+// its own mesh neighbours.
+__device__ __forceinline__ uint32_t cell_hash(int ix, int iy, int iz, int body, uint32_t mask)
 {
-    return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
+    return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u) ^
+            (body ? 0x5bd1e995u : 0u)) & mask;
 }
 
 // Cells spanned per axis by one box are bounded by this; a larger span means
@@ -315,6 +321,10 @@ __device__ void hash_insert_body(const Launch &L, int s, const SceneDev &S, int 
     const double *box = table == 0 ? S.tbox : S.ebox;
     int i = lb * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const int body = i >= (table == 0 ? S.n_gel_tris : S.n_gel_edges) ? 1 : 0;
+    // without self-contact no query looks for a gel edge: a gel edge pairs
+    // with indenter edges only, found from the gel side (a < b)
+    if (table == 1 && body == 0 && !S.self_contact) return;
     uint32_t mask = (1u << S.ht_bits[table]) - 1;
     int32_t *counter = S.ht_count[table];
     const int32_t *start = S.ht_start[table];
@@ -334,7 +344,7 @@ __device__ void hash_insert_body(const Launch &L, int s, const SceneDev &S, int 
     for (int iz = lo[2]; iz <= hi[2]; ++iz)
         for (int iy = lo[1]; iy <= hi[1]; ++iy)
             for (int ix = lo[0]; ix <= hi[0]; ++ix) {
-                uint32_t bkt = cell_hash(ix, iy, iz, mask);
+                uint32_t bkt = cell_hash(ix, iy, iz, body, mask);
                 int pos = atomicAdd(&counter[bkt], 1);
                 if (FILL && start[bkt] + pos < cap) entries[start[bkt] + pos] = make_int4(ix, iy, iz, i);
             }
@@ -428,19 +438,35 @@ __device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, in
         for (int j = 0; j < lane; ++j) o += S.q_lane[(int64_t)kLanesQ * qidx + j];
     }
     int count = 0;
+    // bodies whose entries this query scans: a gel point or edge looks at
+    // the indenter's, and at the gel's under self-contact; an indenter point
+    // at the gel's; an indenter edge at none (its pairs with gel edges have
+    // the gel edge first). Lanes split the (body, cell) pairs; the sort below
+    // puts the query's pairs in b order whatever the split.
+    const int b_gel = KIND == 0 ? S.n_gel_tris : S.n_gel_edges;
+    bool scan0 = false, scan1 = false;
+    if (ok) {
+        const bool a_gel = KIND == 0 ? va0 < S.n_gel : qa < S.n_gel_edges;
+        scan0 = a_gel ? S.self_contact != 0 : KIND == 0;
+        scan1 = a_gel;
+    }
     if (ok) {
         const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1, ncz = chi[2] - clo[2] + 1;
         const int64_t ncell = (int64_t)ncx * ncy * ncz;
-        for (int64_t cc = lane; cc < ncell; cc += kLanesQ) {
+        const int64_t c0 = scan0 ? 0 : ncell, c1 = scan1 ? 2 * ncell : ncell;
+        for (int64_t cb = c0 + lane; cb < c1; cb += kLanesQ) {
+            const int body = cb < ncell ? 0 : 1;
+            const int64_t cc = body ? cb - ncell : cb;
             const int ix = clo[0] + (int)(cc % ncx);
             const int64_t t = cc / ncx;
             const int iy = clo[1] + (int)(t % ncy), iz = clo[2] + (int)(t / ncy);
-            uint32_t bkt = cell_hash(ix, iy, iz, mask);
+            uint32_t bkt = cell_hash(ix, iy, iz, body, mask);
             int kend = min(start[bkt + 1], cap);
             for (int k = start[bkt]; k < kend; ++k) {
                 int4 en = entries[k];
                 if (en.x != ix || en.y != iy || en.z != iz) continue;
                 int b = en.w;
+                if ((b >= b_gel) != (body == 1)) continue;  // another body's entry in this bucket
                 if (KIND == 1 && b <= qa) continue;
                 // box test first: most bucket entries fail it, and it
                 // needs no index loads

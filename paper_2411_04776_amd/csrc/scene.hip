@@ -696,6 +696,8 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     s.h.n_tris = (int)(gtris.size() + itris.size());
     n_gel_edges = (int)gedges.size();
     s.h.n_edges = (int)(gedges.size() + iedges.size());
+    s.h.n_gel_tris = n_gel_tris;
+    s.h.n_gel_edges = n_gel_edges;
     s.h_tris.resize(3 * (size_t)s.h.n_tris);
     s.h_edges.resize(2 * (size_t)s.h.n_edges);
     {
@@ -945,7 +947,6 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     activate(b, {1});
     launch_rest_precompute(b);
     IPC_HIP(hipStreamSynchronize(s.stream));
-    (void)n_gel_edges;
     return IPC_OK;
 }
 
