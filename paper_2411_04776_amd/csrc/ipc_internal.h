@@ -49,7 +49,7 @@ constexpr int kPairsPerBlock = 64;  // contact pairs per pair block of PCG A
 constexpr int64_t kSpmvOneLaneRows = 65536;  // lists with at least this many rows: one thread per row
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
-constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its cells)
+constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its buckets' entries)
 constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
 constexpr int kMasCapM = 512;     // members of a preconditioner group (one block, held in LDS)
 constexpr int kMasCapA = 512;     // aggregates of all levels in a group

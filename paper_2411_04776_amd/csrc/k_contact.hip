@@ -383,7 +383,7 @@ __device__ __forceinline__ bool ee_admissible(const SceneDev &S, int a0, int a1,
 }
 
 // kLanesQ lanes per query primitive (PT: surface point index, EE: edge
-// index) split the cells its box spans. COUNT: each lane's number of
+// index) split the hash entries of the cells its box spans. COUNT: each lane's number of
 // accepted pairs, and the query's total. Else each lane writes its pairs at
 // q_off plus the counts of the lanes before it, and lane 0 sorts the query's
 // segment by b (each pair is found in exactly one cell, so the sorted segment
@@ -450,49 +450,48 @@ __device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, in
         scan0 = a_gel ? S.self_contact != 0 : KIND == 0;
         scan1 = a_gel;
     }
-    if (ok) {
-        const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1, ncz = chi[2] - clo[2] + 1;
-        const int64_t ncell = (int64_t)ncx * ncy * ncz;
-        const int64_t c0 = scan0 ? 0 : ncell, c1 = scan1 ? 2 * ncell : ncell;
-        for (int64_t cb = c0 + lane; cb < c1; cb += kLanesQ) {
-            const int body = cb < ncell ? 0 : 1;
-            const int64_t cc = body ? cb - ncell : cb;
-            const int ix = clo[0] + (int)(cc % ncx);
-            const int64_t t = cc / ncx;
-            const int iy = clo[1] + (int)(t % ncy), iz = clo[2] + (int)(t / ncy);
-            uint32_t bkt = cell_hash(ix, iy, iz, body, mask);
-            int kend = min(start[bkt + 1], cap);
-            for (int k = start[bkt]; k < kend; ++k) {
-                int4 en = entries[k];
-                if (en.x != ix || en.y != iy || en.z != iz) continue;
-                int b = en.w;
-                if ((b >= b_gel) != (body == 1)) continue;  // another body's entry in this bucket
-                if (KIND == 1 && b <= qa) continue;
-                // box test first: most bucket entries fail it, and it
-                // needs no index loads
-                bool ov = true;
-                double corner[3];
-                for (int c = 0; c < 3; ++c) {
-                    double blo = bbox[c * NB + b], bhi = bbox[(3 + c) * NB + b];
-                    ov = ov && (alo[c] <= bhi) && (blo <= ahi[c]);
-                    corner[c] = fmax(alo[c], blo);
+    // the (body, cell) pairs in a fixed order, taken by all the query's
+    // lanes together; a bucket's entries are split over them (entry k to
+    // lane k mod kLanesQ): a query spans one to a few cells, and a bucket
+    // beside the indenter holds tens of entries
+    for (int body = 0; body < 2; ++body) {
+        if (!(body == 0 ? scan0 : scan1)) continue;
+        for (int iz = clo[2]; iz <= chi[2]; ++iz)
+            for (int iy = clo[1]; iy <= chi[1]; ++iy)
+                for (int ix = clo[0]; ix <= chi[0]; ++ix) {
+                    uint32_t bkt = cell_hash(ix, iy, iz, body, mask);
+                    int kend = min(start[bkt + 1], cap);
+                    for (int k = start[bkt] + lane; k < kend; k += kLanesQ) {
+                        int4 en = entries[k];
+                        if (en.x != ix || en.y != iy || en.z != iz) continue;
+                        int b = en.w;
+                        if ((b >= b_gel) != (body == 1)) continue;  // another body's entry in this bucket
+                        if (KIND == 1 && b <= qa) continue;
+                        // box test first: most bucket entries fail it, and it
+                        // needs no index loads
+                        bool ov = true;
+                        double corner[3];
+                        for (int c = 0; c < 3; ++c) {
+                            double blo = bbox[c * NB + b], bhi = bbox[(3 + c) * NB + b];
+                            ov = ov && (alo[c] <= bhi) && (blo <= ahi[c]);
+                            corner[c] = fmax(alo[c], blo);
+                        }
+                        if (!ov) continue;
+                        if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
+                            continue;
+                        if (KIND == 0) {
+                            if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
+                        } else {
+                            if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
+                        }
+                        if (!COUNT && o + count < ocap) {
+                            out[o + count] = KIND;
+                            out[ocap + o + count] = a_id;
+                            out[2 * ocap + o + count] = b;
+                        }
+                        ++count;
+                    }
                 }
-                if (!ov) continue;
-                if (cell_of(corner[0], h) != ix || cell_of(corner[1], h) != iy || cell_of(corner[2], h) != iz)
-                    continue;
-                if (KIND == 0) {
-                    if (!pt_admissible(S, va0, S.trv[b], S.trv[S.n_tris + b], S.trv[2 * S.n_tris + b])) continue;
-                } else {
-                    if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
-                }
-                if (!COUNT && o + count < ocap) {
-                    out[o + count] = KIND;
-                    out[ocap + o + count] = a_id;
-                    out[2 * ocap + o + count] = b;
-                }
-                ++count;
-            }
-        }
     }
     // the query's total over its lanes (every lane of the wavefront takes part)
     int tot = count;
