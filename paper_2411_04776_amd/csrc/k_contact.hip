@@ -661,6 +661,65 @@ __device__ __forceinline__ void rr_pair(int round, int i, int &p, int &q)
     q = a < b ? b : a;
 }
 
+// Cyclic Jacobi on a symmetric 5 x 5 matrix held in registers as its upper
+// triangle (rows and columns past the restriction's dimension are zero and
+// stay zero): eigenvalues left on the diagonal, eigenvectors in V's columns.
+// Every lane of the wavefront runs it on the same matrix (no LDS round
+// trips). The rotation zeroing (p, q) is the one of the 12 x 12 Jacobi below:
+// a_pp -= t a_pq, a_qq += t a_pq, and for r != p, q
+// (a_rp, a_rq) <- (c a_rp - s a_rq, s a_rp + c a_rq).
+__device__ __forceinline__ constexpr int ut5(int a, int b)
+{
+    return a <= b ? a * 5 - a * (a - 1) / 2 + (b - a) : b * 5 - b * (b - 1) / 2 + (a - b);
+}
+
+__device__ __forceinline__ void jacobi5(double (&U)[15], double (&V)[5][5])
+{
+    double fro = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+#pragma unroll
+        for (int b = 0; b < 5; ++b) V[a][b] = a == b ? 1.0 : 0.0;
+#pragma unroll
+        for (int b = a; b < 5; ++b) fro += (a == b ? 1.0 : 2.0) * U[ut5(a, b)] * U[ut5(a, b)];
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = a + 1; b < 5; ++b) off += U[ut5(a, b)] * U[ut5(a, b)];
+        if (off <= 0.5e-36 * fro || off == 0.0) break;
+#pragma unroll
+        for (int p = 0; p < 5; ++p)
+#pragma unroll
+            for (int q = p + 1; q < 5; ++q) {
+                const double apq = U[ut5(p, q)];
+                if (apq == 0.0) continue;
+                double theta = (U[ut5(q, q)] - U[ut5(p, p)]) / (2.0 * apq);
+                double t = fabs(theta) > 1e150 ? 0.5 / theta
+                                                : (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                U[ut5(p, p)] -= t * apq;
+                U[ut5(q, q)] += t * apq;
+                U[ut5(p, q)] = 0.0;
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    if (r == p || r == q) continue;
+                    double arp = U[ut5(r, p)], arq = U[ut5(r, q)];
+                    U[ut5(r, p)] = c * arp - sn * arq;
+                    U[ut5(r, q)] = sn * arp + c * arq;
+                }
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    double vrp = V[r][p], vrq = V[r][q];
+                    V[r][p] = c * vrp - sn * vrq;
+                    V[r][q] = sn * vrp + c * vrq;
+                }
+            }
+    }
+}
+
 // kappa * w * b(d) for each active pair: gradient and PSD Hessian.
 // One wavefront per pair. Projected form: lanes evaluate Hessian entries, then
 // a parallel cyclic Jacobi (six disjoint rotations per round) diagonalises the
@@ -775,7 +834,107 @@ __global__ void __launch_bounds__(64) k_barrier(Launch L)
     if (lane < 4) act_v[(int64_t)lane * act_cap + k] = v[lane];
     __syncthreads();
 
-    // parallel cyclic Jacobi
+    if (!moll) {
+        // Without the mollifier the pair Hessian's range lies in the span of
+        // c (x) e_i (i = 0..2) and the columns of W: s_xx = 2 c c^T (x) I3,
+        // grad s = 2 c (x) r and the envelope term W S W^T, so grad d and
+        // the Hessian of d do too. Its PSD projection is that of its
+        // restriction to an orthonormal basis Q of the span (k <= 5): a k x k
+        // Jacobi instead of the 12 x 12 one.
+        __shared__ double Q[5][12], AQ[12][5], M[5][5], MV[5][5];
+        __shared__ int kq;
+        if (lane == 0) {
+            double cn = sqrt(dd.c[0] * dd.c[0] + dd.c[1] * dd.c[1] + dd.c[2] * dd.c[2] + dd.c[3] * dd.c[3]);
+            for (int i = 0; i < 3; ++i)
+                for (int pp = 0; pp < 12; ++pp) Q[i][pp] = pp % 3 == i ? dd.c[pp / 3] / cn : 0.0;
+            int kk = 3;
+            for (int m = 0; m < dd.np; ++m) {
+                double w[12], n0 = 0.0;
+                for (int pp = 0; pp < 12; ++pp) {
+                    w[pp] = dd.W[pp][m];
+                    n0 += w[pp] * w[pp];
+                }
+                for (int pass = 0; pass < 2; ++pass)  // Gram-Schmidt, repeated once
+                    for (int aa2 = 0; aa2 < kk; ++aa2) {
+                        double dt = 0.0;
+                        for (int pp = 0; pp < 12; ++pp) dt += Q[aa2][pp] * w[pp];
+                        for (int pp = 0; pp < 12; ++pp) w[pp] -= dt * Q[aa2][pp];
+                    }
+                double n = 0.0;
+                for (int pp = 0; pp < 12; ++pp) n += w[pp] * w[pp];
+                if (n > 1e-24 * n0) {  // a direction already in the span adds none
+                    n = sqrt(n);
+                    for (int pp = 0; pp < 12; ++pp) Q[kk][pp] = w[pp] / n;
+                    ++kk;
+                }
+            }
+            kq = kk;
+        }
+        __syncthreads();
+        const int kd = kq;
+        for (int t = lane; t < 12 * kd; t += 64) {  // A Q^T
+            int i = t / kd, bq2 = t % kd;
+            double acc = 0.0;
+            for (int j = 0; j < 12; ++j) acc += A[i * 12 + j] * Q[bq2][j];
+            AQ[i][bq2] = acc;
+        }
+        __syncthreads();
+        for (int t = lane; t < kd * kd; t += 64) {  // M = Q A Q^T
+            int aa2 = t / kd, bq2 = t % kd;
+            double acc = 0.0;
+            for (int i = 0; i < 12; ++i) acc += Q[aa2][i] * AQ[i][bq2];
+            M[aa2][bq2] = acc;
+        }
+        __syncthreads();
+        {
+            double Ur[15], Vr[5][5];
+#pragma unroll
+            for (int aa2 = 0; aa2 < 5; ++aa2)
+#pragma unroll
+                for (int bq2 = aa2; bq2 < 5; ++bq2)
+                    Ur[ut5(aa2, bq2)] = aa2 < kd && bq2 < kd ? 0.5 * (M[aa2][bq2] + M[bq2][aa2]) : 0.0;
+            jacobi5(Ur, Vr);
+            __syncthreads();  // every lane has read M
+            if (lane == 0)
+#pragma unroll
+                for (int aa2 = 0; aa2 < 5; ++aa2)
+#pragma unroll
+                    for (int bq2 = 0; bq2 < 5; ++bq2) {
+                        M[aa2][bq2] = aa2 == bq2 ? Ur[ut5(aa2, aa2)] : 0.0;
+                        MV[aa2][bq2] = Vr[aa2][bq2];
+                    }
+        }
+        __syncthreads();
+        bool negr = false;
+        for (int m = 0; m < kd; ++m) negr |= M[m][m] < 0.0;
+        if (negr) {
+            for (int t = lane; t < 12 * kd; t += 64) {  // P = Q^T MV
+                int i = t / kd, m = t % kd;
+                double acc = 0.0;
+                for (int aa2 = 0; aa2 < kd; ++aa2) acc += Q[aa2][i] * MV[aa2][m];
+                AQ[i][m] = acc;
+            }
+            __syncthreads();
+            for (int e = lane; e < 144; e += 64) {
+                int i = e / 12, j = e % 12;
+                double val = 0.0;
+                for (int m = 0; m < kd; ++m)
+                    if (M[m][m] > 0.0) val += AQ[i][m] * M[m][m] * AQ[j][m];
+                A[e] = val;
+            }
+            __syncthreads();
+        }
+        for (int e = lane; e < 144; e += 64) {
+            int i = e / 12, j = e % 12;
+            double val = negr ? A[e] : A0[e];
+            if (fixed[v[i / 3]] || fixed[v[j / 3]]) val = 0.0;
+            act_H[(int64_t)e * act_cap + k] = (R)val;
+        }
+        if (lane < 12 && fixed[v[lane / 3]]) act_g[(int64_t)lane * act_cap + k] = R(0);
+        return;
+    }
+
+    // mollified edge pairs: parallel cyclic Jacobi
     double fro = 0.0;
     for (int e = lane; e < 144; e += 64) fro += A[e] * A[e];
     fro = wave_sum(fro);
