@@ -321,8 +321,9 @@ static void ensure_scratch(Scene &s, int b0, int b1, int64_t cc, int64_t fc)
 void grow_table(Scene &s, int t, int64_t entries)
 {
     SceneDev &H = s.h;
-    int bits = 10;
-    while ((int64_t(1) << bits) < 2 * entries && bits < 28) ++bits;
+    int bits = 10;  // at least as many buckets as entries: every scan and clear of the buckets
+                    // runs once per broad phase, so a sparser table costs more than it saves
+    while ((int64_t(1) << bits) < entries && bits < 28) ++bits;
     size_t tsize = size_t(1) << bits;
     Staged st(s);
     int32_t *cnt = st.get<int32_t>(tsize + 1), *start = st.get<int32_t>(tsize + 1);
@@ -925,8 +926,11 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     }
     H.pcg = dalloc<PcgState>(s, 1);
     IPC_HIP(hipMemsetAsync(H.pcg, 0, sizeof(PcgState), s.stream));
-    grow_table(s, 0, 16 * (int64_t)std::max(H.n_tris, 1));
-    grow_table(s, 1, 16 * (int64_t)std::max(H.n_edges, 1));
+    // entry capacity: a primitive's box spans about five cells (grown when a
+    // count pass finds more); without self-contact only the indenter's edges
+    // enter the edge table
+    grow_table(s, 0, 8 * (int64_t)std::max(H.n_tris, 1));
+    grow_table(s, 1, 8 * (int64_t)std::max(H.self_contact ? H.n_edges : H.n_edges - H.n_gel_edges, 1));
     H.q_count = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     H.q_off = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     H.q_lane = dalloc<int32_t>(s, (size_t)kLanesQ * ((size_t)H.n_pts + H.n_edges) + 1);
