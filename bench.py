@@ -455,10 +455,10 @@ def soft_ball_leg(args, ipc, scenes, torch):
     forms = (("projected", ipc.IPC_BARRIER_PROJECTED), ("gauss_newton", ipc.IPC_BARRIER_GAUSS_NEWTON))
     for size in ("small", "medium", "large"):
         sc = scenes.soft_ball_scene(size, steps=21)
-        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "pcg_tol": min(args.pcg_tol, 1e-4),
+        out[size] = {"verts": len(sc.X), "tets": len(sc.T), "pcg_tol": min(args.pcg_tol, 3e-5),
                      "paper_gipc_ms_per_frame": PAPER_SOFT_BALL_MS[size]}
         for name, code in forms:
-            g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 1e-4), precond=precond_code(args),
+            g = ipc.GelScene(sc, precision=ipc.IPC_FP64, pcg_tol=min(args.pcg_tol, 3e-5), precond=precond_code(args),
                              barrier_hessian=code)
             g.step()
             torch.cuda.synchronize()
@@ -558,11 +558,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed list steps before the reset to rest")
     ap.add_argument("--batch", type=int, default=256, help="scenes of the headline list")
     ap.add_argument("--seed", type=int, default=0, help="config-2 seed")
-    # PCG tolerance of the timed runs: the loosest that keeps the final error
-    # inside 1e-4 L on every scene checked against the oracle (the 16 sampled
-    # config-3 scenes: 3.4e-5 L; config-2 seeds 0, 1, 3, 4: at most 5.6e-5 L;
-    # 1e-3 let config-2 seed 3 end 6.1e-4 L away); checked in the line itself
-    ap.add_argument("--pcg-tol", type=float, default=1e-4)
+    # PCG tolerance of the timed runs: one that keeps the final error inside
+    # 1e-4 L with a margin on every scene checked against the oracle (config-2
+    # seed 3, the sensitive one, ends 1e-5 L away at 3e-5; at 1e-4 it ends
+    # 5.6e-5 or 5.2e-4 L away depending on the preconditioner's grouping, at
+    # 1e-3 6.1e-4 L); the headline's own sampled scenes are checked in the line
+    ap.add_argument("--pcg-tol", type=float, default=3e-5)
     ap.add_argument("--precond", choices=["multilevel", "jacobi"], default="multilevel")
     ap.add_argument("--barrier-hessian", choices=["projected", "gauss-newton"], default="projected")
     ap.add_argument("--no-per-scene", action="store_true", help="skip the one-at-a-time runs of the 16 sampled scenes")

@@ -51,8 +51,8 @@ constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
 constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its buckets' entries)
 constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
-constexpr int kMasCapM = 512;     // members of a preconditioner group (one block, held in LDS)
-constexpr int kMasCapA = 512;     // aggregates of all levels in a group
+constexpr int kMasCapM = 256;     // members of a preconditioner group (one block, held in LDS)
+constexpr int kMasCapA = 256;     // aggregates of all levels in a group
 constexpr int kMasTarget = 256;   // groups are packed with top-level aggregates up to this many members
 
 // kernels timed by the optional profiler

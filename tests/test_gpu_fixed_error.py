@@ -1,13 +1,16 @@
 """Fixed-error check of config 2 (40x50x8 gel): stepped through all 50 steps
-at the benchmark's PCG tolerance (1e-4), the final positions of every gel
+at the benchmark's PCG tolerance (3e-5), the final positions of every gel
 vertex end within 1e-4 L of the FP64 oracle's
 (tests/golden/c2_seed{S}_final.npz, written by make_fullsize.py from the
 oracle at PCG tolerance 1e-12): seed 0 (cylinder) in FP64 and in the mixed
 form, with either preconditioner and with the Gauss-Newton barrier Hessian;
-seeds 1-5 (cube edge, bumpy plate, ...) in FP64 and mixed. (At tolerance
-1e-3 seed 3 ends 6.1e-4 L away at a vertex beside the contact edge, where
-the barrier is soft: the looser solves take the trajectory elsewhere; seed 0
-stays at 3.0e-5 L, recorded here as a form of its own.)
+seeds 1-5 (cube edge, bumpy plate, ...) in FP64 and mixed. Seed 3 (a
+cylinder) sets the tolerance: its worst vertex, beside the contact edge where
+the soft barrier lets looser solves take the trajectory elsewhere, ends
+1e-5 L away at 3e-5, 5.6e-5 L at 1e-4 with the 512-member preconditioner
+groups and 5.2e-4 L at 1e-4 with the 256-member ones, 6.1e-4 L at 1e-3; at
+3e-5 and 1e-5 the two preconditioners agree (8.9e-6 / 1.0e-5 and 5.3e-6 /
+5.2e-6). Seed 0 at 1e-3 (3.0e-5 L) is recorded as a form of its own.
 
 The Gauss-Newton form is held to the oracle's trajectory in the same form
 (c2_seed0_gn_final.npz): its Newton stop test reads that form's direction,
@@ -25,6 +28,7 @@ from paper_2411_04776_amd import scenes as S
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BENCH_PCG_TOL = 3e-5
 
 
 def say(*a):
@@ -54,7 +58,7 @@ def run(ipc, seed, form):
     dx, L = golden(seed, gn=form == "fp64-gauss-newton")
     sc = S.config2(seed)
     ref = sc.X + dx
-    kw = dict(pcg_tol=1e-3 if form == "fp64-tol1e-3" else 1e-4)
+    kw = dict(pcg_tol=1e-3 if form == "fp64-tol1e-3" else BENCH_PCG_TOL)
     if form == "mixed":
         kw["precision"] = ipc.IPC_MIXED
     if form == "fp64-jacobi":

@@ -20,8 +20,8 @@ from paper_2411_04776_amd import scenes as S
 
 pytestmark = pytest.mark.gpu
 
-CAP_MEMBERS = 512    # members of one preconditioner group (LDS rows)
-CAP_AGGS = 512       # aggregates of one group
+CAP_MEMBERS = 256    # members of one preconditioner group (LDS rows)
+CAP_AGGS = 256       # aggregates of one group
 
 
 def say(*a):

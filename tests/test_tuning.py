@@ -28,16 +28,16 @@ def test_tuning_file_classes(tmp_path):
     f = tmp_path / "tuning.json"
     f.write_text(json.dumps({
         "classes": [
-            {"min_verts": 65536, "name": "large", "spmv_one_lane_rows": 0, "mas_target": 384,
+            {"min_verts": 65536, "name": "large", "spmv_one_lane_rows": 0, "mas_target": 192,
              "pcg_first_chunk": 0.75, "pcg_later_chunk": 0.125, "pcg_list_quantile": 3.0},
             {"min_verts": 0, "name": "small", "spmv_one_lane_rows": 131072, "mas_target": 4096,
              "pcg_first_chunk": 1.0, "pcg_later_chunk": 0.25}],
         "measurements": [{"min_verts": 99, "mas_target": 1}]}))
     small, edge, large = query(str(f), [1000, 65535, 65536])
     assert small == edge
-    assert small["spmv_one_lane_rows"] == 131072 and small["mas_target"] == 512   # clamped to the group cap
+    assert small["spmv_one_lane_rows"] == 131072 and small["mas_target"] == 256   # clamped to the group cap
     assert small["pcg_first_chunk"] == 1.0 and small["from_file"]
-    assert large["spmv_one_lane_rows"] == 0 and large["mas_target"] == 384 and large["pcg_later_chunk"] == 0.125
+    assert large["spmv_one_lane_rows"] == 0 and large["mas_target"] == 192 and large["pcg_later_chunk"] == 0.125
     assert large["pcg_list_quantile"] == 1.0 and small["pcg_list_quantile"] == 0.25   # clamped; default
 
 
