@@ -49,6 +49,7 @@ constexpr int kPairsPerBlock = 64;  // contact pairs per pair block of PCG A
 constexpr int64_t kSpmvOneLaneRows = 65536;  // lists with at least this many rows: one thread per row
 constexpr int kScanTile = 1024;   // elements per scan tile
 constexpr int kHeavyRow = 24;     // incidence rows longer than this get a block of their own
+constexpr int kQueryKeep = 4;     // pairs a query lane keeps from the count pass for the fill pass
 constexpr int kLanesQ = 8;        // broad-phase lanes per query primitive (they split its buckets' entries)
 constexpr int kMasLevels = 3;     // aggregate levels of the multilevel preconditioner
 constexpr int kMasCapM = 256;     // members of a preconditioner group (one block, held in LDS)
@@ -131,6 +132,7 @@ struct SceneDev {
     int32_t ht_bits[2], ht_cap[2];
     int32_t *q_count, *q_off;      // per query primitive (points, then edges): pair counts, offsets
     int32_t *q_lane;               // kLanesQ per query primitive: each lane's pair count
+    int32_t *q_keep;               // kLanesQ * kQueryKeep per query primitive: each lane's first pairs (b)
     // candidates: static list and swept list (SoA type, a, b with stride cap)
     int32_t *cand, *cand_sw;
     int64_t cand_cap, sw_cap;

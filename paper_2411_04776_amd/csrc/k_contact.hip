@@ -432,12 +432,28 @@ __device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, in
     int32_t *out = swept ? S.cand_sw : S.cand;
     int64_t ocap = swept ? S.sw_cap : S.cand_cap;
     int64_t o0 = 0, o = 0;
+    // the count pass keeps a lane's first kQueryKeep pairs; the fill pass
+    // copies them when that was all of them and walks the buckets again only
+    // for lanes that found more
+    int32_t *keep = S.q_keep + ((int64_t)kLanesQ * qidx + lane) * kQueryKeep;
+    bool walk = ok;
+    int count = 0;
     if (!COUNT && ok) {
         o0 = S.q_off[qidx];
         o = o0;
         for (int j = 0; j < lane; ++j) o += S.q_lane[(int64_t)kLanesQ * qidx + j];
+        const int mine = S.q_lane[(int64_t)kLanesQ * qidx + lane];
+        if (mine <= kQueryKeep) {
+            walk = false;
+            for (int j = 0; j < mine; ++j)
+                if (o + j < ocap) {
+                    out[o + j] = KIND;
+                    out[ocap + o + j] = a_id;
+                    out[2 * ocap + o + j] = keep[j];
+                }
+            count = mine;
+        }
     }
-    int count = 0;
     // bodies whose entries this query scans: a gel point or edge looks at
     // the indenter's, and at the gel's under self-contact; an indenter point
     // at the gel's; an indenter edge at none (its pairs with gel edges have
@@ -454,7 +470,7 @@ __device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, in
     // lanes together; a bucket's entries are split over them (entry k to
     // lane k mod kLanesQ): a query spans one to a few cells, and a bucket
     // beside the indenter holds tens of entries
-    for (int body = 0; body < 2; ++body) {
+    for (int body = 0; body < 2 && walk; ++body) {
         if (!(body == 0 ? scan0 : scan1)) continue;
         for (int iz = clo[2]; iz <= chi[2]; ++iz)
             for (int iy = clo[1]; iy <= chi[1]; ++iy)
@@ -484,6 +500,7 @@ __device__ void query_body(const Launch &L, int s, const SceneDev &S, int lb, in
                         } else {
                             if (!ee_admissible(S, va0, va1, S.ev[b], S.ev[S.n_edges + b])) continue;
                         }
+                        if (COUNT && count < kQueryKeep) keep[count] = b;
                         if (!COUNT && o + count < ocap) {
                             out[o + count] = KIND;
                             out[ocap + o + count] = a_id;

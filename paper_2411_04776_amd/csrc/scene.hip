@@ -934,6 +934,7 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.q_count = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     H.q_off = dalloc<int32_t>(s, (size_t)H.n_pts + H.n_edges + 1);
     H.q_lane = dalloc<int32_t>(s, (size_t)kLanesQ * ((size_t)H.n_pts + H.n_edges) + 1);
+    H.q_keep = dalloc<int32_t>(s, (size_t)kQueryKeep * kLanesQ * ((size_t)H.n_pts + H.n_edges) + 1);
     grow_candidates(s, 0, 1024);
     grow_candidates(s, 1, 1024);
     grow_active(s, 256);
@@ -1955,7 +1956,7 @@ int64_t ipc_scene_footprint_bytes(const ipc_scene_desc *d)
     int64_t per_tet = 4 * 4 + 8 * 10 + rs * (12 + 90) + 4 * 16 + 4 * 4;
     int64_t bell = n * 16 * (9 * rs + 4 + 4);
     int64_t surf = 4 * (int64_t)std::pow((double)d->n_verts, 2.0 / 3.0) + d->n_ind_verts + 2 * d->n_ind_tris;
-    int64_t contact = surf * (6 * 8 * 3 + 64 * 4 * 3 + 8 * 16) + surf / 4 * (rs * 156 + 4 * 9);
+    int64_t contact = surf * (6 * 8 * 3 + 64 * 4 * 3 + 8 * 16 + 4 * kQueryKeep * kLanesQ) + surf / 4 * (rs * 156 + 4 * 9);
     return n * per_vertex + m * per_tet + bell + contact + (8 << 20);
 }
 
