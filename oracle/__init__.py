@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("self_contact", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32),
         ("mu_fric", C.c_double), ("eps_v", C.c_double), ("barrier_hessian", C.c_int32),
+        ("target_al", C.c_int32), ("target_al_tol", C.c_double), ("target_al_max", C.c_int32),
     ]
 
 
@@ -44,7 +45,7 @@ class Stats(C.Structure):
         ("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("n_candidates", C.c_int32),
         ("n_active", C.c_int32), ("status", C.c_int32), ("ls_halvings", C.c_int32),
         ("alpha_ccd", C.c_double), ("alpha", C.c_double), ("energy", C.c_double),
-        ("pinf", C.c_double), ("max_target_lag", C.c_double),
+        ("pinf", C.c_double), ("max_target_lag", C.c_double), ("al_updates", C.c_int32),
     ]
 
     def asdict(self):

@@ -746,6 +746,8 @@ struct ora_scene {
     double *x, *v;
     /* step context */
     double *xt, *xtilde, *yhat; /* yhat: 3 per vertex, meaningful for indenter vertices */
+    double *lam_al;             /* augmented-Lagrangian multipliers, 3 per vertex (indenter vertices) */
+    int al_step;                /* 1: the multipliers just changed; the next iteration takes its step */
     /* lagged friction set of the step (pairs active at x^t) */
     int n_fric;
     int32_t *fric_v;  /* 4 per pair */
@@ -976,6 +978,7 @@ ora_scene *ora_scene_create(int32_t n_gel, const double *X, int32_t n_tet, const
     s->xt = (double *)malloc(sizeof(double) * 3 * n);
     s->xtilde = (double *)malloc(sizeof(double) * 3 * n);
     s->yhat = (double *)malloc(sizeof(double) * 3 * n);
+    s->lam_al = (double *)calloc(3 * (size_t)n, sizeof(double));
     memcpy(s->x, s->X, sizeof(double) * 3 * n);
     memcpy(s->xt, s->X, sizeof(double) * 3 * n);
     memcpy(s->xtilde, s->X, sizeof(double) * 3 * n);
@@ -989,7 +992,7 @@ void ora_scene_destroy(ora_scene *s)
     free(s->X); free(s->Yloc); free(s->pose0); free(s->T); free(s->fixed);
     free(s->Bm); free(s->vol); free(s->mass);
     free(s->pts); free(s->edges); free(s->tris); free(s->edge_rest_sq);
-    free(s->x); free(s->v); free(s->xt); free(s->xtilde); free(s->yhat);
+    free(s->x); free(s->v); free(s->xt); free(s->xtilde); free(s->yhat); free(s->lam_al);
     free(s->attached);
     free(s->fric_v); free(s->fric_c); free(s->fric_nrm); free(s->fric_lam);
     free(s);
@@ -1210,6 +1213,7 @@ static double energy_with(const ora_scene *s, const double *x, const ivec *cand)
         double d[3];
         sub3(x + 3 * j, s->yhat + 3 * j, d);
         nsum_add(&acc, 0.5 * s->prm.k_target * dot3(d, d));
+        if (s->prm.target_al) nsum_add(&acc, -dot3(s->lam_al + 3 * j, d));
     }
     for (int i = 0; i < s->n_gel; ++i) {
         if (!is_attached(s, i)) continue;
@@ -1421,7 +1425,7 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
     }
     for (int j = s->n_gel; j < n; ++j)
         for (int c = 0; c < 3; ++c) {
-            A->g[3 * j + c] += s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]);
+            A->g[3 * j + c] += s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]) - s->lam_al[3 * j + c];
             A->diag[9 * j + 4 * c] += s->prm.k_target;
         }
     for (int i = 0; i < s->n_gel; ++i)
@@ -1643,7 +1647,8 @@ void ora_gradient_terms(ora_scene *s, const double *x, double *g_inertia, double
         }
     if (g_target) {
         for (int j = s->n_gel; j < n; ++j)
-            for (int c = 0; c < 3; ++c) g_target[3 * j + c] = s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]);
+            for (int c = 0; c < 3; ++c)
+                g_target[3 * j + c] = s->prm.k_target * (x[3 * j + c] - s->yhat[3 * j + c]) - s->lam_al[3 * j + c];
         for (int i = 0; i < s->n_gel; ++i)
             if (is_attached(s, i))
                 for (int c = 0; c < 3; ++c)
@@ -1772,6 +1777,19 @@ void ora_set_case_pose(ora_scene *s, const double *pose) { memcpy(s->case_pose, 
 
 /* ======================================================================== */
 
+/* max_j |y_j - yhat_j| over indenter vertices */
+static double target_lag(const ora_scene *s, const double *x)
+{
+    double lag = 0.0;
+    for (int j = s->n_gel; j < s->n; ++j) {
+        double d[3];
+        sub3(x + 3 * j, s->yhat + 3 * j, d);
+        double l = sqrt(dot3(d, d));
+        if (l > lag) lag = l;
+    }
+    return lag;
+}
+
 void ora_begin_step(ora_scene *s, const double *pose)
 {
     int n = s->n;
@@ -1790,6 +1808,8 @@ void ora_begin_step(ora_scene *s, const double *pose)
     }
     for (int i = 0; i < s->n_gel; ++i)
         if (is_attached(s, i)) apply_pose(s->case_pose, s->X + 3 * i, s->yhat + 3 * i);
+    memset(s->lam_al, 0, sizeof(double) * 3 * n);
+    s->al_step = 0;
     friction_lag(s);
 }
 
@@ -1820,10 +1840,13 @@ int32_t ora_newton_iterate(ora_scene *s, const double *x_in, double *x_out, ora_
     }
     if (st) st->pinf = pinf;
     memcpy(x_out, x_in, sizeof(double) * m);
-    if (pinf <= s->prm.newton_tol) {
+    /* after a multiplier update the step moves the indenter by about its
+     * remaining lag, below the Newton tolerance: it is taken regardless */
+    if (pinf <= s->prm.newton_tol && !s->al_step) {
         free(p);
         return 1;
     }
+    s->al_step = 0;
     ivec sw = {0, 0, 0};
     candidates_list(s, x_in, p, &sw);
     double accd = ccd_with(s, x_in, p, &sw);
@@ -1869,12 +1892,26 @@ int32_t ora_step(ora_scene *s, const double *pose, ora_stats *st)
     double *xn = (double *)malloc(sizeof(double) * m);
     int status = ORA_OK, k;
     int pcg_warn = 0;
+    const int al_max = s->prm.target_al_max > 0 ? s->prm.target_al_max : 8;
+    int al = 0;
     for (k = 0; k < s->prm.max_newton; ++k) {
         st->status = 0;
         int r = ora_newton_iterate(s, s->x, xn, st);
         st->newton_iters++;
         if (st->status == ORA_W_PCG_MAXITER) pcg_warn = 1;
-        if (r == 1) break;
+        if (r == 1) {
+            /* converged for the current multipliers: update them while the
+             * indenter is further than the tolerance from its targets */
+            if (s->prm.target_al && al < al_max && target_lag(s, s->x) > s->prm.target_al_tol) {
+                for (int j = s->n_gel; j < n; ++j)
+                    for (int c = 0; c < 3; ++c)
+                        s->lam_al[3 * j + c] -= s->prm.k_target * (s->x[3 * j + c] - s->yhat[3 * j + c]);
+                ++al;
+                s->al_step = 1;
+                continue;
+            }
+            break;
+        }
         memcpy(s->x, xn, sizeof(double) * m);
         if (r == 2) {
             status = ORA_W_LS_STALL;
@@ -1884,14 +1921,9 @@ int32_t ora_step(ora_scene *s, const double *pose, ora_stats *st)
     if (k == s->prm.max_newton) status = ORA_W_NEWTON_MAXITER;
     if (status == ORA_OK && pcg_warn) status = ORA_W_PCG_MAXITER;
     for (int i = 0; i < m; ++i) s->v[i] = (s->x[i] - s->xt[i]) / s->prm.h;
-    double lag = 0.0;
-    for (int j = s->n_gel; j < n; ++j) {
-        double d[3];
-        sub3(s->x + 3 * j, s->yhat + 3 * j, d);
-        double l = sqrt(dot3(d, d));
-        if (l > lag) lag = l;
-    }
+    double lag = target_lag(s, s->x);
     st->max_target_lag = lag;
+    st->al_updates = al;
     if (status == ORA_OK && lag > 1e-3 * s->prm.dhat) status = ORA_W_TARGET_LAG;
     st->status = status;
     free(xn);

@@ -45,11 +45,20 @@ typedef struct ora_params {
     double mu_fric;             /* friction coefficient (0: no friction) */
     double eps_v;               /* friction velocity threshold (m/s); the smoothing length is eps_v h */
     int32_t barrier_hessian;    /* 0: PSD-projected pair Hessians, 1: Gauss-Newton form (ora_pair_barrier) */
+    /* Augmented-Lagrangian indenter targets: with target_al = 1 the target
+     * term of indenter vertex j is k_t/2 |y_j - yhat_j|^2 - lambda_j . (y_j - yhat_j),
+     * lambda = 0 at the start of a step; each time Newton converges with
+     * max_j |y_j - yhat_j| > target_al_tol (m), lambda_j -= k_t (y_j - yhat_j)
+     * and Newton goes on, at most target_al_max times per step (0: 8). */
+    int32_t target_al;
+    double target_al_tol;
+    int32_t target_al_max;
 } ora_params;
 
 typedef struct ora_stats {
     int32_t newton_iters, pcg_iters, n_candidates, n_active, status, ls_halvings;
     double alpha_ccd, alpha, energy, pinf, max_target_lag;
+    int32_t al_updates;         /* multiplier updates of the step (augmented-Lagrangian targets) */
 } ora_stats;
 
 typedef struct ora_scene ora_scene;
