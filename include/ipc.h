@@ -111,6 +111,19 @@ typedef struct ipc_scene_desc {
      * inertia and elasticity, P the case pose of the step request, X_i its
      * rest position; fixed vertices stay fixed. Copied at creation. */
     const uint8_t *attached;
+    /* Augmented-Lagrangian indenter targets (the cited IPC work's treatment
+     * of prescribed boundary motion, a variant of the target penalty). With
+     * target_al = 1 the term of indenter vertex j is
+     * k_target/2 |y_j - yhat_j|^2 - lambda_j . (y_j - yhat_j), lambda = 0 at
+     * the start of a step; whenever Newton converges with
+     * max_j |y_j - yhat_j| > target_al_tol (m), lambda_j -= k_target (y_j - yhat_j)
+     * and Newton goes on (the next iteration takes its step whatever its
+     * size), at most target_al_max times per step (0: 8). A softer k_target
+     * then meets a tighter lag than the penalty alone. target_al = 0: the
+     * plain penalty; the other two fields are ignored. */
+    int32_t target_al;
+    double target_al_tol;
+    int32_t target_al_max;
 } ipc_scene_desc;
 
 /* Device memory and stream plumbing. alloc/free may be NULL (then hipMalloc /
@@ -151,6 +164,7 @@ typedef struct ipc_step_stats {
     double ms_total;          /* wall time of the step on the host (ms) */
     double ms_phase[8];       /* host wall time per phase: assemble, contact, pcg, ccd, line search,
                                  other (the device work of a phase may finish in a later one) */
+    int32_t al_updates;       /* multiplier updates of the step (augmented-Lagrangian targets) */
 } ipc_step_stats;
 
 /* Create a scene. Validates the mesh (indices, rest volumes > 0, manifold

@@ -108,6 +108,8 @@ struct SceneDev {
     double mu, lam, h, inv_h2, dhat, kappa, k_target, rho, grav[3], ccd_s, pcg_tol2;
     double mu_fric, eps_fric;  // friction coefficient, smoothing length eps_v h
     int barrier_gn;            // 1: Gauss-Newton pair Hessians kappa w b'' grad d grad d^T
+    int target_al;             // 1: indenter target terms carry the multipliers al_lam
+    double *al_lam;            // augmented-Lagrangian multipliers, 3 per vertex (indenter vertices)
     uint8_t *attached;         // per gel vertex: pulled to case_pose X0 by k_target (NULL: none)
     double case_pose[12];
     double pose[12];
@@ -250,6 +252,8 @@ struct Params {
     double mu_fric, eps_v;
     double ccd_s, ls_min_ratio;
     int self_contact, precision, max_newton, pcg_max_iter, ccd_max_iter, precond, barrier_hessian;
+    int target_al, target_al_max;  // augmented-Lagrangian indenter targets: on, updates per step
+    double target_al_tol;          // lag (m) above which a converged iterate updates the multipliers
 };
 
 // Device allocation through the runtime's callbacks (PyTorch's caching
@@ -429,6 +433,7 @@ class Batch {
 
 void launch_begin_step(Batch &b);
 void launch_end_step(Batch &b);
+void launch_al_update(Batch &b, const std::vector<uint8_t> &on);
 void launch_trial(Batch &b);       // uses b.h_alpha (uploaded by the caller to b.d_alpha)
 void launch_accept(Batch &b);
 void launch_rest_precompute(Batch &b);

@@ -306,6 +306,8 @@ __device__ __forceinline__ void vertex_gradient(const SceneDev &S, int i, double
             for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
     } else {
         for (int c = 0; c < 3; ++c) g[c] += S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
+        if (S.target_al)
+            for (int c = 0; c < 3; ++c) g[c] -= S.al_lam[3 * i + c];
     }
 }
 
@@ -497,6 +499,8 @@ __global__ void __launch_bounds__(kBlock) k_energy_body(Launch L, int trial)
         } else {
             double d0 = x[3 * i] - S.yhat[3 * i], d1 = x[3 * i + 1] - S.yhat[3 * i + 1], d2 = x[3 * i + 2] - S.yhat[3 * i + 2];
             val = 0.5 * S.k_target * (d0 * d0 + d1 * d1 + d2 * d2);
+            if (S.target_al)
+                val -= S.al_lam[3 * i] * d0 + S.al_lam[3 * i + 1] * d1 + S.al_lam[3 * i + 2] * d2;
         }
     }
     CSum c = {val, 0.0};

@@ -998,8 +998,20 @@ __global__ void k_begin_step(Launch L)
         for (int c = 0; c < 3; ++c) {
             S.yhat[3 * i + c] = P[c * 4 + 0] * y[0] + P[c * 4 + 1] * y[1] + P[c * 4 + 2] * y[2] + P[c * 4 + 3];
             S.xtilde[3 * i + c] = S.x[3 * i + c];
+            if (S.target_al) S.al_lam[3 * i + c] = 0.0;
         }
     }
+}
+
+// augmented-Lagrangian targets: lambda_j -= k_t (y_j - yhat_j) for the
+// indenter vertices of the scenes in the launch
+__global__ void k_al_update(Launch L)
+{
+    int lb, s = scene_of_block(L, lb);
+    const SceneDev &S = *L.sc[s];
+    int i = S.n_gel + lb * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    for (int c = 0; c < 3; ++c) S.al_lam[3 * i + c] -= S.k_target * (S.x[3 * i + c] - S.yhat[3 * i + c]);
 }
 
 __global__ void k_end_step(Launch L)
@@ -1200,6 +1212,15 @@ void segmented_scan(Batch &b, ScanWhich which, PhaseKind tiles, const std::vecto
 
 void launch_begin_step(Batch &b) { IPC_LAUNCH(b, k_begin_step, kPhVert, kBlock); }
 void launch_end_step(Batch &b) { IPC_LAUNCH(b, k_end_step, kPhVert, kBlock); }
+
+void launch_al_update(Batch &b, const std::vector<uint8_t> &on)
+{
+    std::vector<int32_t> nb(b.sc.size(), 0);
+    for (size_t i = 0; i < b.sc.size(); ++i)
+        if (on[i]) nb[i] = nblocks(std::max(b.sc[i]->h.n_ind, 1));
+    b.set_phase(kPhOne, nb);
+    IPC_LAUNCH(b, k_al_update, kPhOne, kBlock);
+}
 
 void launch_trial(Batch &b)
 {

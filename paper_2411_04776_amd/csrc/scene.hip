@@ -861,6 +861,9 @@ static int32_t build_scene(Scene &s, const ipc_scene_desc &d)
     H.xt = dalloc<double>(s, n3);
     H.xtilde = dalloc<double>(s, n3);
     H.yhat = dalloc<double>(s, n3);
+    H.target_al = s.prm.target_al;
+    H.al_lam = dalloc<double>(s, n3);
+    IPC_HIP(hipMemsetAsync(H.al_lam, 0, sizeof(double) * n3, s.stream));
     H.xtrial = dalloc<double>(s, n3);
     for (double *p : {H.x, H.xt, H.xtilde, H.yhat, H.xtrial})
         IPC_HIP(hipMemcpyAsync(p, H.X0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s.stream));
@@ -1214,6 +1217,8 @@ struct StepCtl {
     bool pcg_warn = false;
     ipc_step_stats st{};
     double alpha = 0.0, alpha0 = 0.0, E0 = 0.0;
+    int al = 0;            // multiplier updates so far (augmented-Lagrangian targets)
+    bool al_step = false;  // the multipliers just changed: the next iteration takes its step
 };
 
 // scenes that a host phase marked failed leave the list's phases
@@ -1307,11 +1312,49 @@ static void newton_round(Batch &b, std::vector<StepCtl> &ctl)
         c.st.n_candidates = b.h_out[i].n_cand;
         c.st.n_active = b.h_out[i].n_act;
         c.stepped = false;
-        if (b.h_out[i].pinf <= b.sc[i]->prm.newton_tol) {
+        if (b.h_out[i].pinf <= b.sc[i]->prm.newton_tol && !c.al_step) {
             c.active = false;  // converged: this iteration only measured p
         } else {
             ls[i] = 1;
             any = true;
+        }
+        c.al_step = false;
+    }
+    // augmented-Lagrangian targets: a scene that converged with its indenter
+    // further than the tolerance from its targets updates its multipliers
+    // and goes on
+    {
+        std::vector<uint8_t> al(ns, 0);
+        bool any_al = false;
+        for (size_t i = 0; i < ns; ++i) {
+            const Params &pm = b.sc[i]->prm;
+            if (on[i] && !ctl[i].active && !ctl[i].failed && pm.target_al && ctl[i].al < pm.target_al_max) {
+                al[i] = 1;
+                any_al = true;
+            }
+        }
+        if (any_al) {
+            activate(b, al);
+            run_lag_and_mean(b);
+            b.read_out();
+            std::vector<uint8_t> upd(ns, 0);
+            bool any_upd = false;
+            for (size_t i = 0; i < ns; ++i)
+                if (al[i] && b.h_out[i].lag > b.sc[i]->prm.target_al_tol) {
+                    upd[i] = 1;
+                    any_upd = true;
+                }
+            if (any_upd) {
+                activate(b, upd);
+                launch_al_update(b, upd);
+                for (size_t i = 0; i < ns; ++i)
+                    if (upd[i]) {
+                        StepCtl &c = ctl[i];
+                        c.active = true;
+                        c.al_step = true;
+                        c.st.al_updates = ++c.al;
+                    }
+            }
         }
     }
     if (any) {
@@ -1819,6 +1862,7 @@ static bool check_desc(const ipc_scene_desc *d)
     if (!(d->dt > 0) || !(d->dhat > 0) || !(d->kappa > 0) || !(d->E > 0) || !(d->rho > 0)) return false;
     if (!(d->nu > -1.0 && d->nu < 0.5)) return false;
     if (!(d->newton_tol >= 0) || !(d->pcg_tol >= 0) || !(d->k_target >= 0)) return false;
+    if (d->target_al && !(d->target_al_tol >= 0)) return false;
     if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) return false;
     if (d->pcg_max_iter < 0 || d->max_newton < 0 || d->ccd_max_iter < 0) return false;
     if (!(d->mu_friction >= 0.0) || (d->mu_friction > 0.0 && !(d->eps_v > 0.0))) return false;
@@ -1853,6 +1897,9 @@ static Params make_params(const ipc_scene_desc &d)
     p.ccd_max_iter = d.ccd_max_iter > 0 ? d.ccd_max_iter : 10000;
     p.precond = d.precond;
     p.barrier_hessian = d.barrier_hessian;
+    p.target_al = d.target_al ? 1 : 0;
+    p.target_al_tol = d.target_al_tol;
+    p.target_al_max = d.target_al_max > 0 ? d.target_al_max : 8;
     return p;
 }
 

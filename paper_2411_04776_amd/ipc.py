@@ -63,6 +63,7 @@ class ipc_scene_desc(C.Structure):
         ("self_contact", C.c_int32), ("precision", C.c_int32), ("max_newton", C.c_int32),
         ("pcg_max_iter", C.c_int32), ("ccd_max_iter", C.c_int32), ("precond", C.c_int32),
         ("barrier_hessian", C.c_int32), ("attached", _U8),
+        ("target_al", C.c_int32), ("target_al_tol", C.c_double), ("target_al_max", C.c_int32),
     ]
 
 
@@ -86,6 +87,7 @@ class ipc_step_stats(C.Structure):
         ("ls_halvings", C.c_int32), ("n_candidates", C.c_int32), ("n_active", C.c_int32),
         ("alpha_ccd", C.c_double), ("alpha", C.c_double), ("energy", C.c_double), ("pinf", C.c_double),
         ("max_target_lag", C.c_double), ("ms_total", C.c_double), ("ms_phase", C.c_double * 8),
+        ("al_updates", C.c_int32),
     ]
 
     def asdict(self):
@@ -268,7 +270,8 @@ def _track(obj):
 
 
 def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=None,
-              precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED) -> ipc_scene_desc:
+              precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED,
+              target_al=False, target_al_tol=0.0, target_al_max=0) -> ipc_scene_desc:
     """ipc_scene_desc of a scenes.Scene; `keep` collects the numpy arrays that
     must outlive the create call."""
     X = np.ascontiguousarray(scene.X, dtype=np.float64)
@@ -302,6 +305,9 @@ def make_desc(scene, precision=IPC_FP64, pcg_tol=1e-12, max_newton=100, keep=Non
     d.ccd_max_iter = 10000
     d.precond = precond
     d.barrier_hessian = barrier_hessian
+    d.target_al = int(bool(target_al))
+    d.target_al_tol = target_al_tol
+    d.target_al_max = target_al_max
     at = getattr(scene, "attached", None)
     if at is not None:
         at = np.ascontiguousarray(at, dtype=np.uint8)
@@ -341,11 +347,13 @@ class GelScene:
     """One library scene built from a scenes.Scene."""
 
     def __init__(self, scene, runtime: TorchRuntime | None = None, precision=IPC_FP64, pcg_tol=1e-12,
-                 max_newton=100, precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED):
+                 max_newton=100, precond=IPC_PRECOND_MULTILEVEL, barrier_hessian=IPC_BARRIER_PROJECTED,
+                 target_al=False, target_al_tol=0.0, target_al_max=0):
         self.scene = scene
         self.runtime = runtime or TorchRuntime()
         keep = []
-        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep, precond, barrier_hessian)
+        self.desc = make_desc(scene, precision, pcg_tol, max_newton, keep, precond, barrier_hessian,
+                              target_al, target_al_tol, target_al_max)
         self._keep = keep
         h = C.c_void_p()
         _check(lib().ipc_create_scene(C.byref(self.desc), C.byref(self.runtime.rt), C.byref(h)),
