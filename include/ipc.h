@@ -345,6 +345,11 @@ IPC_API int32_t ipcx_tuning(const ipc_scene *s, double *out);
 /* The same six values for a scene of n_verts vertices created now (host
  * only: reads the tuning file, touches no device). */
 IPC_API int32_t ipcx_tuning_for(int32_t n_verts, double *out);
+/* sizeof of the boundary's structs as compiled into the library, for a
+ * binding to check its own layout: out[0] ipc_scene_desc, out[1] ipc_runtime,
+ * out[2] ipc_step_req, out[3] ipc_step_stats, out[4] ipc_height_map_spec.
+ * Host only. */
+IPC_API int32_t ipcx_struct_sizes(int64_t *out);
 IPC_API int32_t ipcx_set_state(ipc_scene *s, const double *x, const double *v);
 IPC_API int32_t ipcx_get_state(const ipc_scene *s, double *x, double *v);
 

@@ -2727,6 +2727,17 @@ int32_t ipcx_tuning_for(int32_t n_verts, double *out)
     });
 }
 
+int32_t ipcx_struct_sizes(int64_t *out)
+{
+    if (!out) return IPC_E_INVALID_ARG;
+    out[0] = (int64_t)sizeof(ipc_scene_desc);
+    out[1] = (int64_t)sizeof(ipc_runtime);
+    out[2] = (int64_t)sizeof(ipc_step_req);
+    out[3] = (int64_t)sizeof(ipc_step_stats);
+    out[4] = (int64_t)sizeof(ipc_height_map_spec);
+    return IPC_OK;
+}
+
 int32_t ipcx_precond_info(const ipc_scene *s, int64_t *out)
 {
     if (!s || !out) return IPC_E_INVALID_ARG;

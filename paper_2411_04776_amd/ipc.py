@@ -138,6 +138,7 @@ _SIGS = {
     "ipcx_profile_totals": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipcx_tuning": (C.c_int32, [C.c_void_p, _D]),
     "ipcx_tuning_for": (C.c_int32, [C.c_int32, _D]),
+    "ipcx_struct_sizes": (C.c_int32, [C.POINTER(C.c_int64)]),
     "ipcx_matrix_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_precond_info": (C.c_int32, [C.c_void_p, _I64]),
     "ipcx_set_state": (C.c_int32, [C.c_void_p, _D, _D]),

@@ -59,3 +59,17 @@ def test_product_and_oracle_share_no_code():
         text = open(path).read()
         assert "paper_2411_04776_amd" not in text.replace("paper_2411_04776_amd/scenes", ""), path
         assert "ipc.h" not in text and "ipc_internal" not in text, path
+
+
+def test_binding_structs_match_the_library():
+    """The ctypes layouts of the boundary's structs have the sizes the
+    library was compiled with (fields appended on one side only would shift
+    every later field)."""
+    from paper_2411_04776_amd import ipc
+    if not os.path.exists(ipc.LIB_PATH):
+        pytest.skip("library not built")
+    out = (ctypes.c_int64 * 5)()
+    assert ipc.lib().ipcx_struct_sizes(out) == 0
+    mine = [ctypes.sizeof(t) for t in (ipc.ipc_scene_desc, ipc.ipc_runtime, ipc.ipc_step_req, ipc.ipc_step_stats,
+                                       ipc.ipc_height_map_spec)]
+    assert list(out) == mine, (list(out), mine)
