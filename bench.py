@@ -106,6 +106,46 @@ def measured_traffic(path):
         return None, None
 
 
+def full_list_hbm(path):
+    """HBM GB/s of a PCG kernel's full-list dispatches (those of at least 90 %
+    of its largest grid) from a committed rocprofv3 --pmc summary: scaled
+    FETCH_SIZE + WRITE_SIZE over the durations of the same dispatches in that
+    counter run; None when the kernel sources changed since."""
+    vals = summary_values(path, ("full_list_dispatches", "full_list_traffic_bytes", "full_list_us",
+                                 "full_list_hbm_gbs", "kernel_source_sha256"))
+    if not vals or vals.get("kernel_source_sha256") != source_hash(PCG_SOURCES) or "full_list_hbm_gbs" not in vals:
+        return None
+    try:
+        return {"dispatches": int(vals["full_list_dispatches"]),
+                "traffic_bytes": int(float(vals["full_list_traffic_bytes"])),
+                "us": float(vals["full_list_us"]), "hbm_gbs": float(vals["full_list_hbm_gbs"]), "source": path}
+    except (KeyError, ValueError):
+        return None
+
+
+def above_llc(large, workload):
+    """The PCG iterations whose SpMV launch moves at least 256 MiB of
+    algorithmic bytes (more than the 256 MiB Infinity Cache): event-timed
+    launches of both kernels (large maps kernel -> (timed launches, summed ms,
+    summed bytes)), their achieved algorithmic GB/s, and the whole iteration's."""
+    if not large or large["k_pcg_A"][0] == 0 or large["k_pcg_B"][0] == 0:
+        return None
+    out = {}
+    it_bytes, it_s = 0.0, 0.0
+    for k, (n, ms, by) in large.items():
+        s = ms / 1e3 / n
+        out[k] = {"timed_launches": n, "avg_launch_us": round(s * 1e6, 2), "bytes_per_launch": int(by / n),
+                  "achieved_gbs": round(by / n / s / 1e9, 1), "pmc_full_list": full_list_hbm(TRAFFIC_PROFILES[workload][k])}
+        it_bytes += by / n
+        it_s += s
+    ach = it_bytes / it_s / 1e9
+    out["iteration"] = {"bytes": int(it_bytes), "us": round(it_s * 1e6, 2), "achieved_gbs": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "frac": round(ach / HBM_PEAK_GBS, 4)}
+    out["note"] = ("PCG iterations whose SpMV launch moves >= 256 MiB (the list's early iterations, most scenes "
+                   "still solving): A + B event-timed on the launch stream, algorithmic bytes")
+    return out
+
+
 def pct(v, q):
     import numpy as np
     return round(float(np.percentile(v, q)), 3) if len(v) else None
@@ -204,6 +244,7 @@ def c3_leg(args, ipc, scenes, torch, np):
     el = time.perf_counter() - t0
     prof = {"k_pcg_A": (*eng.profile_read(0), *eng.profile_totals(0)),
             "k_pcg_B": (*eng.profile_read(1), *eng.profile_totals(1))}
+    large = {"k_pcg_A": eng.profile_large(0), "k_pcg_B": eng.profile_large(1)}
     eng.profile(False)
     err = fixed_error(gs, C3_SAMPLE) if args.steps == 20 else None
     # the same episode with each environment submitting its next step as soon
@@ -233,7 +274,8 @@ def c3_leg(args, ipc, scenes, torch, np):
     eng.close()
     env_steps = args.steps * len(gs)
     res = {"value": env_steps / el, "elapsed": el, "env_steps": env_steps, "newton": newton, "pcg": pcg,
-           "lat": lat, "nv": nv, "nt": nt, "build_s": build_s, "prof": prof, "err": err, "closed": closed}
+           "lat": lat, "nv": nv, "nt": nt, "build_s": build_s, "prof": prof, "err": err, "closed": closed,
+           "large": large}
     # the 16 sampled scenes one at a time: plain FP64 and mixed, from rest
     if not args.no_per_scene and args.steps == 20:
         for name, prec in (("fp64", ipc.IPC_FP64), ("mixed", ipc.IPC_MIXED)):
@@ -630,6 +672,7 @@ def main():
         return
     h = c3_leg(args, ipc, scenes, torch, np)
     roof = pcg_roofline(h["prof"], "c3", "the headline list: 256 scenes share every PCG launch")
+    roof["iterations_above_llc"] = above_llc(h["large"], "c3")
     err = h["err"]
     line = {
         "metric": "env-steps/sec", "value": round(h["value"], 2), "unit": "env-steps/s",

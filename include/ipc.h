@@ -292,6 +292,12 @@ IPC_API int32_t ipc_batch_profile(ipc_batch *b, int32_t enable);
 IPC_API int32_t ipc_batch_profile_totals(ipc_batch *b, int32_t kernel, int64_t *launches, double *bytes_total);
 IPC_API int32_t ipc_batch_profile_read(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total,
                                        double *bytes_total);
+/* The same for the timed launches of the PCG iterations whose SpMV launch
+ * (class 0) moves at least 256 MiB of algorithmic bytes, more than the
+ * MI355X's Infinity Cache holds: both kernels of such an iteration stream
+ * from HBM. Classes 0 and 1. */
+IPC_API int32_t ipc_batch_profile_large(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total,
+                                        double *bytes_total);
 
 IPC_API const char *ipc_status_str(int32_t status);
 /* Last error message of the calling thread; returns its length. */

@@ -275,7 +275,13 @@ struct ProfAcc {
     double bytes = 0.0;
     int64_t launches_all = 0;  // every launch of the class while profiling (PCG classes)
     double bytes_all = 0.0;    // and their algorithmic bytes
+    int64_t launches_big = 0;  // timed PCG launches of iterations whose SpMV moves >= kProfBigBytes
+    double ms_big = 0.0, bytes_big = 0.0;
 };
+
+// PCG iterations whose SpMV launch's algorithmic bytes exceed the 256 MiB
+// Infinity Cache: their traffic cannot be served from it
+constexpr double kProfBigBytes = 256.0 * 1024.0 * 1024.0;
 
 // accumulators shared by the lists of a batch engine
 struct ProfSink {
@@ -403,6 +409,7 @@ class Batch {
         int kernel;
         hipEvent_t a, b;
         double bytes;
+        bool big = false;  // a PCG iteration whose SpMV launch moves >= kProfBigBytes
     };
     std::vector<PendingEv> ev_pending;
     ProfSink *sink = nullptr;  // engine lists: timings go here (any list size)

@@ -1339,14 +1339,19 @@ void run_pcg(Batch &b, std::vector<int> &iters, std::vector<int> &hit_cap)
     // still running there (not finished, or finished with more than it - 1
     // iterations); finished solves exit before their first load.
     std::vector<std::pair<size_t, int>> timed_a, timed_b;  // (pending event index, it)
+    auto launch_bytes = [&](const std::vector<double> &sb, int it_) {
+        double v = 0.0;
+        for (size_t i = 0; i < ns; ++i) {
+            if (sb[i] == 0.0) continue;
+            if (!b.h_out[i].pcg_done || it_ <= b.h_out[i].pcg_iters) v += sb[i];
+        }
+        return v;
+    };
     auto settle = [&](std::vector<std::pair<size_t, int>> &timed, const std::vector<double> &sb) {
         for (auto &ta : timed) {
-            double v = 0.0;
-            for (size_t i = 0; i < ns; ++i) {
-                if (sb[i] == 0.0) continue;
-                if (!b.h_out[i].pcg_done || ta.second <= b.h_out[i].pcg_iters) v += sb[i];
-            }
-            b.ev_pending[ta.first].bytes = v;
+            b.ev_pending[ta.first].bytes = launch_bytes(sb, ta.second);
+            // an iteration above the Infinity Cache: its SpMV launch's bytes decide
+            b.ev_pending[ta.first].big = launch_bytes(scene_bytes, ta.second) >= kProfBigBytes;
         }
         timed.clear();
     };

@@ -1136,6 +1136,11 @@ void Batch::prof_collect()
             acc->launches++;
             acc->ms += ms;
             acc->bytes += p.bytes;
+            if (p.big) {
+                acc->launches_big++;
+                acc->ms_big += ms;
+                acc->bytes_big += p.bytes;
+            }
         }
         ev_pool.push_back(p.a);
         ev_pool.push_back(p.b);
@@ -2408,6 +2413,16 @@ int32_t ipc_batch_profile_totals(ipc_batch *b, int32_t kernel, int64_t *launches
     std::lock_guard<std::mutex> g(b->prof.mu);
     if (launches) *launches = b->prof.acc[kernel].launches_all;
     if (bytes_total) *bytes_total = b->prof.acc[kernel].bytes_all;
+    return IPC_OK;
+}
+
+int32_t ipc_batch_profile_large(ipc_batch *b, int32_t kernel, int64_t *launches, double *ms_total, double *bytes_total)
+{
+    if (!b || kernel < 0 || kernel >= kProfKernels) return IPC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(b->prof.mu);
+    if (launches) *launches = b->prof.acc[kernel].launches_big;
+    if (ms_total) *ms_total = b->prof.acc[kernel].ms_big;
+    if (bytes_total) *bytes_total = b->prof.acc[kernel].bytes_big;
     return IPC_OK;
 }
 

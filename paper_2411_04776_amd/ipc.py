@@ -121,6 +121,7 @@ _SIGS = {
     "ipc_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "ipc_batch_profile_totals": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D]),
     "ipc_batch_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D, _D]),
+    "ipc_batch_profile_large": (C.c_int32, [C.c_void_p, C.c_int32, _I64, _D, _D]),
     "ipc_status_str": (C.c_char_p, [C.c_int32]),
     "ipc_last_error": (C.c_int32, [C.c_char_p, C.c_size_t]),
     "ipcx_begin_step": (C.c_int32, [C.c_void_p, C.POINTER(ipc_step_req)]),
@@ -683,4 +684,15 @@ class Batch:
         by = np.zeros(1)
         _check(lib().ipc_batch_profile_read(self.ptr, int(kernel), n.ctypes.data_as(_I64), _d(ms), _d(by)),
                "ipc_batch_profile_read")
+        return int(n[0]), float(ms[0]), float(by[0])
+
+    def profile_large(self, kernel):
+        """(timed launches, summed ms, summed algorithmic bytes) of a PCG
+        kernel class, over the iterations whose SpMV launch moves at least
+        256 MiB (more than the Infinity Cache holds)."""
+        n = np.zeros(1, dtype=np.int64)
+        ms = np.zeros(1)
+        by = np.zeros(1)
+        _check(lib().ipc_batch_profile_large(self.ptr, int(kernel), n.ctypes.data_as(_I64), _d(ms), _d(by)),
+               "ipc_batch_profile_large")
         return int(n[0]), float(ms[0]), float(by[0])

@@ -49,6 +49,13 @@ def counter(d, name, kernel_substr):
     return vals
 
 
+def dispatches(d, name, kernel_substr):
+    """(counter value, grid size, duration s) per dispatch of a kernel."""
+    return [(float(r["Counter_Value"]), int(r["Grid_Size"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+            for r in _rows(d, "counter_collection.csv")
+            if r.get("Counter_Name") == name and kernel_substr in r["Kernel_Name"]]
+
+
 def trace(args):
     per = {}
     for r in _rows(args.dir, "kernel_trace.csv"):
@@ -83,6 +90,22 @@ def pmc(args):
     tw = sum(w) * 1024.0 * sw
     per = (tf + tw) / max(len(f), 1)
     ratio = per / alg if alg else float("nan")
+    # the full-list dispatches (grid of at least 90 % of the largest): their
+    # traffic over their durations in the FETCH run
+    fd = dispatches(args.fetch, "FETCH_SIZE", args.kernel + "<")
+    wd = dispatches(args.write, "WRITE_SIZE", args.kernel + "<")
+    gmax = max(g for _, g, _ in fd)
+    bf = [(v, t) for v, g, t in fd if g >= 0.9 * gmax]
+    bw = [v for v, g, _ in wd if g >= 0.9 * gmax]
+    full = []
+    if bf and bw:
+        fb = statistics.mean(v for v, _ in bf) * 1024.0 * sf + statistics.mean(bw) * 1024.0 * sw
+        fus = statistics.median(t for _, t in bf) * 1e6
+        full = ["", f"Full-list dispatches (grid of at least 90 % of the largest, {gmax} threads): {len(bf)} in the "
+                    f"FETCH run; {fb / 2**20:.1f} MiB of HBM traffic per dispatch over a median {fus:.1f} us "
+                    f"(durations from the counter run) = {fb / (fus * 1e-6) / 1e9:.0f} GB/s.", "",
+                f"full_list_dispatches: {len(bf)}", f"full_list_traffic_bytes: {int(fb)}", f"full_list_us: {fus:.2f}",
+                f"full_list_hbm_gbs: {fb / (fus * 1e-6) / 1e9:.1f}"]
     lines = [f"# HBM traffic of {args.kernel}: {args.title}", "",
              "Commands (repository root, MI355X box), one counter per run:", "```", *args.commands, "```", "",
              f"Calibration: a {args.copy_mib} MiB device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
@@ -95,7 +118,7 @@ def pmc(args):
              f"Algorithmic bytes the library counted for the same launches ({n_alg} launches in the JSON line of the "
              f"FETCH run): {alg / 2**20:.3f} MiB per launch.", "",
              f"traffic_bytes_per_launch: {int(per)}",
-             f"traffic_over_algorithmic: {ratio:.3f}",
+             f"traffic_over_algorithmic: {ratio:.3f}", *full,
              f"kernel_source_sha256: `{source_hash()}`", "",
              "(the hash covers the PCG kernel sources; bench.py reports `traffic` only while it matches)"]
     with open(args.out, "w") as fh:
