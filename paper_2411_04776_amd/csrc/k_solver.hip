@@ -492,8 +492,8 @@ __global__ void __launch_bounds__(kBlock) k_mas_invert(Launch L)
 // before the block's vertex loads; dq_stage adds them (and any rest) after
 // those and leaves the wavefront sums in LDS; dq_alpha, after a block
 // barrier, forms alpha.
-constexpr int kDqU = 8;   // SpMV-block partials per thread in flight (2048: a scene of 131k vertices)
-constexpr int kDqUP = 2;  // pair-block partials per thread in flight
+constexpr int kDqU = 4;   // SpMV-block partials per thread in flight (1024: a scene of 65k vertices; the rest after)
+constexpr int kDqUP = 1;  // pair-block partials per thread in flight
 struct DqIssue {
     double part[kDqU], pair[kDqUP];
     double rz;
