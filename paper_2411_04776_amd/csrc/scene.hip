@@ -2004,7 +2004,7 @@ int64_t ipc_scene_footprint_bytes(const ipc_scene_desc *d)
     if (!check_desc(d)) return -1;
     int64_t n = (int64_t)d->n_verts + d->n_ind_verts, m = d->n_tets;
     int64_t rs = d->precision == IPC_MIXED ? 4 : 8;
-    int64_t per_vertex = 8 * (3 * 8 + 1) + rs * (3 * 8 + 9) + 4 * 4 + 1;
+    int64_t per_vertex = 8 * (3 * 9 + 1) + rs * (3 * 8 + 9) + 4 * 4 + 1;  // nine FP64 3-vectors (the last the target multipliers) and one scalar; the PCG vectors in R
     int64_t per_tet = 4 * 4 + 8 * 10 + rs * (12 + 90) + 4 * 16 + 4 * 4;
     int64_t bell = n * 16 * (9 * rs + 4 + 4);
     int64_t surf = 4 * (int64_t)std::pow((double)d->n_verts, 2.0 / 3.0) + d->n_ind_verts + 2 * d->n_ind_tris;
