@@ -391,8 +391,12 @@ class Batch {
     std::vector<Scene *> sc;
     hipStream_t stream = nullptr;
     SceneDev **d_list = nullptr;     // device array of scene view pointers
-    int32_t *d_off[kPhKinds] = {};   // device block-offset tables
+    int32_t *d_offs = nullptr;       // the block-offset tables, one allocation: table k at k * (cap + 1)
+    int32_t *d_off[kPhKinds] = {};   // device block-offset table of each phase (into d_offs)
     std::vector<int32_t> h_off[kPhKinds];
+    std::vector<int32_t> h_offs;     // host image of d_offs
+    int pend_lo = kPhKinds, pend_hi = -1;  // tables changed since the last upload
+    char *d_vstage = nullptr;        // device staging of several scene views (cap of them)
     SceneOut *d_out = nullptr;       // per-scene read-back slots (device)
     SceneOut *h_out = nullptr;       // pinned
     double *d_alpha = nullptr;       // per-scene line-search step (device)
@@ -403,6 +407,7 @@ class Batch {
     // slots are reused only after the stream has been synchronized
     char *h_stage = nullptr;
     size_t stage_cap = 0, stage_used = 0;
+    void *stage_alloc(size_t bytes);
     void *stage(const void *src, size_t bytes);
     std::vector<hipEvent_t> ev_pool;
     struct PendingEv {
@@ -418,7 +423,10 @@ class Batch {
     void bind(const std::vector<Scene *> &scenes, hipStream_t strm);
     Launch launch(PhaseKind k) const { return Launch{d_list, d_off[k], d_out, (int)sc.size()}; }
     int blocks(PhaseKind k) const { return h_off[k].empty() ? 0 : h_off[k].back(); }
+    // a changed table is uploaded by the next launch (flush_phases), together
+    // with the other tables changed since: one copy of their range of d_offs
     void set_phase(PhaseKind k, const std::vector<int32_t> &per_scene_blocks);
+    void flush_phases();
     void upload_views();
     void read_out();
     bool prof() const;
@@ -433,7 +441,10 @@ class Batch {
 #define IPC_LAUNCH(b, kernel, kind, bs, ...)                                                              \
     do {                                                                                                  \
         int _nb = (b).blocks(kind);                                                                       \
-        if (_nb > 0) hipLaunchKernelGGL(kernel, dim3(_nb), dim3(bs), 0, (b).stream, (b).launch(kind), ##__VA_ARGS__); \
+        if (_nb > 0) {                                                                                    \
+            (b).flush_phases();                                                                           \
+            hipLaunchKernelGGL(kernel, dim3(_nb), dim3(bs), 0, (b).stream, (b).launch(kind), ##__VA_ARGS__); \
+        }                                                                                                 \
     } while (0)
 
 // ---- kernel launchers (defined in the .hip files) -------------------------
@@ -443,6 +454,11 @@ void launch_end_step(Batch &b);
 void launch_al_update(Batch &b, const std::vector<uint8_t> &on);
 void launch_trial(Batch &b);       // uses b.h_alpha (uploaded by the caller to b.d_alpha)
 void launch_accept(Batch &b);
+// n scene views staged at d_src (n destination pointers, padded to 64 bytes,
+// then the n views) put in place by one kernel
+__host__ __device__ inline int64_t view_head_bytes(int64_t n) { return (n * 8 + 63) / 64 * 64; }
+inline size_t view_stage_bytes(int64_t n) { return (size_t)(view_head_bytes(n) + n * (int64_t)sizeof(SceneDev)); }
+void launch_put_views(hipStream_t strm, int n, const void *d_src);
 void launch_rest_precompute(Batch &b);
 void run_lag_and_mean(Batch &b);
 void launch_gather_surface(Scene &s, double *dst, hipStream_t strm);

@@ -970,6 +970,18 @@ __global__ void k_accept(Launch L)
     for (int c = 0; c < 3; ++c) S.x[3 * i + c] = S.xtrial[3 * i + c];
 }
 
+// scene views put in place: block j copies view j of the staged block into
+// the slot its pointer names, in 8-byte words
+static_assert(sizeof(SceneDev) % 8 == 0, "views are copied in 8-byte words");
+constexpr int kViewWords = (int)(sizeof(SceneDev) / 8);
+__global__ void __launch_bounds__(kBlock) k_put_views(int n, const uint64_t *__restrict__ src)
+{
+    const int j = (int)blockIdx.x;
+    uint64_t *dst = reinterpret_cast<uint64_t *>(src[j]);
+    const uint64_t *from = src + view_head_bytes(n) / 8 + (int64_t)j * kViewWords;
+    for (int w = (int)threadIdx.x; w < kViewWords; w += (int)blockDim.x) dst[w] = from[w];
+}
+
 // step start: keep x^t, inertial predictor for free gel vertices, indenter
 // targets from the scene's pose, attached gel vertices' targets from the case
 // pose
@@ -1231,6 +1243,12 @@ void launch_trial(Batch &b)
 }
 
 void launch_accept(Batch &b) { IPC_LAUNCH(b, k_accept, kPhVert, kBlock); }
+
+void launch_put_views(hipStream_t strm, int n, const void *d_src)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_put_views, dim3(n), dim3(kBlock), 0, strm, n, static_cast<const uint64_t *>(d_src));
+}
 
 static void one_per_active(Batch &b, PhaseKind prod)
 {

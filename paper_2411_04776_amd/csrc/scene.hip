@@ -971,18 +971,19 @@ Batch::~Batch()
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(d_list);
-    for (auto &d : d_off) (void)hipFree(d);
+    (void)hipFree(d_offs);
+    (void)hipFree(d_vstage);
     (void)hipFree(d_out);
     (void)hipFree(d_alpha);
     if (h_out) (void)hipHostFree(h_out);
     if (h_stage) (void)hipHostFree(h_stage);
 }
 
-void *Batch::stage(const void *src, size_t bytes)
+void *Batch::stage_alloc(size_t bytes)
 {
     size_t need = (bytes + 63) & ~size_t(63);
     if (!h_stage) {
-        stage_cap = std::max<size_t>(size_t(1) << 20, need);
+        stage_cap = std::max<size_t>(size_t(4) << 20, need);
         IPC_HIP(hipHostMalloc((void **)&h_stage, stage_cap, 0));
         stage_used = 0;
     }
@@ -997,8 +998,14 @@ void *Batch::stage(const void *src, size_t bytes)
         }
     }
     void *p = h_stage + stage_used;
-    std::memcpy(p, src, bytes);
     stage_used += need;
+    return p;
+}
+
+void *Batch::stage(const void *src, size_t bytes)
+{
+    void *p = stage_alloc(bytes);
+    std::memcpy(p, src, bytes);
     return p;
 }
 
@@ -1018,18 +1025,24 @@ void Batch::bind(const std::vector<Scene *> &scenes, hipStream_t strm)
         int nc = std::max(ns, std::max(4, 2 * cap));
         IPC_HIP(hipStreamSynchronize(stream));
         (void)hipFree(d_list);
-        for (auto &d : d_off) (void)hipFree(d);
+        (void)hipFree(d_offs);
+        (void)hipFree(d_vstage);
         (void)hipFree(d_out);
         (void)hipFree(d_alpha);
         if (h_out) (void)hipHostFree(h_out);
         d_list = nullptr;
+        d_offs = nullptr;
+        d_vstage = nullptr;
         d_out = nullptr;
         d_alpha = nullptr;
         h_out = nullptr;
         for (auto &d : d_off) d = nullptr;
         cap = 0;
         IPC_HIP(hipMalloc(&d_list, sizeof(SceneDev *) * nc));
-        for (auto &d : d_off) IPC_HIP(hipMalloc(&d, sizeof(int32_t) * (nc + 1)));
+        IPC_HIP(hipMalloc(&d_offs, sizeof(int32_t) * kPhKinds * (nc + 1)));
+        for (int k = 0; k < kPhKinds; ++k) d_off[k] = d_offs + (size_t)k * (nc + 1);
+        h_offs.assign((size_t)kPhKinds * (nc + 1), 0);
+        IPC_HIP(hipMalloc(&d_vstage, view_stage_bytes(nc)));
         IPC_HIP(hipMalloc(&d_out, sizeof(SceneOut) * nc));
         IPC_HIP(hipMalloc(&d_alpha, sizeof(double) * nc));
         IPC_HIP(hipHostMalloc((void **)&h_out, sizeof(SceneOut) * nc, 0));
@@ -1043,6 +1056,8 @@ void Batch::bind(const std::vector<Scene *> &scenes, hipStream_t strm)
         IPC_HIP(hipMemcpyAsync(d_list, stage(ptrs.data(), sizeof(SceneDev *) * ns), sizeof(SceneDev *) * ns,
                                hipMemcpyHostToDevice, stream));
     for (auto &h : h_off) h.clear();
+    pend_lo = kPhKinds;
+    pend_hi = -1;
     upload_views();
 }
 
@@ -1052,18 +1067,51 @@ void Batch::set_phase(PhaseKind k, const std::vector<int32_t> &per_scene_blocks)
     for (size_t i = 0; i < per_scene_blocks.size(); ++i) off[i + 1] = off[i] + per_scene_blocks[i];
     if (off == h_off[k]) return;
     h_off[k].swap(off);
-    size_t bytes = sizeof(int32_t) * h_off[k].size();
-    IPC_HIP(hipMemcpyAsync(d_off[k], stage(h_off[k].data(), bytes), bytes, hipMemcpyHostToDevice, stream));
+    std::copy(h_off[k].begin(), h_off[k].end(), h_offs.begin() + (size_t)k * (cap + 1));
+    pend_lo = std::min(pend_lo, (int)k);
+    pend_hi = std::max(pend_hi, (int)k);
 }
 
+void Batch::flush_phases()
+{
+    if (pend_hi < 0) return;
+    const size_t stride = (size_t)cap + 1, first = (size_t)pend_lo * stride;
+    const size_t bytes = sizeof(int32_t) * (size_t)(pend_hi - pend_lo + 1) * stride;
+    IPC_HIP(hipMemcpyAsync(d_offs + first, stage(h_offs.data() + first, bytes), bytes, hipMemcpyHostToDevice, stream));
+    pend_lo = kPhKinds;
+    pend_hi = -1;
+}
+
+// One changed view: a copy. Several: one copy of all of them (with their
+// slots' addresses) into d_vstage, then a kernel puts each in its slot.
 void Batch::upload_views()
 {
+    int nd = 0;
+    Scene *one = nullptr;
     for (Scene *s : sc)
         if (s->dev_dirty) {
-            IPC_HIP(hipMemcpyAsync(s->dev, stage(&s->h, sizeof(SceneDev)), sizeof(SceneDev), hipMemcpyHostToDevice,
-                                   stream));
-            s->dev_dirty = false;
+            ++nd;
+            one = s;
         }
+    if (nd == 0) return;
+    if (nd == 1) {
+        IPC_HIP(hipMemcpyAsync(one->dev, stage(&one->h, sizeof(SceneDev)), sizeof(SceneDev), hipMemcpyHostToDevice,
+                               stream));
+        one->dev_dirty = false;
+        return;
+    }
+    const size_t bytes = view_stage_bytes(nd), head = (size_t)view_head_bytes(nd);
+    char *p = static_cast<char *>(stage_alloc(bytes));
+    int j = 0;
+    for (Scene *s : sc)
+        if (s->dev_dirty) {
+            std::memcpy(p + sizeof(SceneDev *) * j, &s->dev, sizeof(SceneDev *));
+            std::memcpy(p + head + sizeof(SceneDev) * j, &s->h, sizeof(SceneDev));
+            s->dev_dirty = false;
+            ++j;
+        }
+    IPC_HIP(hipMemcpyAsync(d_vstage, p, bytes, hipMemcpyHostToDevice, stream));
+    launch_put_views(stream, nd, d_vstage);
 }
 
 void Batch::read_out()
