@@ -383,12 +383,14 @@ __global__ void __launch_bounds__(kBlock) k_assemble_bell(Launch L)
         if (S.hflag[row]) {  // summed by the row's own block in the gradient kernel
             for (int c = 0; c < 9; ++c) cd[c] = S.hdiag[9 * (int64_t)S.heavy_idx[row] + c];
         } else {
-            thread_row_sums<9>(S, row,
-                               [&](int p, int a, int c) {
-                                   int i = c / 3, j = c % 3;
-                                   return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
-                               },
-                               cd);
+            // one entry's nine loads at a time: four entries in flight held
+            // registers for half of the kernel's resident wavefronts, and
+            // only the diagonal lanes of contact rows take this path
+            auto dblk = [&](int p, int a, int c) {
+                int i = c / 3, j = c % 3;
+                return (double)aH[(int64_t)((3 * a + i) * 12 + 3 * a + j) * cap + p];
+            };
+            thread_row_sums<9, decltype(dblk), 1>(S, row, dblk, cd);
         }
     }
     double A[9];

@@ -666,8 +666,8 @@ constexpr int kMasSlots = kMasCapM / kBlock;  // members per thread of a group b
 // aggregate (members, then children, in order), e = E^-1 r_agg per aggregate,
 // and z = D^-1 r + the corrections of the member's aggregates. The r.z
 // partial is r.D^-1 r + sum over the group's aggregates of r_agg.e. The
-// group's index data is loaded at the start, beside the members' vertex data;
-// the aggregates' inverses where they are applied.
+// members' index data is loaded at the start, beside their vertex data; the
+// aggregates' member ranges and inverses where they are used.
 template <class R>
 __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, int it, BShared &sh)
 {
@@ -675,9 +675,10 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
     const int tid = (int)threadIdx.x;
     int k0, k1;
     mas_group_range(S, grp, -1, k0, k1);
-    // level ranges, LDS bases, this thread's first aggregate per level
+    // level ranges and LDS bases (each aggregate's member range is read in
+    // the level loop: loaded up front, the ranges held enough registers to
+    // cost a wavefront per SIMD)
     int ga0[kMasLevels], ga1[kMasLevels], gbase[kMasLevels];
-    int amb[kMasLevels], ame[kMasLevels];
     const R *Di = as<R>(S.mas_dinv);
     {
         int bsum = 0;
@@ -689,13 +690,6 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             ga1[l] = a1;
             gbase[l] = bsum;
             bsum += a1 - a0;
-            amb[l] = ame[l] = 0;
-            int a = a0 + tid;
-            if (a < a1) {
-                int64_t g = S.mas_off[l] + a;
-                amb[l] = glob(S.mas_mb)[g];
-                ame[l] = glob(S.mas_me)[g];
-            }
         }
     }
     if (tid < kMasLevels) {  // the level loop reads these from LDS (block-uniform)
@@ -806,15 +800,8 @@ __device__ void pcg_B_group(const Launch &L, const SceneDev &S, int s, int grp, 
             const int g0 = sh.lv[l][0], g1 = sh.lv[l][1], gb = sh.lv[l][2];
             const int c0 = l > 0 ? sh.lv[l - 1][0] : 0, cb = l > 0 ? sh.lv[l - 1][2] : 0;
             for (int a = g0 + tid; a < g1; a += kBlock) {
-                int j0, j1;
-                if (a == g0 + tid) {
-                    j0 = lvl(amb, l);
-                    j1 = lvl(ame, l);
-                } else {
-                    int64_t g = S.mas_off[l] + a;
-                    j0 = glob(S.mas_mb)[g];
-                    j1 = glob(S.mas_me)[g];
-                }
+                const int64_t g = (int64_t)sh.lv[l][3] + a;
+                const int j0 = glob(S.mas_mb)[g], j1 = glob(S.mas_me)[g];
                 double acc[3] = {0.0, 0.0, 0.0};
                 for (int j = j0; j < j1; ++j) {
                     const double *src = l == 0 ? sh.rm[j - k0] : sh.ra[cb + j - c0];
