@@ -979,21 +979,27 @@ Batch::~Batch()
     if (h_stage) (void)hipHostFree(h_stage);
 }
 
+// The staging buffer starts small (a list of one stages a few hundred bytes
+// between read-backs) and doubles, up to kStageMax, whenever it fills up
+// between two read-backs: a full buffer costs a stream synchronisation.
+constexpr size_t kStageMin = size_t(64) << 10, kStageMax = size_t(64) << 20;
+
 void *Batch::stage_alloc(size_t bytes)
 {
     size_t need = (bytes + 63) & ~size_t(63);
     if (!h_stage) {
-        stage_cap = std::max<size_t>(size_t(4) << 20, need);
+        stage_cap = std::max(kStageMin, need);
         IPC_HIP(hipHostMalloc((void **)&h_stage, stage_cap, 0));
         stage_used = 0;
     }
     if (stage_used + need > stage_cap) {
         IPC_HIP(hipStreamSynchronize(stream));
         stage_used = 0;
-        if (need > stage_cap) {
+        const size_t grown = std::max(need, std::min(2 * stage_cap, kStageMax));
+        if (grown > stage_cap) {
             IPC_HIP(hipHostFree(h_stage));
             h_stage = nullptr;
-            stage_cap = need;
+            stage_cap = grown;
             IPC_HIP(hipHostMalloc((void **)&h_stage, stage_cap, 0));
         }
     }
