@@ -316,6 +316,21 @@ IPC_API int32_t ipcx_candidates(ipc_scene *s, const double *x, const double *p, 
 IPC_API int32_t ipcx_primitives(const ipc_scene *s, int32_t *points, int32_t *edges, int32_t *tris);
 IPC_API int32_t ipcx_gradient(ipc_scene *s, const double *x, double *g);
 IPC_API int32_t ipcx_hess_apply(ipc_scene *s, const double *x, const double *v, double *y);
+/* The body stage alone (the incremental potential's inertia, Neo-Hookean
+ * elasticity and soft kinematic targets, section "Choice of the Simulation
+ * Methods"): its gradient g at x, Dirichlet rows zeroed, and, when v and y
+ * are both given, y = H_body v with Dirichlet rows/columns as identity. No
+ * barrier or friction pair enters. */
+IPC_API int32_t ipcx_assemble_elastic(ipc_scene *s, const double *x, double *g, const double *v, double *y);
+/* The barrier stage alone: the active pairs at x (static candidates with
+ * d < dhat, in candidate order) as the barrier kernel leaves them, up to cap
+ * of them: kind (0 point-triangle, 1 edge-edge), the 4 vertex ids, the
+ * 12-gradient and the row-major 12x12 Hessian (PSD-projected, or the
+ * Gauss-Newton form the scene asks for), with the rows and columns of
+ * Dirichlet vertices zeroed (they live in the body stage's identity rows).
+ * *count gets the number of active pairs. Any output array may be NULL. */
+IPC_API int32_t ipcx_barrier(ipc_scene *s, const double *x, int64_t cap, int32_t *kind, int32_t *v4, double *g12,
+                             double *H144, int64_t *count);
 IPC_API int32_t ipcx_pcg(ipc_scene *s, const double *x, double *p, int32_t *iters);
 IPC_API int32_t ipcx_energy(ipc_scene *s, const double *x, double *E);
 IPC_API int32_t ipcx_ccd(ipc_scene *s, const double *x, const double *p, double *alpha);

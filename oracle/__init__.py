@@ -89,6 +89,9 @@ def lib():
         L.ora_gradient.argtypes = [C.c_void_p, _D, _D]
         L.ora_gradient_terms.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, _D]
         L.ora_hess_apply.argtypes = [C.c_void_p, _D, _D, _D]
+        L.ora_hess_apply_body.argtypes = [C.c_void_p, _D, _D, _D]
+        L.ora_contact_pairs.restype = C.c_int32
+        L.ora_contact_pairs.argtypes = [C.c_void_p, _D, C.c_int32, _I, _I, _D, _D]
         L.ora_hess_dense.argtypes = [C.c_void_p, _D, _D]
         L.ora_pcg.restype = C.c_int32
         L.ora_pcg.argtypes = [C.c_void_p, _D, _D]
@@ -411,6 +414,25 @@ class OracleScene:
         y = np.zeros((self.n, 3))
         lib().ora_hess_apply(self.ptr, _d(f64(x)), _d(f64(v)), _d(y))
         return y
+
+    def hess_apply_body(self, x, v):
+        """H v of the inertia, elastic and soft-target terms only."""
+        y = np.zeros((self.n, 3))
+        lib().ora_hess_apply_body(self.ptr, _d(f64(x)), _d(f64(v)), _d(y))
+        return y
+
+    def contact_pairs(self, x):
+        """The active barrier pairs at x as the assembly forms them: kind
+        (n,), vertex ids (n, 4), gradients (n, 12), Hessians (n, 12, 12),
+        Dirichlet rows not yet dropped."""
+        xx = f64(x)
+        n = lib().ora_contact_pairs(self.ptr, _d(xx), 0, None, None, None, None)
+        kind = np.zeros(max(n, 1), dtype=np.int32)
+        v4 = np.zeros((max(n, 1), 4), dtype=np.int32)
+        g = np.zeros((max(n, 1), 12))
+        H = np.zeros((max(n, 1), 12, 12))
+        lib().ora_contact_pairs(self.ptr, _d(xx), n, _i(kind), _i(v4), _d(g), _d(H))
+        return kind[:n], v4[:n], g[:n], H[:n]
 
     def hess_dense(self, x):
         m = 3 * self.n

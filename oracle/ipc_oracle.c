@@ -1400,11 +1400,13 @@ typedef struct {
     int n_f;       /* friction pairs (after the n_c contacts) */
     double *diag;  /* 9 per vertex: block diagonal of H */
     int n_cand;
+    int32_t *ckind; /* per active contact: 0 PT, 1 EE */
+    double *gc;     /* 12 per active contact: its barrier gradient */
 } assembly;
 
 static void assembly_free(assembly *A)
 {
-    free(A->g); free(A->Hel); free(A->cv); free(A->Hc); free(A->diag);
+    free(A->g); free(A->Hel); free(A->cv); free(A->Hc); free(A->diag); free(A->ckind); free(A->gc);
 }
 
 static void assemble(const ora_scene *s, const double *x, assembly *A)
@@ -1454,6 +1456,8 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
     A->n_c = 0;
     A->cv = (int32_t *)malloc(sizeof(int32_t) * 4 * (A->n_cand + s->n_fric + 1));
     A->Hc = (double *)malloc(sizeof(double) * 144 * (A->n_cand + s->n_fric + 1));
+    A->ckind = (int32_t *)malloc(sizeof(int32_t) * (A->n_cand + 1));
+    A->gc = (double *)malloc(sizeof(double) * 12 * (A->n_cand + 1));
     for (int i = 0; i < A->n_cand; ++i) {
         const int32_t *c = cand.v + 3 * i;
         int32_t v[4];
@@ -1467,6 +1471,8 @@ static void assemble(const ora_scene *s, const double *x, assembly *A)
         double *H = A->Hc + 144 * A->n_c;
         ora_pair_barrier(c[0], x12, s->prm.dhat, s->prm.kappa, eps_x, s->prm.barrier_hessian == 1 ? 2 : 1, g12, H);
         memcpy(A->cv + 4 * A->n_c, v, sizeof v);
+        A->ckind[A->n_c] = c[0];
+        memcpy(A->gc + 12 * A->n_c, g12, sizeof g12);
         for (int a = 0; a < 4; ++a)
             for (int k = 0; k < 3; ++k) A->g[3 * v[a] + k] += g12[3 * a + k];
         for (int a = 0; a < 4; ++a)
@@ -1694,6 +1700,33 @@ void ora_hess_apply(ora_scene *s, const double *x, const double *v, double *y)
     assemble(s, x, &A);
     hess_apply(s, &A, v, y);
     assembly_free(&A);
+}
+
+void ora_hess_apply_body(ora_scene *s, const double *x, const double *v, double *y)
+{
+    assembly A;
+    memset(&A, 0, sizeof A);
+    assemble(s, x, &A);
+    A.n_c = A.n_f = 0; /* the body terms only: no barrier or friction pair */
+    hess_apply(s, &A, v, y);
+    assembly_free(&A);
+}
+
+int32_t ora_contact_pairs(ora_scene *s, const double *x, int32_t cap, int32_t *kind, int32_t *v4, double *g12,
+                          double *H144)
+{
+    assembly A;
+    memset(&A, 0, sizeof A);
+    assemble(s, x, &A);
+    int n = A.n_c;
+    for (int k = 0; k < n && k < cap; ++k) {
+        if (kind) kind[k] = A.ckind[k];
+        if (v4) memcpy(v4 + 4 * k, A.cv + 4 * k, sizeof(int32_t) * 4);
+        if (g12) memcpy(g12 + 12 * k, A.gc + 12 * k, sizeof(double) * 12);
+        if (H144) memcpy(H144 + 144 * k, A.Hc + 144 * k, sizeof(double) * 144);
+    }
+    assembly_free(&A);
+    return n;
 }
 
 void ora_hess_dense(ora_scene *s, const double *x, double *H)

@@ -118,6 +118,16 @@ void ora_hess_apply(ora_scene *s, const double *x, const double *v, double *y);
  * barrier, friction), Dirichlet rows NOT zeroed; 3n doubles each or NULL. */
 void ora_gradient_terms(ora_scene *s, const double *x, double *g_inertia, double *g_elastic, double *g_target,
                         double *g_contact, double *g_friction);
+/* y = H_body v: inertia, elasticity and soft targets only (no barrier or
+ * friction pair), Dirichlet rows/cols replaced by identity. */
+void ora_hess_apply_body(ora_scene *s, const double *x, const double *v, double *y);
+/* The active barrier pairs at x (static candidates with d < dhat, in candidate
+ * order), as the assembly forms them: kind (0 PT, 1 EE), 4 vertex ids, the
+ * 12-gradient and the 12x12 Hessian (row-major; PSD-projected or Gauss-Newton
+ * as the scene's parameters say), before Dirichlet rows are dropped. Writes at
+ * most cap pairs (any array may be NULL); returns the count. */
+int32_t ora_contact_pairs(ora_scene *s, const double *x, int32_t cap, int32_t *kind, int32_t *v4, double *g12,
+                          double *H144);
 /* Dense 3n x 3n form of the matrix ora_hess_apply applies (small scenes only). */
 void ora_hess_dense(ora_scene *s, const double *x, double *H);
 /* Block-Jacobi PCG solve of H p = -g at x; returns iterations. */

@@ -2663,6 +2663,74 @@ int32_t ipcx_hess_apply(ipc_scene *s, const double *x, const double *v, double *
     IPC_HOOK_END(s)
 }
 
+int32_t ipcx_assemble_elastic(ipc_scene *s, const double *x, double *g, const double *v, double *y)
+{
+    if (!s || !x || !g || (v != nullptr) != (y != nullptr)) return IPC_E_INVALID_ARG;
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        Batch &b = solo(*s);
+        activate(b, {1});
+        // no pair enters the lists: the scene's barrier and friction pair
+        // counts read zero for this call
+        const int32_t nf = s->h.n_fric;
+        s->h.n_fric = 0;
+        s->dev_dirty = true;
+        b.upload_views();
+        SceneOut &o = b.h_out[0];
+        o.n_cand = o.n_act = o.n_pair = o.n_heavy = 0;
+        IPC_HIP(hipMemcpyAsync(b.d_out, &o, sizeof(SceneOut), hipMemcpyHostToDevice, b.stream));
+        launch_contact_incidence(b);
+        launch_elastic_elements(b);
+        launch_assemble(b);
+        if (v) {
+            upload_real(*s, s->h.dB, v, 3 * (size_t)s->h.n);
+            launch_hess_apply(b);
+        }
+        s->h.n_fric = nf;
+        s->dev_dirty = true;
+        b.upload_views();
+        download_real(*s, g, s->h.grad, 3 * (size_t)s->h.n);
+        if (v) download_real(*s, y, s->h.q, 3 * (size_t)s->h.n);
+        return IPC_OK;
+    IPC_HOOK_END(s)
+}
+
+int32_t ipcx_barrier(ipc_scene *s, const double *x, int64_t cap, int32_t *kind, int32_t *v4, double *g12,
+                     double *H144, int64_t *count)
+{
+    if (!s || !x || cap < 0) return IPC_E_INVALID_ARG;
+    IPC_HOOK_BEGIN(s)
+        HookState hs(*s, x);
+        int32_t r = hook_assemble(*s);
+        if (r != IPC_OK) return r;
+        Batch &b = solo(*s);
+        const int64_t n = b.h_out[0].n_act, w = std::min(cap, n), pc = s->h.act_cap;
+        if (count) *count = n;
+        if (w > 0) {
+            std::vector<int32_t> idx(w), type(std::max<int64_t>(b.h_out[0].n_cand, 1)), vv(4 * (size_t)pc);
+            std::vector<double> gg(12 * (size_t)pc), hh(144 * (size_t)pc);
+            IPC_HIP(hipMemcpyAsync(idx.data(), s->h.act_idx, sizeof(int32_t) * w, hipMemcpyDeviceToHost, s->stream));
+            IPC_HIP(hipMemcpyAsync(type.data(), s->h.cand, sizeof(int32_t) * type.size(), hipMemcpyDeviceToHost,
+                                   s->stream));
+            IPC_HIP(hipMemcpyAsync(vv.data(), s->h.act_v, sizeof(int32_t) * vv.size(), hipMemcpyDeviceToHost,
+                                   s->stream));
+            download_real(*s, gg.data(), s->h.act_g, gg.size());
+            download_real(*s, hh.data(), s->h.act_H, hh.size());
+            // component-major (component * act_cap + pair) to pair-major
+            for (int64_t k = 0; k < w; ++k) {
+                if (kind) kind[k] = type[idx[k]];
+                if (v4)
+                    for (int a = 0; a < 4; ++a) v4[4 * k + a] = vv[(size_t)a * pc + k];
+                if (g12)
+                    for (int e = 0; e < 12; ++e) g12[12 * k + e] = gg[(size_t)e * pc + k];
+                if (H144)
+                    for (int e = 0; e < 144; ++e) H144[144 * k + e] = hh[(size_t)e * pc + k];
+            }
+        }
+        return IPC_OK;
+    IPC_HOOK_END(s)
+}
+
 int32_t ipcx_pcg(ipc_scene *s, const double *x, double *p, int32_t *iters)
 {
     if (!s || !x || !p) return IPC_E_INVALID_ARG;

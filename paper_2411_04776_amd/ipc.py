@@ -130,6 +130,8 @@ _SIGS = {
     "ipcx_primitives": (C.c_int32, [C.c_void_p, _I, _I, _I]),
     "ipcx_gradient": (C.c_int32, [C.c_void_p, _D, _D]),
     "ipcx_hess_apply": (C.c_int32, [C.c_void_p, _D, _D, _D]),
+    "ipcx_assemble_elastic": (C.c_int32, [C.c_void_p, _D, _D, _D, _D]),
+    "ipcx_barrier": (C.c_int32, [C.c_void_p, _D, C.c_int64, _I, _I, _D, _D, _I64]),
     "ipcx_pcg": (C.c_int32, [C.c_void_p, _D, _D, _I]),
     "ipcx_energy": (C.c_int32, [C.c_void_p, _D, _D]),
     "ipcx_ccd": (C.c_int32, [C.c_void_p, _D, _D, _D]),
@@ -498,6 +500,32 @@ class GelScene:
         y = np.zeros_like(x)
         _check(lib().ipcx_hess_apply(self.ptr, _d(x), _d(v), _d(y)), "ipcx_hess_apply")
         return y
+
+    def assemble_elastic(self, x, v=None):
+        """The body stage alone: its gradient at x, and H_body v if v is given."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        g = np.zeros_like(x)
+        if v is None:
+            _check(lib().ipcx_assemble_elastic(self.ptr, _d(x), _d(g), None, None), "ipcx_assemble_elastic")
+            return g
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        y = np.zeros_like(x)
+        _check(lib().ipcx_assemble_elastic(self.ptr, _d(x), _d(g), _d(v), _d(y)), "ipcx_assemble_elastic")
+        return g, y
+
+    def barrier_pairs(self, x):
+        """The barrier stage alone: kind (n,), vertex ids (n, 4), gradients
+        (n, 12), Hessians (n, 12, 12) of the active pairs at x."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cnt = C.c_int64()
+        _check(lib().ipcx_barrier(self.ptr, _d(x), 0, None, None, None, None, C.byref(cnt)), "ipcx_barrier")
+        n = cnt.value
+        kind = np.zeros(max(n, 1), dtype=np.int32)
+        v4 = np.zeros((max(n, 1), 4), dtype=np.int32)
+        g = np.zeros((max(n, 1), 12))
+        H = np.zeros((max(n, 1), 12, 12))
+        _check(lib().ipcx_barrier(self.ptr, _d(x), n, _i(kind), _i(v4), _d(g), _d(H), C.byref(cnt)), "ipcx_barrier")
+        return kind[:n], v4[:n], g[:n], H[:n]
 
     def pcg(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
