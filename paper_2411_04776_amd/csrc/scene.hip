@@ -1092,30 +1092,25 @@ void Batch::flush_phases()
 // slots' addresses) into d_vstage, then a kernel puts each in its slot.
 void Batch::upload_views()
 {
-    int nd = 0;
-    Scene *one = nullptr;
+    std::vector<Scene *> dirty;  // each changed scene once (its flag cleared as it is taken)
     for (Scene *s : sc)
         if (s->dev_dirty) {
-            ++nd;
-            one = s;
+            dirty.push_back(s);
+            s->dev_dirty = false;
         }
+    const int nd = (int)dirty.size();
     if (nd == 0) return;
     if (nd == 1) {
-        IPC_HIP(hipMemcpyAsync(one->dev, stage(&one->h, sizeof(SceneDev)), sizeof(SceneDev), hipMemcpyHostToDevice,
-                               stream));
-        one->dev_dirty = false;
+        IPC_HIP(hipMemcpyAsync(dirty[0]->dev, stage(&dirty[0]->h, sizeof(SceneDev)), sizeof(SceneDev),
+                               hipMemcpyHostToDevice, stream));
         return;
     }
     const size_t bytes = view_stage_bytes(nd), head = (size_t)view_head_bytes(nd);
     char *p = static_cast<char *>(stage_alloc(bytes));
-    int j = 0;
-    for (Scene *s : sc)
-        if (s->dev_dirty) {
-            std::memcpy(p + sizeof(SceneDev *) * j, &s->dev, sizeof(SceneDev *));
-            std::memcpy(p + head + sizeof(SceneDev) * j, &s->h, sizeof(SceneDev));
-            s->dev_dirty = false;
-            ++j;
-        }
+    for (int j = 0; j < nd; ++j) {
+        std::memcpy(p + sizeof(SceneDev *) * j, &dirty[j]->dev, sizeof(SceneDev *));
+        std::memcpy(p + head + sizeof(SceneDev) * j, &dirty[j]->h, sizeof(SceneDev));
+    }
     IPC_HIP(hipMemcpyAsync(d_vstage, p, bytes, hipMemcpyHostToDevice, stream));
     launch_put_views(stream, nd, d_vstage);
 }
