@@ -4,7 +4,11 @@ vertex end within 1e-4 L of the FP64 oracle's
 (tests/golden/c2_seed{S}_final.npz, written by make_fullsize.py from the
 oracle at PCG tolerance 1e-12): seed 0 (cylinder) in FP64 and in the mixed
 form, with either preconditioner and with the Gauss-Newton barrier Hessian;
-seeds 1-5 (cube edge, bumpy plate, ...) in FP64 and mixed. Seed 3 (a
+seeds 1-5 (cube edge, bumpy plate, ...) in FP64 and mixed. Seed 5 (a bumpy
+plate) ends its last step at the Newton cap in the oracle's run (100
+iterations, |p|_inf still above 1e-6 m) and in both HIP forms (1.99e-6 m):
+a warning with a feasible state, accepted here; its final positions still
+meet the bound. Seed 3 (a
 cylinder) sets the tolerance: its worst vertex, beside the contact edge where
 the soft barrier lets looser solves take the trajectory elsewhere, ends
 1e-5 L away at 3e-5, 5.6e-5 L at 1e-4 with the 512-member preconditioner
@@ -67,14 +71,20 @@ def run(ipc, seed, form):
         kw["barrier_hessian"] = ipc.IPC_BARRIER_GAUSS_NEWTON
     g = ipc.GelScene(sc, **kw)
     newton = 0
+    capped = []
     for k in range(sc.n_steps):
         rc, st = g.step()
-        assert rc in (0, 4), (k, rc)
+        # 1: the Newton cap spent with a feasible state committed (the
+        # oracle's own run of seed 5 ends its last step there too)
+        assert rc in (0, 1, 4), (k, rc)
+        if rc == 1:
+            capped.append((k + 1, round(st.pinf * 1e6, 3)))
         newton += st.newton_iters
     d = np.linalg.norm(g.x[:len(ref)] - ref, axis=1)
     err = d.max() / L
     say(f"  seed {seed} ({sc.meta['kind']}) {form}: 50 steps, {newton} Newton iterations, final error / L = "
-        f"{err:.3e} ({err * L * 1e6:.3f} um, at vertex {int(d.argmax())}), mean {d.mean() / L:.2e}")
+        f"{err:.3e} ({err * L * 1e6:.3f} um, at vertex {int(d.argmax())}), mean {d.mean() / L:.2e}"
+        + (f"; Newton cap at (step, |p|_inf um) {capped}" if capped else ""))
     g.close()
     return err
 
